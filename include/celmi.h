@@ -1,0 +1,217 @@
+/*
+ * celmi.h -- C ABI of the MI355X (gfx950) library for the variational objective of
+ * Regier et al., "Approximate Inference for Constructing Astronomical Catalogs from
+ * Images" (arXiv 1803.00113).
+ *
+ * The library evaluates, for a catalog of S light sources observed in N images, the
+ * evidence lower bound (ELBO) of Section 4.2 (equation elbo) and its gradient, takes
+ * trust-region Newton steps on per-source parameter blocks (Section 4.3) and runs block
+ * coordinate ascent over non-overlapping sources (Sections 4.3-4.4).
+ *
+ * Conventions
+ *  - Every function returns a cel_status (0 = CEL_OK, < 0 = error, > 0 = information).
+ *    Arguments are validated on the host before anything is enqueued; on error nothing
+ *    is launched and no output is written.  cel_strerror() names a status.
+ *  - "DEVICE" pointers are HIP device memory on the context's device, owned by the
+ *    caller and never retained past the call's stream work.  "HOST" pointers are read
+ *    during the call only.
+ *  - Calls are asynchronous on the given stream (0 = the null stream).  Outputs are valid
+ *    once the caller synchronises that stream.  Nothing allocates during evaluation
+ *    calls: scratch is sized by cel_prepare and owned by the plan.
+ *  - A context and its plans are not thread-safe; use one per host thread.
+ *  - Results are deterministic: a fixed plan and inputs give bitwise-identical outputs,
+ *    independent of launch configuration and of which other sources share a launch.
+ *
+ * Parameters of source s (theta[s*32 + k], float64, unconstrained coordinates):
+ *   0-1   u: position (reference pixel frame; image n sees pixel = A_n u + b_n)
+ *   2     logit(a): a = q(star), Section 4.1 (eq0)
+ *   3,4   mean of log r given galaxy / star
+ *   5,6   log variance of log r given galaxy / star
+ *   7-10  colour means given galaxy;   11-14 colour means given star
+ *   15-18 log colour variances given galaxy; 19-22 given star
+ *   23    galaxy angle (radians) | 24 log half-light radius (pixels)
+ *   25    logit(e_profile) (weight of the de Vaucouleurs profile) | 26 logit(e_axis)
+ *   27-31 unused: read as given, gradient written as 0
+ * Colours are c_k = ln(l_{k+1} / l_k) over bands u,g,r,i,z; the reference flux r is the
+ * r band (index 2).
+ */
+#ifndef CELMI_H
+#define CELMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cel_status;
+#define CEL_OK 0
+#define CEL_EINVAL (-1)        /* invalid argument (null pointer, bad size, bad table)   */
+#define CEL_ENOMEM (-2)        /* device allocation failed (only in cel_prepare)         */
+#define CEL_EHIP (-3)          /* a HIP runtime call failed                              */
+#define CEL_EUNSUPPORTED (-4)  /* a size beyond the library's compiled limits            */
+
+/* per-source status written by cel_newton_step / cel_sweep */
+#define CEL_ST_SKIPPED 0       /* not selected by the mask                               */
+#define CEL_ST_ACCEPTED 1      /* trust-region step accepted                             */
+#define CEL_ST_REJECTED 2      /* step rejected, radius shrunk                           */
+#define CEL_ST_CONVERGED 3     /* convergence test met, theta unchanged                  */
+#define CEL_ST_NONFINITE 4     /* objective or gradient not finite, theta unchanged      */
+
+#define CEL_N_THETA 32
+#define CEL_N_PARAM 27
+#define CEL_MAX_PSF 4
+#define CEL_MAX_PROFILE 8
+#define CEL_N_COLOUR_COMPONENTS 8
+
+/* One image (Section 2.2, Table 3): band, PSF as a Gaussian mixture in pixels (Section
+ * 2.2.3), linear WCS, calibration and a sky knot grid (Section 2.2.1). */
+typedef struct {
+  int32_t band;                 /* 0..4 = u,g,r,i,z                                     */
+  int32_t H, W;                 /* rows, cols                                           */
+  int32_t n_psf;                /* 1..CEL_MAX_PSF                                       */
+  double psf[CEL_MAX_PSF][6];   /* weight, mean_x, mean_y, cov_xx, cov_xy, cov_yy       */
+  double A[2][2];               /* pixel (x=col, y=row) = A u + b                       */
+  double b[2];
+  double iota;                  /* expected counts per unit flux (> 0)                  */
+  int32_t sky_qh, sky_qw;       /* knot grid rows, cols (>= 1), spanning the corners    */
+  int64_t sky_off;              /* offset of the row-major knot grid in sky_knots       */
+} cel_image;
+
+/* The active pixels of one source in one image: a rectangle of pixel centres
+ * cols x0..x0+w-1, rows y0..y0+h-1, stored row-major at pixels[pix_off...]. */
+typedef struct {
+  int32_t src, img, x0, y0, w, h;
+  int64_t pix_off;
+} cel_patch;
+
+/* Prior hyperparameters (Section 2.1, Table 2).  Type index 0 = galaxy, 1 = star. */
+typedef struct {
+  double star_prob;                                  /* A in (0,1)                      */
+  double r[2][2];                                    /* mean, variance of log r         */
+  double c_w[2][CEL_N_COLOUR_COMPONENTS];            /* colour GMM weights (sum 1)      */
+  double c_mean[2][CEL_N_COLOUR_COMPONENTS][4];
+  double c_cov[2][CEL_N_COLOUR_COMPONENTS][4][4];    /* symmetric positive definite     */
+  double radius[2];                                  /* mean, variance of log radius    */
+  double profile[2];                                 /* Beta parameters (> 0)           */
+  double axis[2];                                    /* Beta parameters (> 0)           */
+} cel_prior;
+
+/* Galaxy profile mixtures (Section 2.1.2, equation hsi): sum_j alpha_j N(0, tau_j Sigma). */
+typedef struct {
+  int32_t n_exp, n_dev;                              /* 1..CEL_MAX_PROFILE each          */
+  double exp_alpha[CEL_MAX_PROFILE], exp_tau[CEL_MAX_PROFILE];
+  double dev_alpha[CEL_MAX_PROFILE], dev_tau[CEL_MAX_PROFILE];
+} cel_profiles;
+
+/* A problem.  Tables are HOST memory (copied by cel_prepare); pixels are DEVICE memory
+ * holding integer-valued counts >= 0 (float32).  Patches must be sorted by (src, img),
+ * have at most one patch per (src, img), lie inside their image, have w, h >= 1 and
+ * w*h <= 2^22, and not overlap in `pixels`. */
+typedef struct {
+  int32_t n_sources, n_images, n_patches;
+  const cel_image* images;       /* HOST [n_images]                                     */
+  const double* sky_knots;       /* HOST [n_sky_knots]                                  */
+  int64_t n_sky_knots;
+  const cel_patch* patches;      /* HOST [n_patches]                                    */
+  const float* pixels;           /* DEVICE [n_pixels]; read only inside cel_prepare     */
+  int64_t n_pixels;
+  const cel_prior* prior;        /* HOST                                                */
+  const cel_profiles* profiles;  /* HOST                                                */
+} cel_problem;
+
+typedef struct {
+  int32_t pixels_per_lane;       /* 1, 2 or 4; 0 = default                              */
+  int32_t chunk_pixels;          /* pixels per work item (multiple of 64); 0 = default  */
+  int32_t pixel_fp64;            /* 1: evaluate pixels in float64 instead of float32     */
+  int32_t hessian_fp64;          /* 1: FD Hessian from the float64 pixel path           */
+  double fd_step;                /* central-difference step of the Hessian; 0 = 1e-3     */
+  double radius0, radius_max, eta, gtol, ftol, radius_min;   /* trust region (0 = default) */
+  int32_t timing;                /* 1: record HIP events around each phase (see below)  */
+} cel_options;
+
+typedef struct cel_ctx cel_ctx;
+typedef struct cel_plan cel_plan;
+
+const char* cel_strerror(cel_status s);
+
+/* Create a context on HIP device `hip_device`.  opt may be NULL (defaults). */
+cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_options* opt);
+void cel_destroy(cel_ctx* ctx);
+
+/* Validate a problem and build a plan: patch overlap lists, the source overlap graph and
+ * its greedy colouring (ascending id, smallest free colour), work items sorted by cost,
+ * and device copies of the tables; reads the pixels once (on `stream`, synchronised
+ * before return) to form per-pixel (count, sky) pairs and the per-patch data constants
+ * sum(x log x - x - log x!).  Owns all scratch of later calls.  Synchronous. */
+cel_status cel_prepare(cel_ctx* ctx, const cel_problem* prob, cel_plan** out, void* stream);
+void cel_plan_free(cel_plan* plan);
+
+/* Plan facts.  colours: HOST [n_sources] or NULL; returns counts via out-pointers. */
+cel_status cel_plan_info(const cel_plan* plan, int64_t* n_units, int32_t* n_colours, int32_t* colours,
+                         int64_t* n_work_items);
+
+/* ELBO (Section 4.2, equation elbo).  theta: DEVICE float64 [S*32].
+ * elbo_total: DEVICE float64 [1] -- every pixel of the union of patches once, minus
+ *   every source's KL.
+ * elbo_local: DEVICE float64 [S] or NULL -- L_s = sum over the pixels of s's patches of
+ *   the expected log-likelihood term (with every source's light) minus KL_s; its
+ *   gradient in theta_s equals that of the total. */
+cel_status cel_elbo_eval(cel_ctx* ctx, const cel_plan* plan, const double* theta, double* elbo_total,
+                         double* elbo_local, void* stream);
+
+/* ELBO and its gradient in the unconstrained coordinates: grad DEVICE float64 [S*32]
+ * (entries 27-31 written 0).  elbo_total / elbo_local as above (either may be NULL). */
+cel_status cel_elbo_grad(cel_ctx* ctx, const cel_plan* plan, const double* theta, double* elbo_total,
+                         double* elbo_local, double* grad, void* stream);
+
+/* Same as cel_elbo_grad, one launch sequence per source ("plain" form, for comparison
+ * with the batched form).  Slower by design; identical results. */
+cel_status cel_elbo_grad_plain(cel_ctx* ctx, const cel_plan* plan, const double* theta, double* elbo_total,
+                               double* elbo_local, double* grad, void* stream);
+
+/* One trust-region Newton step (Section 4.3) on every source with mask[s] != 0 (HOST
+ * uint8 [S], NULL = all), all from the same iterate.  Masked sources must be pairwise
+ * non-overlapping (checked against the plan: CEL_EINVAL otherwise).  Hessian by central
+ * differences of the gradient in the unconstrained coordinates; the subproblem is solved
+ * exactly (eigen-decomposition, boundary multiplier by a safeguarded secular-equation
+ * iteration, hard case completed along the lowest eigenvector).
+ * theta: DEVICE [S*32] in/out; radius: DEVICE float64 [S] in/out (trust radii);
+ * step_status: DEVICE int32 [S] out (CEL_ST_*); elbo_local: DEVICE float64 [S] out or
+ * NULL (L_s at the returned theta, NaN for skipped sources). */
+cel_status cel_newton_step(cel_ctx* ctx, const cel_plan* plan, double* theta, double* radius,
+                           const uint8_t* mask, int32_t* step_status, double* elbo_local, void* stream);
+
+typedef struct {
+  int32_t n_sweeps;              /* block coordinate ascent passes (default 3)           */
+  int32_t max_newton_iters;      /* per colour class per sweep (default 50)              */
+  int32_t use_graph;             /* 1: replay a captured HIP graph per colour class      */
+} cel_sweep_opts;
+
+typedef struct {
+  double elbo_total;             /* at the returned theta                                */
+  int32_t n_colours;
+  int64_t n_newton_steps;        /* batched steps taken                                  */
+  double seconds;                /* wall time of the call                                */
+} cel_sweep_report;
+
+/* Block coordinate ascent (Sections 4.3-4.4): for each sweep and each colour class in
+ * ascending colour, Newton steps on the whole class (all members at once: they do not
+ * overlap) until every member has converged or max_newton_iters steps were taken.  The
+ * trust radius of every source starts at radius0 at each sweep.  theta DEVICE in/out;
+ * radius DEVICE float64 [S] out; status DEVICE int32 [S] out (last status per source);
+ * report HOST (filled after an internal stream synchronisation). */
+cel_status cel_sweep(cel_ctx* ctx, const cel_plan* plan, double* theta, double* radius, int32_t* status,
+                     const cel_sweep_opts* opts, cel_sweep_report* report, void* stream);
+
+/* Measurement: with options.timing = 1, every ELBO / gradient evaluation records HIP events
+ * on the caller's stream around its phases.  This returns the summed device milliseconds
+ * since the last reset -- ms[0] component tables, ms[1] pixel kernel, ms[2] finalisation
+ * and total -- and the number of evaluations recorded (it synchronises on the recorded
+ * events).  reset != 0 clears the record.  CEL_EINVAL if timing was not enabled. */
+cel_status cel_phase_times(cel_plan* plan, double* ms, int64_t* n_calls, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CELMI_H */

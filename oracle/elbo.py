@@ -379,7 +379,7 @@ def local_hessian(model, theta, s):
     """d^2 L_s / dtheta_s^2 (27 x 27) by forward-over-reverse autodiff."""
     f = local_objective(model, theta, s)
     ts = torch.as_tensor(np.asarray(theta)[s, :N_PARAM], dtype=DT)
-    return torch.autograd.functional.hessian(f, ts).numpy()
+    return torch.autograd.functional.hessian(f, ts, vectorize=True).numpy()
 
 
 def n_active_pixels(model, s):

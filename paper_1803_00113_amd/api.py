@@ -1,0 +1,246 @@
+"""Python binding of the celmi library: argument marshalling around the C ABI.
+
+Every computation runs in the HIP kernels of libcelmi.so; this module only builds the
+host tables of a problem, moves arrays to the device with torch and passes pointers.
+
+A problem is any object with the array attributes of include/celmi.h's cel_problem in
+numpy form (img_band, img_H, img_W, img_npsf, img_psf, img_A, img_b, img_iota, img_sky_qh,
+img_sky_qw, img_sky_off, sky_knots, patch_src, patch_img, patch_x0, patch_y0, patch_w,
+patch_h, patch_off, pixels, prior_a, prior_r, prior_cw, prior_cmean, prior_ccov,
+prior_radius, prior_profile, prior_axis, exp_alpha, exp_tau, dev_alpha, dev_tau,
+n_sources).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _ffi as F
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class Context:
+    """A library context on one HIP device (cel_create)."""
+
+    def __init__(self, device=0, pixels_per_lane=0, chunk_pixels=0, pixel_fp64=False, hessian_fp64=False,
+                 fd_step=0.0, timing=False, **tr):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the celmi library needs an MI355X (gfx950)")
+        o = F.CelOptions()
+        o.pixels_per_lane = int(pixels_per_lane)
+        o.chunk_pixels = int(chunk_pixels)
+        o.pixel_fp64 = int(bool(pixel_fp64))
+        o.hessian_fp64 = int(bool(hessian_fp64))
+        o.fd_step = float(fd_step)
+        o.timing = int(bool(timing))
+        for k in ("radius0", "radius_max", "eta", "gtol", "ftol", "radius_min"):
+            setattr(o, k, float(tr.get(k, 0.0)))
+        h = C.c_void_p()
+        F.check("cel_create", F.lib.cel_create(C.byref(h), int(device), C.byref(o)))
+        self.h = h
+        self.device = torch.device("cuda", int(device))
+        self.options = o
+
+    def close(self):
+        if getattr(self, "h", None):
+            F.lib.cel_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def host_tables(prob):
+    """cel_image / cel_patch arrays and prior / profile structs of a problem."""
+    N = int(len(prob.img_band))
+    P = int(len(prob.patch_src))
+    images = (F.CelImage * max(N, 1))()
+    for n in range(N):
+        im = images[n]
+        im.band = int(prob.img_band[n])
+        im.H = int(prob.img_H[n])
+        im.W = int(prob.img_W[n])
+        im.n_psf = int(prob.img_npsf[n])
+        for k in range(F.MAX_PSF):
+            for q in range(6):
+                im.psf[k][q] = float(prob.img_psf[n, k, q])
+        for i in range(2):
+            for j in range(2):
+                im.A[i][j] = float(prob.img_A[n, i, j])
+            im.b[i] = float(prob.img_b[n, i])
+        im.iota = float(prob.img_iota[n])
+        im.sky_qh = int(prob.img_sky_qh[n])
+        im.sky_qw = int(prob.img_sky_qw[n])
+        im.sky_off = int(prob.img_sky_off[n])
+    patches = np.zeros(max(P, 1), dtype=np.dtype([("src", "<i4"), ("img", "<i4"), ("x0", "<i4"), ("y0", "<i4"),
+                                                   ("w", "<i4"), ("h", "<i4"), ("pix_off", "<i8")]))
+    patches = patches[:P] if P else patches[:0]
+    patches["src"], patches["img"] = prob.patch_src, prob.patch_img
+    patches["x0"], patches["y0"] = prob.patch_x0, prob.patch_y0
+    patches["w"], patches["h"] = prob.patch_w, prob.patch_h
+    patches["pix_off"] = prob.patch_off
+    patches = np.ascontiguousarray(patches)
+    pr = F.CelPrior()
+    pr.star_prob = float(prob.prior_a)
+    J = prob.prior_cw.shape[1]
+    if J > F.N_COLOUR_COMPONENTS:
+        raise ValueError("at most 8 colour prior components")
+    for i in range(2):
+        pr.r[i][0], pr.r[i][1] = float(prob.prior_r[i, 0]), float(prob.prior_r[i, 1])
+        for j in range(F.N_COLOUR_COMPONENTS):
+            if j < J:
+                pr.c_w[i][j] = float(prob.prior_cw[i, j])
+                for k in range(4):
+                    pr.c_mean[i][j][k] = float(prob.prior_cmean[i, j, k])
+                    for l in range(4):
+                        pr.c_cov[i][j][k][l] = float(prob.prior_ccov[i, j, k, l])
+            else:
+                pr.c_w[i][j] = 0.0
+                for k in range(4):
+                    pr.c_cov[i][j][k][k] = 1.0
+    pr.radius[0], pr.radius[1] = float(prob.prior_radius[0]), float(prob.prior_radius[1])
+    pr.profile[0], pr.profile[1] = float(prob.prior_profile[0]), float(prob.prior_profile[1])
+    pr.axis[0], pr.axis[1] = float(prob.prior_axis[0]), float(prob.prior_axis[1])
+    pf = F.CelProfiles()
+    pf.n_exp, pf.n_dev = len(prob.exp_alpha), len(prob.dev_alpha)
+    if pf.n_exp > F.MAX_PROFILE or pf.n_dev > F.MAX_PROFILE:
+        raise ValueError("at most 8 components per profile")
+    for j in range(pf.n_exp):
+        pf.exp_alpha[j], pf.exp_tau[j] = float(prob.exp_alpha[j]), float(prob.exp_tau[j])
+    for j in range(pf.n_dev):
+        pf.dev_alpha[j], pf.dev_tau[j] = float(prob.dev_alpha[j]), float(prob.dev_tau[j])
+    knots = np.ascontiguousarray(prob.sky_knots, dtype=np.float64)
+    return images, knots, patches, pr, pf
+
+
+class Plan:
+    """A prepared problem (cel_prepare).  Pixels are read once, during construction."""
+
+    def __init__(self, ctx: Context, prob, stream=None):
+        self.ctx = ctx
+        dev = ctx.device
+        images, knots, patches, prior, profiles = host_tables(prob)
+        pixels = torch.as_tensor(np.ascontiguousarray(prob.pixels, dtype=np.float32)).to(dev)
+        cp = F.CelProblem()
+        cp.n_sources = int(prob.n_sources)
+        cp.n_images = int(len(prob.img_band))
+        cp.n_patches = int(len(prob.patch_src))
+        cp.images = C.cast(images, C.POINTER(F.CelImage))
+        cp.sky_knots = knots.ctypes.data_as(C.POINTER(C.c_double))
+        cp.n_sky_knots = int(knots.size)
+        cp.patches = patches.ctypes.data_as(C.POINTER(F.CelPatch))
+        cp.pixels = C.c_void_p(pixels.data_ptr())
+        cp.n_pixels = int(pixels.numel())
+        cp.prior = C.pointer(prior)
+        cp.profiles = C.pointer(profiles)
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            st = stream if stream is not None else _stream(dev)
+            F.check("cel_prepare", F.lib.cel_prepare(ctx.h, C.byref(cp), C.byref(h), st))
+        self.h = h
+        self.S = int(prob.n_sources)
+        nu, nc, nw = C.c_int64(), C.c_int32(), C.c_int64()
+        col = (C.c_int32 * max(self.S, 1))()
+        F.check("cel_plan_info", F.lib.cel_plan_info(h, C.byref(nu), C.byref(nc), col, C.byref(nw)))
+        self.n_units = int(nu.value)
+        self.n_colours = int(nc.value)
+        self.n_work_items = int(nw.value)
+        self.colours = np.array(col[:self.S], dtype=np.int32)
+
+    def close(self):
+        if getattr(self, "h", None):
+            F.lib.cel_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # -- helpers ---------------------------------------------------------------------------
+    def _theta(self, theta):
+        t = torch.as_tensor(theta, dtype=torch.float64, device=self.ctx.device)
+        if t.shape != (self.S, F.N_THETA):
+            raise ValueError(f"theta must be [{self.S}, {F.N_THETA}]")
+        return t.contiguous()
+
+    def phase_times(self, reset=True):
+        """cel_phase_times: (ms[tables, pixels, finalise], n_evaluations) since the last reset."""
+        ms = (C.c_double * 3)()
+        n = C.c_int64()
+        F.check("cel_phase_times", F.lib.cel_phase_times(self.h, ms, C.byref(n), int(bool(reset))))
+        return list(ms), int(n.value)
+
+    def _out(self, *shape):
+        return torch.empty(shape, dtype=torch.float64, device=self.ctx.device)
+
+
+def elbo_eval(plan: Plan, theta):
+    """cel_elbo_eval: returns (elbo_total [1], elbo_local [S]) device tensors."""
+    th = plan._theta(theta)
+    tot, loc = plan._out(1), plan._out(plan.S)
+    F.check("cel_elbo_eval", F.lib.cel_elbo_eval(plan.ctx.h, plan.h, _ptr(th), _ptr(tot), _ptr(loc),
+                                                 _stream(plan.ctx.device)))
+    return tot, loc
+
+
+def elbo_grad(plan: Plan, theta):
+    """cel_elbo_grad: returns (elbo_total [1], elbo_local [S], grad [S,32]) device tensors."""
+    th = plan._theta(theta)
+    tot, loc, g = plan._out(1), plan._out(plan.S), plan._out(plan.S, F.N_THETA)
+    F.check("cel_elbo_grad", F.lib.cel_elbo_grad(plan.ctx.h, plan.h, _ptr(th), _ptr(tot), _ptr(loc), _ptr(g),
+                                                 _stream(plan.ctx.device)))
+    return tot, loc, g
+
+
+def elbo_grad_plain(plan: Plan, theta):
+    """cel_elbo_grad_plain: one launch per source; same outputs as elbo_grad."""
+    th = plan._theta(theta)
+    tot, loc, g = plan._out(1), plan._out(plan.S), plan._out(plan.S, F.N_THETA)
+    F.check("cel_elbo_grad_plain", F.lib.cel_elbo_grad_plain(plan.ctx.h, plan.h, _ptr(th), _ptr(tot), _ptr(loc),
+                                                             _ptr(g), _stream(plan.ctx.device)))
+    return tot, loc, g
+
+
+def newton_step(plan: Plan, theta, radius, mask=None):
+    """cel_newton_step: theta [S,32] and radius [S] device float64 tensors updated in place.
+    mask: host bool/uint8 array [S] or None.  Returns (status [S] int32, elbo_local [S])."""
+    if not (isinstance(theta, torch.Tensor) and theta.is_cuda and theta.dtype == torch.float64
+            and theta.is_contiguous() and theta.shape == (plan.S, F.N_THETA)):
+        raise ValueError("theta must be a contiguous cuda float64 tensor [S,32]")
+    if not (isinstance(radius, torch.Tensor) and radius.is_cuda and radius.dtype == torch.float64
+            and radius.shape == (plan.S,)):
+        raise ValueError("radius must be a cuda float64 tensor [S]")
+    st = torch.empty(plan.S, dtype=torch.int32, device=plan.ctx.device)
+    loc = plan._out(plan.S)
+    m = None
+    if mask is not None:
+        mk = np.ascontiguousarray(np.asarray(mask).astype(np.uint8))
+        if mk.shape != (plan.S,):
+            raise ValueError("mask must have one entry per source")
+        m = mk.ctypes.data_as(C.POINTER(C.c_uint8))
+    F.check("cel_newton_step", F.lib.cel_newton_step(plan.ctx.h, plan.h, _ptr(theta), _ptr(radius), m, _ptr(st),
+                                                     _ptr(loc), _stream(plan.ctx.device)))
+    return st, loc
+
+
+def sweep(plan: Plan, theta, n_sweeps=3, max_newton_iters=50, use_graph=True):
+    """cel_sweep: theta updated in place.  Returns (radius, status, report dict)."""
+    if not (isinstance(theta, torch.Tensor) and theta.is_cuda and theta.dtype == torch.float64
+            and theta.is_contiguous() and theta.shape == (plan.S, F.N_THETA)):
+        raise ValueError("theta must be a contiguous cuda float64 tensor [S,32]")
+    radius = plan._out(plan.S)
+    st = torch.empty(plan.S, dtype=torch.int32, device=plan.ctx.device)
+    o = F.CelSweepOpts(int(n_sweeps), int(max_newton_iters), int(bool(use_graph)))
+    rep = F.CelSweepReport()
+    F.check("cel_sweep", F.lib.cel_sweep(plan.ctx.h, plan.h, _ptr(theta), _ptr(radius), _ptr(st), C.byref(o),
+                                         C.byref(rep), _stream(plan.ctx.device)))
+    return radius, st, dict(elbo=rep.elbo_total, n_colours=rep.n_colours, n_newton_steps=rep.n_newton_steps,
+                            seconds=rep.seconds)

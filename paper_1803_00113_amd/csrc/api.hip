@@ -1,0 +1,785 @@
+// Host side of the celmi C ABI: validation, plan building and launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "device.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace celmi;
+
+extern "C" const char* cel_strerror(cel_status s) {
+  switch (s) {
+    case CEL_OK: return "ok";
+    case CEL_EINVAL: return "invalid argument";
+    case CEL_ENOMEM: return "device allocation failed";
+    case CEL_EHIP: return "HIP runtime error";
+    case CEL_EUNSUPPORTED: return "unsupported size or option";
+    default: return "unknown status";
+  }
+}
+
+namespace celmi {
+
+cel_options default_options() {
+  cel_options o;
+  std::memset(&o, 0, sizeof(o));
+  o.pixels_per_lane = 2;
+  o.chunk_pixels = 512;
+  o.fd_step = 1e-3;
+  o.radius0 = 1.0;
+  o.radius_max = 100.0;
+  o.eta = 0.1;
+  o.gtol = 1e-6;
+  o.ftol = 1e-9;
+  o.radius_min = 1e-8;
+  return o;
+}
+
+static cel_options merge_options(const cel_options* in) {
+  cel_options o = default_options();
+  if (!in) return o;
+  if (in->pixels_per_lane) o.pixels_per_lane = in->pixels_per_lane;
+  if (in->chunk_pixels) o.chunk_pixels = in->chunk_pixels;
+  o.pixel_fp64 = in->pixel_fp64;
+  o.hessian_fp64 = in->hessian_fp64;
+  if (in->fd_step > 0) o.fd_step = in->fd_step;
+  if (in->radius0 > 0) o.radius0 = in->radius0;
+  if (in->radius_max > 0) o.radius_max = in->radius_max;
+  if (in->eta > 0) o.eta = in->eta;
+  if (in->gtol > 0) o.gtol = in->gtol;
+  if (in->ftol > 0) o.ftol = in->ftol;
+  if (in->radius_min > 0) o.radius_min = in->radius_min;
+  o.timing = in->timing;
+  return o;
+}
+
+template <typename X>
+static cel_status dalloc(X** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc((void**)p, n * sizeof(X)) != hipSuccess) {
+    *p = nullptr;
+    return CEL_ENOMEM;
+  }
+  return CEL_OK;
+}
+
+template <typename X>
+static cel_status upload(X** p, const std::vector<X>& v) {
+  cel_status st = dalloc(p, v.size());
+  if (st) return st;
+  if (!v.empty() && hipMemcpy(*p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice) != hipSuccess)
+    return CEL_EHIP;
+  return CEL_OK;
+}
+
+static bool finite(double x) { return std::isfinite(x); }
+
+// inverse and log-determinant of a symmetric positive definite 4x4 matrix (Cholesky)
+static bool spd_inverse4(const double in[4][4], double out[4][4], double* logdet) {
+  double L[4][4] = {};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = in[i][j];
+      for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+      if (i == j) {
+        if (!(s > 0)) return false;
+        L[i][i] = std::sqrt(s);
+      } else {
+        L[i][j] = s / L[j][j];
+      }
+    }
+  *logdet = 0;
+  for (int i = 0; i < 4; ++i) *logdet += 2.0 * std::log(L[i][i]);
+  // inverse via solving L L^T X = I column by column
+  for (int c = 0; c < 4; ++c) {
+    double y[4], x[4];
+    for (int i = 0; i < 4; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+      y[i] = s / L[i][i];
+    }
+    for (int i = 3; i >= 0; --i) {
+      double s = y[i];
+      for (int k = i + 1; k < 4; ++k) s -= L[k][i] * x[k];
+      x[i] = s / L[i][i];
+    }
+    for (int i = 0; i < 4; ++i) out[i][c] = x[i];
+  }
+  return true;
+}
+
+static cel_status validate(const cel_problem* pr) {
+  if (!pr || pr->n_sources < 0 || pr->n_images < 0 || pr->n_patches < 0 || pr->n_pixels < 0 ||
+      pr->n_sky_knots < 0)
+    return CEL_EINVAL;
+  if (pr->n_images > 0 && !pr->images) return CEL_EINVAL;
+  if (pr->n_patches > 0 && (!pr->patches || !pr->pixels)) return CEL_EINVAL;
+  if (!pr->prior || !pr->profiles) return CEL_EINVAL;
+  if (pr->n_sky_knots > 0 && !pr->sky_knots) return CEL_EINVAL;
+  for (int n = 0; n < pr->n_images; ++n) {
+    const cel_image& im = pr->images[n];
+    if (im.band < 0 || im.band > 4 || im.H < 1 || im.W < 1 || im.n_psf < 1) return CEL_EINVAL;
+    if (im.n_psf > kMaxPsf) return CEL_EUNSUPPORTED;
+    for (int k = 0; k < im.n_psf; ++k) {
+      const double* q = im.psf[k];
+      for (int i = 0; i < 6; ++i)
+        if (!finite(q[i])) return CEL_EINVAL;
+      if (q[0] < 0 || !(q[3] > 0) || !(q[3] * q[5] - q[4] * q[4] > 0)) return CEL_EINVAL;
+    }
+    const double det = im.A[0][0] * im.A[1][1] - im.A[0][1] * im.A[1][0];
+    if (!finite(det) || det == 0.0 || !finite(im.b[0]) || !finite(im.b[1])) return CEL_EINVAL;
+    if (!(im.iota > 0) || !finite(im.iota)) return CEL_EINVAL;
+    if (im.sky_qh < 1 || im.sky_qw < 1 || im.sky_off < 0 ||
+        im.sky_off + (int64_t)im.sky_qh * im.sky_qw > pr->n_sky_knots)
+      return CEL_EINVAL;
+    if ((im.sky_qh > 1 && im.H < 2) || (im.sky_qw > 1 && im.W < 2)) return CEL_EINVAL;
+    for (int64_t i = 0; i < (int64_t)im.sky_qh * im.sky_qw; ++i) {
+      const double v = pr->sky_knots[im.sky_off + i];
+      if (!(v > 0) || !finite(v)) return CEL_EINVAL;
+    }
+  }
+  for (int p = 0; p < pr->n_patches; ++p) {
+    const cel_patch& q = pr->patches[p];
+    if (q.src < 0 || q.src >= pr->n_sources || q.img < 0 || q.img >= pr->n_images) return CEL_EINVAL;
+    if (q.w < 1 || q.h < 1) return CEL_EINVAL;
+    if ((int64_t)q.w * q.h > (int64_t(1) << 22)) return CEL_EUNSUPPORTED;
+    const cel_image& im = pr->images[q.img];
+    if (q.x0 < 0 || q.y0 < 0 || (int64_t)q.x0 + q.w > im.W || (int64_t)q.y0 + q.h > im.H) return CEL_EINVAL;
+    if (q.pix_off < 0 || q.pix_off + (int64_t)q.w * q.h > pr->n_pixels) return CEL_EINVAL;
+    if (p > 0) {
+      const cel_patch& r = pr->patches[p - 1];
+      if (r.src > q.src || (r.src == q.src && r.img >= q.img)) return CEL_EINVAL;
+    }
+  }
+  const cel_prior& pp = *pr->prior;
+  if (!(pp.star_prob > 0 && pp.star_prob < 1)) return CEL_EINVAL;
+  for (int i = 0; i < 2; ++i) {
+    if (!finite(pp.r[i][0]) || !(pp.r[i][1] > 0)) return CEL_EINVAL;
+    double sw = 0;
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+      if (!(pp.c_w[i][j] >= 0)) return CEL_EINVAL;
+      sw += pp.c_w[i][j];
+      double inv[4][4], ld;
+      if (pp.c_w[i][j] > 0 && !spd_inverse4(pp.c_cov[i][j], inv, &ld)) return CEL_EINVAL;
+    }
+    if (!(std::fabs(sw - 1.0) < 1e-6)) return CEL_EINVAL;
+  }
+  if (!finite(pp.radius[0]) || !(pp.radius[1] > 0)) return CEL_EINVAL;
+  if (!(pp.profile[0] > 0 && pp.profile[1] > 0 && pp.axis[0] > 0 && pp.axis[1] > 0)) return CEL_EINVAL;
+  const cel_profiles& pf = *pr->profiles;
+  if (pf.n_exp < 1 || pf.n_dev < 1) return CEL_EINVAL;
+  if (pf.n_exp > kMaxProf || pf.n_dev > kMaxProf) return CEL_EUNSUPPORTED;
+  for (int j = 0; j < pf.n_exp; ++j)
+    if (!(pf.exp_alpha[j] >= 0) || !(pf.exp_tau[j] > 0)) return CEL_EINVAL;
+  for (int j = 0; j < pf.n_dev; ++j)
+    if (!(pf.dev_alpha[j] >= 0) || !(pf.dev_tau[j] > 0)) return CEL_EINVAL;
+  return CEL_OK;
+}
+
+void plan_release(cel_plan* p) {
+  if (!p) return;
+  for (auto& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (p->mask_copied) (void)hipEventDestroy(p->mask_copied);
+  if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
+  if (p->h_mask) (void)hipHostFree(p->h_mask);
+  if (p->h_counter) (void)hipHostFree(p->h_counter);
+  if (p->h_total) (void)hipHostFree(p->h_total);
+  for (void* ptr : p->allocs) (void)hipFree(ptr);
+  for (auto& r : p->ev_rec)
+    for (hipEvent_t e : r) p->ev_pool.push_back(e);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  delete p;
+}
+
+void phase_mark(cel_plan* p, int k, hipStream_t sm) {
+  if (!p->opt.timing || !p->marking) return;
+  if (k == 0) {
+    std::array<hipEvent_t, 4> r;
+    for (int i = 0; i < 4; ++i) {
+      if (p->ev_pool.empty()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        p->ev_pool.push_back(e);
+      }
+      r[i] = p->ev_pool.back();
+      p->ev_pool.pop_back();
+    }
+    p->ev_rec.push_back(r);
+  }
+  if (p->ev_rec.empty()) return;
+  (void)hipEventRecord(p->ev_rec.back()[k], sm);
+}
+
+template <typename X>
+static cel_status track(cel_plan* p, X** ptr, size_t n) {
+  cel_status st = dalloc(ptr, n);
+  if (!st) p->allocs.push_back((void*)*ptr);
+  return st;
+}
+
+template <typename X>
+static cel_status track_upload(cel_plan* p, X** ptr, const std::vector<X>& v) {
+  cel_status st = upload(ptr, v);
+  if (*ptr) p->allocs.push_back((void*)*ptr);
+  return st;
+}
+
+// grow the per-variant scratch (tables, slots, per-source outputs) to hold nv variants
+cel_status ensure_variants(cel_plan* p, int nv, bool fp64) {
+  if (fp64 ? (p->nv_d >= nv) : (p->nv_f >= nv)) {
+    if (p->nv_slots >= nv) return CEL_OK;
+  }
+  cel_status st;
+  if (fp64 && p->nv_d < nv) {
+    if ((st = track(p, &p->tables_d, (size_t)nv * std::max(p->P, 1)))) return st;
+    p->nv_d = nv;
+  }
+  if (!fp64 && p->nv_f < nv) {
+    if ((st = track(p, &p->tables_f, (size_t)nv * std::max(p->P, 1)))) return st;
+    p->nv_f = nv;
+  }
+  if (p->nv_slots < nv) {
+    if ((st = track(p, &p->slots, (size_t)nv * std::max<int64_t>(p->n_tasks, 1) * kSlots))) return st;
+    if ((st = track(p, &p->v_local, (size_t)nv * std::max(p->S, 1)))) return st;
+    if ((st = track(p, &p->v_own, (size_t)nv * std::max(p->S, 1)))) return st;
+    if ((st = track(p, &p->v_grad, (size_t)nv * std::max(p->S, 1) * kThetaN))) return st;
+    p->nv_slots = nv;
+  }
+  return CEL_OK;
+}
+
+cel_status ensure_newton(cel_plan* p) {
+  if (p->newton_ready) return CEL_OK;
+  cel_status st;
+  const size_t S1 = std::max(p->S, 1);
+  std::vector<double> npix(S1, 0.0);
+  for (int i = 0; i < p->P; ++i) npix[p->patches_h[i].src] += (double)p->patches_h[i].w * p->patches_h[i].h;
+  std::vector<int32_t> col(S1, 0);
+  for (int s = 0; s < p->S; ++s) col[s] = p->colour[s];
+  if ((st = track(p, &p->d_theta_trial, S1 * kThetaN)) || (st = track(p, &p->d_pred, S1)) ||
+      (st = track(p, &p->d_step_norm, S1)) || (st = track(p, &p->d_trial_active, S1)) ||
+      (st = track(p, &p->d_mask, S1)) || (st = track(p, &p->d_counter, 1)) ||
+      (st = track_upload(p, &p->d_npix, npix)) || (st = track_upload(p, &p->d_colour, col)))
+    return st;
+  if (hipMemset(p->d_trial_active, 0, S1) != hipSuccess) return CEL_EHIP;
+  if (hipHostMalloc((void**)&p->h_mask, S1, 0) != hipSuccess) return CEL_ENOMEM;
+  if (hipHostMalloc((void**)&p->h_counter, sizeof(int32_t), 0) != hipSuccess) return CEL_ENOMEM;
+  if (hipHostMalloc((void**)&p->h_total, sizeof(double), 0) != hipSuccess) return CEL_ENOMEM;
+  if (hipEventCreate(&p->mask_copied) != hipSuccess) return CEL_EHIP;
+  if (hipStreamCreate(&p->own_stream) != hipSuccess) return CEL_EHIP;
+  p->newton_ready = true;
+  return CEL_OK;
+}
+
+hipError_t launch_total_after_eval(cel_plan* p, const double* theta, hipStream_t sm) {
+  const bool fp64 = p->opt.pixel_fp64 != 0;
+  hipError_t e = eval_any(p, theta, nullptr, 0, 1, false, -1, nullptr, sm, true, fp64);
+  if (e == hipSuccess) e = launch_total(p->v_own, p->S, p->d_total, sm);
+  return e;
+}
+
+}  // namespace celmi
+
+extern "C" cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_options* opt) {
+  if (!out) return CEL_EINVAL;
+  *out = nullptr;
+  int nd = 0;
+  if (hipGetDeviceCount(&nd) != hipSuccess) return CEL_EHIP;
+  if (hip_device < 0 || hip_device >= nd) return CEL_EINVAL;
+  cel_options o = merge_options(opt);
+  if (!(o.pixels_per_lane == 1 || o.pixels_per_lane == 2 || o.pixels_per_lane == 4)) return CEL_EINVAL;
+  if (o.chunk_pixels < 64 || o.chunk_pixels % 64 != 0 || o.chunk_pixels > (1 << 20)) return CEL_EINVAL;
+  cel_ctx* c = new cel_ctx;
+  c->device = hip_device;
+  c->opt = o;
+  *out = c;
+  return CEL_OK;
+}
+
+extern "C" void cel_destroy(cel_ctx* ctx) { delete ctx; }
+
+extern "C" void cel_plan_free(cel_plan* plan) {
+  if (!plan) return;
+  (void)hipSetDevice(plan->device);
+  plan_release(plan);
+}
+
+extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan** out, void* stream) {
+  if (!ctx || !out) return CEL_EINVAL;
+  *out = nullptr;
+  cel_status st = validate(pr);
+  if (st) return st;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CEL_EHIP;
+  hipStream_t sm = (hipStream_t)stream;
+  cel_plan* p = new cel_plan;
+  p->device = ctx->device;
+  p->opt = ctx->opt;
+  const int S = pr->n_sources, N = pr->n_images, P = pr->n_patches;
+  p->S = S;
+  p->N = N;
+  p->P = P;
+  p->images_h.assign(pr->images, pr->images + N);
+  // patches: packed offsets in our own (count, sky) array, CSR per source
+  p->patches_h.resize(P);
+  p->patch_ptr_h.assign(S + 1, 0);
+  int64_t off = 0;
+  for (int i = 0; i < P; ++i) {
+    const cel_patch& q = pr->patches[i];
+    DPatch d;
+    d.src = q.src; d.img = q.img; d.x0 = q.x0; d.y0 = q.y0; d.w = q.w; d.h = q.h;
+    d.off = off;
+    off += (int64_t)q.w * q.h;
+    p->patches_h[i] = d;
+    p->patch_ptr_h[q.src + 1]++;
+  }
+  p->n_units = off;
+  for (int s = 0; s < S; ++s) p->patch_ptr_h[s + 1] += p->patch_ptr_h[s];
+  // neighbour patches: same image, other source, intersecting rectangles (sweep over x0)
+  std::vector<std::vector<int>> nbr(P);
+  {
+    std::vector<std::vector<int>> by_img(N);
+    for (int i = 0; i < P; ++i) by_img[p->patches_h[i].img].push_back(i);
+    for (int n = 0; n < N; ++n) {
+      auto& v = by_img[n];
+      std::sort(v.begin(), v.end(), [&](int a, int b) {
+        return p->patches_h[a].x0 < p->patches_h[b].x0 || (p->patches_h[a].x0 == p->patches_h[b].x0 && a < b);
+      });
+      for (size_t ia = 0; ia < v.size(); ++ia) {
+        const DPatch& A = p->patches_h[v[ia]];
+        for (size_t ib = ia + 1; ib < v.size(); ++ib) {
+          const DPatch& B = p->patches_h[v[ib]];
+          if (B.x0 >= A.x0 + A.w) break;
+          if (B.y0 < A.y0 + A.h && A.y0 < B.y0 + B.h && A.src != B.src) {
+            nbr[v[ia]].push_back(v[ib]);
+            nbr[v[ib]].push_back(v[ia]);
+          }
+        }
+      }
+    }
+  }
+  p->nbr_idx_h.clear();
+  for (int i = 0; i < P; ++i) {
+    std::sort(nbr[i].begin(), nbr[i].end());
+    p->patches_h[i].nbr_begin = (int)p->nbr_idx_h.size();
+    for (int q : nbr[i]) p->nbr_idx_h.push_back(q);
+    p->patches_h[i].nbr_end = (int)p->nbr_idx_h.size();
+  }
+  // source overlap graph and greedy colouring (ascending id, smallest free colour)
+  p->adj.assign(S, {});
+  for (int i = 0; i < P; ++i)
+    for (int q : nbr[i]) p->adj[p->patches_h[i].src].push_back(p->patches_h[q].src);
+  for (auto& a : p->adj) {
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+  }
+  p->colour.assign(S, -1);
+  p->n_colours = 0;
+  for (int s = 0; s < S; ++s) {
+    std::vector<char> used(p->adj[s].size() + 1, 0);
+    for (int t : p->adj[s])
+      if (p->colour[t] >= 0 && p->colour[t] < (int)used.size()) used[p->colour[t]] = 1;
+    int c = 0;
+    while (used[c]) ++c;
+    p->colour[s] = c;
+    p->n_colours = std::max(p->n_colours, c + 1);
+  }
+  // work items: runs of chunk pixels per patch (patch-major), launch order by cost
+  const int CH = p->opt.chunk_pixels;
+  p->tasks_h.clear();
+  std::vector<double> cost;
+  for (int i = 0; i < P; ++i) {
+    DPatch& d = p->patches_h[i];
+    const int n = d.w * d.h;
+    d.task_begin = (int)p->tasks_h.size();
+    for (int b = 0; b < n; b += CH) {
+      DTask t;
+      t.patch = i;
+      t.pix_begin = b;
+      t.pix_end = std::min(n, b + CH);
+      t.pad = 0;
+      p->tasks_h.push_back(t);
+      cost.push_back((double)(t.pix_end - t.pix_begin) * (1.0 + 0.5 * (d.nbr_end - d.nbr_begin)));
+    }
+    d.task_end = (int)p->tasks_h.size();
+  }
+  p->n_tasks = (int64_t)p->tasks_h.size();
+  if (p->n_tasks > (int64_t)1 << 30) {
+    plan_release(p);
+    return CEL_EUNSUPPORTED;
+  }
+  p->order_h.resize(p->n_tasks);
+  std::iota(p->order_h.begin(), p->order_h.end(), 0);
+  std::stable_sort(p->order_h.begin(), p->order_h.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  // per-colour lists of patches and work items (for masked launches)
+  p->class_patches.assign(p->n_colours, {});
+  p->class_tasks.assign(p->n_colours, {});
+  p->class_src.assign(p->n_colours, {});
+  for (int s = 0; s < S; ++s) {
+    const int c = p->colour[s];
+    p->class_src[c].push_back(s);
+    for (int i = p->patch_ptr_h[s]; i < p->patch_ptr_h[s + 1]; ++i) p->class_patches[c].push_back(i);
+  }
+  for (int i : p->order_h) {
+    const int c = p->colour[p->patches_h[p->tasks_h[i].patch].src];
+    p->class_tasks[c].push_back(i);
+  }
+  // prior tables
+  {
+    const cel_prior& pp = *pr->prior;
+    DPrior d;
+    std::memset(&d, 0, sizeof(d));
+    d.logit_a = std::log(pp.star_prob / (1 - pp.star_prob));
+    d.log_a = std::log(pp.star_prob);
+    d.log_1ma = std::log1p(-pp.star_prob);
+    for (int i = 0; i < 2; ++i) {
+      d.r[i][0] = pp.r[i][0];
+      d.r[i][1] = pp.r[i][1];
+      for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+        d.c_logw[i][j] = pp.c_w[i][j] > 0 ? std::log(pp.c_w[i][j]) : -1e300;
+        for (int k = 0; k < 4; ++k) d.c_mean[i][j][k] = pp.c_mean[i][j][k];
+        double ld = 0;
+        if (pp.c_w[i][j] > 0) spd_inverse4(pp.c_cov[i][j], d.c_prec[i][j], &ld);
+        d.c_logdet[i][j] = ld;
+      }
+    }
+    d.radius[0] = pp.radius[0];
+    d.radius[1] = pp.radius[1];
+    d.profile[0] = pp.profile[0];
+    d.profile[1] = pp.profile[1];
+    d.axis[0] = pp.axis[0];
+    d.axis[1] = pp.axis[1];
+    d.lbeta_profile = std::lgamma(pp.profile[0]) + std::lgamma(pp.profile[1]) - std::lgamma(pp.profile[0] + pp.profile[1]);
+    d.lbeta_axis = std::lgamma(pp.axis[0]) + std::lgamma(pp.axis[1]) - std::lgamma(pp.axis[0] + pp.axis[1]);
+    p->prior_h = d;
+  }
+  {
+    const cel_profiles& pf = *pr->profiles;
+    DProfiles d;
+    std::memset(&d, 0, sizeof(d));
+    d.n_exp = pf.n_exp;
+    d.n_dev = pf.n_dev;
+    for (int j = 0; j < pf.n_exp; ++j) { d.alpha[j] = pf.exp_alpha[j]; d.tau[j] = pf.exp_tau[j]; }
+    for (int j = 0; j < pf.n_dev; ++j) { d.alpha[pf.n_exp + j] = pf.dev_alpha[j]; d.tau[pf.n_exp + j] = pf.dev_tau[j]; }
+    p->prof_h = d;
+    p->nexp = pf.n_exp;
+    p->ndev = pf.n_dev;
+    std::vector<float> hf(2 * kMaxProf, 0.f);
+    std::vector<double> hd(2 * kMaxProf, 0.0);
+    for (int j = 0; j < pf.n_exp; ++j) { hf[j] = (float)(0.5 * pf.exp_tau[j]); hd[j] = 0.5 * pf.exp_tau[j]; }
+    for (int j = 0; j < pf.n_dev; ++j) {
+      hf[kMaxProf + j] = (float)(0.5 * pf.dev_tau[j]);
+      hd[kMaxProf + j] = 0.5 * pf.dev_tau[j];
+    }
+    p->htau_fh = hf;
+    p->htau_dh = hd;
+  }
+  std::vector<int32_t> npsf(std::max(N, 1), 1);
+  for (int n = 0; n < N; ++n) npsf[n] = pr->images[n].n_psf;
+  std::vector<int64_t> user_off(std::max(P, 1), 0);
+  for (int i = 0; i < P; ++i) user_off[i] = pr->patches[i].pix_off;
+  std::vector<double> knots(pr->sky_knots, pr->sky_knots + pr->n_sky_knots);
+  std::vector<cel_image> imgs = p->images_h;
+  std::vector<DPrior> prior1(1, p->prior_h);
+  std::vector<DProfiles> prof1(1, p->prof_h);
+  int64_t* d_user_off = nullptr;
+  double* d_knots = nullptr;
+  std::vector<int32_t> colour32(p->colour.begin(), p->colour.end());
+  if ((st = track_upload(p, &p->d_patches, p->patches_h)) || (st = track_upload(p, &p->d_images, imgs)) ||
+      (st = track_upload(p, &p->d_nbr, p->nbr_idx_h)) || (st = track_upload(p, &p->d_tasks, p->tasks_h)) ||
+      (st = track_upload(p, &p->d_order, p->order_h)) || (st = track_upload(p, &p->d_patch_ptr, p->patch_ptr_h)) ||
+      (st = track_upload(p, &p->d_npsf, npsf)) || (st = track_upload(p, &p->d_prior, prior1)) ||
+      (st = track_upload(p, &p->d_prof, prof1)) || (st = track_upload(p, &p->d_htau_f, p->htau_fh)) ||
+      (st = track_upload(p, &p->d_htau_d, p->htau_dh)) || (st = track_upload(p, &d_user_off, user_off)) ||
+      (st = track_upload(p, &d_knots, knots)) || (st = track(p, &p->d_xs, (size_t)std::max<int64_t>(p->n_units, 1))) ||
+      (st = track(p, &p->d_pixconst, (size_t)2 * std::max(P, 1))) || (st = track(p, &p->d_total, 1)) ||
+      (st = ensure_variants(p, 1, p->opt.pixel_fp64 != 0))) {
+    plan_release(p);
+    return st;
+  }
+  // class lists on the device
+  p->d_class_patches.assign(p->n_colours, nullptr);
+  p->d_class_tasks.assign(p->n_colours, nullptr);
+  p->d_class_src.assign(p->n_colours, nullptr);
+  for (int c = 0; c < p->n_colours; ++c) {
+    if ((st = track_upload(p, &p->d_class_patches[c], p->class_patches[c])) ||
+        (st = track_upload(p, &p->d_class_tasks[c], p->class_tasks[c])) ||
+        (st = track_upload(p, &p->d_class_src[c], p->class_src[c]))) {
+      plan_release(p);
+      return st;
+    }
+  }
+  if ((p->opt.pixel_fp64 || p->opt.hessian_fp64) &&
+      (st = track(p, &p->d_xs64, (size_t)std::max<int64_t>(p->n_units, 1)))) {
+    plan_release(p);
+    return st;
+  }
+  hipError_t e = launch_pixels(p->d_patches, p->d_images, d_knots, pr->pixels, d_user_off, p->d_xs, p->d_xs64, P, sm);
+  if (e == hipSuccess) e = launch_pixconst(p->d_patches, p->d_nbr, p->d_xs, p->d_pixconst, P, sm);
+  if (e == hipSuccess) e = hipStreamSynchronize(sm);
+  if (e != hipSuccess) {
+    plan_release(p);
+    return CEL_EHIP;
+  }
+  *out = p;
+  return CEL_OK;
+}
+
+extern "C" cel_status cel_plan_info(const cel_plan* plan, int64_t* n_units, int32_t* n_colours, int32_t* colours,
+                                    int64_t* n_work_items) {
+  if (!plan) return CEL_EINVAL;
+  if (n_units) *n_units = plan->n_units;
+  if (n_colours) *n_colours = plan->n_colours;
+  if (n_work_items) *n_work_items = plan->n_tasks;
+  if (colours)
+    for (int s = 0; s < plan->S; ++s) colours[s] = plan->colour[s];
+  return CEL_OK;
+}
+
+namespace celmi {
+
+// Enqueue prep + fused + finalize for `nv` variants starting at variant v0 over either all
+// sources (cls < 0) or one colour class, with optional active mask.  Outputs go to the
+// plan's per-variant arrays.
+template <typename T>
+static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv,
+                               bool grad, int cls, const uint8_t* active, hipStream_t sm, bool prep_base) {
+  Table<T>* tables = reinterpret_cast<Table<T>*>(sizeof(T) == 8 ? (void*)p->tables_d : (void*)p->tables_f);
+  const T* htau = sizeof(T) == 8 ? (const T*)p->d_htau_d : (const T*)p->d_htau_f;
+  hipError_t e = hipSuccess;
+  PrepArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.theta = theta;
+  pa.theta_trial = theta_trial;
+  pa.fd_step = p->opt.fd_step;
+  pa.patches = p->d_patches;
+  pa.images = p->d_images;
+  pa.prof = p->d_prof;
+  pa.tables = tables;
+  pa.n_patches = p->P;
+  phase_mark(p, 0, sm);
+  if (prep_base) {   // variant 0 of every source (neighbours read these)
+    pa.variant0 = 0;
+    e = launch_prep_tables<T>(pa, p->P, 1, sm);
+    if (e != hipSuccess) return e;
+  }
+  int n_items = (int)p->n_tasks;
+  const int32_t* order = p->d_order;
+  if (cls >= 0) {
+    pa.patch_list = p->d_class_patches[cls];
+    n_items = (int)p->class_tasks[cls].size();
+    order = p->d_class_tasks[cls];
+  }
+  pa.active = active;
+  const int vstart = (v0 == 0 && prep_base) ? 1 : 0;   // variant 0 already prepared
+  if (nv - vstart > 0) {
+    pa.variant0 = v0 + vstart;
+    const int np = cls >= 0 ? (int)p->class_patches[cls].size() : p->P;
+    e = launch_prep_tables<T>(pa, np, nv - vstart, sm);
+    if (e != hipSuccess) return e;
+  }
+  phase_mark(p, 1, sm);
+  FusedArgs<T> fa;
+  std::memset(&fa, 0, sizeof(fa));
+  fa.tasks = p->d_tasks;
+  fa.order = order;
+  fa.order_offset = 0;
+  fa.patches = p->d_patches;
+  fa.nbr_idx = p->d_nbr;
+  fa.base = tables;
+  fa.own = tables;
+  fa.variant_stride = p->P;
+  fa.xs = sizeof(T) == 8 ? (const void*)p->d_xs64 : (const void*)p->d_xs;
+  fa.slots = p->slots + (int64_t)v0 * p->n_tasks * kSlots;
+  fa.slot_variant_stride = p->n_tasks * kSlots;
+  fa.active = active;
+  fa.variant0 = v0;
+  fa.img_npsf = p->d_npsf;
+  e = launch_fused<T>(fa, htau, p->nexp, p->ndev, p->opt.pixels_per_lane, grad, n_items, nv, sm);
+  if (e != hipSuccess) return e;
+  phase_mark(p, 2, sm);
+  FinalizeArgs fz;
+  std::memset(&fz, 0, sizeof(fz));
+  fz.n_jobs = p->S;
+  fz.variant0 = v0;
+  fz.active = active;
+  fz.theta = theta;
+  fz.theta_trial = theta_trial;
+  fz.fd_step = p->opt.fd_step;
+  fz.slots = p->slots + (int64_t)v0 * p->n_tasks * kSlots;
+  fz.slot_variant_stride = p->n_tasks * kSlots;
+  fz.patch_ptr = p->d_patch_ptr;
+  fz.patches = p->d_patches;
+  fz.pix_const = p->d_pixconst;
+  fz.images = p->d_images;
+  fz.prior = p->d_prior;
+  fz.want_grad = grad ? 1 : 0;
+  fz.local = p->v_local + (int64_t)v0 * p->S;
+  fz.own = p->v_own + (int64_t)v0 * p->S;
+  fz.grad = p->v_grad + (int64_t)v0 * p->S * kThetaN;
+  fz.out_variant_stride = p->S;
+  if (cls >= 0) {
+    // jobs = members of the class
+    fz.n_jobs = (int)p->class_src[cls].size();
+    fz.job_src = p->d_class_src[cls];
+  }
+  return launch_finalize(fz, nv, sm);
+}
+
+template <typename T>
+static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm) {
+  Table<T>* tables = reinterpret_cast<Table<T>*>(sizeof(T) == 8 ? (void*)p->tables_d : (void*)p->tables_f);
+  const T* htau = sizeof(T) == 8 ? (const T*)p->d_htau_d : (const T*)p->d_htau_f;
+  PrepArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.theta = theta;
+  pa.fd_step = p->opt.fd_step;
+  pa.patches = p->d_patches;
+  pa.images = p->d_images;
+  pa.prof = p->d_prof;
+  pa.tables = tables;
+  pa.n_patches = p->P;
+  hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
+  FusedArgs<T> fa;
+  std::memset(&fa, 0, sizeof(fa));
+  fa.tasks = p->d_tasks;
+  fa.order = nullptr;
+  fa.patches = p->d_patches;
+  fa.nbr_idx = p->d_nbr;
+  fa.base = tables;
+  fa.own = tables;
+  fa.variant_stride = p->P;
+  fa.xs = sizeof(T) == 8 ? (const void*)p->d_xs64 : (const void*)p->d_xs;
+  fa.slots = p->slots;
+  fa.slot_variant_stride = p->n_tasks * kSlots;
+  fa.img_npsf = p->d_npsf;
+  FinalizeArgs fz;
+  std::memset(&fz, 0, sizeof(fz));
+  fz.n_jobs = 1;
+  fz.theta = theta;
+  fz.fd_step = p->opt.fd_step;
+  fz.slots = p->slots;
+  fz.slot_variant_stride = p->n_tasks * kSlots;
+  fz.patch_ptr = p->d_patch_ptr;
+  fz.patches = p->d_patches;
+  fz.pix_const = p->d_pixconst;
+  fz.images = p->d_images;
+  fz.prior = p->d_prior;
+  fz.want_grad = 1;
+  fz.local = p->v_local;
+  fz.own = p->v_own;
+  fz.grad = p->v_grad;
+  fz.out_variant_stride = p->S;
+  for (int s = 0; s < p->S && e == hipSuccess; ++s) {
+    const int pb = p->patch_ptr_h[s], pe = p->patch_ptr_h[s + 1];
+    if (pe > pb) {
+      const int tb = p->patches_h[pb].task_begin, te = p->patches_h[pe - 1].task_end;
+      fa.order_offset = tb;
+      e = launch_fused<T>(fa, htau, p->nexp, p->ndev, p->opt.pixels_per_lane, true, te - tb, 1, sm);
+    }
+    fz.src_offset = s;
+    if (e == hipSuccess) e = launch_finalize(fz, 1, sm);
+  }
+  return e;
+}
+
+hipError_t plain_eval(cel_plan* p, const double* theta, hipStream_t sm, bool fp64) {
+  return fp64 ? plain_eval_t<double>(p, theta, sm) : plain_eval_t<float>(p, theta, sm);
+}
+
+template hipError_t enqueue_eval<float>(cel_plan*, const double*, const double*, int, int, bool, int,
+                                        const uint8_t*, hipStream_t, bool);
+template hipError_t enqueue_eval<double>(cel_plan*, const double*, const double*, int, int, bool, int,
+                                         const uint8_t*, hipStream_t, bool);
+
+hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv, bool grad, int cls,
+                    const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64) {
+  return fp64 ? enqueue_eval<double>(p, theta, theta_trial, v0, nv, grad, cls, active, sm, prep_base)
+              : enqueue_eval<float>(p, theta, theta_trial, v0, nv, grad, cls, active, sm, prep_base);
+}
+
+}  // namespace celmi
+
+static cel_status eval_common(cel_ctx* ctx, const cel_plan* cplan, const double* theta, double* elbo_total,
+                              double* elbo_local, double* grad, void* stream, bool want_grad) {
+  if (!ctx || !cplan || (!theta && cplan->S > 0)) return CEL_EINVAL;
+  cel_plan* p = const_cast<cel_plan*>(cplan);
+  if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
+  hipStream_t sm = (hipStream_t)stream;
+  const bool fp64 = p->opt.pixel_fp64 != 0;
+  cel_status st = ensure_variants(p, 1, fp64);
+  if (st) return st;
+  p->marking = true;
+  hipError_t e = eval_any(p, theta, nullptr, 0, 1, want_grad, -1, nullptr, sm, true, fp64);
+  if (e == hipSuccess && elbo_total) e = launch_total(p->v_own, p->S, elbo_total, sm);
+  phase_mark(p, 3, sm);
+  p->marking = false;
+  if (e == hipSuccess && elbo_local && p->S > 0)
+    e = hipMemcpyAsync(elbo_local, p->v_local, sizeof(double) * p->S, hipMemcpyDeviceToDevice, sm);
+  if (e == hipSuccess && grad && p->S > 0)
+    e = hipMemcpyAsync(grad, p->v_grad, sizeof(double) * p->S * kThetaN, hipMemcpyDeviceToDevice, sm);
+  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+}
+
+extern "C" cel_status cel_elbo_eval(cel_ctx* ctx, const cel_plan* plan, const double* theta, double* elbo_total,
+                                    double* elbo_local, void* stream) {
+  return eval_common(ctx, plan, theta, elbo_total, elbo_local, nullptr, stream, false);
+}
+
+extern "C" cel_status cel_elbo_grad(cel_ctx* ctx, const cel_plan* plan, const double* theta, double* elbo_total,
+                                    double* elbo_local, double* grad, void* stream) {
+  return eval_common(ctx, plan, theta, elbo_total, elbo_local, grad, stream, true);
+}
+
+// Plain form: the same kernels, one launch of the pixel kernel and of the finalisation per
+// source, in source order, with work items in patch order.
+extern "C" cel_status cel_elbo_grad_plain(cel_ctx* ctx, const cel_plan* cplan, const double* theta,
+                                          double* elbo_total, double* elbo_local, double* grad, void* stream) {
+  if (!ctx || !cplan || (!theta && cplan->S > 0)) return CEL_EINVAL;
+  cel_plan* p = const_cast<cel_plan*>(cplan);
+  if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
+  hipStream_t sm = (hipStream_t)stream;
+  const bool fp64 = p->opt.pixel_fp64 != 0;
+  cel_status st = ensure_variants(p, 1, fp64);
+  if (st) return st;
+  hipError_t e = plain_eval(p, theta, sm, fp64);
+  if (e == hipSuccess && elbo_total) e = launch_total(p->v_own, p->S, elbo_total, sm);
+  if (e == hipSuccess && elbo_local && p->S > 0)
+    e = hipMemcpyAsync(elbo_local, p->v_local, sizeof(double) * p->S, hipMemcpyDeviceToDevice, sm);
+  if (e == hipSuccess && grad && p->S > 0)
+    e = hipMemcpyAsync(grad, p->v_grad, sizeof(double) * p->S * kThetaN, hipMemcpyDeviceToDevice, sm);
+  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+}
+
+extern "C" cel_status cel_phase_times(cel_plan* p, double* ms, int64_t* n_calls, int32_t reset) {
+  if (!p || !p->opt.timing) return CEL_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
+  double acc[3] = {0, 0, 0};
+  int64_t n = 0;
+  for (auto& r : p->ev_rec) {
+    if (hipEventSynchronize(r[3]) != hipSuccess) return CEL_EHIP;
+    for (int k = 0; k < 3; ++k) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, r[k], r[k + 1]) != hipSuccess) return CEL_EHIP;
+      acc[k] += t;
+    }
+    ++n;
+  }
+  if (ms)
+    for (int k = 0; k < 3; ++k) ms[k] = acc[k];
+  if (n_calls) *n_calls = n;
+  if (reset) {
+    for (auto& r : p->ev_rec)
+      for (hipEvent_t e : r) p->ev_pool.push_back(e);
+    p->ev_rec.clear();
+  }
+  return CEL_OK;
+}

@@ -1,0 +1,94 @@
+// Internal device-side layouts of the celmi library (gfx950).  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/celmi.h"
+
+namespace celmi {
+
+constexpr int kThetaN = CEL_N_THETA;
+constexpr int kParamN = CEL_N_PARAM;
+constexpr int kMaxPsf = CEL_MAX_PSF;
+constexpr int kMaxProf = CEL_MAX_PROFILE;
+constexpr int kSlots = 16;          // fp64 partial sums per work item (13 used)
+constexpr int kVariants = 56;       // 0 base, 1..27 +h, 28..54 -h, 55 trial point
+constexpr int kWave = 64;
+
+// slot indices of the per-(work item) partial sums
+enum Slot {
+  S_CE_F0 = 0,   // sum c_E f0
+  S_CE_F1,       // sum c_E f1
+  S_CV_F00,      // sum c_V f0^2
+  S_CV_F11,      // sum c_V f1^2
+  S_CV_F01,      // sum c_V f0 f1
+  S_MU_X,        // sum rho0 df0/dmu_x + rho1 df1/dmu_x
+  S_MU_Y,
+  S_S_XX,        // sum rho0 df0/dS_xx  (S = pixel-frame galaxy covariance)
+  S_S_XY,        // sum rho0 df0/dS_xy  (symmetric: both off-diagonal entries)
+  S_S_YY,
+  S_PI,          // sum rho0 df0/de_profile
+  S_T,           // sum of the centred pixel term over the work item
+  S_T_OWN,       // same, pixels owned by this source only
+};
+
+// Per (variant, patch) table of mixture components in patch-local pixel coordinates.
+// hdr: L0, L1, w0, w1, k0, k1, w01, pi  (E_s = w0 L0 f0 + w1 L1 f1,
+//      V_s = k0 f0^2 + k1 f1^2 + w01 (L0 f0 - L1 f1)^2, f0 = pi f_dev + (1 - pi) f_exp)
+// star[k]: mean_x, mean_y, P_xx, P_xy, P_yy, log2 weight (weight includes the normaliser)
+// gal[k][j]: P_xx, P_xy, P_yy, log2 weight  (j < n_exp: exponential, then de Vaucouleurs)
+template <typename T>
+struct alignas(16) Table {
+  T hdr[8];
+  T star[kMaxPsf][8];
+  T gal[kMaxPsf][2 * kMaxProf][4];
+};
+
+struct DPatch {
+  int32_t src, img, x0, y0, w, h;
+  int64_t off;            // into the (count, sky) pixel array
+  int32_t nbr_begin, nbr_end;   // into nbr_idx: other sources' patches intersecting this one
+  int32_t task_begin, task_end; // work items of this patch (patch-major order)
+};
+
+struct DTask {
+  int32_t patch, pix_begin, pix_end, pad;
+};
+
+struct DPrior {
+  double logit_a, log_a, log_1ma;
+  double r[2][2];
+  double c_logw[2][CEL_N_COLOUR_COMPONENTS];
+  double c_mean[2][CEL_N_COLOUR_COMPONENTS][4];
+  double c_prec[2][CEL_N_COLOUR_COMPONENTS][4][4];
+  double c_logdet[2][CEL_N_COLOUR_COMPONENTS];
+  double radius[2];
+  double profile[2], axis[2];
+  double lbeta_profile, lbeta_axis;
+};
+
+struct DProfiles {
+  int32_t n_exp, n_dev;
+  double alpha[2 * kMaxProf], tau[2 * kMaxProf];   // exp first, then dev
+};
+
+// Arguments of the pixel kernel.
+template <typename T>
+struct FusedArgs {
+  const DTask* tasks;
+  const int32_t* order;        // launch order -> task id (nullptr = identity)
+  int32_t order_offset;        // first entry of `order` (or task id) for this launch
+  const DPatch* patches;
+  const int32_t* nbr_idx;
+  const Table<T>* base;        // variant-0 tables [P]
+  const Table<T>* own;         // tables of the variant being evaluated, [P] per variant
+  int64_t variant_stride;      // tables per variant (= P)
+  const void* xs;              // (count, sky) per packed pixel: float2 (T=float) or double2
+  double* slots;               // [variant][n_tasks][kSlots]
+  int64_t slot_variant_stride; // = n_tasks * kSlots
+  const uint8_t* active;       // per source (nullptr = all)
+  int32_t variant0;            // variant index of blockIdx.y == 0
+  const int32_t* img_npsf;     // PSF components per image
+};
+
+}  // namespace celmi

@@ -1,0 +1,57 @@
+// Launch interface of the celmi kernels (internal).
+#pragma once
+#include "device.h"
+
+namespace celmi {
+
+struct PrepArgs {
+  const double* theta;         // [S*32]
+  const double* theta_trial;   // [S*32] used by the trial variant (may be null)
+  double fd_step;
+  int32_t variant0;            // variant of blockIdx.y == 0
+  const int32_t* patch_list;   // patches to prepare (null = patch_offset + blockIdx.x)
+  int32_t patch_offset;
+  const DPatch* patches;
+  const cel_image* images;
+  const DProfiles* prof;
+  void* tables;                // Table<T>[variants][n_patches]
+  int32_t n_patches;
+  const uint8_t* active;       // per source (null = all)
+};
+
+struct FinalizeArgs {
+  int32_t n_jobs;              // sources handled by this launch
+  const int32_t* job_src;      // job -> source (null: source = job + src_offset)
+  int32_t src_offset;
+  int32_t variant0;
+  const uint8_t* active;
+  const double* theta;
+  const double* theta_trial;
+  double fd_step;
+  const double* slots;
+  int64_t slot_variant_stride;
+  const int32_t* patch_ptr;    // [S+1]
+  const DPatch* patches;
+  const double* pix_const;     // [P][2]
+  const cel_image* images;
+  const DPrior* prior;
+  int32_t want_grad;
+  double* local;               // [variants][S] (null = not written)
+  double* own;                 // [variants][S]
+  double* grad;                // [variants][S][32]
+  int64_t out_variant_stride;  // = S
+};
+
+template <typename T>
+hipError_t launch_prep_tables(const PrepArgs& a, int n_patches_launch, int n_variants, hipStream_t st);
+template <typename T>
+hipError_t launch_fused(const FusedArgs<T>& a, const T* htau, int nexp, int ndev, int ppl, bool grad, int n_items,
+                        int n_variants, hipStream_t st);
+hipError_t launch_finalize(const FinalizeArgs& a, int n_variants, hipStream_t st);
+hipError_t launch_total(const double* own, int n, double* out, hipStream_t st);
+hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const double* knots, const float* pixels,
+                         const int64_t* user_off, float2* xs, double2* xs64, int n_patches, hipStream_t st);
+hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, double* out,
+                           int n_patches, hipStream_t st);
+
+}  // namespace celmi

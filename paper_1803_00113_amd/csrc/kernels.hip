@@ -1,0 +1,751 @@
+// HIP kernels (gfx950) of the variational objective of arXiv 1803.00113.
+//
+// Pipeline of one evaluation (ELBO, Section 4.2, and its gradient):
+//   k_prep_tables  per (variant, patch): theta -> mixture component table (FP64 math,
+//                  stored in the pixel precision) -- light kernels of Section 2.1.2
+//                  (equation hsi) convolved with the image PSF (Section 2.2.3), flux
+//                  moments of equation conditional
+//   k_fused        per work item (a run of <= chunk pixels of one patch): for every pixel
+//                  the own source's mixture value and partial derivatives, every
+//                  overlapping neighbour's value, E_q[lambda] and V_q[lambda] (equations
+//                  conditional, vareq), the delta-method pixel term (equation
+//                  eq:log_p_last, Section 4.2.2) and its adjoint coefficients; FP64 sums
+//                  reduced across the wavefront into one slot row per work item
+//   k_finalize     per source: fixed-order reduction of its slot rows, FP64 chain rule to
+//                  the unconstrained parameters, KL_s and its gradient (equations eq:kl,
+//                  kleq, the GMM colour bound and Supplement A)
+//   k_total        one workgroup: fixed-order sum of the per-source owned objectives
+#include <math.h>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace celmi {
+
+// ----------------------------------------------------------------------------------------
+// precision helpers
+
+template <typename T> __device__ __forceinline__ T fexp2(T x);
+template <> __device__ __forceinline__ float fexp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <> __device__ __forceinline__ double fexp2<double>(double x) { return exp2(x); }
+template <typename T> __device__ __forceinline__ T flog(T x);
+template <> __device__ __forceinline__ float flog<float>(float x) { return logf(x); }
+template <> __device__ __forceinline__ double flog<double>(double x) { return log(x); }
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLog2TwoPi = 2.6514961294723187980;   // log2(2 pi)
+constexpr double kNegHuge = -1.0e30;
+
+// log l_b = log r + W[b] . c,  c_k = ln(l_{k+1} / l_k), reference band r = index 2
+__device__ __constant__ double c_W[5][4] = {
+    {-1, -1, 0, 0}, {0, -1, 0, 0}, {0, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 1, 1}};
+
+__device__ __forceinline__ double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+__device__ __forceinline__ double softplus(double x) { return x > 0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
+
+// Parameters of variant v of a source: base theta, +/- h along one coordinate, or trial.
+__device__ __forceinline__ void load_theta(const double* theta, const double* theta_trial, int s, int v,
+                                           double h, double* th) {
+  const double* src = (v == kVariants - 1 && theta_trial) ? theta_trial + (int64_t)s * kThetaN
+                                                          : theta + (int64_t)s * kThetaN;
+#pragma unroll
+  for (int k = 0; k < kThetaN; ++k) th[k] = src[k];
+  if (v >= 1 && v <= kParamN) th[v - 1] += h;
+  else if (v > kParamN && v <= 2 * kParamN) th[v - 1 - kParamN] -= h;
+}
+
+// Galaxy covariance Sigma_s = R^T diag(r^2, axis^2 r^2) R, R = [[c,-s],[s,c]] (Section 2.1.2)
+__device__ __forceinline__ void galaxy_cov(double angle, double radius, double axis, double* sig) {
+  double c = cos(angle), s = sin(angle), r2 = radius * radius, a2 = axis * axis;
+  sig[0] = r2 * (c * c + a2 * s * s);
+  sig[1] = r2 * (a2 - 1.0) * c * s;
+  sig[2] = r2 * (s * s + a2 * c * c);
+}
+
+// ----------------------------------------------------------------------------------------
+// k_prep_tables: one wavefront per (variant, patch)
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
+  const int pi_ = a.patch_list ? a.patch_list[blockIdx.x] : a.patch_offset + (int)blockIdx.x;
+  const int v = a.variant0 + blockIdx.y;
+  const DPatch P = a.patches[pi_];
+  if (a.active && !a.active[P.src]) return;
+  const cel_image& im = a.images[P.img];
+  double th[kThetaN];
+  load_theta(a.theta, a.theta_trial, P.src, v, a.fd_step, th);
+  Table<T>* tb = reinterpret_cast<Table<T>*>(a.tables) + (int64_t)v * a.n_patches + pi_;
+  const int lane = threadIdx.x;
+  // position in patch-local pixel coordinates: mu = A u + b - (x0, y0)
+  const double mux = im.A[0][0] * th[0] + im.A[0][1] * th[1] + im.b[0] - P.x0;
+  const double muy = im.A[1][0] * th[0] + im.A[1][1] * th[1] + im.b[1] - P.y0;
+  double sig[3];
+  galaxy_cov(th[23], exp(th[24]), sigmoid(th[26]), sig);
+  // pixel-frame galaxy covariance S = A Sigma A^T
+  const double a00 = im.A[0][0], a01 = im.A[0][1], a10 = im.A[1][0], a11 = im.A[1][1];
+  const double t00 = a00 * sig[0] + a01 * sig[1], t01 = a00 * sig[1] + a01 * sig[2];
+  const double t10 = a10 * sig[0] + a11 * sig[1], t11 = a10 * sig[1] + a11 * sig[2];
+  const double Sxx = t00 * a00 + t01 * a01, Sxy = t00 * a10 + t01 * a11, Syy = t10 * a10 + t11 * a11;
+  const int K = im.n_psf;
+  if (lane == 0) {
+    // flux moments given the type (equation conditional): log l ~ N(m, v)
+    const double aa = sigmoid(th[2]);
+    const double w[2] = {1.0 - aa, aa};
+    double L[2], kk[2];
+    for (int i = 0; i < 2; ++i) {
+      double m = th[3 + i], var = exp(th[5 + i]);
+      for (int c = 0; c < 4; ++c) {
+        const double W = c_W[im.band][c];
+        m += W * th[7 + 4 * i + c];
+        var += W * W * exp(th[15 + 4 * i + c]);
+      }
+      L[i] = im.iota * exp(m + 0.5 * var);
+      kk[i] = w[i] * L[i] * L[i] * expm1(var);
+    }
+    tb->hdr[0] = (T)L[0];
+    tb->hdr[1] = (T)L[1];
+    tb->hdr[2] = (T)w[0];
+    tb->hdr[3] = (T)w[1];
+    tb->hdr[4] = (T)kk[0];
+    tb->hdr[5] = (T)kk[1];
+    tb->hdr[6] = (T)(w[0] * w[1]);
+    tb->hdr[7] = (T)sigmoid(th[25]);
+  }
+  // components: 4 star slots then 4 x 16 galaxy slots
+  for (int c = lane; c < kMaxPsf + kMaxPsf * 2 * kMaxProf; c += 64) {
+    if (c < kMaxPsf) {
+      const int k = c;
+      T* r = tb->star[k];
+      if (k < K) {
+        const double cxx = im.psf[k][3], cxy = im.psf[k][4], cyy = im.psf[k][5];
+        const double det = cxx * cyy - cxy * cxy;
+        r[0] = (T)(mux + im.psf[k][1]);
+        r[1] = (T)(muy + im.psf[k][2]);
+        r[2] = (T)(cyy / det);
+        r[3] = (T)(-cxy / det);
+        r[4] = (T)(cxx / det);
+        r[5] = im.psf[k][0] > 0 ? (T)(log2(im.psf[k][0]) - kLog2TwoPi - 0.5 * log2(det)) : (T)kNegHuge;
+      } else {
+        r[0] = r[1] = r[2] = r[3] = r[4] = (T)0;
+        r[5] = (T)kNegHuge;
+      }
+      r[6] = r[7] = (T)0;
+    } else {
+      const int k = (c - kMaxPsf) / (2 * kMaxProf), j = (c - kMaxPsf) % (2 * kMaxProf);
+      T* r = tb->gal[k][j];
+      const bool isdev = j >= kMaxProf;
+      const int jj = isdev ? j - kMaxProf : j;
+      const int nj = isdev ? a.prof->n_dev : a.prof->n_exp;
+      if (k < K && jj < nj) {
+        const double tau = a.prof->tau[isdev ? a.prof->n_exp + jj : jj];
+        const double alpha = a.prof->alpha[isdev ? a.prof->n_exp + jj : jj];
+        const double cxx = im.psf[k][3] + tau * Sxx, cxy = im.psf[k][4] + tau * Sxy, cyy = im.psf[k][5] + tau * Syy;
+        const double det = cxx * cyy - cxy * cxy;
+        const double wt = im.psf[k][0] * alpha;
+        r[0] = (T)(cyy / det);
+        r[1] = (T)(-cxy / det);
+        r[2] = (T)(cxx / det);
+        r[3] = wt > 0 ? (T)(log2(wt) - kLog2TwoPi - 0.5 * log2(det)) : (T)kNegHuge;
+      } else {
+        r[0] = r[1] = r[2] = (T)0;
+        r[3] = (T)kNegHuge;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// k_fused: the per-pixel hot loop
+
+// Values of a source's star (f1) and galaxy (f0) light at PPL pixels (local coords of the
+// source's own patch).  Neighbour evaluation: no derivatives.
+template <typename T, int PPL, int NEXP, int NDEV>
+__device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int K, const T* px, const T* py,
+                                            T* f0, T* f1) {
+  T fe[PPL], fd[PPL];
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) fe[i] = fd[i] = f1[i] = (T)0;
+  const T hl = (T)(-0.5 * kLog2e);
+  for (int k = 0; k < K; ++k) {
+    const T mx = tb->star[k][0], my = tb->star[k][1];
+    T dx[PPL], dy[PPL], xx[PPL], xy[PPL], yy[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      dx[i] = px[i] - mx;
+      dy[i] = py[i] - my;
+      xx[i] = dx[i] * dx[i];
+      xy[i] = (T)2 * dx[i] * dy[i];
+      yy[i] = dy[i] * dy[i];
+    }
+    {
+      const T pxx = tb->star[k][2] * hl, pxy = tb->star[k][3] * hl, pyy = tb->star[k][4] * hl, lw = tb->star[k][5];
+#pragma unroll
+      for (int i = 0; i < PPL; ++i) f1[i] += fexp2<T>(fma(pxx, xx[i], fma(pxy, xy[i], fma(pyy, yy[i], lw))));
+    }
+#pragma unroll
+    for (int j = 0; j < NEXP; ++j) {
+      const T pxx = tb->gal[k][j][0] * hl, pxy = tb->gal[k][j][1] * hl, pyy = tb->gal[k][j][2] * hl,
+              lw = tb->gal[k][j][3];
+#pragma unroll
+      for (int i = 0; i < PPL; ++i) fe[i] += fexp2<T>(fma(pxx, xx[i], fma(pxy, xy[i], fma(pyy, yy[i], lw))));
+    }
+#pragma unroll
+    for (int j = 0; j < NDEV; ++j) {
+      const T pxx = tb->gal[k][kMaxProf + j][0] * hl, pxy = tb->gal[k][kMaxProf + j][1] * hl,
+              pyy = tb->gal[k][kMaxProf + j][2] * hl, lw = tb->gal[k][kMaxProf + j][3];
+#pragma unroll
+      for (int i = 0; i < PPL; ++i) fd[i] += fexp2<T>(fma(pxx, xx[i], fma(pxy, xy[i], fma(pyy, yy[i], lw))));
+    }
+  }
+  const T pi = tb->hdr[7];
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) f0[i] = pi * fd[i] + ((T)1 - pi) * fe[i];
+}
+
+// Own source: values and partial derivatives w.r.t. the pixel-frame centre mu, the
+// pixel-frame galaxy covariance S and the profile weight.  For N = weight * normal(p; m, C)
+// with P = C^{-1}, u = P (p - m):  dN/dmu = N u,  dN/dC = N (u u^T - P) / 2,  dC/dS = tau.
+template <typename T, int PPL>
+struct OwnPix {
+  T f1[PPL], g1x[PPL], g1y[PPL];
+  T fe[PPL], gex[PPL], gey[PPL], sexx[PPL], sexy[PPL], seyy[PPL];
+  T fd[PPL], gdx[PPL], gdy[PPL], sdxx[PPL], sdxy[PPL], sdyy[PPL];
+};
+
+// MODE 0: value only; 1: value and d/dmu; 2: value, d/dmu and d/dS
+template <typename T, int PPL, int MODE>
+__device__ __forceinline__ void comp_own(T pxx, T pxy, T pyy, T lw, T htau, const T* dx, const T* dy, T* f, T* gx,
+                                         T* gy, T* sxx, T* sxy, T* syy) {
+  const T hl = (T)(-0.5 * kLog2e);
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const T ux = fma(pxx, dx[i], pxy * dy[i]);
+    const T uy = fma(pxy, dx[i], pyy * dy[i]);
+    const T q = fma(dx[i], ux, dy[i] * uy);
+    const T N = fexp2<T>(fma(q, hl, lw));
+    f[i] += N;
+    if (MODE >= 1) {
+      gx[i] = fma(N, ux, gx[i]);
+      gy[i] = fma(N, uy, gy[i]);
+    }
+    if (MODE >= 2) {
+      const T tN = htau * N;
+      sxx[i] = fma(tN, fma(ux, ux, -pxx), sxx[i]);
+      sxy[i] = fma(tN, fma(ux, uy, -pxy), sxy[i]);
+      syy[i] = fma(tN, fma(uy, uy, -pyy), syy[i]);
+    }
+  }
+}
+
+// The own source's values (and, with DERIV, partial derivatives).  The values are formed
+// by the same operations with or without DERIV, so the ELBO-only and the gradient paths
+// give bitwise-identical objectives.
+template <typename T, int PPL, int NEXP, int NDEV, bool DERIV>
+__device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const T* __restrict__ htau, int K,
+                                         const T* px, const T* py, OwnPix<T, PPL>& o) {
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    o.f1[i] = o.g1x[i] = o.g1y[i] = (T)0;
+    o.fe[i] = o.gex[i] = o.gey[i] = o.sexx[i] = o.sexy[i] = o.seyy[i] = (T)0;
+    o.fd[i] = o.gdx[i] = o.gdy[i] = o.sdxx[i] = o.sdxy[i] = o.sdyy[i] = (T)0;
+  }
+  for (int k = 0; k < K; ++k) {
+    const T mx = tb->star[k][0], my = tb->star[k][1];
+    T dx[PPL], dy[PPL], z[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) z[i] = (T)0;
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      dx[i] = px[i] - mx;
+      dy[i] = py[i] - my;
+    }
+    comp_own<T, PPL, DERIV ? 1 : 0>(tb->star[k][2], tb->star[k][3], tb->star[k][4], tb->star[k][5], (T)0, dx, dy,
+                                    o.f1, o.g1x, o.g1y, z, z, z);
+#pragma unroll
+    for (int j = 0; j < NEXP; ++j)
+      comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], htau[j], dx,
+                              dy, o.fe, o.gex, o.gey, o.sexx, o.sexy, o.seyy);
+#pragma unroll
+    for (int j = 0; j < NDEV; ++j)
+      comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
+                              tb->gal[k][kMaxProf + j][3], htau[kMaxProf + j], dx, dy, o.fd, o.gdx, o.gdy, o.sdxx,
+                              o.sdxy, o.sdyy);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T, int PPL, bool GRAD, int NEXP, int NDEV>
+__global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restrict__ htau) {
+  const int v = a.variant0 + blockIdx.y;
+  const int wi = a.order_offset + blockIdx.x;
+  const int t = a.order ? a.order[wi] : wi;
+  const DTask task = a.tasks[t];
+  const DPatch P = a.patches[task.patch];
+  if (a.active && !a.active[P.src]) return;
+  const Table<T>* __restrict__ tb = a.own + (int64_t)v * a.variant_stride + task.patch;
+  const int K = a.img_npsf[P.img];
+  const int lane = threadIdx.x;
+  const float inv_w = 1.0f / (float)P.w;
+  const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
+  const T k0 = tb->hdr[4], k1 = tb->hdr[5], w01 = tb->hdr[6], pi = tb->hdr[7];
+  double acc[13];
+#pragma unroll
+  for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+
+  for (int base = task.pix_begin; base < task.pix_end; base += 64 * PPL) {
+    T px[PPL], py[PPL], xv[PPL], sky[PPL];
+    bool valid[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      int idx = base + i * 64 + lane;
+      valid[i] = idx < task.pix_end;
+      if (!valid[i]) idx = task.pix_begin;
+      int row = (int)(((float)idx + 0.5f) * inv_w);
+      int col = idx - row * P.w;
+      if (col < 0) { row -= 1; col += P.w; }
+      else if (col >= P.w) { row += 1; col -= P.w; }
+      px[i] = (T)col;
+      py[i] = (T)row;
+      if constexpr (sizeof(T) == 8) {
+        const double2 xs = reinterpret_cast<const double2*>(a.xs)[P.off + idx];
+        xv[i] = (T)xs.x;
+        sky[i] = (T)xs.y;
+      } else {
+        const float2 xs = reinterpret_cast<const float2*>(a.xs)[P.off + idx];
+        xv[i] = (T)xs.x;
+        sky[i] = (T)xs.y;
+      }
+    }
+    // own source
+    T f0[PPL], f1[PPL];
+    OwnPix<T, PPL> o;
+    eval_own<T, PPL, NEXP, NDEV, GRAD>(tb, htau, K, px, py, o);
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      f1[i] = o.f1[i];
+      f0[i] = fma(pi, o.fd[i], ((T)1 - pi) * o.fe[i]);
+    }
+    T E[PPL], V[PPL], d[PPL];
+    bool own[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      const T a0 = L0 * f0[i], a1 = L1 * f1[i];
+      d[i] = a0 - a1;
+      E[i] = sky[i] + w0 * a0 + w1 * a1;
+      V[i] = fma(k0 * f0[i], f0[i], fma(k1 * f1[i], f1[i], w01 * d[i] * d[i]));
+      own[i] = true;
+    }
+    // neighbours whose patch in this image covers the pixel (Section 2.2.3: sum over sources)
+    for (int nb = P.nbr_begin; nb < P.nbr_end; ++nb) {
+      const int q = a.nbr_idx[nb];
+      const DPatch Q = a.patches[q];
+      const int ox = P.x0 - Q.x0, oy = P.y0 - Q.y0;
+      T qx[PPL], qy[PPL];
+      bool in[PPL];
+      bool any = false;
+#pragma unroll
+      for (int i = 0; i < PPL; ++i) {
+        const int cx = (int)px[i] + ox, cy = (int)py[i] + oy;
+        in[i] = valid[i] && cx >= 0 && cx < Q.w && cy >= 0 && cy < Q.h;
+        qx[i] = (T)cx;
+        qy[i] = (T)cy;
+        any |= in[i];
+      }
+      if (__ballot(any) == 0) continue;
+      const Table<T>* __restrict__ tq = a.base + q;
+      T g0[PPL], g1[PPL];
+      eval_values<T, PPL, NEXP, NDEV>(tq, K, qx, qy, g0, g1);
+      const T QL0 = tq->hdr[0], QL1 = tq->hdr[1], Qw0 = tq->hdr[2], Qw1 = tq->hdr[3];
+      const T Qk0 = tq->hdr[4], Qk1 = tq->hdr[5], Qw01 = tq->hdr[6];
+      const bool lower = Q.src < P.src;
+#pragma unroll
+      for (int i = 0; i < PPL; ++i) {
+        const T a0 = QL0 * g0[i], a1 = QL1 * g1[i], dd = a0 - a1;
+        const T Eq = Qw0 * a0 + Qw1 * a1;
+        const T Vq = fma(Qk0 * g0[i], g0[i], fma(Qk1 * g1[i], g1[i], Qw01 * dd * dd));
+        E[i] += in[i] ? Eq : (T)0;
+        V[i] += in[i] ? Vq : (T)0;
+        if (lower && in[i]) own[i] = false;
+      }
+    }
+    // pixel term (centred: the data constant x log x - x - log x! is added per patch in
+    // FP64) and adjoint coefficients
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      const T x = xv[i];
+      const T invE = (T)1 / E[i];
+      const T xr = x * invE * invE;
+      T Tm = (x > (T)0 ? x * flog<T>(E[i] / x) : (T)0) - (E[i] - x) - (T)0.5 * xr * V[i];
+      if (!valid[i]) Tm = (T)0;
+      acc[S_T] += (double)Tm;
+      acc[S_T_OWN] += own[i] ? (double)Tm : 0.0;
+      if (GRAD) {
+        T cE = fma(xr * invE, V[i], (x - E[i]) * invE);
+        T cV = (T)-0.5 * xr;
+        if (!valid[i]) cE = cV = (T)0;
+        const T rho0 = cE * w0 * L0 + (T)2 * cV * fma(k0, f0[i], w01 * L0 * d[i]);
+        const T rho1 = cE * w1 * L1 + (T)2 * cV * fma(k1, f1[i], -w01 * L1 * d[i]);
+        const T omp = (T)1 - pi;
+        const T g0x = pi * o.gdx[i] + omp * o.gex[i], g0y = pi * o.gdy[i] + omp * o.gey[i];
+        const T s0xx = pi * o.sdxx[i] + omp * o.sexx[i];
+        const T s0xy = (T)2 * (pi * o.sdxy[i] + omp * o.sexy[i]);
+        const T s0yy = pi * o.sdyy[i] + omp * o.seyy[i];
+        acc[S_CE_F0] += (double)(cE * f0[i]);
+        acc[S_CE_F1] += (double)(cE * f1[i]);
+        acc[S_CV_F00] += (double)(cV * f0[i] * f0[i]);
+        acc[S_CV_F11] += (double)(cV * f1[i] * f1[i]);
+        acc[S_CV_F01] += (double)(cV * f0[i] * f1[i]);
+        acc[S_MU_X] += (double)fma(rho0, g0x, rho1 * o.g1x[i]);
+        acc[S_MU_Y] += (double)fma(rho0, g0y, rho1 * o.g1y[i]);
+        acc[S_S_XX] += (double)(rho0 * s0xx);
+        acc[S_S_XY] += (double)(rho0 * s0xy);
+        acc[S_S_YY] += (double)(rho0 * s0yy);
+        acc[S_PI] += (double)(rho0 * (o.fd[i] - o.fe[i]));
+      }
+    }
+  }
+  double* out = a.slots + (int64_t)blockIdx.y * a.slot_variant_stride + (int64_t)t * kSlots;
+#pragma unroll
+  for (int q = 0; q < 13; ++q) {
+    if (!GRAD && q != S_T && q != S_T_OWN) continue;
+    const double s = wave_sum<T>(acc[q]);
+    if (lane == 0) out[q] = s;
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// k_finalize: one thread per (variant, source)
+
+// KL(q(z_s) || p(z_s)) and its gradient in the unconstrained coordinates (equations eq:kl,
+// kleq; Supplement A with the readings: flux KL is the normal KL of log r with variances;
+// colour KL is the bound of Section 4.2.3 at its optimal weights; point-mass terms are
+// minus the log prior density; direction and angle terms are constants and dropped).
+__device__ double kl_source(const DPrior& pr, const double* th, double* g) {
+  const double eta = th[2];
+  const double a = sigmoid(eta);
+  const double log_a = -softplus(-eta), log_1ma = -softplus(eta);
+  double kl = a * (log_a - pr.log_a) + (1.0 - a) * (log_1ma - pr.log_1ma);
+  double dk_da = eta - pr.logit_a;          // d KL_a / d a
+  const double q[2] = {1.0 - a, a};
+  double part[2];
+  for (int i = 0; i < 2; ++i) {
+    const double rm = th[3 + i], lrv = th[5 + i], rv = exp(lrv);
+    const double R1 = pr.r[i][0], R2 = pr.r[i][1];
+    double kr = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
+    g[3 + i] -= q[i] * (rm - R1) / R2;
+    g[5 + i] -= q[i] * (-0.5 + rv / (2.0 * R2));
+    // colour bound: -log sum_j w_j exp(-D_j); gradient sum_j xi_j dD_j
+    double cm[4], cv[4], lcv[4];
+    for (int k = 0; k < 4; ++k) {
+      cm[k] = th[7 + 4 * i + k];
+      lcv[k] = th[15 + 4 * i + k];
+      cv[k] = exp(lcv[k]);
+    }
+    double D[CEL_N_COLOUR_COMPONENTS], mx = -1e300;
+    double sum_lcv = lcv[0] + lcv[1] + lcv[2] + lcv[3];
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+      double tr = 0, maha = 0;
+      for (int k = 0; k < 4; ++k) {
+        tr += pr.c_prec[i][j][k][k] * cv[k];
+        double row = 0;
+        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
+        maha += (pr.c_mean[i][j][k] - cm[k]) * row;
+      }
+      D[j] = 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - sum_lcv);
+      const double e = pr.c_logw[i][j] - D[j];
+      if (e > mx) mx = e;
+    }
+    double z = 0;
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - D[j] - mx);
+    const double kc = -(mx + log(z));
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+      const double xi = exp(pr.c_logw[i][j] - D[j] - mx) / z;
+      if (xi == 0.0) continue;
+      for (int k = 0; k < 4; ++k) {
+        double row = 0;
+        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
+        g[7 + 4 * i + k] -= q[i] * xi * row;
+        g[15 + 4 * i + k] -= q[i] * xi * 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
+      }
+    }
+    part[i] = kr + kc;
+    kl += q[i] * part[i];
+  }
+  dk_da += part[1] - part[0];
+  g[2] -= dk_da * a * (1.0 - a);
+  // radius: point mass vs log-normal
+  const double lr = th[24], E1 = pr.radius[0], E2 = pr.radius[1];
+  kl += lr + 0.5 * log(2.0 * M_PI * E2) + (lr - E1) * (lr - E1) / (2.0 * E2);
+  g[24] -= 1.0 + (lr - E1) / E2;
+  // profile and axis: point mass vs Beta
+  {
+    const double e = th[25], p = sigmoid(e), lp = -softplus(-e), l1p = -softplus(e);
+    kl += -(pr.profile[0] - 1.0) * lp - (pr.profile[1] - 1.0) * l1p + pr.lbeta_profile;
+    g[25] -= -(pr.profile[0] - 1.0) * (1.0 - p) + (pr.profile[1] - 1.0) * p;
+  }
+  {
+    const double e = th[26], p = sigmoid(e), lp = -softplus(-e), l1p = -softplus(e);
+    kl += -(pr.axis[0] - 1.0) * lp - (pr.axis[1] - 1.0) * l1p + pr.lbeta_axis;
+    g[26] -= -(pr.axis[0] - 1.0) * (1.0 - p) + (pr.axis[1] - 1.0) * p;
+  }
+  return kl;
+}
+
+__global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
+  const int jj = blockIdx.x * 64 + threadIdx.x;
+  if (jj >= a.n_jobs) return;
+  const int s = a.job_src ? a.job_src[jj] : jj + a.src_offset;
+  const int vv = blockIdx.y;
+  const int v = a.variant0 + vv;
+  if (a.active && !a.active[s]) return;
+  double th[kThetaN];
+  load_theta(a.theta, a.theta_trial, s, v, a.fd_step, th);
+  double g[kThetaN];
+  for (int k = 0; k < kThetaN; ++k) g[k] = 0.0;
+  const double aa = sigmoid(th[2]);
+  const double w0 = 1.0 - aa, w1 = aa;
+  const double ang = th[23], rad = exp(th[24]), prof = sigmoid(th[25]), axis = sigmoid(th[26]);
+  double sig[3];
+  galaxy_cov(ang, rad, axis, sig);
+  double local = 0, own = 0, gS[3] = {0, 0, 0}, gpi = 0;
+  const double* slots = a.slots + (int64_t)vv * a.slot_variant_stride;
+  for (int p = a.patch_ptr[s]; p < a.patch_ptr[s + 1]; ++p) {
+    const DPatch P = a.patches[p];
+    double sm[13];
+    for (int q = 0; q < 13; ++q) sm[q] = 0.0;
+    for (int t = P.task_begin; t < P.task_end; ++t)
+      for (int q = 0; q < 13; ++q) sm[q] += slots[(int64_t)t * kSlots + q];
+    local += sm[S_T] + a.pix_const[2 * p];
+    own += sm[S_T_OWN] + a.pix_const[2 * p + 1];
+    if (!a.want_grad) continue;
+    const cel_image& im = a.images[P.img];
+    double L[2], M[2], var[2];
+    for (int i = 0; i < 2; ++i) {
+      double m = th[3 + i];
+      var[i] = exp(th[5 + i]);
+      for (int c = 0; c < 4; ++c) {
+        const double W = c_W[im.band][c];
+        m += W * th[7 + 4 * i + c];
+        var[i] += W * W * exp(th[15 + 4 * i + c]);
+      }
+      L[i] = im.iota * exp(m + 0.5 * var[i]);
+      M[i] = im.iota * im.iota * exp(2.0 * m + 2.0 * var[i]);
+    }
+    // E_s = w0 L0 f0 + w1 L1 f1,  V_s = w0 M0 f0^2 + w1 M1 f1^2 - E_s^2
+    const double A0 = sm[S_CE_F0], A1 = sm[S_CE_F1], B00 = sm[S_CV_F00], B11 = sm[S_CV_F11], B01 = sm[S_CV_F01];
+    const double gL0 = w0 * A0 - 2.0 * w0 * (w0 * L[0] * B00 + w1 * L[1] * B01);
+    const double gL1 = w1 * A1 - 2.0 * w1 * (w0 * L[0] * B01 + w1 * L[1] * B11);
+    const double gM0 = w0 * B00, gM1 = w1 * B11;
+    const double ga = L[1] * A1 - L[0] * A0 + M[1] * B11 - M[0] * B00 -
+                      2.0 * (w0 * L[0] * L[1] * B01 - w0 * L[0] * L[0] * B00 + w1 * L[1] * L[1] * B11 -
+                             w1 * L[0] * L[1] * B01);
+    g[2] += ga * aa * (1.0 - aa);
+    const double gL[2] = {gL0, gL1}, gM[2] = {gM0, gM1};
+    for (int i = 0; i < 2; ++i) {
+      const double gm = gL[i] * L[i] + 2.0 * gM[i] * M[i];
+      const double gv = 0.5 * gL[i] * L[i] + 2.0 * gM[i] * M[i];
+      g[3 + i] += gm;
+      g[5 + i] += gv * exp(th[5 + i]);
+      for (int c = 0; c < 4; ++c) {
+        const double W = c_W[im.band][c];
+        g[7 + 4 * i + c] += gm * W;
+        g[15 + 4 * i + c] += gv * W * W * exp(th[15 + 4 * i + c]);
+      }
+    }
+    // centre: mu = A u + b
+    g[0] += im.A[0][0] * sm[S_MU_X] + im.A[1][0] * sm[S_MU_Y];
+    g[1] += im.A[0][1] * sm[S_MU_X] + im.A[1][1] * sm[S_MU_Y];
+    // covariance: S = A Sigma A^T;  d/dSigma (matrix) = A^T G A
+    const double Gxx = sm[S_S_XX], Gxy = 0.5 * sm[S_S_XY], Gyy = sm[S_S_YY];
+    const double a00 = im.A[0][0], a01 = im.A[0][1], a10 = im.A[1][0], a11 = im.A[1][1];
+    const double h00 = a00 * (Gxx * a00 + Gxy * a10) + a10 * (Gxy * a00 + Gyy * a10);
+    const double h01 = a00 * (Gxx * a01 + Gxy * a11) + a10 * (Gxy * a01 + Gyy * a11);
+    const double h11 = a01 * (Gxx * a01 + Gxy * a11) + a11 * (Gxy * a01 + Gyy * a11);
+    gS[0] += h00;
+    gS[1] += 2.0 * h01;
+    gS[2] += h11;
+    gpi += sm[S_PI];
+  }
+  double kl = kl_source(*a.prior, th, g);   // subtracts KL gradient
+  local -= kl;
+  own -= kl;
+  if (a.want_grad) {
+    // Sigma(angle, radius, axis) chain rule
+    const double c = cos(ang), sn = sin(ang), r2 = rad * rad, a2 = axis * axis;
+    const double dxx_dt = 2.0 * r2 * c * sn * (a2 - 1.0), dyy_dt = -dxx_dt;
+    const double dxy_dt = r2 * (a2 - 1.0) * (c * c - sn * sn);
+    g[23] += gS[0] * dxx_dt + gS[1] * dxy_dt + gS[2] * dyy_dt;
+    g[24] += 2.0 * (gS[0] * sig[0] + gS[1] * sig[1] + gS[2] * sig[2]);   // d/dlog r
+    const double dxx_da = 2.0 * axis * r2 * sn * sn, dyy_da = 2.0 * axis * r2 * c * c,
+                 dxy_da = 2.0 * axis * r2 * c * sn;
+    g[26] += (gS[0] * dxx_da + gS[1] * dxy_da + gS[2] * dyy_da) * axis * (1.0 - axis);
+    g[25] += gpi * prof * (1.0 - prof);
+  }
+  const int64_t out = (int64_t)vv * a.out_variant_stride + s;
+  if (a.local) a.local[out] = local;
+  if (a.own) a.own[out] = own;
+  if (a.want_grad && a.grad) {
+    for (int k = 0; k < kParamN; ++k) a.grad[out * kThetaN + k] = g[k];
+    for (int k = kParamN; k < kThetaN; ++k) a.grad[out * kThetaN + k] = 0.0;
+  }
+}
+
+// deterministic sum of n values (fixed per-thread stride order, then a fixed tree)
+__global__ __launch_bounds__(256) void k_total(const double* __restrict__ own, int n, double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += own[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// ----------------------------------------------------------------------------------------
+// preparation kernels: per-pixel (count, sky) and per-patch data constants
+
+__global__ __launch_bounds__(256) void k_pixels(const DPatch* __restrict__ patches, const cel_image* __restrict__ images,
+                                                const double* __restrict__ knots, const float* __restrict__ pixels,
+                                                const int64_t* __restrict__ user_off, float2* __restrict__ xs,
+                                                double2* __restrict__ xs64) {
+  const DPatch P = patches[blockIdx.x];
+  const cel_image& im = images[P.img];
+  const double* kn = knots + im.sky_off;
+  const int n = P.w * P.h;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const int row = P.y0 + i / P.w, col = P.x0 + i % P.w;
+    // bilinear interpolation on a knot grid spanning the image corners (Section 2.2.1)
+    double fy = 0, fx = 0;
+    int iy = 0, ix = 0;
+    if (im.sky_qh > 1) {
+      fy = (double)row * (im.sky_qh - 1) / (double)(im.H - 1);
+      iy = min(max((int)floor(fy), 0), im.sky_qh - 2);
+      fy -= iy;
+    }
+    if (im.sky_qw > 1) {
+      fx = (double)col * (im.sky_qw - 1) / (double)(im.W - 1);
+      ix = min(max((int)floor(fx), 0), im.sky_qw - 2);
+      fx -= ix;
+    }
+    const int iy1 = min(iy + 1, im.sky_qh - 1), ix1 = min(ix + 1, im.sky_qw - 1);
+    const double sky = (1 - fy) * (1 - fx) * kn[iy * im.sky_qw + ix] + (1 - fy) * fx * kn[iy * im.sky_qw + ix1] +
+                       fy * (1 - fx) * kn[iy1 * im.sky_qw + ix] + fy * fx * kn[iy1 * im.sky_qw + ix1];
+    const float x = pixels[user_off[blockIdx.x] + i];
+    xs[P.off + i] = make_float2(x, (float)sky);
+    if (xs64) xs64[P.off + i] = make_double2((double)x, sky);
+  }
+}
+
+// sum over the patch of C(x) = x log x - x - log x! (all pixels, and owned pixels only)
+__global__ __launch_bounds__(256) void k_pixconst(const DPatch* __restrict__ patches, const int32_t* __restrict__ nbr_idx,
+                                                  const float2* __restrict__ xs, double* __restrict__ out) {
+  __shared__ double sh[2][256];
+  const DPatch P = patches[blockIdx.x];
+  const int n = P.w * P.h;
+  double all = 0, own = 0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double x = xs[P.off + i].x;
+    const double c = x > 0 ? x * log(x) - x - lgamma(x + 1.0) : 0.0;
+    all += c;
+    const int col = P.x0 + i % P.w, row = P.y0 + i / P.w;
+    bool mine = true;
+    for (int nb = P.nbr_begin; nb < P.nbr_end; ++nb) {
+      const DPatch Q = patches[nbr_idx[nb]];
+      if (Q.src < P.src && col >= Q.x0 && col < Q.x0 + Q.w && row >= Q.y0 && row < Q.y0 + Q.h) mine = false;
+    }
+    if (mine) own += c;
+  }
+  sh[0][threadIdx.x] = all;
+  sh[1][threadIdx.x] = own;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = sh[0][0];
+    out[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// launch wrappers
+
+template <typename T>
+hipError_t launch_prep_tables(const PrepArgs& a, int n_patches_launch, int n_variants, hipStream_t st) {
+  if (n_patches_launch <= 0 || n_variants <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prep_tables<T>, dim3(n_patches_launch, n_variants), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int PPL, bool GRAD>
+static hipError_t fused_dispatch(const FusedArgs<T>& a, const T* htau, int nexp, int ndev, int n_items, int n_var,
+                                 hipStream_t st) {
+  dim3 grid(n_items, n_var);
+  if (nexp == 6 && ndev == 8)
+    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 6, 8>), grid, dim3(64), 0, st, a, htau);
+  else
+    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 8, 8>), grid, dim3(64), 0, st, a, htau);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fused(const FusedArgs<T>& a, const T* htau, int nexp, int ndev, int ppl, bool grad, int n_items,
+                        int n_variants, hipStream_t st) {
+  if (n_items <= 0 || n_variants <= 0) return hipSuccess;
+  switch (ppl * 2 + (grad ? 1 : 0)) {
+    case 2: return fused_dispatch<T, 1, false>(a, htau, nexp, ndev, n_items, n_variants, st);
+    case 3: return fused_dispatch<T, 1, true>(a, htau, nexp, ndev, n_items, n_variants, st);
+    case 4: return fused_dispatch<T, 2, false>(a, htau, nexp, ndev, n_items, n_variants, st);
+    case 5: return fused_dispatch<T, 2, true>(a, htau, nexp, ndev, n_items, n_variants, st);
+    case 8: return fused_dispatch<T, 4, false>(a, htau, nexp, ndev, n_items, n_variants, st);
+    case 9: return fused_dispatch<T, 4, true>(a, htau, nexp, ndev, n_items, n_variants, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, int n_variants, hipStream_t st) {
+  if (a.n_jobs <= 0 || n_variants <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3((a.n_jobs + 63) / 64, n_variants), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_total(const double* own, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_total, dim3(1), dim3(256), 0, st, own, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const double* knots, const float* pixels,
+                         const int64_t* user_off, float2* xs, double2* xs64, int n_patches, hipStream_t st) {
+  if (n_patches <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pixels, dim3(n_patches), dim3(256), 0, st, patches, images, knots, pixels, user_off, xs, xs64);
+  return hipGetLastError();
+}
+
+hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, double* out, int n_patches,
+                           hipStream_t st) {
+  if (n_patches <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pixconst, dim3(n_patches), dim3(256), 0, st, patches, nbr_idx, xs, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_prep_tables<float>(const PrepArgs&, int, int, hipStream_t);
+template hipError_t launch_prep_tables<double>(const PrepArgs&, int, int, hipStream_t);
+template hipError_t launch_fused<float>(const FusedArgs<float>&, const float*, int, int, int, bool, int, int,
+                                        hipStream_t);
+template hipError_t launch_fused<double>(const FusedArgs<double>&, const double*, int, int, int, bool, int, int,
+                                         hipStream_t);
+
+}  // namespace celmi

@@ -1,0 +1,101 @@
+// Plan and context structures (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <vector>
+
+#include "device.h"
+
+struct cel_ctx {
+  int device;
+  cel_options opt;
+};
+
+struct cel_plan {
+  int device = 0;
+  cel_options opt;
+  int S = 0, N = 0, P = 0;
+  int64_t n_units = 0, n_tasks = 0;
+  int nexp = 0, ndev = 0;
+  // host copies
+  std::vector<cel_image> images_h;
+  std::vector<celmi::DPatch> patches_h;
+  std::vector<int32_t> patch_ptr_h, nbr_idx_h, order_h;
+  std::vector<celmi::DTask> tasks_h;
+  std::vector<std::vector<int>> adj;
+  std::vector<int> colour;
+  int n_colours = 0;
+  std::vector<std::vector<int32_t>> class_patches, class_tasks, class_src;
+  celmi::DPrior prior_h;
+  celmi::DProfiles prof_h;
+  std::vector<float> htau_fh;
+  std::vector<double> htau_dh;
+  // device tables
+  celmi::DPatch* d_patches = nullptr;
+  cel_image* d_images = nullptr;
+  int32_t* d_nbr = nullptr;
+  celmi::DTask* d_tasks = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_patch_ptr = nullptr;
+  int32_t* d_npsf = nullptr;
+  celmi::DPrior* d_prior = nullptr;
+  celmi::DProfiles* d_prof = nullptr;
+  float* d_htau_f = nullptr;
+  double* d_htau_d = nullptr;
+  float2* d_xs = nullptr;
+  double2* d_xs64 = nullptr;    // only with float64 pixel / Hessian options
+  double* d_pixconst = nullptr;
+  double* d_total = nullptr;
+  std::vector<int32_t*> d_class_patches, d_class_tasks, d_class_src;
+  // per-variant scratch
+  int nv_f = 0, nv_d = 0, nv_slots = 0;
+  celmi::Table<float>* tables_f = nullptr;
+  celmi::Table<double>* tables_d = nullptr;
+  double* slots = nullptr;
+  double* v_local = nullptr;
+  double* v_own = nullptr;
+  double* v_grad = nullptr;
+  // Newton scratch
+  bool newton_ready = false;
+  double* d_theta_trial = nullptr;
+  double* d_pred = nullptr;
+  double* d_step_norm = nullptr;
+  double* d_npix = nullptr;
+  int32_t* d_colour = nullptr;
+  uint8_t* d_trial_active = nullptr;
+  uint8_t* d_mask = nullptr;
+  int32_t* d_counter = nullptr;
+  uint8_t* h_mask = nullptr;      // pinned
+  int32_t* h_counter = nullptr;   // pinned
+  double* h_total = nullptr;      // pinned
+  hipEvent_t mask_copied = nullptr;
+  hipStream_t own_stream = nullptr;
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    double* theta = nullptr;
+    double* radius = nullptr;
+    int32_t* status = nullptr;
+    hipStream_t stream = nullptr;
+  };
+  std::vector<Graph> graphs;
+  bool marking = false;
+  std::vector<void*> allocs;
+  // measurement: events per recorded evaluation (start, after tables, after pixels, end)
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::array<hipEvent_t, 4>> ev_rec;
+};
+
+namespace celmi {
+cel_options default_options();
+void plan_release(cel_plan* p);
+cel_status ensure_variants(cel_plan* p, int nv, bool fp64);
+hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv, bool grad, int cls,
+                    const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64);
+hipError_t plain_eval(cel_plan* p, const double* theta, hipStream_t sm, bool fp64);
+// record a phase boundary event (k = 0..3) of the current evaluation when timing is on
+void phase_mark(cel_plan* p, int k, hipStream_t sm);
+cel_status ensure_newton(cel_plan* p);
+// global ELBO at theta into p->d_total (tables, ELBO-only pixel pass, finalisation, total)
+hipError_t launch_total_after_eval(cel_plan* p, const double* theta, hipStream_t sm);
+}  // namespace celmi

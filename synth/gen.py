@@ -496,8 +496,8 @@ def subset(prob, sources=None, images=None, name=None):
     """The problem restricted to some sources and images (ids renumbered in order).  Pure
     bookkeeping on the arrays; used to make small test problems and serving requests."""
     S, N = prob.n_sources, prob.n_images
-    src = np.arange(S) if sources is None else np.asarray(sorted(sources))
-    img = np.arange(N) if images is None else np.asarray(sorted(images))
+    src = np.arange(S) if sources is None else np.asarray(sorted(sources), dtype=np.int64)
+    img = np.arange(N) if images is None else np.asarray(sorted(images), dtype=np.int64)
     smap = np.full(S, -1)
     smap[src] = np.arange(len(src))
     imap = np.full(N, -1)

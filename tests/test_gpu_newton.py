@@ -1,0 +1,123 @@
+"""GPU: trust-region Newton step and block coordinate ascent through the C ABI, against the
+oracle; batched equals one-source-at-a-time; graph replay equals eager launches."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import elbo as E  # noqa: E402
+from oracle import newton as NW  # noqa: E402
+from paper_1803_00113_amd import _ffi, api  # noqa: E402
+from synth import gen  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def tiny():
+    return gen.crop_patches(gen.subset(gen.config2(n_sources=6), images=[0, 2, 7]), 22)
+
+
+def one_step(prob, mask, **opts):
+    ctx = api.Context(0, **opts)
+    plan = api.Plan(ctx, prob)
+    th = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    r = torch.ones(prob.n_sources, dtype=torch.float64, device="cuda")
+    st, loc = api.newton_step(plan, th, r, mask)
+    torch.cuda.synchronize()
+    return th.cpu().numpy(), r.cpu().numpy(), st.cpu().numpy(), loc.cpu().numpy(), plan
+
+
+def check_step(m, theta0, s, th_gpu, r_gpu, st_gpu, loc_gpu, fp64):
+    """One Newton step against the oracle's.  Along flat directions of the Hessian small
+    differences in it move the step without changing the objective, so the step is judged
+    by the oracle's own objective at both new points (relative to the gain), plus a loose
+    element-wise bound, identical status and radius."""
+    o_th, o_r, o_st, o_loc = NW.newton_step_source(m, theta0, s, 1.0)
+    assert st_gpu == o_st
+    L0 = E.local_value_grad(m, theta0, s)[0]
+    th = theta0.copy()
+    th[s] = th_gpu
+    Lg = E.elbo(m, th, sources=[s], with_total=False)[1][s].item()
+    gain = abs(o_loc - L0)
+    tol_gain, tol_el, tol_r = (1e-6, 1e-3, 1e-3) if fp64 else (1e-3, 3e-2, 3e-2)
+    step = np.abs(o_th - theta0[s]).max()
+    say(f"  s={s} status {st_gpu}/{o_st} |dtheta|max {np.abs(th_gpu - o_th).max():.2e} (step {step:.2e}) "
+        f"L_oracle(gpu point) - L_oracle(oracle point) {Lg - o_loc:.3e} (gain {gain:.3e}) radius {r_gpu}/{o_r}")
+    assert abs(Lg - o_loc) <= tol_gain * max(gain, 1e-9 * abs(L0)) + 1e-12 * abs(L0)
+    assert np.abs(th_gpu - o_th).max() <= tol_el * max(1.0, step)
+    assert abs(r_gpu - o_r) <= tol_r * max(1.0, o_r)
+    assert abs(loc_gpu - o_loc) <= 1e-5 * abs(o_loc)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_newton_step_config1(fp64):
+    say(f"case: newton step config1 fp64={fp64}")
+    prob = gen.config1()
+    m = E.Model(prob)
+    with pytest.raises(_ffi.CelError):          # the two sources overlap
+        one_step(prob, None)
+    for s in range(2):
+        mask = np.zeros(2, bool)
+        mask[s] = True
+        th, r, st, loc, _ = one_step(prob, mask, hessian_fp64=fp64)
+        assert st[1 - s] == _ffi.ST_SKIPPED and np.isnan(loc[1 - s])
+        assert np.array_equal(th[1 - s], prob.theta0[1 - s])
+        check_step(m, prob.theta0, s, th[s], r[s], st[s], loc[s], fp64)
+
+
+def test_newton_step_class_batched_equals_single():
+    say("case: newton class batched vs single")
+    prob = tiny()
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    mask = plan.colours == 0
+    th = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    r = torch.ones(prob.n_sources, dtype=torch.float64, device="cuda")
+    st, loc = api.newton_step(plan, th, r, mask)
+    th2 = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    r2 = torch.ones(prob.n_sources, dtype=torch.float64, device="cuda")
+    for s in np.nonzero(mask)[0]:
+        one = np.zeros(prob.n_sources, bool)
+        one[s] = True
+        st1, loc1 = api.newton_step(plan, th2, r2, one)
+        assert st1[s].item() == st[s].item() and loc1[s].item() == loc[s].item()
+    torch.cuda.synchronize()
+    assert torch.equal(th, th2) and torch.equal(r, r2)
+    # against the oracle for every stepped source
+    m = E.Model(prob)
+    thn, rn, stn, locn = th.cpu().numpy(), r.cpu().numpy(), st.cpu().numpy(), loc.cpu().numpy()
+    for s in np.nonzero(mask)[0]:
+        check_step(m, prob.theta0, int(s), thn[s], rn[s], stn[s], locn[s], False)
+
+
+def test_sweep_graph_equals_eager_and_matches_oracle():
+    say("case: sweep graph vs eager vs oracle")
+    prob = gen.crop_patches(gen.subset(gen.config2(n_sources=4), sources=[0, 1, 2], images=[1, 6]), 14)
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    res = []
+    for use_graph in (True, False, True):
+        th = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+        r, st, rep = api.sweep(plan, th, n_sweeps=2, max_newton_iters=20, use_graph=use_graph)
+        torch.cuda.synchronize()
+        res.append((th.cpu().numpy(), r.cpu().numpy(), st.cpu().numpy(), rep))
+        say(f"  graph={use_graph}: elbo {rep['elbo']:.6f}, steps {rep['n_newton_steps']}, {rep['seconds']:.3f} s")
+    for k in (1, 2):
+        assert np.array_equal(res[0][0], res[k][0]) and np.array_equal(res[0][2], res[k][2])
+        assert res[0][3]["elbo"] == res[k][3]["elbo"]
+    m = E.Model(prob)
+    o_th, _, o_st, o_rep = NW.sweep(m, prob.theta0, dict(n_sweeps=2, max_iter=20))
+    th = res[0][0]
+    say(f"  oracle elbo {o_rep['elbo']:.6f}; max |dtheta| {np.abs(th - o_th).max():.2e}")
+    start = E.elbo(m, prob.theta0)[0].item()
+    assert res[0][3]["elbo"] > start
+    assert abs(res[0][3]["elbo"] - o_rep["elbo"]) <= 1e-5 * abs(o_rep["elbo"])
+    # the GPU's final point, evaluated by the oracle, is as good as the oracle's own
+    assert E.elbo(m, th)[0].item() >= o_rep["elbo"] - 1e-5 * abs(o_rep["elbo"])
