@@ -21,13 +21,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per unit, counted from the method as computed ("Roofline"):
-# own source value + gradient at a pixel: 3 PSF x (1 star + 14 galaxy) Gaussian components
-# with their mu/S derivatives, the delta-method pixel term and the adjoint accumulation;
-# and per (pixel, covering neighbour) pair: the neighbour's 45-component mixture value.
+# Algorithmic work, counted from the method as computed ("Roofline"):
+# pixel kernel, per active pixel: the own source's 3 PSF x (1 star + 14 galaxy) Gaussian
+# components with their mu / S / profile derivatives, the delta-method pixel term and the
+# adjoint accumulation; per (pixel, covering neighbour) pair: adding its moments.
+# map kernel, per active pixel: the source's 45-component mixture value and its moments.
 FLOP_OWN = 1368 + 47          # FP arithmetic + transcendentals (45 exp, 1 log, 1 reciprocal)
-FLOP_NBR = 352 + 45
-BYTES_UNIT = 8                # (count, sky) pair per active pixel
+FLOP_PAIR = 2
+FLOP_MAP = 348 + 45
+BYTES_UNIT = 8                # (count, sky) pair per active pixel read by the pixel kernel
+BYTES_PAIR = 8                # (E_t, V_t) of a covering neighbour
+BYTES_MAP = 8                 # (E_s, V_s) written by the map kernel
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
 
 
@@ -126,15 +130,22 @@ def main():
     assert np.isfinite(out[0].item())
 
     pairs = covering_pairs(prob)
-    flops = units * FLOP_OWN + pairs * FLOP_NBR
-    kernel_ms = ms_phase[1] / max(ncalls, 1)
+    flops = units * FLOP_OWN + pairs * FLOP_PAIR
+    nb = max(ncalls, 1)
+    kernel_ms = ms_phase[2] / nb
+    maps_ms = ms_phase[1] / nb
     achieved = flops / (kernel_ms * 1e-3) / 1e12
+    bytes_fused = units * BYTES_UNIT + pairs * BYTES_PAIR
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
                     kernel="k_fused<float, 2 px/lane, grad>", kernel_ms=round(kernel_ms, 4),
                     algorithmic_flop_per_launch=flops, covering_pairs=pairs,
-                    algorithmic_bytes_per_launch=units * BYTES_UNIT,
-                    achieved_hbm_GBps=round(units * BYTES_UNIT / (kernel_ms * 1e-3) / 1e9, 1))
+                    algorithmic_bytes_per_launch=bytes_fused,
+                    achieved_hbm_GBps=round(bytes_fused / (kernel_ms * 1e-3) / 1e9, 1),
+                    map_kernel=dict(kernel="k_maps<float, 2 px/lane>", kernel_ms=round(maps_ms, 4),
+                                    achieved=round(units * FLOP_MAP / (maps_ms * 1e-3) / 1e12, 3),
+                                    algorithmic_flop_per_launch=units * FLOP_MAP),
+                    phases_ms=[round(x / nb, 4) for x in ms_phase])
 
     plain = None
     if not args.no_plain:

@@ -125,7 +125,8 @@ typedef struct {
   int32_t chunk_pixels;          /* pixels per work item (multiple of 64); 0 = default  */
   int32_t pixel_fp64;            /* 1: evaluate pixels in float64 instead of float32     */
   int32_t hessian_fp64;          /* 1: FD Hessian from the float64 pixel path           */
-  double fd_step;                /* central-difference step of the Hessian; 0 = 1e-3     */
+  double fd_step;                /* central-difference step of the Hessian; 0 = 1e-2 with
+                                    float32 gradients, 1e-3 with float64 ones             */
   double radius0, radius_max, eta, gtol, ftol, radius_min;   /* trust region (0 = default) */
   int32_t timing;                /* 1: record HIP events around each phase (see below)  */
 } cel_options;
@@ -206,9 +207,10 @@ cel_status cel_sweep(cel_ctx* ctx, const cel_plan* plan, double* theta, double* 
 
 /* Measurement: with options.timing = 1, every ELBO / gradient evaluation records HIP events
  * on the caller's stream around its phases.  This returns the summed device milliseconds
- * since the last reset -- ms[0] component tables, ms[1] pixel kernel, ms[2] finalisation
- * and total -- and the number of evaluations recorded (it synchronises on the recorded
- * events).  reset != 0 clears the record.  CEL_EINVAL if timing was not enabled. */
+ * since the last reset -- ms[0] component tables, ms[1] neighbour moment maps, ms[2] pixel
+ * kernel, ms[3] finalisation and total (ms: HOST double[4]) -- and the number of
+ * evaluations recorded (it synchronises on the recorded events).  reset != 0 clears the
+ * record.  CEL_EINVAL if timing was not enabled. */
 cel_status cel_phase_times(cel_plan* plan, double* ms, int64_t* n_calls, int32_t reset);
 
 #ifdef __cplusplus

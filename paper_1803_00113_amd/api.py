@@ -172,8 +172,8 @@ class Plan:
         return t.contiguous()
 
     def phase_times(self, reset=True):
-        """cel_phase_times: (ms[tables, pixels, finalise], n_evaluations) since the last reset."""
-        ms = (C.c_double * 3)()
+        """cel_phase_times: (ms[tables, maps, pixels, finalise], n_evaluations) since the last reset."""
+        ms = (C.c_double * 4)()
         n = C.c_int64()
         F.check("cel_phase_times", F.lib.cel_phase_times(self.h, ms, C.byref(n), int(bool(reset))))
         return list(ms), int(n.value)

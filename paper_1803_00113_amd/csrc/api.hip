@@ -32,7 +32,7 @@ cel_options default_options() {
   std::memset(&o, 0, sizeof(o));
   o.pixels_per_lane = 2;
   o.chunk_pixels = 512;
-  o.fd_step = 1e-3;
+  o.fd_step = 0.0;   // resolved in merge_options: 1e-2 (float32 pixels), 1e-3 (float64)
   o.radius0 = 1.0;
   o.radius_max = 100.0;
   o.eta = 0.1;
@@ -58,6 +58,12 @@ static cel_options merge_options(const cel_options* in) {
   if (in->radius_min > 0) o.radius_min = in->radius_min;
   o.timing = in->timing;
   return o;
+}
+
+static void resolve_fd_step(cel_options& o) {
+  // central differences of a gradient carrying float32 rounding noise eps: error ~ eps/h +
+  // h^2 |f'''|, so float32 gradients take a larger step than float64 ones
+  if (!(o.fd_step > 0)) o.fd_step = (o.pixel_fp64 || o.hessian_fp64) ? 1e-3 : 1e-2;
 }
 
 template <typename X>
@@ -203,8 +209,8 @@ void plan_release(cel_plan* p) {
 void phase_mark(cel_plan* p, int k, hipStream_t sm) {
   if (!p->opt.timing || !p->marking) return;
   if (k == 0) {
-    std::array<hipEvent_t, 4> r;
-    for (int i = 0; i < 4; ++i) {
+    std::array<hipEvent_t, 5> r;
+    for (int i = 0; i < 5; ++i) {
       if (p->ev_pool.empty()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
@@ -296,6 +302,7 @@ extern "C" cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_op
   if (hipGetDeviceCount(&nd) != hipSuccess) return CEL_EHIP;
   if (hip_device < 0 || hip_device >= nd) return CEL_EINVAL;
   cel_options o = merge_options(opt);
+  resolve_fd_step(o);
   if (!(o.pixels_per_lane == 1 || o.pixels_per_lane == 2 || o.pixels_per_lane == 4)) return CEL_EINVAL;
   if (o.chunk_pixels < 64 || o.chunk_pixels % 64 != 0 || o.chunk_pixels > (1 << 20)) return CEL_EINVAL;
   cel_ctx* c = new cel_ctx;
@@ -419,6 +426,22 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   p->order_h.resize(p->n_tasks);
   std::iota(p->order_h.begin(), p->order_h.end(), 0);
   std::stable_sort(p->order_h.begin(), p->order_h.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  // the moment maps are read only where another source's patch overlaps: keep the work
+  // items whose pixel rows meet a neighbour's rectangle
+  p->map_order_h.clear();
+  for (int t : p->order_h) {
+    const DTask& tk = p->tasks_h[t];
+    const DPatch& d = p->patches_h[tk.patch];
+    const int r0 = d.y0 + tk.pix_begin / d.w, r1 = d.y0 + (tk.pix_end - 1) / d.w;
+    const int c0 = r0 == r1 ? d.x0 + tk.pix_begin % d.w : d.x0;
+    const int c1 = r0 == r1 ? d.x0 + (tk.pix_end - 1) % d.w : d.x0 + d.w - 1;
+    bool need = false;
+    for (int nb = d.nbr_begin; nb < d.nbr_end && !need; ++nb) {
+      const DPatch& q = p->patches_h[p->nbr_idx_h[nb]];
+      need = q.x0 <= c1 && c0 < q.x0 + q.w && q.y0 <= r1 && r0 < q.y0 + q.h;
+    }
+    if (need) p->map_order_h.push_back(t);
+  }
   // per-colour lists of patches and work items (for masked launches)
   p->class_patches.assign(p->n_colours, {});
   p->class_tasks.assign(p->n_colours, {});
@@ -495,7 +518,7 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   std::vector<int32_t> colour32(p->colour.begin(), p->colour.end());
   if ((st = track_upload(p, &p->d_patches, p->patches_h)) || (st = track_upload(p, &p->d_images, imgs)) ||
       (st = track_upload(p, &p->d_nbr, p->nbr_idx_h)) || (st = track_upload(p, &p->d_tasks, p->tasks_h)) ||
-      (st = track_upload(p, &p->d_order, p->order_h)) || (st = track_upload(p, &p->d_patch_ptr, p->patch_ptr_h)) ||
+      (st = track_upload(p, &p->d_order, p->order_h)) || (st = track_upload(p, &p->d_map_order, p->map_order_h)) || (st = track_upload(p, &p->d_patch_ptr, p->patch_ptr_h)) ||
       (st = track_upload(p, &p->d_npsf, npsf)) || (st = track_upload(p, &p->d_prior, prior1)) ||
       (st = track_upload(p, &p->d_prof, prof1)) || (st = track_upload(p, &p->d_htau_f, p->htau_fh)) ||
       (st = track_upload(p, &p->d_htau_d, p->htau_dh)) || (st = track_upload(p, &d_user_off, user_off)) ||
@@ -517,8 +540,10 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
       return st;
     }
   }
-  if ((p->opt.pixel_fp64 || p->opt.hessian_fp64) &&
-      (st = track(p, &p->d_xs64, (size_t)std::max<int64_t>(p->n_units, 1)))) {
+  if ((st = track(p, &p->d_maps, (size_t)std::max<int64_t>(p->n_units, 1))) ||
+      ((p->opt.pixel_fp64 || p->opt.hessian_fp64) &&
+       ((st = track(p, &p->d_xs64, (size_t)std::max<int64_t>(p->n_units, 1))) ||
+        (st = track(p, &p->d_maps64, (size_t)std::max<int64_t>(p->n_units, 1)))))) {
     plan_release(p);
     return st;
   }
@@ -546,6 +571,20 @@ extern "C" cel_status cel_plan_info(const cel_plan* plan, int64_t* n_units, int3
 
 namespace celmi {
 
+template <typename T>
+static hipError_t launch_maps_t(cel_plan* p, const Table<T>* tables, hipStream_t sm) {
+  MapArgs ma;
+  std::memset(&ma, 0, sizeof(ma));
+  ma.tasks = p->d_tasks;
+  ma.order = p->d_map_order;
+  ma.patches = p->d_patches;
+  ma.base = tables;
+  ma.maps = sizeof(T) == 8 ? (void*)p->d_maps64 : (void*)p->d_maps;
+  ma.img_npsf = p->d_npsf;
+  // the value-only pass keeps 4 pixels per lane: more independent exponentials per wavefront
+  return launch_maps<T>(ma, p->nexp, p->ndev, 4, (int)p->map_order_h.size(), sm);
+}
+
 // Enqueue prep + fused + finalize for `nv` variants starting at variant v0 over either all
 // sources (cls < 0) or one colour class, with optional active mask.  Outputs go to the
 // plan's per-variant arrays.
@@ -566,9 +605,12 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   pa.tables = tables;
   pa.n_patches = p->P;
   phase_mark(p, 0, sm);
-  if (prep_base) {   // variant 0 of every source (neighbours read these)
+  if (prep_base) {   // variant 0 of every source and its moment maps (neighbours read these)
     pa.variant0 = 0;
     e = launch_prep_tables<T>(pa, p->P, 1, sm);
+    if (e != hipSuccess) return e;
+    phase_mark(p, 1, sm);
+    e = launch_maps_t<T>(p, tables, sm);
     if (e != hipSuccess) return e;
   }
   int n_items = (int)p->n_tasks;
@@ -586,7 +628,7 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
     e = launch_prep_tables<T>(pa, np, nv - vstart, sm);
     if (e != hipSuccess) return e;
   }
-  phase_mark(p, 1, sm);
+  phase_mark(p, 2, sm);
   FusedArgs<T> fa;
   std::memset(&fa, 0, sizeof(fa));
   fa.tasks = p->d_tasks;
@@ -598,6 +640,7 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   fa.own = tables;
   fa.variant_stride = p->P;
   fa.xs = sizeof(T) == 8 ? (const void*)p->d_xs64 : (const void*)p->d_xs;
+  fa.maps = sizeof(T) == 8 ? (const void*)p->d_maps64 : (const void*)p->d_maps;
   fa.slots = p->slots + (int64_t)v0 * p->n_tasks * kSlots;
   fa.slot_variant_stride = p->n_tasks * kSlots;
   fa.active = active;
@@ -605,7 +648,7 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   fa.img_npsf = p->d_npsf;
   e = launch_fused<T>(fa, htau, p->nexp, p->ndev, p->opt.pixels_per_lane, grad, n_items, nv, sm);
   if (e != hipSuccess) return e;
-  phase_mark(p, 2, sm);
+  phase_mark(p, 3, sm);
   FinalizeArgs fz;
   std::memset(&fz, 0, sizeof(fz));
   fz.n_jobs = p->S;
@@ -648,6 +691,7 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
   pa.tables = tables;
   pa.n_patches = p->P;
   hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
+  if (e == hipSuccess) e = launch_maps_t<T>(p, tables, sm);
   FusedArgs<T> fa;
   std::memset(&fa, 0, sizeof(fa));
   fa.tasks = p->d_tasks;
@@ -658,6 +702,7 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
   fa.own = tables;
   fa.variant_stride = p->P;
   fa.xs = sizeof(T) == 8 ? (const void*)p->d_xs64 : (const void*)p->d_xs;
+  fa.maps = sizeof(T) == 8 ? (const void*)p->d_maps64 : (const void*)p->d_maps;
   fa.slots = p->slots;
   fa.slot_variant_stride = p->n_tasks * kSlots;
   fa.img_npsf = p->d_npsf;
@@ -720,7 +765,7 @@ static cel_status eval_common(cel_ctx* ctx, const cel_plan* cplan, const double*
   p->marking = true;
   hipError_t e = eval_any(p, theta, nullptr, 0, 1, want_grad, -1, nullptr, sm, true, fp64);
   if (e == hipSuccess && elbo_total) e = launch_total(p->v_own, p->S, elbo_total, sm);
-  phase_mark(p, 3, sm);
+  phase_mark(p, 4, sm);
   p->marking = false;
   if (e == hipSuccess && elbo_local && p->S > 0)
     e = hipMemcpyAsync(elbo_local, p->v_local, sizeof(double) * p->S, hipMemcpyDeviceToDevice, sm);
@@ -762,11 +807,11 @@ extern "C" cel_status cel_elbo_grad_plain(cel_ctx* ctx, const cel_plan* cplan, c
 extern "C" cel_status cel_phase_times(cel_plan* p, double* ms, int64_t* n_calls, int32_t reset) {
   if (!p || !p->opt.timing) return CEL_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
-  double acc[3] = {0, 0, 0};
+  double acc[4] = {0, 0, 0, 0};
   int64_t n = 0;
   for (auto& r : p->ev_rec) {
-    if (hipEventSynchronize(r[3]) != hipSuccess) return CEL_EHIP;
-    for (int k = 0; k < 3; ++k) {
+    if (hipEventSynchronize(r[4]) != hipSuccess) return CEL_EHIP;
+    for (int k = 0; k < 4; ++k) {
       float t = 0;
       if (hipEventElapsedTime(&t, r[k], r[k + 1]) != hipSuccess) return CEL_EHIP;
       acc[k] += t;
@@ -774,7 +819,7 @@ extern "C" cel_status cel_phase_times(cel_plan* p, double* ms, int64_t* n_calls,
     ++n;
   }
   if (ms)
-    for (int k = 0; k < 3; ++k) ms[k] = acc[k];
+    for (int k = 0; k < 4; ++k) ms[k] = acc[k];
   if (n_calls) *n_calls = n;
   if (reset) {
     for (auto& r : p->ev_rec)

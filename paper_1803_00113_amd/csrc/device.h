@@ -37,11 +37,15 @@ enum Slot {
 //      V_s = k0 f0^2 + k1 f1^2 + w01 (L0 f0 - L1 f1)^2, f0 = pi f_dev + (1 - pi) f_exp)
 // star[k]: mean_x, mean_y, P_xx, P_xy, P_yy, log2 weight (weight includes the normaliser)
 // gal[k][j]: P_xx, P_xy, P_yy, log2 weight  (j < n_exp: exponential, then de Vaucouleurs)
+// rc2s[k], rc2[k][j]: squared distance from the component's centre beyond which its value
+// is below 2^-60 (from the smallest eigenvalue of its precision); -1 = negligible everywhere
 template <typename T>
 struct alignas(16) Table {
   T hdr[8];
   T star[kMaxPsf][8];
   T gal[kMaxPsf][2 * kMaxProf][4];
+  T rc2s[kMaxPsf];
+  T rc2[kMaxPsf][2 * kMaxProf];
 };
 
 struct DPatch {
@@ -84,11 +88,21 @@ struct FusedArgs {
   const Table<T>* own;         // tables of the variant being evaluated, [P] per variant
   int64_t variant_stride;      // tables per variant (= P)
   const void* xs;              // (count, sky) per packed pixel: float2 (T=float) or double2
+  const void* maps;            // (E_s, V_s) of each patch's own source per packed pixel
   double* slots;               // [variant][n_tasks][kSlots]
   int64_t slot_variant_stride; // = n_tasks * kSlots
   const uint8_t* active;       // per source (nullptr = all)
   int32_t variant0;            // variant index of blockIdx.y == 0
   const int32_t* img_npsf;     // PSF components per image
+};
+
+struct MapArgs {
+  const DTask* tasks;
+  const int32_t* order;        // work items to run (null = identity)
+  const DPatch* patches;
+  const void* base;            // variant-0 tables
+  void* maps;                  // out: (E_s, V_s) per packed pixel
+  const int32_t* img_npsf;
 };
 
 }  // namespace celmi

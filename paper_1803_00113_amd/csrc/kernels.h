@@ -47,6 +47,8 @@ hipError_t launch_prep_tables(const PrepArgs& a, int n_patches_launch, int n_var
 template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, const T* htau, int nexp, int ndev, int ppl, bool grad, int n_items,
                         int n_variants, hipStream_t st);
+template <typename T>
+hipError_t launch_maps(const MapArgs& a, int nexp, int ndev, int ppl, int n_items, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs& a, int n_variants, hipStream_t st);
 hipError_t launch_total(const double* own, int n, double* out, hipStream_t st);
 hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const double* knots, const float* pixels,

@@ -35,6 +35,15 @@ template <> __device__ __forceinline__ double flog<double>(double x) { return lo
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLog2TwoPi = 2.6514961294723187980;   // log2(2 pi)
 constexpr double kNegHuge = -1.0e30;
+constexpr double kCutLog2 = -60.0;   // components below 2^-60 over a wavefront's pixels are skipped
+
+// squared radius beyond which 2^(lw - log2(e)/2 d^T C^{-1} d) < 2^kCutLog2
+__device__ __forceinline__ double cut_radius2(double lw, double cxx, double cxy, double cyy) {
+  const double room = lw - kCutLog2;
+  if (!(room > 0)) return -1.0;
+  const double lmax = 0.5 * (cxx + cyy) + sqrt(0.25 * (cxx - cyy) * (cxx - cyy) + cxy * cxy);
+  return room / (0.5 * kLog2e / lmax);
+}
 
 // log l_b = log r + W[b] . c,  c_k = ln(l_{k+1} / l_k), reference band r = index 2
 __device__ __constant__ double c_W[5][4] = {
@@ -124,10 +133,13 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
         r[2] = (T)(cyy / det);
         r[3] = (T)(-cxy / det);
         r[4] = (T)(cxx / det);
-        r[5] = im.psf[k][0] > 0 ? (T)(log2(im.psf[k][0]) - kLog2TwoPi - 0.5 * log2(det)) : (T)kNegHuge;
+        const double lw = im.psf[k][0] > 0 ? log2(im.psf[k][0]) - kLog2TwoPi - 0.5 * log2(det) : kNegHuge;
+        r[5] = (T)lw;
+        tb->rc2s[k] = (T)cut_radius2(lw, cxx, cxy, cyy);
       } else {
         r[0] = r[1] = r[2] = r[3] = r[4] = (T)0;
         r[5] = (T)kNegHuge;
+        tb->rc2s[k] = (T)-1;
       }
       r[6] = r[7] = (T)0;
     } else {
@@ -145,10 +157,13 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
         r[0] = (T)(cyy / det);
         r[1] = (T)(-cxy / det);
         r[2] = (T)(cxx / det);
-        r[3] = wt > 0 ? (T)(log2(wt) - kLog2TwoPi - 0.5 * log2(det)) : (T)kNegHuge;
+        const double lw = wt > 0 ? log2(wt) - kLog2TwoPi - 0.5 * log2(det) : kNegHuge;
+        r[3] = (T)lw;
+        tb->rc2[k][j] = (T)cut_radius2(lw, cxx, cxy, cyy);
       } else {
         r[0] = r[1] = r[2] = (T)0;
         r[3] = (T)kNegHuge;
+        tb->rc2[k][j] = (T)-1;
       }
     }
   }
@@ -159,9 +174,17 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
 
 // Values of a source's star (f1) and galaxy (f0) light at PPL pixels (local coords of the
 // source's own patch).  Neighbour evaluation: no derivatives.
+// Squared distance from (mx, my) to the wavefront's pixel box [bx0, bx1] x [by0, by1].
+template <typename T>
+__device__ __forceinline__ T box_dist2(T mx, T my, const T* box) {
+  const T ddx = fmax(fmax(box[0] - mx, mx - box[1]), (T)0);
+  const T ddy = fmax(fmax(box[2] - my, my - box[3]), (T)0);
+  return ddx * ddx + ddy * ddy;
+}
+
 template <typename T, int PPL, int NEXP, int NDEV>
 __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int K, const T* px, const T* py,
-                                            T* f0, T* f1) {
+                                            const T* box, T* f0, T* f1) {
   T fe[PPL], fd[PPL];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) fe[i] = fd[i] = f1[i] = (T)0;
@@ -177,13 +200,15 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
       xy[i] = (T)2 * dx[i] * dy[i];
       yy[i] = dy[i] * dy[i];
     }
-    {
+    const T d2 = box_dist2<T>(mx, my, box);
+    if (d2 <= tb->rc2s[k]) {
       const T pxx = tb->star[k][2] * hl, pxy = tb->star[k][3] * hl, pyy = tb->star[k][4] * hl, lw = tb->star[k][5];
 #pragma unroll
       for (int i = 0; i < PPL; ++i) f1[i] += fexp2<T>(fma(pxx, xx[i], fma(pxy, xy[i], fma(pyy, yy[i], lw))));
     }
 #pragma unroll
     for (int j = 0; j < NEXP; ++j) {
+      if (!(d2 <= tb->rc2[k][j])) continue;
       const T pxx = tb->gal[k][j][0] * hl, pxy = tb->gal[k][j][1] * hl, pyy = tb->gal[k][j][2] * hl,
               lw = tb->gal[k][j][3];
 #pragma unroll
@@ -191,6 +216,7 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
     }
 #pragma unroll
     for (int j = 0; j < NDEV; ++j) {
+      if (!(d2 <= tb->rc2[k][kMaxProf + j])) continue;
       const T pxx = tb->gal[k][kMaxProf + j][0] * hl, pxy = tb->gal[k][kMaxProf + j][1] * hl,
               pyy = tb->gal[k][kMaxProf + j][2] * hl, lw = tb->gal[k][kMaxProf + j][3];
 #pragma unroll
@@ -242,7 +268,7 @@ __device__ __forceinline__ void comp_own(T pxx, T pxy, T pyy, T lw, T htau, cons
 // give bitwise-identical objectives.
 template <typename T, int PPL, int NEXP, int NDEV, bool DERIV>
 __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const T* __restrict__ htau, int K,
-                                         const T* px, const T* py, OwnPix<T, PPL>& o) {
+                                         const T* px, const T* py, const T* box, OwnPix<T, PPL>& o) {
 #pragma unroll
   for (int i = 0; i < PPL; ++i) {
     o.f1[i] = o.g1x[i] = o.g1y[i] = (T)0;
@@ -259,17 +285,78 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
       dx[i] = px[i] - mx;
       dy[i] = py[i] - my;
     }
-    comp_own<T, PPL, DERIV ? 1 : 0>(tb->star[k][2], tb->star[k][3], tb->star[k][4], tb->star[k][5], (T)0, dx, dy,
-                                    o.f1, o.g1x, o.g1y, z, z, z);
+    const T d2 = box_dist2<T>(mx, my, box);
+    if (d2 <= tb->rc2s[k])
+      comp_own<T, PPL, DERIV ? 1 : 0>(tb->star[k][2], tb->star[k][3], tb->star[k][4], tb->star[k][5], (T)0, dx, dy,
+                                      o.f1, o.g1x, o.g1y, z, z, z);
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
-      comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], htau[j], dx,
+      if (d2 <= tb->rc2[k][j])
+        comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], htau[j], dx,
                               dy, o.fe, o.gex, o.gey, o.sexx, o.sexy, o.seyy);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
-      comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
+      if (d2 <= tb->rc2[k][kMaxProf + j])
+        comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
                               tb->gal[k][kMaxProf + j][3], htau[kMaxProf + j], dx, dy, o.fd, o.gdx, o.gdy, o.sdxx,
                               o.sdxy, o.sdyy);
+  }
+}
+
+// Pixel box (patch-local columns x0..x1, rows y0..y1) of the run [base, end) of a
+// row-major patch of width w.
+template <typename T>
+__device__ __forceinline__ void run_box(int base, int end, int w, T* box) {
+  const int last = end - 1;
+  const int r0 = base / w, r1 = last / w;
+  box[0] = (T)(r0 == r1 ? base - r0 * w : 0);
+  box[1] = (T)(r0 == r1 ? last - r1 * w : w - 1);
+  box[2] = (T)r0;
+  box[3] = (T)r1;
+}
+
+// k_maps: every source's own moments E_s, V_s (values only) on every pixel of its
+// patches at the base parameters, read by the pixel kernel for overlapping neighbours.
+template <typename T, int PPL, int NEXP, int NDEV>
+__global__ __launch_bounds__(64) void k_maps(MapArgs a) {
+  const int t = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+  const DTask task = a.tasks[t];
+  const DPatch P = a.patches[task.patch];
+  const Table<T>* __restrict__ tb = reinterpret_cast<const Table<T>*>(a.base) + task.patch;
+  const int K = a.img_npsf[P.img];
+  const int lane = threadIdx.x;
+  const float inv_w = 1.0f / (float)P.w;
+  const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
+  const T k0 = tb->hdr[4], k1 = tb->hdr[5], w01 = tb->hdr[6];
+  for (int base = task.pix_begin; base < task.pix_end; base += 64 * PPL) {
+    T px[PPL], py[PPL];
+    int idxs[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      int idx = base + i * 64 + lane;
+      idxs[i] = idx;
+      if (idx >= task.pix_end) idx = task.pix_begin;
+      int row = (int)(((float)idx + 0.5f) * inv_w);
+      int col = idx - row * P.w;
+      if (col < 0) { row -= 1; col += P.w; }
+      else if (col >= P.w) { row += 1; col -= P.w; }
+      px[i] = (T)col;
+      py[i] = (T)row;
+    }
+    T f0[PPL], f1[PPL], box[4];
+    run_box<T>(base, min(base + 64 * PPL, task.pix_end), P.w, box);
+    eval_values<T, PPL, NEXP, NDEV>(tb, K, px, py, box, f0, f1);
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      if (idxs[i] >= task.pix_end) continue;
+      const T a0 = L0 * f0[i], a1 = L1 * f1[i], d = a0 - a1;
+      const T Es = w0 * a0 + w1 * a1;
+      const T Vs = fma(k0 * f0[i], f0[i], fma(k1 * f1[i], f1[i], w01 * d * d));
+      if constexpr (sizeof(T) == 8)
+        reinterpret_cast<double2*>(a.maps)[P.off + idxs[i]] = make_double2(Es, Vs);
+      else
+        reinterpret_cast<float2*>(a.maps)[P.off + idxs[i]] = make_float2(Es, Vs);
+    }
   }
 }
 
@@ -325,7 +412,9 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
     // own source
     T f0[PPL], f1[PPL];
     OwnPix<T, PPL> o;
-    eval_own<T, PPL, NEXP, NDEV, GRAD>(tb, htau, K, px, py, o);
+    T box[4];
+    run_box<T>(base, min(base + 64 * PPL, task.pix_end), P.w, box);
+    eval_own<T, PPL, NEXP, NDEV, GRAD>(tb, htau, K, px, py, box, o);
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
       f1[i] = o.f1[i];
@@ -341,37 +430,29 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
       V[i] = fma(k0 * f0[i], f0[i], fma(k1 * f1[i], f1[i], w01 * d[i] * d[i]));
       own[i] = true;
     }
-    // neighbours whose patch in this image covers the pixel (Section 2.2.3: sum over sources)
+    // neighbours whose patch in this image covers the pixel (Section 2.2.3: the rate sums
+    // over sources): their moments E_t, V_t at the pixel come from the per-patch maps
     for (int nb = P.nbr_begin; nb < P.nbr_end; ++nb) {
-      const int q = a.nbr_idx[nb];
-      const DPatch Q = a.patches[q];
+      const DPatch Q = a.patches[a.nbr_idx[nb]];
       const int ox = P.x0 - Q.x0, oy = P.y0 - Q.y0;
-      T qx[PPL], qy[PPL];
-      bool in[PPL];
-      bool any = false;
-#pragma unroll
-      for (int i = 0; i < PPL; ++i) {
-        const int cx = (int)px[i] + ox, cy = (int)py[i] + oy;
-        in[i] = valid[i] && cx >= 0 && cx < Q.w && cy >= 0 && cy < Q.h;
-        qx[i] = (T)cx;
-        qy[i] = (T)cy;
-        any |= in[i];
-      }
-      if (__ballot(any) == 0) continue;
-      const Table<T>* __restrict__ tq = a.base + q;
-      T g0[PPL], g1[PPL];
-      eval_values<T, PPL, NEXP, NDEV>(tq, K, qx, qy, g0, g1);
-      const T QL0 = tq->hdr[0], QL1 = tq->hdr[1], Qw0 = tq->hdr[2], Qw1 = tq->hdr[3];
-      const T Qk0 = tq->hdr[4], Qk1 = tq->hdr[5], Qw01 = tq->hdr[6];
       const bool lower = Q.src < P.src;
 #pragma unroll
       for (int i = 0; i < PPL; ++i) {
-        const T a0 = QL0 * g0[i], a1 = QL1 * g1[i], dd = a0 - a1;
-        const T Eq = Qw0 * a0 + Qw1 * a1;
-        const T Vq = fma(Qk0 * g0[i], g0[i], fma(Qk1 * g1[i], g1[i], Qw01 * dd * dd));
-        E[i] += in[i] ? Eq : (T)0;
-        V[i] += in[i] ? Vq : (T)0;
-        if (lower && in[i]) own[i] = false;
+        const int cx = (int)px[i] + ox, cy = (int)py[i] + oy;
+        const bool in = valid[i] && cx >= 0 && cx < Q.w && cy >= 0 && cy < Q.h;
+        if (in) {
+          const int64_t at = Q.off + (int64_t)cy * Q.w + cx;
+          if constexpr (sizeof(T) == 8) {
+            const double2 ev = reinterpret_cast<const double2*>(a.maps)[at];
+            E[i] += (T)ev.x;
+            V[i] += (T)ev.y;
+          } else {
+            const float2 ev = reinterpret_cast<const float2*>(a.maps)[at];
+            E[i] += (T)ev.x;
+            V[i] += (T)ev.y;
+          }
+          if (lower) own[i] = false;
+        }
       }
     }
     // pixel term (centred: the data constant x log x - x - log x! is added per patch in
@@ -497,9 +578,11 @@ __device__ double kl_source(const DPrior& pr, const double* th, double* g) {
   return kl;
 }
 
+// one wavefront per (variant, source): lanes take the source's patches, partial sums are
+// combined by a fixed butterfly, lane 0 applies the shape chain rule and the KL
 __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
-  const int jj = blockIdx.x * 64 + threadIdx.x;
-  if (jj >= a.n_jobs) return;
+  const int jj = blockIdx.x;
+  const int lane = threadIdx.x;
   const int s = a.job_src ? a.job_src[jj] : jj + a.src_offset;
   const int vv = blockIdx.y;
   const int v = a.variant0 + vv;
@@ -515,7 +598,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   galaxy_cov(ang, rad, axis, sig);
   double local = 0, own = 0, gS[3] = {0, 0, 0}, gpi = 0;
   const double* slots = a.slots + (int64_t)vv * a.slot_variant_stride;
-  for (int p = a.patch_ptr[s]; p < a.patch_ptr[s + 1]; ++p) {
+  for (int p = a.patch_ptr[s] + lane; p < a.patch_ptr[s + 1]; p += 64) {
     const DPatch P = a.patches[p];
     double sm[13];
     for (int q = 0; q < 13; ++q) sm[q] = 0.0;
@@ -572,7 +655,21 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
     gS[2] += h11;
     gpi += sm[S_PI];
   }
-  double kl = kl_source(*a.prior, th, g);   // subtracts KL gradient
+  // combine the lanes' partial sums (fixed order: deterministic)
+  local = wave_sum<double>(local);
+  own = wave_sum<double>(own);
+  if (a.want_grad) {
+    for (int k = 0; k < kParamN; ++k) g[k] = wave_sum<double>(g[k]);
+    for (int k = 0; k < 3; ++k) gS[k] = wave_sum<double>(gS[k]);
+    gpi = wave_sum<double>(gpi);
+  }
+  if (lane != 0) return;
+  // the central-difference variants (1..54) carry the pixel part of the gradient only: the
+  // KL part of the Hessian is taken analytically by the trust-region kernel
+  const bool fd_variant = v >= 1 && v <= 2 * kParamN;
+  double gkl[kThetaN];
+  for (int k = 0; k < kThetaN; ++k) gkl[k] = 0.0;
+  double kl = kl_source(*a.prior, th, fd_variant ? gkl : g);   // subtracts the KL gradient
   local -= kl;
   own -= kl;
   if (a.want_grad) {
@@ -716,9 +813,28 @@ hipError_t launch_fused(const FusedArgs<T>& a, const T* htau, int nexp, int ndev
   }
 }
 
+template <typename T>
+hipError_t launch_maps(const MapArgs& a, int nexp, int ndev, int ppl, int n_items, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  const bool std_prof = nexp == 6 && ndev == 8;
+  if (ppl == 1) {
+    if (std_prof) hipLaunchKernelGGL((k_maps<T, 1, 6, 8>), dim3(n_items), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_maps<T, 1, 8, 8>), dim3(n_items), dim3(64), 0, st, a);
+  } else if (ppl == 2) {
+    if (std_prof) hipLaunchKernelGGL((k_maps<T, 2, 6, 8>), dim3(n_items), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_maps<T, 2, 8, 8>), dim3(n_items), dim3(64), 0, st, a);
+  } else if (ppl == 4) {
+    if (std_prof) hipLaunchKernelGGL((k_maps<T, 4, 6, 8>), dim3(n_items), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_maps<T, 4, 8, 8>), dim3(n_items), dim3(64), 0, st, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const FinalizeArgs& a, int n_variants, hipStream_t st) {
   if (a.n_jobs <= 0 || n_variants <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3((a.n_jobs + 63) / 64, n_variants), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(k_finalize, dim3(a.n_jobs, n_variants), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -743,6 +859,8 @@ hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const 
 
 template hipError_t launch_prep_tables<float>(const PrepArgs&, int, int, hipStream_t);
 template hipError_t launch_prep_tables<double>(const PrepArgs&, int, int, hipStream_t);
+template hipError_t launch_maps<float>(const MapArgs&, int, int, int, int, hipStream_t);
+template hipError_t launch_maps<double>(const MapArgs&, int, int, int, int, hipStream_t);
 template hipError_t launch_fused<float>(const FusedArgs<float>&, const float*, int, int, int, bool, int, int,
                                         hipStream_t);
 template hipError_t launch_fused<double>(const FusedArgs<double>&, const double*, int, int, int, bool, int, int,

@@ -4,8 +4,10 @@
 //   1. component tables of every source at the current iterate (variant 0), and of each
 //      stepped source at theta +/- h e_k for the 27 parameters (variants 1..54)
 //   2. the fused pixel kernel and finalisation for those 55 variants: L_s and gradients
-//   3. k_trsolve, one wavefront per source: the Hessian by central differences of the
-//      gradient (symmetrised), convergence tests, eigen-decomposition of -H by cyclic
+//   3. k_trsolve, one wavefront per source: the Hessian -- its pixel part by central
+//      differences of the pixel gradient (symmetrised), its KL part analytically, since the
+//      tight colour-prior mixture makes the KL's higher derivatives far too large for
+//      differencing -- convergence tests, eigen-decomposition of -H by cyclic
 //      Jacobi in LDS (FP64), the trust-region subproblem (boundary multiplier by
 //      bisection on |p(lambda)| = radius, hard case along the lowest eigenvector), and
 //      the trial point
@@ -31,6 +33,106 @@ namespace celmi {
 constexpr int kN = kParamN;   // 27
 constexpr int kLd = kN + 1;   // padded LDS row
 
+
+__device__ __forceinline__ double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+// Hessian of KL_s in the unconstrained coordinates (the same KL as the objective: the type
+// KL, the normal KL of log r, the colour bound -log sum_j w_j exp(-D_j), and minus the log
+// prior densities of the radius, profile and axis point masses), added into B (27 x kLd).
+// KL = KL_a(eta) + KL_radius + KL_profile + KL_axis + (1 - a) K_0 + a K_1.
+__device__ void kl_hessian_add(const DPrior& pr, const double* th, double B[kN][kLd]) {
+  const double eta = th[2], a = sigm(eta);
+  const double aa = a * (1.0 - a);
+  double K[2], dK[2][kN];
+  for (int i = 0; i < 2; ++i) {
+    for (int k = 0; k < kN; ++k) dK[i][k] = 0.0;
+    const double rm = th[3 + i], lrv = th[5 + i], rv = exp(lrv);
+    const double R1 = pr.r[i][0], R2 = pr.r[i][1];
+    const double q = i == 0 ? 1.0 - a : a;
+    K[i] = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
+    dK[i][3 + i] = (rm - R1) / R2;
+    dK[i][5 + i] = -0.5 + rv / (2.0 * R2);
+    B[3 + i][3 + i] += q / R2;
+    B[5 + i][5 + i] += q * rv / (2.0 * R2);
+    // colour bound
+    double cm[4], cv[4], lcv = 0;
+    for (int k = 0; k < 4; ++k) {
+      cm[k] = th[7 + 4 * i + k];
+      cv[k] = exp(th[15 + 4 * i + k]);
+      lcv += th[15 + 4 * i + k];
+    }
+    double D[CEL_N_COLOUR_COMPONENTS], mx = -1e300;
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+      double tr = 0, maha = 0;
+      for (int k = 0; k < 4; ++k) {
+        tr += pr.c_prec[i][j][k][k] * cv[k];
+        double row = 0;
+        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
+        maha += (pr.c_mean[i][j][k] - cm[k]) * row;
+      }
+      D[j] = 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - lcv);
+      mx = fmax(mx, pr.c_logw[i][j] - D[j]);
+    }
+    double z = 0;
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - D[j] - mx);
+    K[i] += -(mx + log(z));
+    // grad F = sum xi dD;  hess F = sum xi (d2D - dD dD^T) + gradF gradF^T  (8 variables)
+    double gF[8] = {0, 0, 0, 0, 0, 0, 0, 0}, hF[8][8];
+    for (int u = 0; u < 8; ++u)
+      for (int w = 0; w < 8; ++w) hF[u][w] = 0.0;
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+      const double xi = exp(pr.c_logw[i][j] - D[j] - mx) / z;
+      if (xi == 0.0) continue;
+      double dD[8];
+      for (int k = 0; k < 4; ++k) {
+        double row = 0;
+        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
+        dD[k] = row;
+        dD[4 + k] = 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
+      }
+      for (int u = 0; u < 8; ++u) {
+        gF[u] += xi * dD[u];
+        for (int w = 0; w < 8; ++w) hF[u][w] -= xi * dD[u] * dD[w];
+      }
+      for (int k = 0; k < 4; ++k) {
+        for (int l = 0; l < 4; ++l) hF[k][l] += xi * pr.c_prec[i][j][k][l];
+        hF[4 + k][4 + k] += xi * 0.5 * pr.c_prec[i][j][k][k] * cv[k];
+      }
+    }
+    for (int u = 0; u < 8; ++u)
+      for (int w = 0; w < 8; ++w) hF[u][w] += gF[u] * gF[w];
+    int idx[8];
+    for (int k = 0; k < 4; ++k) {
+      idx[k] = 7 + 4 * i + k;
+      idx[4 + k] = 15 + 4 * i + k;
+    }
+    for (int u = 0; u < 8; ++u) {
+      dK[i][idx[u]] += gF[u];
+      for (int w = 0; w < 8; ++w) B[idx[u]][idx[w]] += q * hF[u][w];
+    }
+  }
+  // type weight: dKL/deta = a(1-a) [eta - logit A + K1 - K0]
+  const double t = eta - pr.logit_a + K[1] - K[0];
+  B[2][2] += aa * (1.0 - 2.0 * a) * t + aa;
+  for (int k = 0; k < kN; ++k) {
+    const double c = aa * (dK[1][k] - dK[0][k]);
+    if (c != 0.0 && k != 2) {
+      B[2][k] += c;
+      B[k][2] += c;
+    }
+  }
+  // point masses
+  B[24][24] += 1.0 / pr.radius[1];
+  {
+    const double p = sigm(th[25]);
+    B[25][25] += (pr.profile[0] + pr.profile[1] - 2.0) * p * (1.0 - p);
+  }
+  {
+    const double p = sigm(th[26]);
+    B[26][26] += (pr.axis[0] + pr.axis[1] - 2.0) * p * (1.0 - p);
+  }
+}
+
 struct TrArgs {
   const int32_t* job_src;     // sources of this launch
   int32_t n_jobs;
@@ -48,6 +150,7 @@ struct TrArgs {
   double* pred;               // out: predicted gain
   double* pnorm;              // out: |p|
   int32_t* status;            // out: CONVERGED / NONFINITE for sources not tried
+  const DPrior* prior;
 };
 
 __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
@@ -82,6 +185,14 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
       B[i][k] = v;
       B[k][i] = v;
     }
+  }
+  __syncthreads();
+  // B = -H = -(H_pixels - H_KL): the pixel part by central differences (above), the KL part
+  // analytically
+  if (lane == 0) {
+    double th[kN];
+    for (int k = 0; k < kN; ++k) th[k] = a.theta[(int64_t)s * kThetaN + k];
+    kl_hessian_add(*a.prior, th, B);
   }
   __syncthreads();
   // finiteness and the gradient test
@@ -414,6 +525,7 @@ static hipError_t enqueue_newton_class(cel_plan* p, double* theta, double* radiu
   ta.pred = p->d_pred;
   ta.pnorm = p->d_step_norm;
   ta.status = status;
+  ta.prior = p->d_prior;
   hipLaunchKernelGGL(k_trsolve, dim3(nsrc), dim3(64), 0, sm, ta);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // objective at the trial points

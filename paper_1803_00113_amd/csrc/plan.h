@@ -21,7 +21,7 @@ struct cel_plan {
   // host copies
   std::vector<cel_image> images_h;
   std::vector<celmi::DPatch> patches_h;
-  std::vector<int32_t> patch_ptr_h, nbr_idx_h, order_h;
+  std::vector<int32_t> patch_ptr_h, nbr_idx_h, order_h, map_order_h;
   std::vector<celmi::DTask> tasks_h;
   std::vector<std::vector<int>> adj;
   std::vector<int> colour;
@@ -37,6 +37,7 @@ struct cel_plan {
   int32_t* d_nbr = nullptr;
   celmi::DTask* d_tasks = nullptr;
   int32_t* d_order = nullptr;
+  int32_t* d_map_order = nullptr;
   int32_t* d_patch_ptr = nullptr;
   int32_t* d_npsf = nullptr;
   celmi::DPrior* d_prior = nullptr;
@@ -45,6 +46,8 @@ struct cel_plan {
   double* d_htau_d = nullptr;
   float2* d_xs = nullptr;
   double2* d_xs64 = nullptr;    // only with float64 pixel / Hessian options
+  float2* d_maps = nullptr;     // (E_s, V_s) of each patch's source at the base parameters
+  double2* d_maps64 = nullptr;
   double* d_pixconst = nullptr;
   double* d_total = nullptr;
   std::vector<int32_t*> d_class_patches, d_class_tasks, d_class_src;
@@ -81,9 +84,9 @@ struct cel_plan {
   std::vector<Graph> graphs;
   bool marking = false;
   std::vector<void*> allocs;
-  // measurement: events per recorded evaluation (start, after tables, after pixels, end)
+  // measurement: events per recorded evaluation (start, tables, maps, pixels, end)
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::array<hipEvent_t, 4>> ev_rec;
+  std::vector<std::array<hipEvent_t, 5>> ev_rec;
 };
 
 namespace celmi {
@@ -93,7 +96,7 @@ cel_status ensure_variants(cel_plan* p, int nv, bool fp64);
 hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv, bool grad, int cls,
                     const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64);
 hipError_t plain_eval(cel_plan* p, const double* theta, hipStream_t sm, bool fp64);
-// record a phase boundary event (k = 0..3) of the current evaluation when timing is on
+// record a phase boundary event (k = 0..4) of the current evaluation when timing is on
 void phase_mark(cel_plan* p, int k, hipStream_t sm);
 cel_status ensure_newton(cel_plan* p);
 // global ELBO at theta into p->d_total (tables, ELBO-only pixel pass, finalisation, total)

@@ -46,7 +46,9 @@ def check_step(m, theta0, s, th_gpu, r_gpu, st_gpu, loc_gpu, fp64):
     th[s] = th_gpu
     Lg = E.elbo(m, th, sources=[s], with_total=False)[1][s].item()
     gain = abs(o_loc - L0)
-    tol_gain, tol_el, tol_r = (1e-6, 1e-3, 1e-3) if fp64 else (1e-3, 3e-2, 3e-2)
+    # FD Hessian (h = 1e-3, float64 gradients): truncation ~h^2 -> 2e-5 of the gain;
+    # float32 gradients (h = 1e-2): rounding noise / h + h^2 -> 1e-2 of the gain
+    tol_gain, tol_el, tol_r = (2e-5, 1e-3, 1e-3) if fp64 else (1e-2, 5e-2, 5e-2)
     step = np.abs(o_th - theta0[s]).max()
     say(f"  s={s} status {st_gpu}/{o_st} |dtheta|max {np.abs(th_gpu - o_th).max():.2e} (step {step:.2e}) "
         f"L_oracle(gpu point) - L_oracle(oracle point) {Lg - o_loc:.3e} (gain {gain:.3e}) radius {r_gpu}/{o_r}")
