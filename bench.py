@@ -57,6 +57,24 @@ def covering_pairs(prob):
     return int(total)
 
 
+def counted_traffic():
+    """HBM bytes per k_fused launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    profile, or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    prof = os.path.join(ROOT, "profiles", "k_fused_batched_1000src_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_1803_00113_amd", "csrc", "kernels.hip")
+    try:
+        text = open(prof).read()
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch=(\d+) kernels_hip_sha256_prefix=([0-9a-f]+)", text)
+    if not m or m.group(2) != h:
+        return None
+    return int(m.group(1))
+
+
 def cpu_baseline(prob, seconds):
     """The float64 reference timed on the host's cores on the first sources of the same
     workload until `seconds` have elapsed (local objective + gradient of each source)."""
@@ -137,7 +155,7 @@ def main():
     achieved = flops / (kernel_ms * 1e-3) / 1e12
     bytes_fused = units * BYTES_UNIT + pairs * BYTES_PAIR
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
+                    frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=counted_traffic(),
                     kernel="k_fused<float, 2 px/lane, grad>", kernel_ms=round(kernel_ms, 4),
                     algorithmic_flop_per_launch=flops, covering_pairs=pairs,
                     algorithmic_bytes_per_launch=bytes_fused,

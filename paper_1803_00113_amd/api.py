@@ -125,11 +125,18 @@ def host_tables(prob):
 class Plan:
     """A prepared problem (cel_prepare).  Pixels are read once, during construction."""
 
-    def __init__(self, ctx: Context, prob, stream=None):
+    def __init__(self, ctx: Context, prob, stream=None, pixels_device=None):
+        """pixels_device: optional float32 cuda tensor holding the packed pixels (else
+        prob.pixels is copied to the device)."""
         self.ctx = ctx
         dev = ctx.device
         images, knots, patches, prior, profiles = host_tables(prob)
-        pixels = torch.as_tensor(np.ascontiguousarray(prob.pixels, dtype=np.float32)).to(dev)
+        if pixels_device is not None:
+            if not (pixels_device.is_cuda and pixels_device.dtype == torch.float32 and pixels_device.is_contiguous()):
+                raise ValueError("pixels_device must be a contiguous cuda float32 tensor")
+            pixels = pixels_device
+        else:
+            pixels = torch.as_tensor(np.ascontiguousarray(prob.pixels, dtype=np.float32)).to(dev)
         cp = F.CelProblem()
         cp.n_sources = int(prob.n_sources)
         cp.n_images = int(len(prob.img_band))

@@ -57,10 +57,11 @@ __device__ __forceinline__ void load_theta(const double* theta, const double* th
                                            double h, double* th) {
   const double* src = (v == kVariants - 1 && theta_trial) ? theta_trial + (int64_t)s * kThetaN
                                                           : theta + (int64_t)s * kThetaN;
+  // the perturbed coordinate is selected arithmetically so that th stays in registers
+  const int kp = (v >= 1 && v <= kParamN) ? v - 1 : -1;
+  const int km = (v > kParamN && v <= 2 * kParamN) ? v - 1 - kParamN : -1;
 #pragma unroll
-  for (int k = 0; k < kThetaN; ++k) th[k] = src[k];
-  if (v >= 1 && v <= kParamN) th[v - 1] += h;
-  else if (v > kParamN && v <= 2 * kParamN) th[v - 1 - kParamN] -= h;
+  for (int k = 0; k < kThetaN; ++k) th[k] = src[k] + (k == kp ? h : 0.0) - (k == km ? h : 0.0);
 }
 
 // Galaxy covariance Sigma_s = R^T diag(r^2, axis^2 r^2) R, R = [[c,-s],[s,c]] (Section 2.1.2)
@@ -507,7 +508,7 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
 // kleq; Supplement A with the readings: flux KL is the normal KL of log r with variances;
 // colour KL is the bound of Section 4.2.3 at its optimal weights; point-mass terms are
 // minus the log prior density; direction and angle terms are constants and dropped).
-__device__ double kl_source(const DPrior& pr, const double* th, double* g) {
+__device__ double kl_source(const DPrior& pr, const double* th, double* g, double gs) {
   const double eta = th[2];
   const double a = sigmoid(eta);
   const double log_a = -softplus(-eta), log_1ma = -softplus(eta);
@@ -515,14 +516,16 @@ __device__ double kl_source(const DPrior& pr, const double* th, double* g) {
   double dk_da = eta - pr.logit_a;          // d KL_a / d a
   const double q[2] = {1.0 - a, a};
   double part[2];
+#pragma unroll
   for (int i = 0; i < 2; ++i) {
     const double rm = th[3 + i], lrv = th[5 + i], rv = exp(lrv);
     const double R1 = pr.r[i][0], R2 = pr.r[i][1];
     double kr = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
-    g[3 + i] -= q[i] * (rm - R1) / R2;
-    g[5 + i] -= q[i] * (-0.5 + rv / (2.0 * R2));
+    g[3 + i] -= gs * q[i] * (rm - R1) / R2;
+    g[5 + i] -= gs * q[i] * (-0.5 + rv / (2.0 * R2));
     // colour bound: -log sum_j w_j exp(-D_j); gradient sum_j xi_j dD_j
     double cm[4], cv[4], lcv[4];
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
       cm[k] = th[7 + 4 * i + k];
       lcv[k] = th[15 + 4 * i + k];
@@ -530,11 +533,14 @@ __device__ double kl_source(const DPrior& pr, const double* th, double* g) {
     }
     double D[CEL_N_COLOUR_COMPONENTS], mx = -1e300;
     double sum_lcv = lcv[0] + lcv[1] + lcv[2] + lcv[3];
+#pragma unroll
     for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
       double tr = 0, maha = 0;
+#pragma unroll
       for (int k = 0; k < 4; ++k) {
         tr += pr.c_prec[i][j][k][k] * cv[k];
         double row = 0;
+#pragma unroll
         for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
         maha += (pr.c_mean[i][j][k] - cm[k]) * row;
       }
@@ -543,37 +549,40 @@ __device__ double kl_source(const DPrior& pr, const double* th, double* g) {
       if (e > mx) mx = e;
     }
     double z = 0;
+#pragma unroll
     for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - D[j] - mx);
     const double kc = -(mx + log(z));
+#pragma unroll
     for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
       const double xi = exp(pr.c_logw[i][j] - D[j] - mx) / z;
-      if (xi == 0.0) continue;
+#pragma unroll
       for (int k = 0; k < 4; ++k) {
         double row = 0;
+#pragma unroll
         for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
-        g[7 + 4 * i + k] -= q[i] * xi * row;
-        g[15 + 4 * i + k] -= q[i] * xi * 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
+        g[7 + 4 * i + k] -= gs * q[i] * xi * row;
+        g[15 + 4 * i + k] -= gs * q[i] * xi * 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
       }
     }
     part[i] = kr + kc;
     kl += q[i] * part[i];
   }
   dk_da += part[1] - part[0];
-  g[2] -= dk_da * a * (1.0 - a);
+  g[2] -= gs * (dk_da * a * (1.0 - a));
   // radius: point mass vs log-normal
   const double lr = th[24], E1 = pr.radius[0], E2 = pr.radius[1];
   kl += lr + 0.5 * log(2.0 * M_PI * E2) + (lr - E1) * (lr - E1) / (2.0 * E2);
-  g[24] -= 1.0 + (lr - E1) / E2;
+  g[24] -= gs * (1.0 + (lr - E1) / E2);
   // profile and axis: point mass vs Beta
   {
     const double e = th[25], p = sigmoid(e), lp = -softplus(-e), l1p = -softplus(e);
     kl += -(pr.profile[0] - 1.0) * lp - (pr.profile[1] - 1.0) * l1p + pr.lbeta_profile;
-    g[25] -= -(pr.profile[0] - 1.0) * (1.0 - p) + (pr.profile[1] - 1.0) * p;
+    g[25] -= gs * (-(pr.profile[0] - 1.0) * (1.0 - p) + (pr.profile[1] - 1.0) * p);
   }
   {
     const double e = th[26], p = sigmoid(e), lp = -softplus(-e), l1p = -softplus(e);
     kl += -(pr.axis[0] - 1.0) * lp - (pr.axis[1] - 1.0) * l1p + pr.lbeta_axis;
-    g[26] -= -(pr.axis[0] - 1.0) * (1.0 - p) + (pr.axis[1] - 1.0) * p;
+    g[26] -= gs * (-(pr.axis[0] - 1.0) * (1.0 - p) + (pr.axis[1] - 1.0) * p);
   }
   return kl;
 }
@@ -590,6 +599,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   double th[kThetaN];
   load_theta(a.theta, a.theta_trial, s, v, a.fd_step, th);
   double g[kThetaN];
+  #pragma unroll
   for (int k = 0; k < kThetaN; ++k) g[k] = 0.0;
   const double aa = sigmoid(th[2]);
   const double w0 = 1.0 - aa, w1 = aa;
@@ -601,17 +611,21 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   for (int p = a.patch_ptr[s] + lane; p < a.patch_ptr[s + 1]; p += 64) {
     const DPatch P = a.patches[p];
     double sm[13];
+    #pragma unroll
     for (int q = 0; q < 13; ++q) sm[q] = 0.0;
     for (int t = P.task_begin; t < P.task_end; ++t)
+      #pragma unroll
       for (int q = 0; q < 13; ++q) sm[q] += slots[(int64_t)t * kSlots + q];
     local += sm[S_T] + a.pix_const[2 * p];
     own += sm[S_T_OWN] + a.pix_const[2 * p + 1];
     if (!a.want_grad) continue;
     const cel_image& im = a.images[P.img];
     double L[2], M[2], var[2];
+    #pragma unroll
     for (int i = 0; i < 2; ++i) {
       double m = th[3 + i];
       var[i] = exp(th[5 + i]);
+      #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const double W = c_W[im.band][c];
         m += W * th[7 + 4 * i + c];
@@ -630,11 +644,13 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
                              w1 * L[0] * L[1] * B01);
     g[2] += ga * aa * (1.0 - aa);
     const double gL[2] = {gL0, gL1}, gM[2] = {gM0, gM1};
+    #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const double gm = gL[i] * L[i] + 2.0 * gM[i] * M[i];
       const double gv = 0.5 * gL[i] * L[i] + 2.0 * gM[i] * M[i];
       g[3 + i] += gm;
       g[5 + i] += gv * exp(th[5 + i]);
+      #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const double W = c_W[im.band][c];
         g[7 + 4 * i + c] += gm * W;
@@ -659,7 +675,9 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   local = wave_sum<double>(local);
   own = wave_sum<double>(own);
   if (a.want_grad) {
+    #pragma unroll
     for (int k = 0; k < kParamN; ++k) g[k] = wave_sum<double>(g[k]);
+    #pragma unroll
     for (int k = 0; k < 3; ++k) gS[k] = wave_sum<double>(gS[k]);
     gpi = wave_sum<double>(gpi);
   }
@@ -667,9 +685,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   // the central-difference variants (1..54) carry the pixel part of the gradient only: the
   // KL part of the Hessian is taken analytically by the trust-region kernel
   const bool fd_variant = v >= 1 && v <= 2 * kParamN;
-  double gkl[kThetaN];
-  for (int k = 0; k < kThetaN; ++k) gkl[k] = 0.0;
-  double kl = kl_source(*a.prior, th, fd_variant ? gkl : g);   // subtracts the KL gradient
+  double kl = kl_source(*a.prior, th, g, fd_variant ? 0.0 : 1.0);   // subtracts the KL gradient
   local -= kl;
   own -= kl;
   if (a.want_grad) {
@@ -688,7 +704,9 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   if (a.local) a.local[out] = local;
   if (a.own) a.own[out] = own;
   if (a.want_grad && a.grad) {
+    #pragma unroll
     for (int k = 0; k < kParamN; ++k) a.grad[out * kThetaN + k] = g[k];
+    #pragma unroll
     for (int k = kParamN; k < kThetaN; ++k) a.grad[out * kThetaN + k] = 0.0;
   }
 }

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
   }
   __shared__ double B[kN][kLd];
   __shared__ double V[kN][kLd];
-  __shared__ double g[kN], lam[kN], y[kN];
+  __shared__ double g[kN], lam[kN], y[kN], gt[kN];
   __shared__ int ok_flag;
   __shared__ double red[64];
   const int lane = threadIdx.x;
@@ -306,9 +306,9 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
     y[lane] = acc;
   }
   __syncthreads();
+  if (lane < kN) gt[lane] = y[lane];
+  __syncthreads();
   if (lane == 0) {
-    double gt[kN];
-    for (int i = 0; i < kN; ++i) gt[i] = y[i];
     double gnorm = 0;
     for (int i = 0; i < kN; ++i) gnorm += g[i] * g[i];
     gnorm = sqrt(gnorm);

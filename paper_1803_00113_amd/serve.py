@@ -1,0 +1,242 @@
+"""Continuous-batching request loop over the celmi library (sky-region cataloging requests).
+
+Each request is a region: its own sources, patches, pixels and initial parameters.  The
+loop keeps a set of resident requests whose variational state (theta, trust radii) stays
+in device memory.  At every device step:
+  1. requests that have arrived are admitted, oldest first, while the estimated device
+     footprint of the resident set stays within the HBM budget (a request that does not
+     fit waits; it is never failed for lack of memory);
+  2. if the resident set changed, the resident requests are merged into one plan (their
+     pixel arrays are concatenated on the device; sources of different requests never
+     overlap, so the merged colouring restricted to a request equals its own);
+  3. one trust-radius Newton round runs, in one batched cel_newton_step, on every resident
+     request's current colour class (a request cycles through its classes);
+  4. requests that have completed their rounds leave: their parameters and objective are
+     copied to the host and the latency (arrival to result on the host) is recorded.
+Work of different requests shares launches; a request's results do not depend on which
+others are resident (every per-source reduction has a fixed order).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import api
+
+TABLE_BYTES = 1536           # per patch and variant, float32 component table (upper bound)
+VARIANTS = 56                # Newton: base, 54 central differences, trial
+
+
+def footprint_bytes(prob):
+    """Estimated device bytes a request needs inside a merged plan (pixels, per-pixel
+    arrays, Newton tables and slots, per-source scratch)."""
+    units = int(np.sum(prob.patch_w.astype(np.int64) * prob.patch_h))
+    P = int(len(prob.patch_src))
+    S = int(prob.n_sources)
+    items = int(np.sum((prob.patch_w.astype(np.int64) * prob.patch_h + 511) // 512))
+    return (units * (4 + 8 + 8) + P * VARIANTS * TABLE_BYTES + items * VARIANTS * 16 * 8
+            + S * VARIANTS * (8 + 8 + 32 * 8) + S * 32 * 8 * 3 + P * 64)
+
+
+def merge(probs):
+    """One problem holding the given requests side by side (ids offset; images, patches,
+    sky knots and pixels concatenated).  All requests must share the prior and profiles."""
+    base = probs[0]
+    S_off, N_off, K_off, X_off = 0, 0, 0, 0
+    cols = {k: [] for k in ("img_band", "img_H", "img_W", "img_npsf", "img_psf", "img_A", "img_b", "img_iota",
+                            "img_sky_qh", "img_sky_qw", "img_sky_off", "sky_knots", "patch_src", "patch_img",
+                            "patch_x0", "patch_y0", "patch_w", "patch_h", "patch_off", "theta0")}
+    for p in probs:
+        for k in ("img_band", "img_H", "img_W", "img_npsf", "img_psf", "img_A", "img_b", "img_iota", "img_sky_qh",
+                  "img_sky_qw", "patch_x0", "patch_y0", "patch_w", "patch_h", "theta0", "sky_knots"):
+            cols[k].append(getattr(p, k))
+        cols["img_sky_off"].append(p.img_sky_off + K_off)
+        cols["patch_src"].append(p.patch_src + S_off)
+        cols["patch_img"].append(p.patch_img + N_off)
+        cols["patch_off"].append(p.patch_off + X_off)
+        S_off += p.n_sources
+        N_off += len(p.img_band)
+        K_off += len(p.sky_knots)
+        X_off += len(p.pixels)
+    out = _Merged()
+    for k, v in cols.items():
+        setattr(out, k, np.concatenate(v) if v else v)
+    out.n_sources = S_off
+    for k in ("prior_a", "prior_r", "prior_cw", "prior_cmean", "prior_ccov", "prior_radius", "prior_profile",
+              "prior_axis", "exp_alpha", "exp_tau", "dev_alpha", "dev_tau"):
+        setattr(out, k, getattr(base, k))
+    out.pixels = np.zeros(0, np.float32)   # pixels are passed on the device
+    return out
+
+
+class _Merged:
+    pass
+
+
+@dataclass
+class Request:
+    rid: int
+    prob: object
+    arrival: float                     # seconds since the loop started
+    rounds: int = 10
+    # device state
+    theta: torch.Tensor = None
+    radius: torch.Tensor = None
+    pixels: torch.Tensor = None
+    colours: np.ndarray = None
+    n_colours: int = 1
+    done_rounds: int = 0
+    admitted: float = None
+    finished: float = None
+    result_theta: np.ndarray = None
+    result_local: np.ndarray = None
+    result_status: np.ndarray = None
+    footprint: int = 0
+    units: int = 0
+    offset: int = 0
+
+
+@dataclass
+class Stats:
+    latencies: list = field(default_factory=list)
+    steps: int = 0
+    deferred_admissions: int = 0
+    rebuilds: int = 0
+    units_evaluated: int = 0
+    wall: float = 0.0
+
+    def summary(self):
+        lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                    mean_ms=float(lat.mean() * 1e3), completed=len(self.latencies),
+                    req_per_s=len(self.latencies) / max(self.wall, 1e-9), steps=self.steps,
+                    deferred_admissions=self.deferred_admissions, rebuilds=self.rebuilds,
+                    units_per_s=self.units_evaluated / max(self.wall, 1e-9), wall_s=self.wall)
+
+
+class Server:
+    """Continuous-batching loop on one device."""
+
+    def __init__(self, device=0, hbm_budget_bytes=16 << 30, rounds=10, **ctx_opts):
+        self.ctx = api.Context(device, **ctx_opts)
+        self.dev = self.ctx.device
+        self.budget = int(hbm_budget_bytes)
+        self.rounds = int(rounds)
+        self.resident: list[Request] = []
+        self.plan = None
+        self.dirty = False
+        self.stats = Stats()
+
+    # -- admission and merging ---------------------------------------------------------------
+    def _attach(self, r: Request, now):
+        p = r.prob
+        r.theta = torch.as_tensor(p.theta0, dtype=torch.float64, device=self.dev).contiguous()
+        r.radius = torch.full((p.n_sources,), 1.0, dtype=torch.float64, device=self.dev)
+        r.pixels = torch.as_tensor(np.ascontiguousarray(p.pixels, np.float32)).to(self.dev)
+        r.admitted = now
+        r.rounds = self.rounds
+        r.units = int(np.sum(p.patch_w.astype(np.int64) * p.patch_h))
+
+    def _rebuild(self):
+        self.plan = None
+        if not self.resident:
+            return
+        merged = merge([r.prob for r in self.resident])
+        pixels = torch.cat([r.pixels for r in self.resident]) if self.resident else None
+        self.plan = api.Plan(self.ctx, merged, pixels_device=pixels)
+        off = 0
+        for r in self.resident:
+            r.colours = self.plan.colours[off:off + r.prob.n_sources]
+            r.n_colours = int(r.colours.max()) + 1 if r.prob.n_sources else 1
+            r.offset = off
+            off += r.prob.n_sources
+        self.stats.rebuilds += 1
+
+    def step(self, now, pending):
+        """Admit what fits from `pending` (arrived requests, oldest first), run one Newton
+        round for every resident request, retire finished ones.  Returns retired requests."""
+        changed = False
+        used = sum(r.footprint for r in self.resident)
+        while pending:
+            r = pending[0]
+            r.footprint = r.footprint or footprint_bytes(r.prob)
+            if used + r.footprint > self.budget and self.resident:
+                self.stats.deferred_admissions += 1
+                break
+            pending.pop(0)
+            self._attach(r, now)
+            self.resident.append(r)
+            used += r.footprint
+            changed = True
+        if changed or self.dirty:
+            self._rebuild()
+            self.dirty = False
+        if not self.resident:
+            return []
+        S = self.plan.S
+        theta = torch.cat([r.theta for r in self.resident])
+        radius = torch.cat([r.radius for r in self.resident])
+        mask = np.zeros(S, bool)
+        for r in self.resident:
+            c = r.done_rounds % r.n_colours
+            mask[r.offset:r.offset + r.prob.n_sources] = r.colours == c
+        status, local = api.newton_step(self.plan, theta, radius, mask)
+        self.stats.steps += 1
+        self.stats.units_evaluated += sum(r.units for r in self.resident)
+        finished, keep = [], []
+        for r in self.resident:
+            sl = slice(r.offset, r.offset + r.prob.n_sources)
+            r.theta = theta[sl].clone()
+            r.radius = radius[sl].clone()
+            r.done_rounds += 1
+            if r.done_rounds >= r.rounds:
+                finished.append(r)
+            else:
+                keep.append(r)
+        if finished:
+            tot_local = local.cpu().numpy()
+            st = status.cpu().numpy()
+            t_done = time.perf_counter()
+            for r in finished:
+                sl = slice(r.offset, r.offset + r.prob.n_sources)
+                r.result_theta = r.theta.cpu().numpy()
+                r.result_local = tot_local[sl]
+                r.result_status = st[sl]
+                r.finished = t_done
+            self.resident = keep
+            self.dirty = True
+        return finished
+
+    def run(self, requests, realtime=True):
+        """Serve `requests` (each with .arrival seconds from start).  Returns the stats
+        summary; results are left on the Request objects."""
+        order = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        t0 = time.perf_counter()
+        pending, i, done = [], 0, 0
+        while done < len(order):
+            now = time.perf_counter() - t0 if realtime else float("inf")
+            while i < len(order) and order[i].arrival <= now:
+                pending.append(order[i])
+                i += 1
+            if not pending and not self.resident:
+                if realtime and i < len(order):
+                    time.sleep(max(0.0, order[i].arrival - now))
+                continue
+            fin = self.step(now, pending)
+            for r in fin:
+                self.stats.latencies.append((r.finished - t0) - r.arrival if realtime else r.finished - t0)
+                done += 1
+        torch.cuda.synchronize(self.dev)
+        self.stats.wall = time.perf_counter() - t0
+        return self.stats.summary()
+
+
+def solo(prob, rounds=10, device=0, **ctx_opts):
+    """The same rounds for one request alone (reference for the mixed runs)."""
+    srv = Server(device, rounds=rounds, **ctx_opts)
+    r = Request(0, prob, 0.0)
+    srv.run([r], realtime=False)
+    return r
