@@ -75,6 +75,85 @@ def counted_traffic():
     return int(m.group(1))
 
 
+def sweep_leg(log, plain_sweeps=1):
+    """Field workload: 3 block-coordinate Newton sweeps batched (one captured graph per
+    colour class) and, for comparison, the plain form (host loop, one source per launch)
+    for `plain_sweeps` sweep(s)."""
+    import torch
+    from paper_1803_00113_amd import api
+    from synth import gen
+    prob = gen.config4()
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    th = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    tot0 = api.elbo_eval(plan, th)[0].item()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, st, rep = api.sweep(plan, th, n_sweeps=3, max_newton_iters=50, use_graph=True)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    log(f"field sweep batched: {t_batched:.3f} s, ELBO {tot0:.1f} -> {rep['elbo']:.1f}, "
+        f"{rep['n_newton_steps']} batched steps, {plan.n_colours} colours")
+    out = dict(workload=prob.name, n_sources=prob.n_sources, active_pixels=plan.n_units, n_colours=plan.n_colours,
+               elbo_start=tot0, batched=dict(sweeps=3, seconds=t_batched, elbo=rep["elbo"],
+                                            newton_steps=rep["n_newton_steps"]))
+    # plain: every source on its own, in colour order, one Newton step per call
+    th2 = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    rad = torch.ones(prob.n_sources, dtype=torch.float64, device="cuda")
+    order = np.argsort(plan.colours, kind="stable")
+    t0 = time.perf_counter()
+    calls = 0
+    for _ in range(plain_sweeps):
+        rad.fill_(1.0)
+        for s in order:
+            m = np.zeros(prob.n_sources, bool)
+            m[s] = True
+            for _it in range(50):
+                stt, _ = api.newton_step(plan, th2, rad, m)
+                calls += 1
+                if int(stt[s].item()) in (3, 4):
+                    break
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    # batched run restricted to the same number of sweeps, for a like-for-like ratio
+    th3 = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, rep1 = api.sweep(plan, th3, n_sweeps=plain_sweeps, max_newton_iters=50, use_graph=True)
+    torch.cuda.synchronize()
+    t_b1 = time.perf_counter() - t0
+    e_plain = api.elbo_eval(plan, th2)[0].item()
+    log(f"field sweep plain ({plain_sweeps} sweep): {t_plain:.2f} s in {calls} calls, ELBO {e_plain:.1f}; "
+        f"batched same sweeps {t_b1:.3f} s, ELBO {rep1['elbo']:.1f}")
+    out["plain"] = dict(sweeps=plain_sweeps, seconds=t_plain, calls=calls, elbo=e_plain)
+    out["batched_same_sweeps"] = dict(sweeps=plain_sweeps, seconds=t_b1, elbo=rep1["elbo"])
+    out["batched_vs_plain"] = t_plain / t_b1
+    return out
+
+
+def serve_leg(log, rates=(20.0, 50.0), n_requests=40, pool=8):
+    """Region requests of 1-200 sources (patch side 16-96, 5 bands) arriving as a Poisson
+    process; each request takes 10 Newton rounds.  Arrivals cycle through `pool` generated
+    regions."""
+    from paper_1803_00113_amd import serve
+    from synth import gen
+    regions = [gen.config5_request(gen.SEED_BASE + 5 + 100 * i) for i in range(pool)]
+    out = []
+    for rate in rates:
+        rng = np.random.default_rng(int(rate))
+        t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+        reqs = [serve.Request(i, regions[i % pool], float(t[i]), rounds=10) for i in range(n_requests)]
+        srv = serve.Server(0, rounds=10)
+        st = srv.run(reqs)
+        st["rate_req_per_s"] = rate
+        st["requests"] = n_requests
+        st["mean_sources_per_request"] = float(np.mean([r.prob.n_sources for r in reqs]))
+        log(f"serving at {rate} req/s: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
+            f"{st['req_per_s']:.1f} req/s served")
+        out.append(st)
+    return out
+
+
 def cpu_baseline(prob, seconds):
     """The float64 reference timed on the host's cores on the first sources of the same
     workload until `seconds` have elapsed (local objective + gradient of each source)."""
@@ -106,6 +185,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--pixels-per-lane", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -186,6 +267,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 1 GiB read + 1 GiB written")
 
+    sweep = None if args.no_sweep else sweep_leg(log)
+    serving = None if args.no_serve else serve_leg(log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the float64 reference on the host")
@@ -200,6 +284,8 @@ def main():
                    "active_pixels": units, "seed": gen.SEED_BASE + 2},
         "roofline": roofline, "cpu_baseline": cpu,
         "plain": plain, "batched_vs_plain": (value / plain["value"]) if plain else None,
+        "p99_region_latency_ms": serving[0]["p99_ms"] if serving else None,
+        "serving": serving, "sweep": sweep,
     }
     print(json.dumps(line), flush=True)
 
