@@ -131,7 +131,47 @@ def sweep_leg(log, plain_sweeps=1):
     return out
 
 
-def serve_leg(log, rates=(20.0, 50.0), n_requests=40, pool=8):
+def hessian_leg(log, prob, reps=5):
+    """Second-order work on the batched workload: per-source Hessians of every source
+    (exact), and one Newton step of the largest colour class with the exact Hessian and
+    with the difference Hessian (54 extra gradient variants)."""
+    import torch
+    from paper_1803_00113_amd import api
+    out = {}
+    th0 = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    for name, opts in (("exact", {}), ("differences", dict(hessian_fd=1))):
+        ctx = api.Context(0, **opts)
+        plan = api.Plan(ctx, prob)
+        cls = int(np.bincount(plan.colours).argmax())
+        mask = plan.colours == cls
+        res = dict(class_sources=int(mask.sum()))
+        if name == "exact":
+            api.elbo_hessian(plan, th0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                api.elbo_hessian(plan, th0)
+            torch.cuda.synchronize()
+            res["hessian_all_sources_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+        th = th0.clone()
+        r = torch.ones(prob.n_sources, dtype=torch.float64, device="cuda")
+        api.newton_step(plan, th, r, mask)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            th.copy_(th0)
+            r.fill_(1.0)
+            api.newton_step(plan, th, r, mask)
+        torch.cuda.synchronize()
+        res["newton_step_class_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+        log(f"hessian ({name}): {res}")
+        out[name] = res
+    out["newton_exact_vs_differences"] = (out["differences"]["newton_step_class_ms"]
+                                          / out["exact"]["newton_step_class_ms"])
+    return out
+
+
+def serve_leg(log, rates=(20.0, 50.0, 100.0, 200.0), n_requests=40, pool=8):
     """Region requests of 1-200 sources (patch side 16-96, 5 bands) arriving as a Poisson
     process; each request takes 10 Newton rounds.  Arrivals cycle through `pool` generated
     regions."""
@@ -187,6 +227,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-hessian", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -267,6 +308,7 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 1 GiB read + 1 GiB written")
 
+    hess = None if args.no_hessian else hessian_leg(log, prob)
     sweep = None if args.no_sweep else sweep_leg(log)
     serving = None if args.no_serve else serve_leg(log)
 
@@ -285,7 +327,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "plain": plain, "batched_vs_plain": (value / plain["value"]) if plain else None,
         "p99_region_latency_ms": serving[0]["p99_ms"] if serving else None,
-        "serving": serving, "sweep": sweep,
+        "serving": serving, "sweep": sweep, "hessian": hess,
     }
     print(json.dumps(line), flush=True)
 

@@ -124,7 +124,9 @@ typedef struct {
   int32_t pixels_per_lane;       /* 1, 2 or 4; 0 = default                              */
   int32_t chunk_pixels;          /* pixels per work item (multiple of 64); 0 = default  */
   int32_t pixel_fp64;            /* 1: evaluate pixels in float64 instead of float32     */
-  int32_t hessian_fp64;          /* 1: FD Hessian from the float64 pixel path           */
+  int32_t hessian_fp64;          /* 1: Newton steps from the float64 pixel path          */
+  int32_t hessian_fd;            /* 1: pixel Hessian by central differences of the
+                                    gradient (54 variants); 0 (default): analytic       */
   double fd_step;                /* central-difference step of the Hessian; 0 = 1e-2 with
                                     float32 gradients, 1e-3 with float64 ones             */
   double radius0, radius_max, eta, gtol, ftol, radius_min;   /* trust region (0 = default) */
@@ -171,10 +173,19 @@ cel_status cel_elbo_grad(cel_ctx* ctx, const cel_plan* plan, const double* theta
 cel_status cel_elbo_grad_plain(cel_ctx* ctx, const cel_plan* plan, const double* theta, double* elbo_total,
                                double* elbo_local, double* grad, void* stream);
 
+/* Per-source Hessians of L_s in the unconstrained coordinates, every other source fixed
+ * (the dense Newton Hessian of Section 4.3; also what a Laplace approximation needs).
+ * Exact (analytic) in both the pixel and the KL parts.  mask: HOST uint8 [S] or NULL
+ * (all sources).  hess: DEVICE float64 [S][27][27] out (rows of unmasked sources left
+ * untouched); grad: DEVICE float64 [S][32] out or NULL; elbo_local: DEVICE [S] or NULL. */
+cel_status cel_elbo_hessian(cel_ctx* ctx, const cel_plan* plan, const double* theta, const uint8_t* mask,
+                            double* hess, double* grad, double* elbo_local, void* stream);
+
 /* One trust-region Newton step (Section 4.3) on every source with mask[s] != 0 (HOST
  * uint8 [S], NULL = all), all from the same iterate.  Masked sources must be pairwise
- * non-overlapping (checked against the plan: CEL_EINVAL otherwise).  Hessian by central
- * differences of the gradient in the unconstrained coordinates; the subproblem is solved
+ * non-overlapping (checked against the plan: CEL_EINVAL otherwise).  Hessian exact (as
+ * cel_elbo_hessian), or with options.hessian_fd by central differences of the gradient
+ * (pixel part; the KL part is always exact); the subproblem is solved
  * exactly (eigen-decomposition, boundary multiplier by a safeguarded secular-equation
  * iteration, hard case completed along the lowest eigenvector).
  * theta: DEVICE [S*32] in/out; radius: DEVICE float64 [S] in/out (trust radii);

@@ -53,7 +53,7 @@ class CelProblem(C.Structure):
 
 class CelOptions(C.Structure):
     _fields_ = [("pixels_per_lane", C.c_int32), ("chunk_pixels", C.c_int32), ("pixel_fp64", C.c_int32),
-                ("hessian_fp64", C.c_int32), ("fd_step", C.c_double), ("radius0", C.c_double),
+                ("hessian_fp64", C.c_int32), ("hessian_fd", C.c_int32), ("fd_step", C.c_double), ("radius0", C.c_double),
                 ("radius_max", C.c_double), ("eta", C.c_double), ("gtol", C.c_double), ("ftol", C.c_double),
                 ("radius_min", C.c_double), ("timing", C.c_int32)]
 
@@ -84,6 +84,7 @@ _sig = {
     "cel_elbo_eval": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cel_elbo_grad": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cel_elbo_grad_plain": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cel_elbo_hessian": (C.c_int32, [_vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, _vp, _vp, _vp]),
     "cel_newton_step": (C.c_int32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, _vp, _vp]),
     "cel_phase_times": (C.c_int32, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "cel_sweep": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(CelSweepOpts), C.POINTER(CelSweepReport), _vp]),

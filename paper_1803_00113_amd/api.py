@@ -32,7 +32,7 @@ class Context:
     """A library context on one HIP device (cel_create)."""
 
     def __init__(self, device=0, pixels_per_lane=0, chunk_pixels=0, pixel_fp64=False, hessian_fp64=False,
-                 fd_step=0.0, timing=False, **tr):
+                 hessian_fd=False, fd_step=0.0, timing=False, **tr):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the celmi library needs an MI355X (gfx950)")
         o = F.CelOptions()
@@ -40,6 +40,7 @@ class Context:
         o.chunk_pixels = int(chunk_pixels)
         o.pixel_fp64 = int(bool(pixel_fp64))
         o.hessian_fp64 = int(bool(hessian_fp64))
+        o.hessian_fd = int(bool(hessian_fd))
         o.fd_step = float(fd_step)
         o.timing = int(bool(timing))
         for k in ("radius0", "radius_max", "eta", "gtol", "ftol", "radius_min"):
@@ -47,13 +48,15 @@ class Context:
         h = C.c_void_p()
         F.check("cel_create", F.lib.cel_create(C.byref(h), int(device), C.byref(o)))
         self.h = h
+        self._lib = F.lib          # kept for close() during interpreter shutdown
         self.device = torch.device("cuda", int(device))
         self.options = o
 
     def close(self):
-        if getattr(self, "h", None):
-            F.lib.cel_destroy(self.h)
-            self.h = None
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "h", None) and lib is not None:
+            lib.cel_destroy(self.h)
+        self.h = None
 
     def __del__(self):
         self.close()
@@ -154,6 +157,7 @@ class Plan:
             st = stream if stream is not None else _stream(dev)
             F.check("cel_prepare", F.lib.cel_prepare(ctx.h, C.byref(cp), C.byref(h), st))
         self.h = h
+        self._lib = F.lib
         self.S = int(prob.n_sources)
         nu, nc, nw = C.c_int64(), C.c_int32(), C.c_int64()
         col = (C.c_int32 * max(self.S, 1))()
@@ -164,9 +168,10 @@ class Plan:
         self.colours = np.array(col[:self.S], dtype=np.int32)
 
     def close(self):
-        if getattr(self, "h", None):
-            F.lib.cel_plan_free(self.h)
-            self.h = None
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "h", None) and lib is not None:
+            lib.cel_plan_free(self.h)
+        self.h = None
 
     def __del__(self):
         self.close()
@@ -214,6 +219,27 @@ def elbo_grad_plain(plan: Plan, theta):
     F.check("cel_elbo_grad_plain", F.lib.cel_elbo_grad_plain(plan.ctx.h, plan.h, _ptr(th), _ptr(tot), _ptr(loc),
                                                              _ptr(g), _stream(plan.ctx.device)))
     return tot, loc, g
+
+
+def _mask(plan, mask):
+    if mask is None:
+        return None, None
+    mk = np.ascontiguousarray(np.asarray(mask).astype(np.uint8))
+    if mk.shape != (plan.S,):
+        raise ValueError("mask must have one entry per source")
+    return mk, mk.ctypes.data_as(C.POINTER(C.c_uint8))
+
+
+def elbo_hessian(plan: Plan, theta, mask=None):
+    """cel_elbo_hessian: returns (hess [S,27,27], grad [S,32], elbo_local [S]) device tensors
+    (rows of unmasked sources are zero)."""
+    th = plan._theta(theta)
+    h = torch.zeros((plan.S, F.N_PARAM, F.N_PARAM), dtype=torch.float64, device=plan.ctx.device)
+    g, loc = plan._out(plan.S, F.N_THETA), plan._out(plan.S)
+    keep, m = _mask(plan, mask)
+    F.check("cel_elbo_hessian", F.lib.cel_elbo_hessian(plan.ctx.h, plan.h, _ptr(th), m, _ptr(h), _ptr(g), _ptr(loc),
+                                                       _stream(plan.ctx.device)))
+    return h, g, loc
 
 
 def newton_step(plan: Plan, theta, radius, mask=None):

@@ -49,6 +49,7 @@ static cel_options merge_options(const cel_options* in) {
   if (in->chunk_pixels) o.chunk_pixels = in->chunk_pixels;
   o.pixel_fp64 = in->pixel_fp64;
   o.hessian_fp64 = in->hessian_fp64;
+  o.hessian_fd = in->hessian_fd;
   if (in->fd_step > 0) o.fd_step = in->fd_step;
   if (in->radius0 > 0) o.radius0 = in->radius0;
   if (in->radius_max > 0) o.radius_max = in->radius_max;
@@ -274,7 +275,9 @@ cel_status ensure_newton(cel_plan* p) {
   if ((st = track(p, &p->d_theta_trial, S1 * kThetaN)) || (st = track(p, &p->d_pred, S1)) ||
       (st = track(p, &p->d_step_norm, S1)) || (st = track(p, &p->d_trial_active, S1)) ||
       (st = track(p, &p->d_mask, S1)) || (st = track(p, &p->d_counter, 1)) ||
-      (st = track_upload(p, &p->d_npix, npix)) || (st = track_upload(p, &p->d_colour, col)))
+      (st = track_upload(p, &p->d_npix, npix)) || (st = track_upload(p, &p->d_colour, col)) ||
+      (st = track(p, &p->d_hslots, (size_t)std::max<int64_t>(p->n_tasks, 1) * 80)) ||
+      (st = track(p, &p->d_hess, S1 * kParamN * kParamN)))
     return st;
   if (hipMemset(p->d_trial_active, 0, S1) != hipSuccess) return CEL_EHIP;
   if (hipHostMalloc((void**)&p->h_mask, S1, 0) != hipSuccess) return CEL_ENOMEM;
@@ -604,6 +607,8 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   pa.prof = p->d_prof;
   pa.tables = tables;
   pa.n_patches = p->P;
+  pa.trial_variant = p->trial_variant;
+  pa.fd = p->fd_mode;
   phase_mark(p, 0, sm);
   if (prep_base) {   // variant 0 of every source and its moment maps (neighbours read these)
     pa.variant0 = 0;
@@ -669,6 +674,8 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   fz.own = p->v_own + (int64_t)v0 * p->S;
   fz.grad = p->v_grad + (int64_t)v0 * p->S * kThetaN;
   fz.out_variant_stride = p->S;
+  fz.trial_variant = p->trial_variant;
+  fz.fd = p->fd_mode;
   if (cls >= 0) {
     // jobs = members of the class
     fz.n_jobs = (int)p->class_src[cls].size();
@@ -690,6 +697,8 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
   pa.prof = p->d_prof;
   pa.tables = tables;
   pa.n_patches = p->P;
+  pa.trial_variant = p->trial_variant;
+  pa.fd = p->fd_mode;
   hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
   if (e == hipSuccess) e = launch_maps_t<T>(p, tables, sm);
   FusedArgs<T> fa;
@@ -719,6 +728,8 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
   fz.images = p->d_images;
   fz.prior = p->d_prior;
   fz.want_grad = 1;
+  fz.trial_variant = p->trial_variant;
+  fz.fd = p->fd_mode;
   fz.local = p->v_local;
   fz.own = p->v_own;
   fz.grad = p->v_grad;
@@ -738,6 +749,29 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
 
 hipError_t plain_eval(cel_plan* p, const double* theta, hipStream_t sm, bool fp64) {
   return fp64 ? plain_eval_t<double>(p, theta, sm) : plain_eval_t<float>(p, theta, sm);
+}
+
+template <typename T>
+static hipError_t prep_base_t(cel_plan* p, const double* theta, hipStream_t sm) {
+  Table<T>* tables = reinterpret_cast<Table<T>*>(sizeof(T) == 8 ? (void*)p->tables_d : (void*)p->tables_f);
+  PrepArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.theta = theta;
+  pa.fd_step = p->opt.fd_step;
+  pa.patches = p->d_patches;
+  pa.images = p->d_images;
+  pa.prof = p->d_prof;
+  pa.tables = tables;
+  pa.n_patches = p->P;
+  pa.trial_variant = p->trial_variant;
+  pa.fd = p->fd_mode;
+  hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
+  if (e == hipSuccess) e = launch_maps_t<T>(p, tables, sm);
+  return e;
+}
+
+hipError_t prep_base(cel_plan* p, const double* theta, hipStream_t sm, bool fp64) {
+  return fp64 ? prep_base_t<double>(p, theta, sm) : prep_base_t<float>(p, theta, sm);
 }
 
 template hipError_t enqueue_eval<float>(cel_plan*, const double*, const double*, int, int, bool, int,

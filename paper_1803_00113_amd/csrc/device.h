@@ -39,13 +39,17 @@ enum Slot {
 // gal[k][j]: P_xx, P_xy, P_yy, log2 weight  (j < n_exp: exponential, then de Vaucouleurs)
 // rc2s[k], rc2[k][j]: squared distance from the component's centre beyond which its value
 // is below 2^-60 (from the smallest eigenvalue of its precision); -1 = negligible everywhere
+// hdr[8..9]: e0, e1 = expm1(variance of log l given the type) (for the analytic Hessian)
+// gt[k][j]: tau, tau^2, then tau^2/2 tr(E1 P E2 P) for the S-parameter pairs (xx,xx),
+//           (xx,xy), (xx,yy), (xy,xy), (xy,yy), (yy,yy)
 template <typename T>
 struct alignas(16) Table {
-  T hdr[8];
+  T hdr[16];
   T star[kMaxPsf][8];
   T gal[kMaxPsf][2 * kMaxProf][4];
   T rc2s[kMaxPsf];
   T rc2[kMaxPsf][2 * kMaxProf];
+  T gt[kMaxPsf][2 * kMaxProf][8];
 };
 
 struct DPatch {

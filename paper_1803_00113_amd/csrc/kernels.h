@@ -17,6 +17,8 @@ struct PrepArgs {
   void* tables;                // Table<T>[variants][n_patches]
   int32_t n_patches;
   const uint8_t* active;       // per source (null = all)
+  int32_t trial_variant;       // variant evaluated at theta_trial
+  int32_t fd;                  // variants 1..54 are central-difference points
 };
 
 struct FinalizeArgs {
@@ -40,6 +42,8 @@ struct FinalizeArgs {
   double* own;                 // [variants][S]
   double* grad;                // [variants][S][32]
   int64_t out_variant_stride;  // = S
+  int32_t trial_variant;
+  int32_t fd;
 };
 
 template <typename T>

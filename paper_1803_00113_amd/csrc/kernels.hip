@@ -19,47 +19,19 @@
 
 #include "device.h"
 #include "kernels.h"
+#include "pixmath.h"
 
 namespace celmi {
 
-// ----------------------------------------------------------------------------------------
-// precision helpers
-
-template <typename T> __device__ __forceinline__ T fexp2(T x);
-template <> __device__ __forceinline__ float fexp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
-template <> __device__ __forceinline__ double fexp2<double>(double x) { return exp2(x); }
-template <typename T> __device__ __forceinline__ T flog(T x);
-template <> __device__ __forceinline__ float flog<float>(float x) { return logf(x); }
-template <> __device__ __forceinline__ double flog<double>(double x) { return log(x); }
-
-constexpr double kLog2e = 1.4426950408889634074;
-constexpr double kLog2TwoPi = 2.6514961294723187980;   // log2(2 pi)
-constexpr double kNegHuge = -1.0e30;
-constexpr double kCutLog2 = -60.0;   // components below 2^-60 over a wavefront's pixels are skipped
-
-// squared radius beyond which 2^(lw - log2(e)/2 d^T C^{-1} d) < 2^kCutLog2
-__device__ __forceinline__ double cut_radius2(double lw, double cxx, double cxy, double cyy) {
-  const double room = lw - kCutLog2;
-  if (!(room > 0)) return -1.0;
-  const double lmax = 0.5 * (cxx + cyy) + sqrt(0.25 * (cxx - cyy) * (cxx - cyy) + cxy * cxy);
-  return room / (0.5 * kLog2e / lmax);
-}
-
-// log l_b = log r + W[b] . c,  c_k = ln(l_{k+1} / l_k), reference band r = index 2
-__device__ __constant__ double c_W[5][4] = {
-    {-1, -1, 0, 0}, {0, -1, 0, 0}, {0, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 1, 1}};
-
-__device__ __forceinline__ double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
-__device__ __forceinline__ double softplus(double x) { return x > 0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
-
 // Parameters of variant v of a source: base theta, +/- h along one coordinate, or trial.
+// (central differences only when fd != 0; the trial point is variant trial_v)
 __device__ __forceinline__ void load_theta(const double* theta, const double* theta_trial, int s, int v,
-                                           double h, double* th) {
-  const double* src = (v == kVariants - 1 && theta_trial) ? theta_trial + (int64_t)s * kThetaN
-                                                          : theta + (int64_t)s * kThetaN;
+                                           double h, double* th, int trial_v, int fd) {
+  const double* src = (v == trial_v && theta_trial) ? theta_trial + (int64_t)s * kThetaN
+                                                    : theta + (int64_t)s * kThetaN;
   // the perturbed coordinate is selected arithmetically so that th stays in registers
-  const int kp = (v >= 1 && v <= kParamN) ? v - 1 : -1;
-  const int km = (v > kParamN && v <= 2 * kParamN) ? v - 1 - kParamN : -1;
+  const int kp = (fd && v >= 1 && v <= kParamN) ? v - 1 : -1;
+  const int km = (fd && v > kParamN && v <= 2 * kParamN) ? v - 1 - kParamN : -1;
 #pragma unroll
   for (int k = 0; k < kThetaN; ++k) th[k] = src[k] + (k == kp ? h : 0.0) - (k == km ? h : 0.0);
 }
@@ -83,7 +55,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
   if (a.active && !a.active[P.src]) return;
   const cel_image& im = a.images[P.img];
   double th[kThetaN];
-  load_theta(a.theta, a.theta_trial, P.src, v, a.fd_step, th);
+  load_theta(a.theta, a.theta_trial, P.src, v, a.fd_step, th, a.trial_variant, a.fd);
   Table<T>* tb = reinterpret_cast<Table<T>*>(a.tables) + (int64_t)v * a.n_patches + pi_;
   const int lane = threadIdx.x;
   // position in patch-local pixel coordinates: mu = A u + b - (x0, y0)
@@ -101,7 +73,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
     // flux moments given the type (equation conditional): log l ~ N(m, v)
     const double aa = sigmoid(th[2]);
     const double w[2] = {1.0 - aa, aa};
-    double L[2], kk[2];
+    double L[2], kk[2], ee[2];
     for (int i = 0; i < 2; ++i) {
       double m = th[3 + i], var = exp(th[5 + i]);
       for (int c = 0; c < 4; ++c) {
@@ -110,8 +82,11 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
         var += W * W * exp(th[15 + 4 * i + c]);
       }
       L[i] = im.iota * exp(m + 0.5 * var);
-      kk[i] = w[i] * L[i] * L[i] * expm1(var);
+      ee[i] = expm1(var);
+      kk[i] = w[i] * L[i] * L[i] * ee[i];
     }
+    tb->hdr[8] = (T)ee[0];
+    tb->hdr[9] = (T)ee[1];
     tb->hdr[0] = (T)L[0];
     tb->hdr[1] = (T)L[1];
     tb->hdr[2] = (T)w[0];
@@ -161,10 +136,21 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
         const double lw = wt > 0 ? log2(wt) - kLog2TwoPi - 0.5 * log2(det) : kNegHuge;
         r[3] = (T)lw;
         tb->rc2[k][j] = (T)cut_radius2(lw, cxx, cxy, cyy);
+        const double Pxx = cyy / det, Pxy = -cxy / det, Pyy = cxx / det, h = 0.5 * tau * tau;
+        T* q = tb->gt[k][j];
+        q[0] = (T)tau;
+        q[1] = (T)(tau * tau);
+        q[2] = (T)(h * Pxx * Pxx);
+        q[3] = (T)(h * 2.0 * Pxx * Pxy);
+        q[4] = (T)(h * Pxy * Pxy);
+        q[5] = (T)(h * (2.0 * Pxy * Pxy + 2.0 * Pxx * Pyy));
+        q[6] = (T)(h * 2.0 * Pxy * Pyy);
+        q[7] = (T)(h * Pyy * Pyy);
       } else {
         r[0] = r[1] = r[2] = (T)0;
         r[3] = (T)kNegHuge;
         tb->rc2[k][j] = (T)-1;
+        for (int e = 0; e < 8; ++e) tb->gt[k][j][e] = (T)0;
       }
     }
   }
@@ -175,14 +161,6 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
 
 // Values of a source's star (f1) and galaxy (f0) light at PPL pixels (local coords of the
 // source's own patch).  Neighbour evaluation: no derivatives.
-// Squared distance from (mx, my) to the wavefront's pixel box [bx0, bx1] x [by0, by1].
-template <typename T>
-__device__ __forceinline__ T box_dist2(T mx, T my, const T* box) {
-  const T ddx = fmax(fmax(box[0] - mx, mx - box[1]), (T)0);
-  const T ddy = fmax(fmax(box[2] - my, my - box[3]), (T)0);
-  return ddx * ddx + ddy * ddy;
-}
-
 template <typename T, int PPL, int NEXP, int NDEV>
 __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int K, const T* px, const T* py,
                                             const T* box, T* f0, T* f1) {
@@ -304,18 +282,6 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
   }
 }
 
-// Pixel box (patch-local columns x0..x1, rows y0..y1) of the run [base, end) of a
-// row-major patch of width w.
-template <typename T>
-__device__ __forceinline__ void run_box(int base, int end, int w, T* box) {
-  const int last = end - 1;
-  const int r0 = base / w, r1 = last / w;
-  box[0] = (T)(r0 == r1 ? base - r0 * w : 0);
-  box[1] = (T)(r0 == r1 ? last - r1 * w : w - 1);
-  box[2] = (T)r0;
-  box[3] = (T)r1;
-}
-
 // k_maps: every source's own moments E_s, V_s (values only) on every pixel of its
 // patches at the base parameters, read by the pixel kernel for overlapping neighbours.
 template <typename T, int PPL, int NEXP, int NDEV>
@@ -359,13 +325,6 @@ __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
         reinterpret_cast<float2*>(a.maps)[P.off + idxs[i]] = make_float2(Es, Vs);
     }
   }
-}
-
-template <typename T>
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
 }
 
 template <typename T, int PPL, bool GRAD, int NEXP, int NDEV>
@@ -504,89 +463,6 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
 // ----------------------------------------------------------------------------------------
 // k_finalize: one thread per (variant, source)
 
-// KL(q(z_s) || p(z_s)) and its gradient in the unconstrained coordinates (equations eq:kl,
-// kleq; Supplement A with the readings: flux KL is the normal KL of log r with variances;
-// colour KL is the bound of Section 4.2.3 at its optimal weights; point-mass terms are
-// minus the log prior density; direction and angle terms are constants and dropped).
-__device__ double kl_source(const DPrior& pr, const double* th, double* g, double gs) {
-  const double eta = th[2];
-  const double a = sigmoid(eta);
-  const double log_a = -softplus(-eta), log_1ma = -softplus(eta);
-  double kl = a * (log_a - pr.log_a) + (1.0 - a) * (log_1ma - pr.log_1ma);
-  double dk_da = eta - pr.logit_a;          // d KL_a / d a
-  const double q[2] = {1.0 - a, a};
-  double part[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const double rm = th[3 + i], lrv = th[5 + i], rv = exp(lrv);
-    const double R1 = pr.r[i][0], R2 = pr.r[i][1];
-    double kr = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
-    g[3 + i] -= gs * q[i] * (rm - R1) / R2;
-    g[5 + i] -= gs * q[i] * (-0.5 + rv / (2.0 * R2));
-    // colour bound: -log sum_j w_j exp(-D_j); gradient sum_j xi_j dD_j
-    double cm[4], cv[4], lcv[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      cm[k] = th[7 + 4 * i + k];
-      lcv[k] = th[15 + 4 * i + k];
-      cv[k] = exp(lcv[k]);
-    }
-    double D[CEL_N_COLOUR_COMPONENTS], mx = -1e300;
-    double sum_lcv = lcv[0] + lcv[1] + lcv[2] + lcv[3];
-#pragma unroll
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
-      double tr = 0, maha = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        tr += pr.c_prec[i][j][k][k] * cv[k];
-        double row = 0;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
-        maha += (pr.c_mean[i][j][k] - cm[k]) * row;
-      }
-      D[j] = 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - sum_lcv);
-      const double e = pr.c_logw[i][j] - D[j];
-      if (e > mx) mx = e;
-    }
-    double z = 0;
-#pragma unroll
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - D[j] - mx);
-    const double kc = -(mx + log(z));
-#pragma unroll
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
-      const double xi = exp(pr.c_logw[i][j] - D[j] - mx) / z;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double row = 0;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
-        g[7 + 4 * i + k] -= gs * q[i] * xi * row;
-        g[15 + 4 * i + k] -= gs * q[i] * xi * 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
-      }
-    }
-    part[i] = kr + kc;
-    kl += q[i] * part[i];
-  }
-  dk_da += part[1] - part[0];
-  g[2] -= gs * (dk_da * a * (1.0 - a));
-  // radius: point mass vs log-normal
-  const double lr = th[24], E1 = pr.radius[0], E2 = pr.radius[1];
-  kl += lr + 0.5 * log(2.0 * M_PI * E2) + (lr - E1) * (lr - E1) / (2.0 * E2);
-  g[24] -= gs * (1.0 + (lr - E1) / E2);
-  // profile and axis: point mass vs Beta
-  {
-    const double e = th[25], p = sigmoid(e), lp = -softplus(-e), l1p = -softplus(e);
-    kl += -(pr.profile[0] - 1.0) * lp - (pr.profile[1] - 1.0) * l1p + pr.lbeta_profile;
-    g[25] -= gs * (-(pr.profile[0] - 1.0) * (1.0 - p) + (pr.profile[1] - 1.0) * p);
-  }
-  {
-    const double e = th[26], p = sigmoid(e), lp = -softplus(-e), l1p = -softplus(e);
-    kl += -(pr.axis[0] - 1.0) * lp - (pr.axis[1] - 1.0) * l1p + pr.lbeta_axis;
-    g[26] -= gs * (-(pr.axis[0] - 1.0) * (1.0 - p) + (pr.axis[1] - 1.0) * p);
-  }
-  return kl;
-}
-
 // one wavefront per (variant, source): lanes take the source's patches, partial sums are
 // combined by a fixed butterfly, lane 0 applies the shape chain rule and the KL
 __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
@@ -597,7 +473,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   const int v = a.variant0 + vv;
   if (a.active && !a.active[s]) return;
   double th[kThetaN];
-  load_theta(a.theta, a.theta_trial, s, v, a.fd_step, th);
+  load_theta(a.theta, a.theta_trial, s, v, a.fd_step, th, a.trial_variant, a.fd);
   double g[kThetaN];
   #pragma unroll
   for (int k = 0; k < kThetaN; ++k) g[k] = 0.0;
@@ -684,7 +560,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   if (lane != 0) return;
   // the central-difference variants (1..54) carry the pixel part of the gradient only: the
   // KL part of the Hessian is taken analytically by the trust-region kernel
-  const bool fd_variant = v >= 1 && v <= 2 * kParamN;
+  const bool fd_variant = a.fd && v >= 1 && v <= 2 * kParamN;
   double kl = kl_source(*a.prior, th, g, fd_variant ? 0.0 : 1.0);   // subtracts the KL gradient
   local -= kl;
   own -= kl;

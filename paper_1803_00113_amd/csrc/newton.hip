@@ -26,6 +26,7 @@
 
 #include "device.h"
 #include "kernels.h"
+#include "pixmath.h"
 #include "plan.h"
 
 namespace celmi {
@@ -34,14 +35,13 @@ constexpr int kN = kParamN;   // 27
 constexpr int kLd = kN + 1;   // padded LDS row
 
 
-__device__ __forceinline__ double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
 
 // Hessian of KL_s in the unconstrained coordinates (the same KL as the objective: the type
 // KL, the normal KL of log r, the colour bound -log sum_j w_j exp(-D_j), and minus the log
 // prior densities of the radius, profile and axis point masses), added into B (27 x kLd).
 // KL = KL_a(eta) + KL_radius + KL_profile + KL_axis + (1 - a) K_0 + a K_1.
 __device__ void kl_hessian_add(const DPrior& pr, const double* th, double B[kN][kLd]) {
-  const double eta = th[2], a = sigm(eta);
+  const double eta = th[2], a = sigmoid(eta);
   const double aa = a * (1.0 - a);
   double K[2], dK[2][kN];
   for (int i = 0; i < 2; ++i) {
@@ -124,13 +124,561 @@ __device__ void kl_hessian_add(const DPrior& pr, const double* th, double B[kN][
   // point masses
   B[24][24] += 1.0 / pr.radius[1];
   {
-    const double p = sigm(th[25]);
+    const double p = sigmoid(th[25]);
     B[25][25] += (pr.profile[0] + pr.profile[1] - 2.0) * p * (1.0 - p);
   }
   {
-    const double p = sigm(th[26]);
+    const double p = sigmoid(th[26]);
     B[26][26] += (pr.axis[0] + pr.axis[1] - 2.0) * p * (1.0 - p);
   }
+}
+
+
+// ----------------------------------------------------------------------------------------
+// Analytic Hessian of the pixel part of L_s (Section 4.3 uses a dense Newton Hessian).
+//
+// Per patch the pixel sum depends on theta_s through 11 primitives
+//   y = (a, L0, L1, e0, e1, mu_x, mu_y, S_xx, S_xy, S_yy, pi)
+// (type probability, flux moments L_i = E[l | a=i] and e_i = expm1(Var log l | a=i), the
+// pixel-frame centre and galaxy covariance, the de Vaucouleurs weight), with
+//   E_s = w0 L0 f0 + w1 L1 f1,  V_s = w0 L0^2 e0 f0^2 + w1 L1^2 e1 f1^2 + w0 w1 d^2,
+//   d = L0 f0 - L1 f1,  w0 = 1 - a, w1 = a.
+// For T(E, V) = -E + x (log E - V / (2 E^2)):  T_E = c_E, T_V = c_V,
+//   T_EE = -x/E^2 - 3 x V / E^4, T_EV = x / E^3, T_VV = 0, so per pixel
+//   d2T/du dv = T_EE E_u E_v + T_EV (E_u V_v + E_v V_u) + c_E E_uv + c_V V_uv.
+// f0, f1 and their first and second derivatives in (mu, S, pi) come from the Gaussian
+// identities (N = normal density with precision P, u = P (p - m)):
+//   dN/dmu = N u,  d2N/dmu dmu = N (u u^T - P),  dN/dC[dC] = N (u^T dC u - tr(P dC)) / 2,
+//   d2N/dmu dC[dC] = dN[dC] u - N P dC u,
+//   d2N/dC dC[dC1, dC2] = dN[dC1] dN[dC2] / N - N u^T dC1 P dC2 u + N tr(dC1 P dC2 P) / 2,
+// with dC = tau dS for a galaxy component.  The kernel sums G_u and the 66 entries Q_uv
+// per work item; k_hess_finalize maps them to theta_s by the chain rule.
+
+constexpr int kPrim = 11;
+constexpr int kHQ = 66;
+constexpr int kHSlots = 80;   // T, T_own, G[11], Q[66], pad
+
+__host__ __device__ constexpr int qidx(int u, int v) { return u * kPrim - u * (u - 1) / 2 + (v - u); }
+__host__ __device__ constexpr int zidx(int i, int j) { return i * 6 - i * (i - 1) / 2 + (j - i); }
+
+template <typename T>
+struct PixH {
+  T f0, f1;
+  T g0[6];   // mu_x, mu_y, S_xx, S_xy, S_yy, pi
+  T g1[2];
+  T h0[21];  // upper triangle (zidx)
+  T h1[3];   // xx, xy, yy
+};
+
+// one galaxy component of one profile: value, first derivatives (per profile) and the
+// profile-weighted second derivatives in (mu, S)
+template <typename T>
+__device__ __forceinline__ void gal_hess(T Pxx, T Pxy, T Pyy, T lw, const T* gt, T wP, T dx, T dy, T& f, T* gm,
+                                         T* gs, T* hmm, T* hms, T* hss) {
+  const T hl = (T)(-0.5 * kLog2e);
+  const T ux = fma(Pxx, dx, Pxy * dy);
+  const T uy = fma(Pxy, dx, Pyy * dy);
+  const T q = fma(dx, ux, dy * uy);
+  const T N = fexp2<T>(fma(q, hl, lw));
+  const T qxx = fma(ux, ux, -Pxx), qxy = fma(ux, uy, -Pxy), qyy = fma(uy, uy, -Pyy);
+  const T tau = gt[0], tau2 = gt[1];
+  const T Nh = (T)0.5 * tau * N;
+  f += N;
+  gm[0] = fma(N, ux, gm[0]);
+  gm[1] = fma(N, uy, gm[1]);
+  const T Nxx = Nh * qxx, Nxy = (T)2 * Nh * qxy, Nyy = Nh * qyy;
+  gs[0] += Nxx;
+  gs[1] += Nxy;
+  gs[2] += Nyy;
+  const T Nw = N * wP;
+  hmm[0] = fma(Nw, qxx, hmm[0]);
+  hmm[1] = fma(Nw, qxy, hmm[1]);
+  hmm[2] = fma(Nw, qyy, hmm[2]);
+  const T Ntw = Nw * tau;
+  const T vxx_x = ux * Pxx, vxx_y = ux * Pxy;
+  const T vxy_x = fma(Pxx, uy, Pxy * ux), vxy_y = fma(Pxy, uy, Pyy * ux);
+  const T vyy_x = uy * Pxy, vyy_y = uy * Pyy;
+  const T w0e = Nxx * wP, w1e = Nxy * wP, w2e = Nyy * wP;
+  hms[0] += fma(w0e, ux, -Ntw * vxx_x);
+  hms[3] += fma(w0e, uy, -Ntw * vxx_y);
+  hms[1] += fma(w1e, ux, -Ntw * vxy_x);
+  hms[4] += fma(w1e, uy, -Ntw * vxy_y);
+  hms[2] += fma(w2e, ux, -Ntw * vyy_x);
+  hms[5] += fma(w2e, uy, -Ntw * vyy_y);
+  const T q1 = (T)2 * qxy;
+  const T Nwt2 = Nw * tau2;
+  hss[0] += fma(Nwt2, (T)0.25 * qxx * qxx - ux * vxx_x, Nw * gt[2]);
+  hss[1] += fma(Nwt2, (T)0.25 * qxx * q1 - ux * vxy_x, Nw * gt[3]);
+  hss[2] += fma(Nwt2, (T)0.25 * qxx * qyy - ux * vyy_x, Nw * gt[4]);
+  hss[3] += fma(Nwt2, (T)0.25 * q1 * q1 - fma(uy, vxy_x, ux * vxy_y), Nw * gt[5]);
+  hss[4] += fma(Nwt2, (T)0.25 * q1 * qyy - uy * vxy_y, Nw * gt[6]);
+  hss[5] += fma(Nwt2, (T)0.25 * qyy * qyy - uy * vyy_y, Nw * gt[7]);
+}
+
+template <typename T, int NEXP, int NDEV>
+__device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, int K, T px, T py, const T* box,
+                                              PixH<T>& o) {
+  const T hl = (T)(-0.5 * kLog2e);
+  T fe = 0, fd = 0, gme[2] = {0, 0}, gmd[2] = {0, 0}, gse[3] = {0, 0, 0}, gsd[3] = {0, 0, 0};
+  T hmm[3] = {0, 0, 0}, hms[6] = {0, 0, 0, 0, 0, 0}, hss[6] = {0, 0, 0, 0, 0, 0};
+  T f1 = 0, g1x = 0, g1y = 0, h1[3] = {0, 0, 0};
+  const T pi = tb->hdr[7], omp = (T)1 - pi;
+  for (int k = 0; k < K; ++k) {
+    const T mx = tb->star[k][0], my = tb->star[k][1];
+    const T dx = px - mx, dy = py - my;
+    const T d2 = box_dist2<T>(mx, my, box);
+    if (d2 <= tb->rc2s[k]) {
+      const T Pxx = tb->star[k][2], Pxy = tb->star[k][3], Pyy = tb->star[k][4], lw = tb->star[k][5];
+      const T ux = fma(Pxx, dx, Pxy * dy), uy = fma(Pxy, dx, Pyy * dy);
+      const T N = fexp2<T>(fma(fma(dx, ux, dy * uy), hl, lw));
+      f1 += N;
+      g1x = fma(N, ux, g1x);
+      g1y = fma(N, uy, g1y);
+      h1[0] = fma(N, fma(ux, ux, -Pxx), h1[0]);
+      h1[1] = fma(N, fma(ux, uy, -Pxy), h1[1]);
+      h1[2] = fma(N, fma(uy, uy, -Pyy), h1[2]);
+    }
+#pragma unroll
+    for (int j = 0; j < NEXP; ++j)
+      if (d2 <= tb->rc2[k][j])
+        gal_hess<T>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], tb->gt[k][j], omp, dx,
+                    dy, fe, gme, gse, hmm, hms, hss);
+#pragma unroll
+    for (int j = 0; j < NDEV; ++j)
+      if (d2 <= tb->rc2[k][kMaxProf + j])
+        gal_hess<T>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
+                    tb->gal[k][kMaxProf + j][3], tb->gt[k][kMaxProf + j], pi, dx, dy, fd, gmd, gsd, hmm, hms, hss);
+  }
+  o.f1 = f1;
+  o.g1[0] = g1x;
+  o.g1[1] = g1y;
+  o.h1[0] = h1[0];
+  o.h1[1] = h1[1];
+  o.h1[2] = h1[2];
+  o.f0 = fma(pi, fd, omp * fe);
+  o.g0[0] = fma(pi, gmd[0], omp * gme[0]);
+  o.g0[1] = fma(pi, gmd[1], omp * gme[1]);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) o.g0[2 + e] = fma(pi, gsd[e], omp * gse[e]);
+  o.g0[5] = fd - fe;
+  o.h0[zidx(0, 0)] = hmm[0];
+  o.h0[zidx(0, 1)] = hmm[1];
+  o.h0[zidx(1, 1)] = hmm[2];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    o.h0[zidx(0, 2 + e)] = hms[e];
+    o.h0[zidx(1, 2 + e)] = hms[3 + e];
+  }
+  o.h0[zidx(2, 2)] = hss[0];
+  o.h0[zidx(2, 3)] = hss[1];
+  o.h0[zidx(2, 4)] = hss[2];
+  o.h0[zidx(3, 3)] = hss[3];
+  o.h0[zidx(3, 4)] = hss[4];
+  o.h0[zidx(4, 4)] = hss[5];
+  o.h0[zidx(0, 5)] = gmd[0] - gme[0];
+  o.h0[zidx(1, 5)] = gmd[1] - gme[1];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) o.h0[zidx(2 + e, 5)] = gsd[e] - gse[e];
+  o.h0[zidx(5, 5)] = 0;
+}
+
+struct HessArgs {
+  const DTask* tasks;
+  const int32_t* order;
+  const DPatch* patches;
+  const int32_t* nbr_idx;
+  const void* tables;          // variant-0 tables
+  const void* xs;
+  const void* maps;
+  double* hslots;              // [n_tasks][kHSlots]
+  const uint8_t* active;
+  const int32_t* img_npsf;
+};
+
+template <typename T, int NEXP, int NDEV>
+__global__ __launch_bounds__(64) void k_hess(HessArgs a) {
+  const int t = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+  const DTask task = a.tasks[t];
+  const DPatch P = a.patches[task.patch];
+  if (a.active && !a.active[P.src]) return;
+  const Table<T>* __restrict__ tb = reinterpret_cast<const Table<T>*>(a.tables) + task.patch;
+  const int K = a.img_npsf[P.img];
+  const int lane = threadIdx.x;
+  const float inv_w = 1.0f / (float)P.w;
+  const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
+  const T e0 = tb->hdr[8], e1 = tb->hdr[9];
+  const T w01 = w0 * w1, aa = w1, oma2 = (T)1 - (T)2 * aa;
+  double tsum = 0, town = 0;
+  T G[kPrim], Q[kHQ];
+#pragma unroll
+  for (int u = 0; u < kPrim; ++u) G[u] = 0;
+#pragma unroll
+  for (int u = 0; u < kHQ; ++u) Q[u] = 0;
+  for (int base = task.pix_begin; base < task.pix_end; base += 64) {
+    int idx = base + lane;
+    const bool valid = idx < task.pix_end;
+    if (!valid) idx = task.pix_begin;
+    int row = (int)(((float)idx + 0.5f) * inv_w);
+    int col = idx - row * P.w;
+    if (col < 0) { row -= 1; col += P.w; }
+    else if (col >= P.w) { row += 1; col -= P.w; }
+    T xv, sky;
+    if constexpr (sizeof(T) == 8) {
+      const double2 xs = reinterpret_cast<const double2*>(a.xs)[P.off + idx];
+      xv = xs.x; sky = xs.y;
+    } else {
+      const float2 xs = reinterpret_cast<const float2*>(a.xs)[P.off + idx];
+      xv = xs.x; sky = xs.y;
+    }
+    T box[4];
+    run_box<T>(base, min(base + 64, task.pix_end), P.w, box);
+    PixH<T> o;
+    eval_own_hess<T, NEXP, NDEV>(tb, K, (T)col, (T)row, box, o);
+    T Eb = sky, Vb = 0;
+    bool own = true;
+    for (int nb = P.nbr_begin; nb < P.nbr_end; ++nb) {
+      const DPatch Qp = a.patches[a.nbr_idx[nb]];
+      const int cx = col + P.x0 - Qp.x0, cy = row + P.y0 - Qp.y0;
+      if (valid && cx >= 0 && cx < Qp.w && cy >= 0 && cy < Qp.h) {
+        const int64_t at = Qp.off + (int64_t)cy * Qp.w + cx;
+        if constexpr (sizeof(T) == 8) {
+          const double2 ev = reinterpret_cast<const double2*>(a.maps)[at];
+          Eb += ev.x; Vb += ev.y;
+        } else {
+          const float2 ev = reinterpret_cast<const float2*>(a.maps)[at];
+          Eb += ev.x; Vb += ev.y;
+        }
+        if (Qp.src < P.src) own = false;
+      }
+    }
+    const T f0 = o.f0, f1 = o.f1;
+    const T d = L0 * f0 - L1 * f1;
+    const T Es = w0 * L0 * f0 + w1 * L1 * f1;
+    const T k0 = w0 * L0 * L0 * e0, k1 = w1 * L1 * L1 * e1;
+    const T Vs = fma(k0 * f0, f0, fma(k1 * f1, f1, w01 * d * d));
+    const T E = Eb + Es, V = Vb + Vs, x = xv;
+    const T invE = (T)1 / E;
+    const T xr = x * invE * invE;
+    T Tm = (x > (T)0 ? x * flog<T>(E / x) : (T)0) - (E - x) - (T)0.5 * xr * V;
+    T cE = fma(xr * invE, V, (x - E) * invE);
+    T cV = (T)-0.5 * xr;
+    T TEE = -xr - (T)3 * xr * V * invE * invE;
+    T TEV = xr * invE;
+    if (!valid) Tm = cE = cV = TEE = TEV = 0;
+    tsum += (double)Tm;
+    town += own ? (double)Tm : 0.0;
+    // z-derivatives of f1 (zero outside mu) and of d
+    T g1z[6], dz[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      g1z[j] = j < 2 ? o.g1[j] : (T)0;
+      dz[j] = L0 * o.g0[j] - L1 * g1z[j];
+    }
+    T Eu[kPrim], Vu[kPrim];
+    Eu[0] = -d;
+    Eu[1] = w0 * f0;
+    Eu[2] = w1 * f1;
+    Eu[3] = 0;
+    Eu[4] = 0;
+    Vu[0] = -L0 * L0 * e0 * f0 * f0 + L1 * L1 * e1 * f1 * f1 + oma2 * d * d;
+    Vu[1] = (T)2 * w0 * L0 * e0 * f0 * f0 + (T)2 * w01 * d * f0;
+    Vu[2] = (T)2 * w1 * L1 * e1 * f1 * f1 - (T)2 * w01 * d * f1;
+    Vu[3] = w0 * L0 * L0 * f0 * f0;
+    Vu[4] = w1 * L1 * L1 * f1 * f1;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      Eu[5 + j] = w0 * L0 * o.g0[j] + w1 * L1 * g1z[j];
+      Vu[5 + j] = (T)2 * (k0 * f0 * o.g0[j] + k1 * f1 * g1z[j] + w01 * d * dz[j]);
+    }
+#pragma unroll
+    for (int u = 0; u < kPrim; ++u) {
+      G[u] = fma(cE, Eu[u], fma(cV, Vu[u], G[u]));
+      const T te = TEE * Eu[u], tv = TEV * Vu[u], tu = TEV * Eu[u];
+#pragma unroll
+      for (int v = u; v < kPrim; ++v) Q[qidx(u, v)] += fma(te, Eu[v], fma(tu, Vu[v], tv * Eu[v]));
+    }
+    // second derivatives of E_s and V_s
+    Q[qidx(0, 0)] += cV * (T)-2 * d * d;
+    Q[qidx(0, 1)] += fma(cE, -f0, cV * ((T)-2 * L0 * e0 * f0 * f0 + (T)2 * oma2 * d * f0));
+    Q[qidx(0, 2)] += fma(cE, f1, cV * ((T)2 * L1 * e1 * f1 * f1 - (T)2 * oma2 * d * f1));
+    Q[qidx(0, 3)] += cV * (-L0 * L0 * f0 * f0);
+    Q[qidx(0, 4)] += cV * (L1 * L1 * f1 * f1);
+    Q[qidx(1, 1)] += cV * ((T)2 * w0 * e0 * f0 * f0 + (T)2 * w01 * f0 * f0);
+    Q[qidx(1, 2)] += cV * ((T)-2 * w01 * f0 * f1);
+    Q[qidx(1, 3)] += cV * ((T)2 * w0 * L0 * f0 * f0);
+    Q[qidx(2, 2)] += cV * ((T)2 * w1 * e1 * f1 * f1 + (T)2 * w01 * f1 * f1);
+    Q[qidx(2, 4)] += cV * ((T)2 * w1 * L1 * f1 * f1);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const T g0j = o.g0[j], g1j = g1z[j], dzj = dz[j];
+      Q[qidx(0, 5 + j)] += fma(cE, -dzj, cV * ((T)-2 * L0 * L0 * e0 * f0 * g0j + (T)2 * L1 * L1 * e1 * f1 * g1j +
+                                               (T)2 * oma2 * d * dzj));
+      Q[qidx(1, 5 + j)] += fma(cE, w0 * g0j, cV * ((T)4 * w0 * L0 * e0 * f0 * g0j + (T)2 * w01 * (dzj * f0 + d * g0j)));
+      Q[qidx(2, 5 + j)] += fma(cE, w1 * g1j, cV * ((T)4 * w1 * L1 * e1 * f1 * g1j - (T)2 * w01 * (dzj * f1 + d * g1j)));
+      Q[qidx(3, 5 + j)] += cV * ((T)2 * w0 * L0 * L0 * f0 * g0j);
+      Q[qidx(4, 5 + j)] += cV * ((T)2 * w1 * L1 * L1 * f1 * g1j);
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+      for (int j = i; j < 6; ++j) {
+        const T h0ij = o.h0[zidx(i, j)];
+        const T h1ij = (i < 2 && j < 2) ? o.h1[i + j] : (T)0;
+        const T Euv = w0 * L0 * h0ij + w1 * L1 * h1ij;
+        const T Vuv = (T)2 * (k0 * (o.g0[i] * o.g0[j] + f0 * h0ij) + k1 * (g1z[i] * g1z[j] + f1 * h1ij) +
+                              w01 * (dz[i] * dz[j] + d * (L0 * h0ij - L1 * h1ij)));
+        Q[qidx(5 + i, 5 + j)] += fma(cE, Euv, cV * Vuv);
+      }
+    }
+  }
+  double* out = a.hslots + (int64_t)t * kHSlots;
+  const double ts = wave_sum<double>(tsum), to = wave_sum<double>(town);
+  if (lane == 0) {
+    out[0] = ts;
+    out[1] = to;
+  }
+#pragma unroll
+  for (int u = 0; u < kPrim; ++u) {
+    const double v = wave_sum<double>((double)G[u]);
+    if (lane == 0) out[2 + u] = v;
+  }
+#pragma unroll
+  for (int u = 0; u < kHQ; ++u) {
+    const double v = wave_sum<double>((double)Q[u]);
+    if (lane == 0) out[2 + kPrim + u] = v;
+  }
+}
+
+// Sigma_s(angle, log r, logit axis) and its first and second derivatives in those three
+// coordinates (Section 2.1.2): out d1[t][e], d2[t][t'][e] with e = (xx, xy, yy).
+__device__ void sigma_derivs(double ang, double lr, double eta, double d1[3][3], double d2[3][3][3]) {
+  const double c = cos(ang), s = sin(ang), r2 = exp(2.0 * lr), rho = sigmoid(eta);
+  const double rp = rho * (1.0 - rho), rpp = rp * (1.0 - 2.0 * rho);
+  const double sig[3] = {r2 * (c * c + rho * rho * s * s), r2 * (rho * rho - 1.0) * c * s,
+                         r2 * (s * s + rho * rho * c * c)};
+  const double dt[3] = {2.0 * r2 * c * s * (rho * rho - 1.0), r2 * (rho * rho - 1.0) * (c * c - s * s),
+                        -2.0 * r2 * c * s * (rho * rho - 1.0)};
+  const double dtt[3] = {2.0 * r2 * (rho * rho - 1.0) * (c * c - s * s), -4.0 * r2 * (rho * rho - 1.0) * c * s,
+                         -2.0 * r2 * (rho * rho - 1.0) * (c * c - s * s)};
+  const double dr[3] = {2.0 * rho * r2 * s * s, 2.0 * rho * r2 * c * s, 2.0 * rho * r2 * c * c};
+  const double drr[3] = {2.0 * r2 * s * s, 2.0 * r2 * c * s, 2.0 * r2 * c * c};
+  const double dtr[3] = {4.0 * rho * r2 * c * s, 2.0 * rho * r2 * (c * c - s * s), -4.0 * rho * r2 * c * s};
+  for (int e = 0; e < 3; ++e) {
+    d1[0][e] = dt[e];
+    d1[1][e] = 2.0 * sig[e];
+    d1[2][e] = dr[e] * rp;
+    d2[0][0][e] = dtt[e];
+    d2[1][1][e] = 4.0 * sig[e];
+    d2[2][2][e] = drr[e] * rp * rp + dr[e] * rpp;
+    d2[0][1][e] = d2[1][0][e] = 2.0 * dt[e];
+    d2[1][2][e] = d2[2][1][e] = 2.0 * dr[e] * rp;
+    d2[0][2][e] = d2[2][0][e] = dtr[e] * rp;
+  }
+}
+
+// S = A M A^T for a symmetric M given as (xx, xy, yy)
+__device__ __forceinline__ void conj_A(const double A[2][2], const double* m, double* out) {
+  const double t00 = A[0][0] * m[0] + A[0][1] * m[1], t01 = A[0][0] * m[1] + A[0][1] * m[2];
+  const double t10 = A[1][0] * m[0] + A[1][1] * m[1], t11 = A[1][0] * m[1] + A[1][1] * m[2];
+  out[0] = t00 * A[0][0] + t01 * A[0][1];
+  out[1] = t00 * A[1][0] + t01 * A[1][1];
+  out[2] = t10 * A[1][0] + t11 * A[1][1];
+}
+
+struct HessFinArgs {
+  const int32_t* job_src;
+  int32_t n_jobs;
+  const uint8_t* active;
+  const double* theta;
+  const double* hslots;
+  const int32_t* patch_ptr;
+  const DPatch* patches;
+  const double* pix_const;
+  const cel_image* images;
+  const DPrior* prior;
+  int32_t with_kl;             // 1: the Hessian includes the KL part (value and gradient always do)
+  double* local;               // [S]
+  double* grad;                // [S][32]
+  double* hess;                // [S][27][27]
+};
+
+__global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
+  const int s = a.job_src ? a.job_src[blockIdx.x] : (int)blockIdx.x;
+  if (a.active && !a.active[s]) return;
+  const int lane = threadIdx.x;
+  __shared__ double sm[kHSlots];
+  __shared__ double Qy[kPrim][kPrim], Qr[kPrim][kPrim], Gr[kPrim];
+  __shared__ double J[kPrim][kN], T1[kPrim][kN];
+  __shared__ double Hs[kN][kLd], gs[kN];
+  double th[kN];
+#pragma unroll
+  for (int k = 0; k < kN; ++k) th[k] = a.theta[(int64_t)s * kThetaN + k];
+  for (int idx = lane; idx < kN * kN; idx += 64) Hs[idx / kN][idx % kN] = 0.0;
+  if (lane < kN) gs[lane] = 0.0;
+  double local = 0.0;
+  const double aa = sigmoid(th[2]), pi = sigmoid(th[25]);
+  double sd1[3][3], sd2[3][3][3];
+  sigma_derivs(th[23], th[24], th[26], sd1, sd2);
+  __syncthreads();
+  for (int p = a.patch_ptr[s]; p < a.patch_ptr[s + 1]; ++p) {
+    const DPatch P = a.patches[p];
+    for (int l = lane; l < 2 + kPrim + kHQ; l += 64) {
+      double acc = 0;
+      for (int t = P.task_begin; t < P.task_end; ++t) acc += a.hslots[(int64_t)t * kHSlots + l];
+      sm[l] = acc;
+    }
+    __syncthreads();
+    const cel_image& im = a.images[P.img];
+    local += sm[0] + a.pix_const[2 * p];
+    // flux moments of this band: L_i, e_i and their derivatives in (m_i, v_i)
+    double L[2], ev[2], cvv[2][4], rv[2];
+    for (int i = 0; i < 2; ++i) {
+      double m = th[3 + i];
+      rv[i] = exp(th[5 + i]);
+      double var = rv[i];
+      for (int c = 0; c < 4; ++c) {
+        const double W = c_W[im.band][c];
+        m += W * th[7 + 4 * i + c];
+        cvv[i][c] = exp(th[15 + 4 * i + c]);
+        var += W * W * cvv[i][c];
+      }
+      L[i] = im.iota * exp(m + 0.5 * var);
+      ev[i] = exp(var);
+    }
+    // stage 1: y = (a, L0, L1, e0, e1, z) -> r = (a, m0, v0, m1, v1, z)
+    for (int idx = lane; idx < kPrim * kPrim; idx += 64) {
+      const int u = idx / kPrim, v = idx % kPrim;
+      Qy[u][v] = sm[2 + kPrim + (u <= v ? qidx(u, v) : qidx(v, u))];
+    }
+    __syncthreads();
+    if (lane == 0) {
+      // Jy[y][r]: identity except L_i(m_i, v_i), e_i(v_i)
+      double Jy[kPrim][kPrim];
+      for (int u = 0; u < kPrim; ++u)
+        for (int v = 0; v < kPrim; ++v) Jy[u][v] = (u == v) ? 1.0 : 0.0;
+      for (int i = 0; i < 2; ++i) {
+        const int iL = 1 + i, ie = 3 + i, im_ = 1 + 2 * i, iv = 2 + 2 * i;
+        for (int v = 0; v < kPrim; ++v) Jy[iL][v] = Jy[ie][v] = 0.0;
+        Jy[iL][im_] = L[i];
+        Jy[iL][iv] = 0.5 * L[i];
+        Jy[ie][iv] = ev[i];
+      }
+      const double* Gy = sm + 2;
+      for (int r = 0; r < kPrim; ++r) {
+        double g = 0;
+        for (int u = 0; u < kPrim; ++u) g += Jy[u][r] * Gy[u];
+        Gr[r] = g;
+      }
+      for (int r = 0; r < kPrim; ++r)
+        for (int r2 = r; r2 < kPrim; ++r2) {
+          double v = 0;
+          for (int u = 0; u < kPrim; ++u) {
+            if (Jy[u][r] == 0.0) continue;
+            for (int w = 0; w < kPrim; ++w) v += Jy[u][r] * Qy[u][w] * Jy[w][r2];
+          }
+          Qr[r][r2] = Qr[r2][r] = v;
+        }
+      // second derivatives of y in r: L_i: mm = L, mv = L/2, vv = L/4; e_i: vv = e^v
+      for (int i = 0; i < 2; ++i) {
+        const int im_ = 1 + 2 * i, iv = 2 + 2 * i;
+        const double gL = Gy[1 + i], ge = Gy[3 + i];
+        Qr[im_][im_] += gL * L[i];
+        Qr[im_][iv] += gL * 0.5 * L[i];
+        Qr[iv][im_] += gL * 0.5 * L[i];
+        Qr[iv][iv] += gL * 0.25 * L[i] + ge * ev[i];
+      }
+      // stage 2 Jacobian J[r][theta]
+      for (int r = 0; r < kPrim; ++r)
+        for (int k = 0; k < kN; ++k) J[r][k] = 0.0;
+      J[0][2] = aa * (1.0 - aa);
+      for (int i = 0; i < 2; ++i) {
+        const int im_ = 1 + 2 * i, iv = 2 + 2 * i;
+        J[im_][3 + i] = 1.0;
+        J[iv][5 + i] = rv[i];
+        for (int c = 0; c < 4; ++c) {
+          const double W = c_W[im.band][c];
+          J[im_][7 + 4 * i + c] = W;
+          J[iv][15 + 4 * i + c] = W * W * cvv[i][c];
+        }
+      }
+      J[5][0] = im.A[0][0];
+      J[5][1] = im.A[0][1];
+      J[6][0] = im.A[1][0];
+      J[6][1] = im.A[1][1];
+      const int tix[3] = {23, 24, 26};
+      for (int t = 0; t < 3; ++t) {
+        double sv[3];
+        conj_A(im.A, sd1[t], sv);
+        for (int e = 0; e < 3; ++e) J[7 + e][tix[t]] = sv[e];
+      }
+      J[10][25] = pi * (1.0 - pi);
+    }
+    __syncthreads();
+    // T1 = Qr J
+    for (int idx = lane; idx < kPrim * kN; idx += 64) {
+      const int r = idx / kN, k = idx % kN;
+      double v = 0;
+      for (int r2 = 0; r2 < kPrim; ++r2) v += Qr[r][r2] * J[r2][k];
+      T1[r][k] = v;
+    }
+    __syncthreads();
+    // H += J^T T1;  g += J^T Gr
+    for (int idx = lane; idx < kN * kN; idx += 64) {
+      const int i = idx / kN, k = idx % kN;
+      double v = 0;
+      for (int r = 0; r < kPrim; ++r) v += J[r][i] * T1[r][k];
+      Hs[i][k] += v;
+    }
+    if (lane < kN) {
+      double v = 0;
+      for (int r = 0; r < kPrim; ++r) v += J[r][lane] * Gr[r];
+      gs[lane] += v;
+    }
+    __syncthreads();
+    if (lane == 0) {
+      // second derivatives of r in theta: a, v_i, S, pi
+      Hs[2][2] += Gr[0] * aa * (1.0 - aa) * (1.0 - 2.0 * aa);
+      for (int i = 0; i < 2; ++i) {
+        const int iv = 2 + 2 * i;
+        Hs[5 + i][5 + i] += Gr[iv] * rv[i];
+        for (int c = 0; c < 4; ++c) {
+          const double W = c_W[im.band][c];
+          Hs[15 + 4 * i + c][15 + 4 * i + c] += Gr[iv] * W * W * cvv[i][c];
+        }
+      }
+      const int tix[3] = {23, 24, 26};
+      for (int t = 0; t < 3; ++t)
+        for (int t2 = 0; t2 < 3; ++t2) {
+          double sv[3];
+          conj_A(im.A, sd2[t][t2], sv);
+          Hs[tix[t]][tix[t2]] += Gr[7] * sv[0] + Gr[8] * sv[1] + Gr[9] * sv[2];
+        }
+      Hs[25][25] += Gr[10] * pi * (1.0 - pi) * (1.0 - 2.0 * pi);
+    }
+    __syncthreads();
+  }
+  // KL: value, gradient and (optionally) Hessian
+  if (lane == 0) {
+    double gk[kThetaN];
+#pragma unroll
+    for (int k = 0; k < kThetaN; ++k) gk[k] = 0.0;
+    const double kl = kl_source(*a.prior, th, gk, 1.0);   // gk = -grad KL
+    local -= kl;
+    if (a.local) a.local[s] = local;
+    for (int k = 0; k < kN; ++k) gs[k] += gk[k];
+    if (a.with_kl) {
+      // Hs currently holds +H_pixels; kl_hessian_add adds +H_KL: negate around it
+      for (int i = 0; i < kN; ++i)
+        for (int k = 0; k < kN; ++k) Hs[i][k] = -Hs[i][k];
+      kl_hessian_add(*a.prior, th, Hs);
+      for (int i = 0; i < kN; ++i)
+        for (int k = 0; k < kN; ++k) Hs[i][k] = -Hs[i][k];
+    }
+  }
+  __syncthreads();
+  if (a.grad && lane < kThetaN) a.grad[(int64_t)s * kThetaN + lane] = lane < kN ? gs[lane] : 0.0;
+  for (int idx = lane; idx < kN * kN; idx += 64)
+    a.hess[(int64_t)s * kN * kN + idx] = Hs[idx / kN][idx % kN];
 }
 
 struct TrArgs {
@@ -151,6 +699,7 @@ struct TrArgs {
   double* pnorm;              // out: |p|
   int32_t* status;            // out: CONVERGED / NONFINITE for sources not tried
   const DPrior* prior;
+  const double* hess;         // analytic pixel Hessians [S][27][27] (null: central differences)
 };
 
 __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
@@ -170,8 +719,9 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
   const double L = a.v_local[s];
   for (int idx = lane; idx < kN * kN; idx += 64) {
     const int i = idx / kN, k = idx % kN;
-    const double hik = (a.v_grad[(int64_t)(1 + k) * vs + (int64_t)s * kThetaN + i] -
-                        a.v_grad[(int64_t)(1 + kN + k) * vs + (int64_t)s * kThetaN + i]) / h2;
+    const double hik = a.hess ? a.hess[(int64_t)s * kN * kN + idx]
+                              : (a.v_grad[(int64_t)(1 + k) * vs + (int64_t)s * kThetaN + i] -
+                                 a.v_grad[(int64_t)(1 + kN + k) * vs + (int64_t)s * kThetaN + i]) / h2;
     B[i][k] = -hik;
     V[i][k] = (i == k) ? 1.0 : 0.0;
   }
@@ -496,14 +1046,77 @@ __global__ __launch_bounds__(256) void k_count_active(const uint8_t* __restrict_
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+template <typename T>
+static hipError_t launch_hess_t(cel_plan* p, const int32_t* order, int n_items, const uint8_t* active,
+                                hipStream_t sm) {
+  if (n_items <= 0) return hipSuccess;
+  HessArgs ha;
+  std::memset(&ha, 0, sizeof(ha));
+  ha.tasks = p->d_tasks;
+  ha.order = order;
+  ha.patches = p->d_patches;
+  ha.nbr_idx = p->d_nbr;
+  ha.tables = sizeof(T) == 8 ? (const void*)p->tables_d : (const void*)p->tables_f;
+  ha.xs = sizeof(T) == 8 ? (const void*)p->d_xs64 : (const void*)p->d_xs;
+  ha.maps = sizeof(T) == 8 ? (const void*)p->d_maps64 : (const void*)p->d_maps;
+  ha.hslots = p->d_hslots;
+  ha.active = active;
+  ha.img_npsf = p->d_npsf;
+  if (p->nexp == 6 && p->ndev == 8)
+    hipLaunchKernelGGL((k_hess<T, 6, 8>), dim3(n_items), dim3(64), 0, sm, ha);
+  else
+    hipLaunchKernelGGL((k_hess<T, 8, 8>), dim3(n_items), dim3(64), 0, sm, ha);
+  return hipGetLastError();
+}
+
+// Analytic per-source Hessians (pixel part, plus the KL part when with_kl) of the sources
+// flagged in `active` among `srcs` (device list, n_src entries; null = 0..S-1), with their
+// gradients and local objectives.  The base tables and maps must be current.
+static hipError_t enqueue_hessian(cel_plan* p, const double* theta, const int32_t* order, int n_items,
+                                  const int32_t* srcs, int n_src, const uint8_t* active, bool with_kl, double* local,
+                                  double* grad, double* hess, hipStream_t sm) {
+  const bool fp64 = p->opt.pixel_fp64 || p->opt.hessian_fp64;
+  hipError_t e = fp64 ? launch_hess_t<double>(p, order, n_items, active, sm)
+                      : launch_hess_t<float>(p, order, n_items, active, sm);
+  if (e != hipSuccess || n_src <= 0) return e;
+  HessFinArgs fa;
+  std::memset(&fa, 0, sizeof(fa));
+  fa.job_src = srcs;
+  fa.n_jobs = n_src;
+  fa.active = active;
+  fa.theta = theta;
+  fa.hslots = p->d_hslots;
+  fa.patch_ptr = p->d_patch_ptr;
+  fa.patches = p->d_patches;
+  fa.pix_const = p->d_pixconst;
+  fa.images = p->d_images;
+  fa.prior = p->d_prior;
+  fa.with_kl = with_kl ? 1 : 0;
+  fa.local = local;
+  fa.grad = grad;
+  fa.hess = hess;
+  hipLaunchKernelGGL(k_hess_finalize, dim3(n_src), dim3(64), 0, sm, fa);
+  return hipGetLastError();
+}
+
 // One Newton iteration of colour class `cls` on the sources flagged in `active`.
 static hipError_t enqueue_newton_class(cel_plan* p, double* theta, double* radius, uint8_t* active, int cls,
                                        int32_t* status, double* out_local, bool clear_done, hipStream_t sm) {
   const bool fp64 = p->opt.pixel_fp64 || p->opt.hessian_fp64;
   const int nsrc = (int)p->class_src[cls].size();
   if (nsrc == 0) return hipSuccess;
-  // gradients at the iterate and at the 54 central-difference points
-  hipError_t e = eval_any(p, theta, nullptr, 0, 2 * kParamN + 1, true, cls, active, sm, true, fp64);
+  hipError_t e;
+  const bool analytic = !p->opt.hessian_fd;
+  if (analytic) {
+    // tables and maps at the iterate, then the exact pixel Hessians with the gradients
+    e = prep_base(p, theta, sm, fp64);
+    if (e == hipSuccess)
+      e = enqueue_hessian(p, theta, p->d_class_tasks[cls], (int)p->class_tasks[cls].size(), p->d_class_src[cls], nsrc,
+                          active, false, p->v_local, p->v_grad, p->d_hess, sm);
+  } else {
+    // gradients at the iterate and at the 54 central-difference points
+    e = eval_any(p, theta, nullptr, 0, 2 * kParamN + 1, true, cls, active, sm, true, fp64);
+  }
   if (e != hipSuccess) return e;
   TrArgs ta;
   std::memset(&ta, 0, sizeof(ta));
@@ -526,10 +1139,11 @@ static hipError_t enqueue_newton_class(cel_plan* p, double* theta, double* radiu
   ta.pnorm = p->d_step_norm;
   ta.status = status;
   ta.prior = p->d_prior;
+  ta.hess = analytic ? p->d_hess : nullptr;
   hipLaunchKernelGGL(k_trsolve, dim3(nsrc), dim3(64), 0, sm, ta);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // objective at the trial points
-  e = eval_any(p, theta, p->d_theta_trial, kVariants - 1, 1, false, cls, p->d_trial_active, sm, false, fp64);
+  e = eval_any(p, theta, p->d_theta_trial, p->trial_variant, 1, false, cls, p->d_trial_active, sm, false, fp64);
   if (e != hipSuccess) return e;
   AcceptArgs aa;
   std::memset(&aa, 0, sizeof(aa));
@@ -539,7 +1153,7 @@ static hipError_t enqueue_newton_class(cel_plan* p, double* theta, double* radiu
   aa.clear_done = clear_done ? 1 : 0;
   aa.trial_active = p->d_trial_active;
   aa.local0 = p->v_local;
-  aa.local_trial = p->v_local + (int64_t)(kVariants - 1) * p->S;
+  aa.local_trial = p->v_local + (int64_t)p->trial_variant * p->S;
   aa.pred = p->d_pred;
   aa.pnorm = p->d_step_norm;
   aa.theta = theta;
@@ -559,7 +1173,10 @@ using namespace celmi;
 
 static cel_status newton_scratch(cel_plan* p) {
   const bool fp64 = p->opt.pixel_fp64 || p->opt.hessian_fp64;
-  cel_status st = ensure_variants(p, kVariants, fp64);
+  // analytic Hessian: variants 0 (iterate) and 1 (trial); differences: 0, 1..54, 55 (trial)
+  p->fd_mode = p->opt.hessian_fd ? 1 : 0;
+  p->trial_variant = p->opt.hessian_fd ? kVariants - 1 : 1;
+  cel_status st = ensure_variants(p, p->trial_variant + 1, fp64);
   if (st) return st;
   return ensure_newton(p);
 }
@@ -696,5 +1313,27 @@ extern "C" cel_status cel_sweep(cel_ctx* ctx, const cel_plan* cplan, double* the
     report->n_newton_steps = steps;
     report->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
+  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+}
+
+extern "C" cel_status cel_elbo_hessian(cel_ctx* ctx, const cel_plan* cplan, const double* theta, const uint8_t* mask,
+                                       double* hess, double* grad, double* elbo_local, void* stream) {
+  if (!ctx || !cplan) return CEL_EINVAL;
+  cel_plan* p = const_cast<cel_plan*>(cplan);
+  if (p->S > 0 && (!theta || !hess)) return CEL_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
+  hipStream_t sm = (hipStream_t)stream;
+  cel_status st = newton_scratch(p);
+  if (st) return st;
+  if (p->S == 0) return CEL_OK;
+  const bool fp64 = p->opt.pixel_fp64 || p->opt.hessian_fp64;
+  if (hipEventSynchronize(p->mask_copied) != hipSuccess) return CEL_EHIP;
+  for (int s = 0; s < p->S; ++s) p->h_mask[s] = mask ? (mask[s] ? 1 : 0) : 1;
+  hipError_t e = hipMemcpyAsync(p->d_mask, p->h_mask, p->S, hipMemcpyHostToDevice, sm);
+  if (e == hipSuccess) e = hipEventRecord(p->mask_copied, sm);
+  if (e == hipSuccess) e = prep_base(p, theta, sm, fp64);
+  if (e == hipSuccess)
+    e = enqueue_hessian(p, theta, p->d_order, (int)p->n_tasks, nullptr, p->S, p->d_mask, true,
+                        elbo_local ? elbo_local : p->v_local, grad ? grad : p->v_grad, hess, sm);
   return e == hipSuccess ? CEL_OK : CEL_EHIP;
 }

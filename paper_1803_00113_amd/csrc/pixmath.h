@@ -1,0 +1,152 @@
+// Device helpers shared by the celmi kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "device.h"
+
+namespace celmi {
+
+// ----------------------------------------------------------------------------------------
+// precision helpers
+
+template <typename T> __device__ __forceinline__ T fexp2(T x);
+template <> __device__ __forceinline__ float fexp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <> __device__ __forceinline__ double fexp2<double>(double x) { return exp2(x); }
+template <typename T> __device__ __forceinline__ T flog(T x);
+template <> __device__ __forceinline__ float flog<float>(float x) { return logf(x); }
+template <> __device__ __forceinline__ double flog<double>(double x) { return log(x); }
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLog2TwoPi = 2.6514961294723187980;   // log2(2 pi)
+constexpr double kNegHuge = -1.0e30;
+constexpr double kCutLog2 = -60.0;   // components below 2^-60 over a wavefront's pixels are skipped
+
+// squared radius beyond which 2^(lw - log2(e)/2 d^T C^{-1} d) < 2^kCutLog2
+__device__ __forceinline__ double cut_radius2(double lw, double cxx, double cxy, double cyy) {
+  const double room = lw - kCutLog2;
+  if (!(room > 0)) return -1.0;
+  const double lmax = 0.5 * (cxx + cyy) + sqrt(0.25 * (cxx - cyy) * (cxx - cyy) + cxy * cxy);
+  return room / (0.5 * kLog2e / lmax);
+}
+
+// log l_b = log r + W[b] . c,  c_k = ln(l_{k+1} / l_k), reference band r = index 2
+static __device__ __constant__ double c_W[5][4] = {
+    {-1, -1, 0, 0}, {0, -1, 0, 0}, {0, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 1, 1}};
+
+__device__ __forceinline__ double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+__device__ __forceinline__ double softplus(double x) { return x > 0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
+
+
+
+// Squared distance from (mx, my) to the wavefront's pixel box [bx0, bx1] x [by0, by1].
+template <typename T>
+__device__ __forceinline__ T box_dist2(T mx, T my, const T* box) {
+  const T ddx = fmax(fmax(box[0] - mx, mx - box[1]), (T)0);
+  const T ddy = fmax(fmax(box[2] - my, my - box[3]), (T)0);
+  return ddx * ddx + ddy * ddy;
+}
+
+// Pixel box (patch-local columns x0..x1, rows y0..y1) of the run [base, end) of a
+// row-major patch of width w.
+template <typename T>
+__device__ __forceinline__ void run_box(int base, int end, int w, T* box) {
+  const int last = end - 1;
+  const int r0 = base / w, r1 = last / w;
+  box[0] = (T)(r0 == r1 ? base - r0 * w : 0);
+  box[1] = (T)(r0 == r1 ? last - r1 * w : w - 1);
+  box[2] = (T)r0;
+  box[3] = (T)r1;
+}
+
+template <typename T>
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// KL(q(z_s) || p(z_s)) and its gradient in the unconstrained coordinates (equations eq:kl,
+// kleq; Supplement A with the readings: flux KL is the normal KL of log r with variances;
+// colour KL is the bound of Section 4.2.3 at its optimal weights; point-mass terms are
+// minus the log prior density; direction and angle terms are constants and dropped).
+__device__ inline double kl_source(const DPrior& pr, const double* th, double* g, double gs) {
+  const double eta = th[2];
+  const double a = sigmoid(eta);
+  const double log_a = -softplus(-eta), log_1ma = -softplus(eta);
+  double kl = a * (log_a - pr.log_a) + (1.0 - a) * (log_1ma - pr.log_1ma);
+  double dk_da = eta - pr.logit_a;          // d KL_a / d a
+  const double q[2] = {1.0 - a, a};
+  double part[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double rm = th[3 + i], lrv = th[5 + i], rv = exp(lrv);
+    const double R1 = pr.r[i][0], R2 = pr.r[i][1];
+    double kr = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
+    g[3 + i] -= gs * q[i] * (rm - R1) / R2;
+    g[5 + i] -= gs * q[i] * (-0.5 + rv / (2.0 * R2));
+    // colour bound: -log sum_j w_j exp(-D_j); gradient sum_j xi_j dD_j
+    double cm[4], cv[4], lcv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cm[k] = th[7 + 4 * i + k];
+      lcv[k] = th[15 + 4 * i + k];
+      cv[k] = exp(lcv[k]);
+    }
+    double D[CEL_N_COLOUR_COMPONENTS], mx = -1e300;
+    double sum_lcv = lcv[0] + lcv[1] + lcv[2] + lcv[3];
+#pragma unroll
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+      double tr = 0, maha = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        tr += pr.c_prec[i][j][k][k] * cv[k];
+        double row = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
+        maha += (pr.c_mean[i][j][k] - cm[k]) * row;
+      }
+      D[j] = 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - sum_lcv);
+      const double e = pr.c_logw[i][j] - D[j];
+      if (e > mx) mx = e;
+    }
+    double z = 0;
+#pragma unroll
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - D[j] - mx);
+    const double kc = -(mx + log(z));
+#pragma unroll
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+      const double xi = exp(pr.c_logw[i][j] - D[j] - mx) / z;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double row = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
+        g[7 + 4 * i + k] -= gs * q[i] * xi * row;
+        g[15 + 4 * i + k] -= gs * q[i] * xi * 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
+      }
+    }
+    part[i] = kr + kc;
+    kl += q[i] * part[i];
+  }
+  dk_da += part[1] - part[0];
+  g[2] -= gs * (dk_da * a * (1.0 - a));
+  // radius: point mass vs log-normal
+  const double lr = th[24], E1 = pr.radius[0], E2 = pr.radius[1];
+  kl += lr + 0.5 * log(2.0 * M_PI * E2) + (lr - E1) * (lr - E1) / (2.0 * E2);
+  g[24] -= gs * (1.0 + (lr - E1) / E2);
+  // profile and axis: point mass vs Beta
+  {
+    const double e = th[25], p = sigmoid(e), lp = -softplus(-e), l1p = -softplus(e);
+    kl += -(pr.profile[0] - 1.0) * lp - (pr.profile[1] - 1.0) * l1p + pr.lbeta_profile;
+    g[25] -= gs * (-(pr.profile[0] - 1.0) * (1.0 - p) + (pr.profile[1] - 1.0) * p);
+  }
+  {
+    const double e = th[26], p = sigmoid(e), lp = -softplus(-e), l1p = -softplus(e);
+    kl += -(pr.axis[0] - 1.0) * lp - (pr.axis[1] - 1.0) * l1p + pr.lbeta_axis;
+    g[26] -= gs * (-(pr.axis[0] - 1.0) * (1.0 - p) + (pr.axis[1] - 1.0) * p);
+  }
+  return kl;
+}
+
+}  // namespace celmi

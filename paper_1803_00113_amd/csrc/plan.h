@@ -83,6 +83,11 @@ struct cel_plan {
   };
   std::vector<Graph> graphs;
   bool marking = false;
+  // variant bookkeeping: central-difference variants on/off, index of the trial variant
+  int fd_mode = 1;
+  int trial_variant = celmi::kVariants - 1;
+  double* d_hslots = nullptr;     // analytic Hessian partial sums [n_tasks][80]
+  double* d_hess = nullptr;       // per-source pixel Hessians [S][27][27]
   std::vector<void*> allocs;
   // measurement: events per recorded evaluation (start, tables, maps, pixels, end)
   std::vector<hipEvent_t> ev_pool;
@@ -96,6 +101,8 @@ cel_status ensure_variants(cel_plan* p, int nv, bool fp64);
 hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv, bool grad, int cls,
                     const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64);
 hipError_t plain_eval(cel_plan* p, const double* theta, hipStream_t sm, bool fp64);
+// component tables at the iterate for every patch and the neighbour moment maps
+hipError_t prep_base(cel_plan* p, const double* theta, hipStream_t sm, bool fp64);
 // record a phase boundary event (k = 0..4) of the current evaluation when timing is on
 void phase_mark(cel_plan* p, int k, hipStream_t sm);
 cel_status ensure_newton(cel_plan* p);

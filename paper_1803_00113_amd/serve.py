@@ -27,24 +27,38 @@ import torch
 from . import api
 
 TABLE_BYTES = 1536           # per patch and variant, float32 component table (upper bound)
-VARIANTS = 56                # Newton: base, 54 central differences, trial
+VARIANTS_EXACT = 2           # Newton with the exact Hessian: iterate, trial
+VARIANTS_FD = 56             # Newton with a difference Hessian: iterate, 54 differences, trial
 
 
-def footprint_bytes(prob):
+def footprint_bytes(prob, variants=VARIANTS_EXACT):
     """Estimated device bytes a request needs inside a merged plan (pixels, per-pixel
-    arrays, Newton tables and slots, per-source scratch)."""
+    arrays, Newton tables and slots, Hessian slots and matrices, per-source scratch)."""
     units = int(np.sum(prob.patch_w.astype(np.int64) * prob.patch_h))
     P = int(len(prob.patch_src))
     S = int(prob.n_sources)
     items = int(np.sum((prob.patch_w.astype(np.int64) * prob.patch_h + 511) // 512))
-    return (units * (4 + 8 + 8) + P * VARIANTS * TABLE_BYTES + items * VARIANTS * 16 * 8
-            + S * VARIANTS * (8 + 8 + 32 * 8) + S * 32 * 8 * 3 + P * 64)
+    return (units * (4 + 8 + 8) + P * variants * TABLE_BYTES + items * (variants * 16 + 80) * 8
+            + S * variants * (8 + 8 + 32 * 8) + S * (32 * 8 * 3 + 27 * 27 * 8) + P * 64)
+
+
+SHARED = ("prior_a", "prior_r", "prior_cw", "prior_cmean", "prior_ccov", "prior_radius", "prior_profile",
+          "prior_axis", "exp_alpha", "exp_tau", "dev_alpha", "dev_tau")
+
+
+def same_model(a, b):
+    """True when two requests share the prior and the galaxy profile mixtures."""
+    return all(np.array_equal(np.asarray(getattr(a, k)), np.asarray(getattr(b, k))) for k in SHARED)
 
 
 def merge(probs):
     """One problem holding the given requests side by side (ids offset; images, patches,
-    sky knots and pixels concatenated).  All requests must share the prior and profiles."""
+    sky knots and pixels concatenated).  All requests must share the prior and profiles
+    (ValueError otherwise)."""
     base = probs[0]
+    for p in probs[1:]:
+        if not same_model(base, p):
+            raise ValueError("requests with different priors or profiles cannot share a plan")
     S_off, N_off, K_off, X_off = 0, 0, 0, 0
     cols = {k: [] for k in ("img_band", "img_H", "img_W", "img_npsf", "img_psf", "img_A", "img_b", "img_iota",
                             "img_sky_qh", "img_sky_qw", "img_sky_off", "sky_knots", "patch_src", "patch_img",
@@ -65,8 +79,7 @@ def merge(probs):
     for k, v in cols.items():
         setattr(out, k, np.concatenate(v) if v else v)
     out.n_sources = S_off
-    for k in ("prior_a", "prior_r", "prior_cw", "prior_cmean", "prior_ccov", "prior_radius", "prior_profile",
-              "prior_axis", "exp_alpha", "exp_tau", "dev_alpha", "dev_tau"):
+    for k in SHARED:
         setattr(out, k, getattr(base, k))
     out.pixels = np.zeros(0, np.float32)   # pixels are passed on the device
     return out
@@ -123,6 +136,7 @@ class Server:
     def __init__(self, device=0, hbm_budget_bytes=16 << 30, rounds=10, **ctx_opts):
         self.ctx = api.Context(device, **ctx_opts)
         self.dev = self.ctx.device
+        self.variants = VARIANTS_FD if ctx_opts.get("hessian_fd") else VARIANTS_EXACT
         self.budget = int(hbm_budget_bytes)
         self.rounds = int(rounds)
         self.resident: list[Request] = []
@@ -162,7 +176,7 @@ class Server:
         used = sum(r.footprint for r in self.resident)
         while pending:
             r = pending[0]
-            r.footprint = r.footprint or footprint_bytes(r.prob)
+            r.footprint = r.footprint or footprint_bytes(r.prob, self.variants)
             if used + r.footprint > self.budget and self.resident:
                 self.stats.deferred_admissions += 1
                 break

@@ -36,6 +36,7 @@ N_THETA = 32
 N_COLOUR_COMPONENTS = 8
 MAX_PSF = 4
 SEED_BASE = 180300110
+SURVEY_PRIOR_SEED = SEED_BASE + 55   # the prior every region request of one survey shares
 
 
 def load_profiles():
@@ -342,11 +343,13 @@ def _image(rng, band, H, W, sky0, A=None, b=None, sky_grad=0.0, qh=2, qw=2, npsf
 
 
 def _grouped(name, seed, n_sources, side_lo, side_hi, n_epochs, flux_mode, max_group=5,
-             spacing=None, epoch_shift=0.5):
-    """Sources in isolated groups of 1..max_group whose patches overlap pairwise."""
+             spacing=None, epoch_shift=0.5, prior_seed=None):
+    """Sources in isolated groups of 1..max_group whose patches overlap pairwise.  The prior
+    is drawn from `prior_seed` when given (one prior shared by every region of a survey),
+    else from the problem's own stream."""
     rng = np.random.default_rng(seed)
     profiles = load_profiles()
-    prior = make_prior(rng)
+    prior = make_prior(rng) if prior_seed is None else make_prior(np.random.default_rng(prior_seed))
     groups = []
     left = n_sources
     while left > 0:
@@ -440,7 +443,7 @@ def config3(seed=SEED_BASE + 3, n_sources=4096):
 def config5_request(seed, n_sources=None):
     rng = np.random.default_rng(seed)
     n = int(n_sources if n_sources is not None else rng.integers(1, 201))
-    return _grouped(f"request_{n}src_5b_side16-96", seed + 7, n, 16, 96, 1, "prior")
+    return _grouped(f"request_{n}src_5b_side16-96", seed + 7, n, 16, 96, 1, "prior", prior_seed=SURVEY_PRIOR_SEED)
 
 
 def _extent_halfwidth(src, psf_sigma_max):

@@ -34,7 +34,7 @@ def one_step(prob, mask, **opts):
     return th.cpu().numpy(), r.cpu().numpy(), st.cpu().numpy(), loc.cpu().numpy(), plan
 
 
-def check_step(m, theta0, s, th_gpu, r_gpu, st_gpu, loc_gpu, fp64):
+def check_step(m, theta0, s, th_gpu, r_gpu, st_gpu, loc_gpu, fp64, fd=False):
     """One Newton step against the oracle's.  Along flat directions of the Hessian small
     differences in it move the step without changing the objective, so the step is judged
     by the oracle's own objective at both new points (relative to the gain), plus a loose
@@ -46,9 +46,14 @@ def check_step(m, theta0, s, th_gpu, r_gpu, st_gpu, loc_gpu, fp64):
     th[s] = th_gpu
     Lg = E.elbo(m, th, sources=[s], with_total=False)[1][s].item()
     gain = abs(o_loc - L0)
-    # FD Hessian (h = 1e-3, float64 gradients): truncation ~h^2 -> 2e-5 of the gain;
-    # float32 gradients (h = 1e-2): rounding noise / h + h^2 -> 1e-2 of the gain
-    tol_gain, tol_el, tol_r = (2e-5, 1e-3, 1e-3) if fp64 else (1e-2, 5e-2, 5e-2)
+    if fd:
+        # FD Hessian (h = 1e-3, float64 gradients): truncation ~h^2 -> 2e-5 of the gain;
+        # float32 gradients (h = 1e-2): rounding noise / h + h^2 -> 1e-2 of the gain
+        tol_gain, tol_el, tol_r = (2e-5, 1e-3, 1e-3) if fp64 else (1e-2, 5e-2, 5e-2)
+    else:
+        # exact Hessian: float64 differs from the oracle by summation order only; float32
+        # per-pixel terms carry ~1e-5 relative error into the Hessian
+        tol_gain, tol_el, tol_r = (1e-10, 1e-8, 1e-8) if fp64 else (1e-5, 1e-4, 1e-4)
     step = np.abs(o_th - theta0[s]).max()
     say(f"  s={s} status {st_gpu}/{o_st} |dtheta|max {np.abs(th_gpu - o_th).max():.2e} (step {step:.2e}) "
         f"L_oracle(gpu point) - L_oracle(oracle point) {Lg - o_loc:.3e} (gain {gain:.3e}) radius {r_gpu}/{o_r}")
@@ -58,9 +63,9 @@ def check_step(m, theta0, s, th_gpu, r_gpu, st_gpu, loc_gpu, fp64):
     assert abs(loc_gpu - o_loc) <= 1e-5 * abs(o_loc)
 
 
-@pytest.mark.parametrize("fp64", [True, False])
-def test_newton_step_config1(fp64):
-    say(f"case: newton step config1 fp64={fp64}")
+@pytest.mark.parametrize("fp64,fd", [(True, False), (False, False), (True, True), (False, True)])
+def test_newton_step_config1(fp64, fd):
+    say(f"case: newton step config1 fp64={fp64} fd={fd}")
     prob = gen.config1()
     m = E.Model(prob)
     with pytest.raises(_ffi.CelError):          # the two sources overlap
@@ -68,10 +73,10 @@ def test_newton_step_config1(fp64):
     for s in range(2):
         mask = np.zeros(2, bool)
         mask[s] = True
-        th, r, st, loc, _ = one_step(prob, mask, hessian_fp64=fp64)
+        th, r, st, loc, _ = one_step(prob, mask, hessian_fp64=fp64, hessian_fd=fd)
         assert st[1 - s] == _ffi.ST_SKIPPED and np.isnan(loc[1 - s])
         assert np.array_equal(th[1 - s], prob.theta0[1 - s])
-        check_step(m, prob.theta0, s, th[s], r[s], st[s], loc[s], fp64)
+        check_step(m, prob.theta0, s, th[s], r[s], st[s], loc[s], fp64, fd)
 
 
 def test_newton_step_class_batched_equals_single():
