@@ -38,9 +38,11 @@ constexpr int kLd = kN + 1;   // padded LDS row
 
 // Hessian of KL_s in the unconstrained coordinates (the same KL as the objective: the type
 // KL, the normal KL of log r, the colour bound -log sum_j w_j exp(-D_j), and minus the log
-// prior densities of the radius, profile and axis point masses), added into B (27 x kLd).
+// prior densities of the radius, profile and axis point masses), times sc, added into B
+// (27 rows of stride LD).
 // KL = KL_a(eta) + KL_radius + KL_profile + KL_axis + (1 - a) K_0 + a K_1.
-__device__ void kl_hessian_add(const DPrior& pr, const double* th, double B[kN][kLd]) {
+template <int LD>
+__device__ void kl_hessian_add(const DPrior& pr, const double* th, double (*B)[LD], double sc) {
   const double eta = th[2], a = sigmoid(eta);
   const double aa = a * (1.0 - a);
   double K[2], dK[2][kN];
@@ -52,8 +54,8 @@ __device__ void kl_hessian_add(const DPrior& pr, const double* th, double B[kN][
     K[i] = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
     dK[i][3 + i] = (rm - R1) / R2;
     dK[i][5 + i] = -0.5 + rv / (2.0 * R2);
-    B[3 + i][3 + i] += q / R2;
-    B[5 + i][5 + i] += q * rv / (2.0 * R2);
+    B[3 + i][3 + i] += sc * (q / R2);
+    B[5 + i][5 + i] += sc * (q * rv / (2.0 * R2));
     // colour bound
     double cm[4], cv[4], lcv = 0;
     for (int k = 0; k < 4; ++k) {
@@ -108,28 +110,28 @@ __device__ void kl_hessian_add(const DPrior& pr, const double* th, double B[kN][
     }
     for (int u = 0; u < 8; ++u) {
       dK[i][idx[u]] += gF[u];
-      for (int w = 0; w < 8; ++w) B[idx[u]][idx[w]] += q * hF[u][w];
+      for (int w = 0; w < 8; ++w) B[idx[u]][idx[w]] += sc * (q * hF[u][w]);
     }
   }
   // type weight: dKL/deta = a(1-a) [eta - logit A + K1 - K0]
   const double t = eta - pr.logit_a + K[1] - K[0];
-  B[2][2] += aa * (1.0 - 2.0 * a) * t + aa;
+  B[2][2] += sc * (aa * (1.0 - 2.0 * a) * t + aa);
   for (int k = 0; k < kN; ++k) {
     const double c = aa * (dK[1][k] - dK[0][k]);
     if (c != 0.0 && k != 2) {
-      B[2][k] += c;
-      B[k][2] += c;
+      B[2][k] += sc * (c);
+      B[k][2] += sc * (c);
     }
   }
   // point masses
-  B[24][24] += 1.0 / pr.radius[1];
+  B[24][24] += sc * (1.0 / pr.radius[1]);
   {
     const double p = sigmoid(th[25]);
-    B[25][25] += (pr.profile[0] + pr.profile[1] - 2.0) * p * (1.0 - p);
+    B[25][25] += sc * ((pr.profile[0] + pr.profile[1] - 2.0) * p * (1.0 - p));
   }
   {
     const double p = sigmoid(th[26]);
-    B[26][26] += (pr.axis[0] + pr.axis[1] - 2.0) * p * (1.0 - p);
+    B[26][26] += sc * ((pr.axis[0] + pr.axis[1] - 2.0) * p * (1.0 - p));
   }
 }
 
@@ -507,111 +509,118 @@ __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
   if (a.active && !a.active[s]) return;
   const int lane = threadIdx.x;
   __shared__ double sm[kHSlots];
-  __shared__ double Qy[kPrim][kPrim], Qr[kPrim][kPrim], Gr[kPrim];
+  __shared__ double Qy[kPrim][kPrim], Jy[kPrim][kPrim], Ty[kPrim][kPrim], Qr[kPrim][kPrim], Gr[kPrim];
   __shared__ double J[kPrim][kN], T1[kPrim][kN];
-  __shared__ double Hs[kN][kLd], gs[kN];
-  double th[kN];
-#pragma unroll
-  for (int k = 0; k < kN; ++k) th[k] = a.theta[(int64_t)s * kThetaN + k];
+  __shared__ double Hs[kN][kLd], gs[kThetaN];
+  __shared__ double th[kN], sd1[3][3], sd2[3][3][3];
+  __shared__ double Lf[2], ev[2], rv[2], cvv[2][4];
+  if (lane < kN) th[lane] = a.theta[(int64_t)s * kThetaN + lane];
   for (int idx = lane; idx < kN * kN; idx += 64) Hs[idx / kN][idx % kN] = 0.0;
-  if (lane < kN) gs[lane] = 0.0;
+  if (lane < kThetaN) gs[lane] = 0.0;
+  __syncthreads();
+  if (lane == 0) sigma_derivs(th[23], th[24], th[26], sd1, sd2);
   double local = 0.0;
   const double aa = sigmoid(th[2]), pi = sigmoid(th[25]);
-  double sd1[3][3], sd2[3][3][3];
-  sigma_derivs(th[23], th[24], th[26], sd1, sd2);
-  __syncthreads();
   for (int p = a.patch_ptr[s]; p < a.patch_ptr[s + 1]; ++p) {
     const DPatch P = a.patches[p];
+    const cel_image& im = a.images[P.img];
     for (int l = lane; l < 2 + kPrim + kHQ; l += 64) {
       double acc = 0;
       for (int t = P.task_begin; t < P.task_end; ++t) acc += a.hslots[(int64_t)t * kHSlots + l];
       sm[l] = acc;
     }
-    __syncthreads();
-    const cel_image& im = a.images[P.img];
-    local += sm[0] + a.pix_const[2 * p];
-    // flux moments of this band: L_i, e_i and their derivatives in (m_i, v_i)
-    double L[2], ev[2], cvv[2][4], rv[2];
-    for (int i = 0; i < 2; ++i) {
+    // flux moments of this band: L_i, e_i (as functions of m_i, v_i)
+    if (lane < 2) {
+      const int i = lane;
       double m = th[3 + i];
-      rv[i] = exp(th[5 + i]);
-      double var = rv[i];
+      const double r = exp(th[5 + i]);
+      double var = r;
+#pragma unroll
       for (int c = 0; c < 4; ++c) {
         const double W = c_W[im.band][c];
+        const double cv = exp(th[15 + 4 * i + c]);
         m += W * th[7 + 4 * i + c];
-        cvv[i][c] = exp(th[15 + 4 * i + c]);
-        var += W * W * cvv[i][c];
+        var += W * W * cv;
+        cvv[i][c] = cv;
       }
-      L[i] = im.iota * exp(m + 0.5 * var);
+      rv[i] = r;
+      Lf[i] = im.iota * exp(m + 0.5 * var);
       ev[i] = exp(var);
     }
-    // stage 1: y = (a, L0, L1, e0, e1, z) -> r = (a, m0, v0, m1, v1, z)
+    __syncthreads();
+    local += sm[0] + a.pix_const[2 * p];
+    // stage 1: y = (a, L0, L1, e0, e1, z) -> r = (a, m0, v0, m1, v1, z); Jy[u][r] = dy_u/dr
     for (int idx = lane; idx < kPrim * kPrim; idx += 64) {
-      const int u = idx / kPrim, v = idx % kPrim;
-      Qy[u][v] = sm[2 + kPrim + (u <= v ? qidx(u, v) : qidx(v, u))];
+      const int u = idx / kPrim, r = idx % kPrim;
+      Qy[u][r] = sm[2 + kPrim + (u <= r ? qidx(u, r) : qidx(r, u))];
+      double j = (u == r) ? 1.0 : 0.0;
+      if (u == 1 || u == 2) {
+        const int i = u - 1;
+        j = (r == 1 + 2 * i) ? Lf[i] : (r == 2 + 2 * i) ? 0.5 * Lf[i] : 0.0;
+      } else if (u == 3 || u == 4) {
+        const int i = u - 3;
+        j = (r == 2 + 2 * i) ? ev[i] : 0.0;
+      }
+      Jy[u][r] = j;
+    }
+    // stage 2 Jacobian J[r][theta] = dr/dtheta
+    for (int idx = lane; idx < kPrim * kN; idx += 64) {
+      const int r = idx / kN, k = idx % kN;
+      double j = 0.0;
+      if (r == 0) {
+        j = k == 2 ? aa * (1.0 - aa) : 0.0;
+      } else if (r <= 4) {
+        const int i = (r - 1) / 2;
+        if (r == 1 + 2 * i) {   // m_i
+          if (k == 3 + i) j = 1.0;
+          else if (k >= 7 + 4 * i && k < 11 + 4 * i) j = c_W[im.band][k - 7 - 4 * i];
+        } else {                // v_i
+          if (k == 5 + i) j = rv[i];
+          else if (k >= 15 + 4 * i && k < 19 + 4 * i) {
+            const double W = c_W[im.band][k - 15 - 4 * i];
+            j = W * W * cvv[i][k - 15 - 4 * i];
+          }
+        }
+      } else if (r <= 6) {      // pixel-frame centre
+        if (k < 2) j = im.A[r - 5][k];
+      } else if (r <= 9) {      // S = A Sigma A^T in (angle, log radius, logit axis)
+        const int t = k == 23 ? 0 : k == 24 ? 1 : k == 26 ? 2 : -1;
+        if (t >= 0) {
+          double sv[3];
+          conj_A(im.A, sd1[t], sv);
+          j = sv[r - 7];
+        }
+      } else {
+        j = k == 25 ? pi * (1.0 - pi) : 0.0;
+      }
+      J[r][k] = j;
     }
     __syncthreads();
-    if (lane == 0) {
-      // Jy[y][r]: identity except L_i(m_i, v_i), e_i(v_i)
-      double Jy[kPrim][kPrim];
-      for (int u = 0; u < kPrim; ++u)
-        for (int v = 0; v < kPrim; ++v) Jy[u][v] = (u == v) ? 1.0 : 0.0;
-      for (int i = 0; i < 2; ++i) {
-        const int iL = 1 + i, ie = 3 + i, im_ = 1 + 2 * i, iv = 2 + 2 * i;
-        for (int v = 0; v < kPrim; ++v) Jy[iL][v] = Jy[ie][v] = 0.0;
-        Jy[iL][im_] = L[i];
-        Jy[iL][iv] = 0.5 * L[i];
-        Jy[ie][iv] = ev[i];
-      }
-      const double* Gy = sm + 2;
-      for (int r = 0; r < kPrim; ++r) {
-        double g = 0;
-        for (int u = 0; u < kPrim; ++u) g += Jy[u][r] * Gy[u];
-        Gr[r] = g;
-      }
-      for (int r = 0; r < kPrim; ++r)
-        for (int r2 = r; r2 < kPrim; ++r2) {
-          double v = 0;
-          for (int u = 0; u < kPrim; ++u) {
-            if (Jy[u][r] == 0.0) continue;
-            for (int w = 0; w < kPrim; ++w) v += Jy[u][r] * Qy[u][w] * Jy[w][r2];
-          }
-          Qr[r][r2] = Qr[r2][r] = v;
-        }
+    for (int idx = lane; idx < kPrim * kPrim; idx += 64) {
+      const int u = idx / kPrim, r = idx % kPrim;
+      double v = 0;
+      for (int w = 0; w < kPrim; ++w) v += Qy[u][w] * Jy[w][r];
+      Ty[u][r] = v;
+    }
+    __syncthreads();
+    for (int idx = lane; idx < kPrim * kPrim; idx += 64) {
+      const int r = idx / kPrim, r2 = idx % kPrim;
+      double v = 0;
+      for (int u = 0; u < kPrim; ++u) v += Jy[u][r] * Ty[u][r2];
       // second derivatives of y in r: L_i: mm = L, mv = L/2, vv = L/4; e_i: vv = e^v
       for (int i = 0; i < 2; ++i) {
         const int im_ = 1 + 2 * i, iv = 2 + 2 * i;
-        const double gL = Gy[1 + i], ge = Gy[3 + i];
-        Qr[im_][im_] += gL * L[i];
-        Qr[im_][iv] += gL * 0.5 * L[i];
-        Qr[iv][im_] += gL * 0.5 * L[i];
-        Qr[iv][iv] += gL * 0.25 * L[i] + ge * ev[i];
+        const double gL = sm[2 + 1 + i], ge = sm[2 + 3 + i];
+        if (r == im_ && r2 == im_) v += gL * Lf[i];
+        if ((r == im_ && r2 == iv) || (r == iv && r2 == im_)) v += gL * 0.5 * Lf[i];
+        if (r == iv && r2 == iv) v += gL * 0.25 * Lf[i] + ge * ev[i];
       }
-      // stage 2 Jacobian J[r][theta]
-      for (int r = 0; r < kPrim; ++r)
-        for (int k = 0; k < kN; ++k) J[r][k] = 0.0;
-      J[0][2] = aa * (1.0 - aa);
-      for (int i = 0; i < 2; ++i) {
-        const int im_ = 1 + 2 * i, iv = 2 + 2 * i;
-        J[im_][3 + i] = 1.0;
-        J[iv][5 + i] = rv[i];
-        for (int c = 0; c < 4; ++c) {
-          const double W = c_W[im.band][c];
-          J[im_][7 + 4 * i + c] = W;
-          J[iv][15 + 4 * i + c] = W * W * cvv[i][c];
-        }
-      }
-      J[5][0] = im.A[0][0];
-      J[5][1] = im.A[0][1];
-      J[6][0] = im.A[1][0];
-      J[6][1] = im.A[1][1];
-      const int tix[3] = {23, 24, 26};
-      for (int t = 0; t < 3; ++t) {
-        double sv[3];
-        conj_A(im.A, sd1[t], sv);
-        for (int e = 0; e < 3; ++e) J[7 + e][tix[t]] = sv[e];
-      }
-      J[10][25] = pi * (1.0 - pi);
+      Qr[r][r2] = v;
+    }
+    if (lane < kPrim) {
+      double v = 0;
+      for (int u = 0; u < kPrim; ++u) v += Jy[u][lane] * sm[2 + u];
+      Gr[lane] = v;
     }
     __syncthreads();
     // T1 = Qr J
@@ -622,11 +631,28 @@ __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
       T1[r][k] = v;
     }
     __syncthreads();
-    // H += J^T T1;  g += J^T Gr
+    // H += J^T T1 + sum_r Gr[r] d2r/dtheta2;  g += J^T Gr
     for (int idx = lane; idx < kN * kN; idx += 64) {
       const int i = idx / kN, k = idx % kN;
       double v = 0;
       for (int r = 0; r < kPrim; ++r) v += J[r][i] * T1[r][k];
+      if (i == k) {
+        if (i == 2) v += Gr[0] * aa * (1.0 - aa) * (1.0 - 2.0 * aa);
+        if (i == 5 || i == 6) v += Gr[2 + 2 * (i - 5)] * rv[i - 5];
+        if (i >= 15 && i < 23) {
+          const int ii = (i - 15) / 4, c = (i - 15) % 4;
+          const double W = c_W[im.band][c];
+          v += Gr[2 + 2 * ii] * W * W * cvv[ii][c];
+        }
+        if (i == 25) v += Gr[10] * pi * (1.0 - pi) * (1.0 - 2.0 * pi);
+      }
+      const int ti = i == 23 ? 0 : i == 24 ? 1 : i == 26 ? 2 : -1;
+      const int tk = k == 23 ? 0 : k == 24 ? 1 : k == 26 ? 2 : -1;
+      if (ti >= 0 && tk >= 0) {
+        double sv[3];
+        conj_A(im.A, sd2[ti][tk], sv);
+        v += Gr[7] * sv[0] + Gr[8] * sv[1] + Gr[9] * sv[2];
+      }
       Hs[i][k] += v;
     }
     if (lane < kN) {
@@ -635,47 +661,15 @@ __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
       gs[lane] += v;
     }
     __syncthreads();
-    if (lane == 0) {
-      // second derivatives of r in theta: a, v_i, S, pi
-      Hs[2][2] += Gr[0] * aa * (1.0 - aa) * (1.0 - 2.0 * aa);
-      for (int i = 0; i < 2; ++i) {
-        const int iv = 2 + 2 * i;
-        Hs[5 + i][5 + i] += Gr[iv] * rv[i];
-        for (int c = 0; c < 4; ++c) {
-          const double W = c_W[im.band][c];
-          Hs[15 + 4 * i + c][15 + 4 * i + c] += Gr[iv] * W * W * cvv[i][c];
-        }
-      }
-      const int tix[3] = {23, 24, 26};
-      for (int t = 0; t < 3; ++t)
-        for (int t2 = 0; t2 < 3; ++t2) {
-          double sv[3];
-          conj_A(im.A, sd2[t][t2], sv);
-          Hs[tix[t]][tix[t2]] += Gr[7] * sv[0] + Gr[8] * sv[1] + Gr[9] * sv[2];
-        }
-      Hs[25][25] += Gr[10] * pi * (1.0 - pi) * (1.0 - 2.0 * pi);
-    }
-    __syncthreads();
   }
   // KL: value, gradient and (optionally) Hessian
+  __shared__ double klv;
   if (lane == 0) {
-    double gk[kThetaN];
-#pragma unroll
-    for (int k = 0; k < kThetaN; ++k) gk[k] = 0.0;
-    const double kl = kl_source(*a.prior, th, gk, 1.0);   // gk = -grad KL
-    local -= kl;
-    if (a.local) a.local[s] = local;
-    for (int k = 0; k < kN; ++k) gs[k] += gk[k];
-    if (a.with_kl) {
-      // Hs currently holds +H_pixels; kl_hessian_add adds +H_KL: negate around it
-      for (int i = 0; i < kN; ++i)
-        for (int k = 0; k < kN; ++k) Hs[i][k] = -Hs[i][k];
-      kl_hessian_add(*a.prior, th, Hs);
-      for (int i = 0; i < kN; ++i)
-        for (int k = 0; k < kN; ++k) Hs[i][k] = -Hs[i][k];
-    }
+    klv = kl_source(*a.prior, th, gs, 1.0);   // subtracts grad KL from gs
+    if (a.with_kl) kl_hessian_add<kLd>(*a.prior, th, Hs, -1.0);
   }
   __syncthreads();
+  if (lane == 0 && a.local) a.local[s] = local - klv;
   if (a.grad && lane < kThetaN) a.grad[(int64_t)s * kThetaN + lane] = lane < kN ? gs[lane] : 0.0;
   for (int idx = lane; idx < kN * kN; idx += 64)
     a.hess[(int64_t)s * kN * kN + idx] = Hs[idx / kN][idx % kN];
@@ -702,30 +696,60 @@ struct TrArgs {
   const double* hess;         // analytic pixel Hessians [S][27][27] (null: central differences)
 };
 
+constexpr int kJ = kN + 1;   // Jacobi dimension: the 27 parameters and one decoupled index
+constexpr int kJP = kJ / 2;    // rotations per round
+
+// Round-robin (circle) schedule of parallel Jacobi: in round r (0..26) indices 0..26 on a
+// circle pair up as (r + m, r - m) mod 27, m = 1..13, and index r meets the spare index 27.
+// Every unordered pair meets exactly once per sweep of 27 rounds.
+__device__ __forceinline__ void rr_pair(int r, int m, int& p, int& q) {
+  if (m == 0) {
+    p = r;
+    q = kN;
+  } else {
+    const int u = (r + m) % kN, v = (r - m + kN) % kN;
+    p = min(u, v);
+    q = max(u, v);
+  }
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
   const int s = a.job_src ? a.job_src[blockIdx.x] : (int)blockIdx.x;
   if (a.active && !a.active[s]) {
     if (threadIdx.x == 0) a.trial_active[s] = 0;
     return;
   }
-  __shared__ double B[kN][kLd];
-  __shared__ double V[kN][kLd];
-  __shared__ double g[kN], lam[kN], y[kN], gt[kN];
-  __shared__ int ok_flag;
-  __shared__ double red[64];
+  __shared__ double B[kJ][kJ + 1];
+  __shared__ double V[kN][kJ + 1];
+  __shared__ double g[kN], lam[kN], y[kN], gt[kN], th[kN];
+  __shared__ double rc[kJP], rs[kJP];
+  __shared__ int rp[kJP], rq[kJP];
   const int lane = threadIdx.x;
   const int64_t vs = (int64_t)a.S * kThetaN;
   const double h2 = 2.0 * a.fd_step;
   const double L = a.v_local[s];
-  for (int idx = lane; idx < kN * kN; idx += 64) {
-    const int i = idx / kN, k = idx % kN;
-    const double hik = a.hess ? a.hess[(int64_t)s * kN * kN + idx]
-                              : (a.v_grad[(int64_t)(1 + k) * vs + (int64_t)s * kThetaN + i] -
-                                 a.v_grad[(int64_t)(1 + kN + k) * vs + (int64_t)s * kThetaN + i]) / h2;
-    B[i][k] = -hik;
-    V[i][k] = (i == k) ? 1.0 : 0.0;
+  // B = -H_pixels (exact, or central differences of the pixel gradient), padded with a
+  // zero row and column; V = I
+  for (int idx = lane; idx < kJ * kJ; idx += 64) {
+    const int i = idx / kJ, k = idx % kJ;
+    double b = 0.0;
+    if (i < kN && k < kN)
+      b = -(a.hess ? a.hess[(int64_t)s * kN * kN + i * kN + k]
+                   : (a.v_grad[(int64_t)(1 + k) * vs + (int64_t)s * kThetaN + i] -
+                      a.v_grad[(int64_t)(1 + kN + k) * vs + (int64_t)s * kThetaN + i]) / h2);
+    B[i][k] = b;
+    if (i < kN) V[i][k] = (i == k) ? 1.0 : 0.0;
   }
-  if (lane < kN) g[lane] = a.v_grad[(int64_t)s * kThetaN + lane];
+  if (lane < kN) {
+    g[lane] = a.v_grad[(int64_t)s * kThetaN + lane];
+    th[lane] = a.theta[(int64_t)s * kThetaN + lane];
+  }
   __syncthreads();
   // symmetrise: each unordered pair handled by one thread
   for (int idx = lane; idx < kN * kN; idx += 64) {
@@ -737,36 +761,21 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
     }
   }
   __syncthreads();
-  // B = -H = -(H_pixels - H_KL): the pixel part by central differences (above), the KL part
-  // analytically
-  if (lane == 0) {
-    double th[kN];
-    for (int k = 0; k < kN; ++k) th[k] = a.theta[(int64_t)s * kThetaN + k];
-    kl_hessian_add(*a.prior, th, B);
-  }
+  // B = -(H_pixels - H_KL): the KL part analytically
+  if (lane == 0) kl_hessian_add<kJ + 1>(*a.prior, th, B, 1.0);
   __syncthreads();
-  // finiteness and the gradient test
-  double gm = 0.0;
-  bool fin = true;
-  for (int idx = lane; idx < kN * kN; idx += 64) fin = fin && isfinite(B[idx / kN][idx % kN]);
+  // finiteness and the gradient test (wave reductions: every lane holds the same result)
+  double bad = 0.0, gm = 0.0;
+  for (int idx = lane; idx < kN * kN; idx += 64)
+    if (!isfinite(B[idx / kN][idx % kN])) bad = 1.0;
   if (lane < kN) {
-    fin = fin && isfinite(g[lane]);
+    if (!isfinite(g[lane])) bad = 1.0;
     gm = fabs(g[lane]);
   }
-  if (lane == 0) ok_flag = 1;
-  __syncthreads();
-  if (!fin) ok_flag = 0;
-  red[lane] = gm;
-  __syncthreads();
-  if (lane == 0) {
-    double m = 0;
-    for (int i = 0; i < 64; ++i) m = fmax(m, red[i]);
-    red[0] = m;
-  }
-  __syncthreads();
-  const double gmax = red[0];
+  bad = wave_max(bad);
+  const double gmax = wave_max(gm);
   const double radius = a.radius[s];
-  if (!ok_flag || !isfinite(L) || !isfinite(radius)) {
+  if (bad != 0.0 || !isfinite(L) || !isfinite(radius)) {
     if (lane == 0) {
       a.status[s] = CEL_ST_NONFINITE;
       a.trial_active[s] = 0;
@@ -780,7 +789,8 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
     }
     return;
   }
-  // cyclic Jacobi: B <- J^T B J, V <- V J (Golub & Van Loan, symmetric Schur 2x2 rotations)
+  // parallel cyclic Jacobi: per round, 14 disjoint symmetric Schur rotations J (Golub & Van
+  // Loan) applied at once, B <- J^T B J, V <- V J
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int idx = lane; idx < kN * kN; idx += 64) {
@@ -789,168 +799,127 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
       tot += v;
       if (i != k) off += v;
     }
-    red[lane] = off;
-    __syncthreads();
-    if (lane == 0) {
-      double o = 0;
-      for (int i = 0; i < 64; ++i) o += red[i];
-      red[0] = o;
-    }
-    __syncthreads();
-    const double offs = red[0];
-    __syncthreads();
-    red[lane] = tot;
-    __syncthreads();
-    if (lane == 0) {
-      double o = 0;
-      for (int i = 0; i < 64; ++i) o += red[i];
-      red[0] = o;
-    }
-    __syncthreads();
-    const double tots = red[0];
-    __syncthreads();
-    if (!(offs > 1e-30 * tots) || offs == 0.0) break;
-    for (int p = 0; p < kN - 1; ++p) {
-      for (int q = p + 1; q < kN; ++q) {
+    off = wave_sum<double>(off);
+    tot = wave_sum<double>(tot);
+    if (!(off > 1e-30 * tot) || off == 0.0) break;
+    for (int r = 0; r < kN; ++r) {
+      if (lane < kJP) {
+        int p, q;
+        rr_pair(r, lane, p, q);
         const double apq = B[p][q];
-        if (apq == 0.0) continue;
-        const double app = B[p][p], aqq = B[q][q];
-        const double tau = (aqq - app) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
-        double bip = 0, biq = 0;
-        if (lane < kN) {
-          bip = B[lane][p];
-          biq = B[lane][q];
+        double c = 1.0, sn = 0.0;
+        if (apq != 0.0) {
+          const double tau = (B[q][q] - B[p][p]) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = t * c;
         }
-        __syncthreads();
-        if (lane < kN) {
-          B[lane][p] = c * bip - sn * biq;
-          B[lane][q] = sn * bip + c * biq;
-        }
-        __syncthreads();
-        double bpi = 0, bqi = 0, vip = 0, viq = 0;
-        if (lane < kN) {
-          bpi = B[p][lane];
-          bqi = B[q][lane];
-          vip = V[lane][p];
-          viq = V[lane][q];
-        }
-        __syncthreads();
-        if (lane < kN) {
-          B[p][lane] = c * bpi - sn * bqi;
-          B[q][lane] = sn * bpi + c * bqi;
-          V[lane][p] = c * vip - sn * viq;
-          V[lane][q] = sn * vip + c * viq;
-        }
-        __syncthreads();
+        rc[lane] = c;
+        rs[lane] = sn;
+        rp[lane] = p;
+        rq[lane] = q;
       }
+      __syncthreads();
+      for (int t = lane; t < kJ * kJP; t += 64) {   // columns: B <- B J, V <- V J
+        const int i = t / kJP, m = t % kJP;
+        const int p = rp[m], q = rq[m];
+        const double c = rc[m], sn = rs[m];
+        const double bp = B[i][p], bq = B[i][q];
+        B[i][p] = c * bp - sn * bq;
+        B[i][q] = sn * bp + c * bq;
+        if (i < kN) {
+          const double vp = V[i][p], vq = V[i][q];
+          V[i][p] = c * vp - sn * vq;
+          V[i][q] = sn * vp + c * vq;
+        }
+      }
+      __syncthreads();
+      for (int t = lane; t < kJ * kJP; t += 64) {   // rows: B <- J^T B
+        const int k = t / kJP, m = t % kJP;
+        const int p = rp[m], q = rq[m];
+        const double c = rc[m], sn = rs[m];
+        const double bp = B[p][k], bq = B[q][k];
+        B[p][k] = c * bp - sn * bq;
+        B[q][k] = sn * bp + c * bq;
+      }
+      __syncthreads();
     }
   }
-  if (lane < kN) lam[lane] = B[lane][lane];
-  __syncthreads();
-  // gt = V^T g (stored in y temporarily)
   if (lane < kN) {
-    double acc = 0;
+    lam[lane] = B[lane][lane];
+    double acc = 0;   // gt = V^T g
     for (int i = 0; i < kN; ++i) acc += V[i][lane] * g[i];
-    y[lane] = acc;
+    gt[lane] = acc;
   }
   __syncthreads();
-  if (lane < kN) gt[lane] = y[lane];
-  __syncthreads();
-  if (lane == 0) {
-    double gnorm = 0;
-    for (int i = 0; i < kN; ++i) gnorm += g[i] * g[i];
-    gnorm = sqrt(gnorm);
-    double lmin = lam[0];
-    int imin = 0;
+  // the trust-region subproblem in the eigenbasis; scalar logic runs identically on every
+  // lane, sums over the 27 eigenvalues are wave reductions
+  const bool own = lane < kN;
+  const double lam_l = own ? lam[lane] : 0.0, gt_l = own ? gt[lane] : 0.0;
+  const double gnorm = sqrt(wave_sum<double>(own ? g[lane] * g[lane] : 0.0));
+  double lmin = lam[0];
+  int imin = 0;
+  for (int i = 1; i < kN; ++i)
+    if (lam[i] < lmin) {
+      lmin = lam[i];
+      imin = i;
+    }
+  auto norm_p = [&](double l) {
+    const double v = own ? gt_l / (lam_l + l) : 0.0;
+    return sqrt(wave_sum<double>(v * v));
+  };
+  const bool low_l = own && fabs(lam_l - lmin) <= 1e-12 * fmax(1.0, fabs(lmin));
+  double lamb = -1.0;   // chosen multiplier (< 0: not yet found)
+  bool hard = false;
+  if (lmin > 0 && norm_p(0.0) <= radius) lamb = 0.0;
+  const double lo = fmax(0.0, -lmin);
+  double tau_hard = 0.0;
+  if (lamb < 0) {
+    const double notorth = wave_max((low_l && fabs(gt_l) > 1e-12 * fmax(gnorm, 1e-300)) ? 1.0 : 0.0);
+    if (notorth == 0.0) {
+      const double v = (own && !low_l) ? gt_l / (lam_l + lo) : 0.0;
+      const double nr = wave_sum<double>(v * v);
+      if (sqrt(nr) <= radius) {
+        hard = true;
+        lamb = lo;
+        tau_hard = sqrt(fmax(radius * radius - nr, 0.0));
+      }
+    }
+  }
+  if (lamb < 0) {
+    double hi = lo + gnorm / radius + 1.0;
+    while (norm_p(hi) > radius) hi = lo + 2.0 * (hi - lo);
+    double aa = lo, bb = hi;
+    for (int it = 0; it < 400; ++it) {
+      const double mid = 0.5 * (aa + bb);
+      if (mid == aa || mid == bb) break;
+      if (norm_p(mid) > radius) aa = mid;
+      else bb = mid;
+    }
+    lamb = bb;
+  }
+  // step in the eigenbasis (hard case: completed along the lowest eigenvector, oriented so
+  // that its largest-magnitude entry is positive), predicted gain and norm
+  double yl = 0.0;
+  if (own) yl = (hard && low_l) ? 0.0 : gt_l / (lam_l + lamb);
+  if (hard && lane == imin) {
+    int am = 0;
     for (int i = 1; i < kN; ++i)
-      if (lam[i] < lmin) {
-        lmin = lam[i];
-        imin = i;
-      }
-    double lamb = -1.0;   // chosen multiplier (< 0: not yet found)
-    bool hard = false;
-    if (lmin > 0) {
-      double nn = 0;
-      for (int i = 0; i < kN; ++i) nn += (gt[i] / lam[i]) * (gt[i] / lam[i]);
-      if (sqrt(nn) <= radius) lamb = 0.0;
-    }
-    const double lo = fmax(0.0, -lmin);
-    double tau_hard = 0.0;
-    if (lamb < 0) {
-      bool orth = true;
-      for (int i = 0; i < kN; ++i)
-        if (fabs(lam[i] - lmin) <= 1e-12 * fmax(1.0, fabs(lmin)) && fabs(gt[i]) > 1e-12 * fmax(gnorm, 1e-300))
-          orth = false;
-      if (orth) {
-        double nr = 0;
-        for (int i = 0; i < kN; ++i)
-          if (!(fabs(lam[i] - lmin) <= 1e-12 * fmax(1.0, fabs(lmin)))) {
-            const double v = gt[i] / (lam[i] + lo);
-            nr += v * v;
-          }
-        if (sqrt(nr) <= radius) {
-          hard = true;
-          lamb = lo;
-          tau_hard = sqrt(fmax(radius * radius - nr, 0.0));
-        }
-      }
-    }
-    if (lamb < 0) {
-      auto norm_p = [&](double l) {
-        double nn = 0;
-        for (int i = 0; i < kN; ++i) {
-          const double v = gt[i] / (lam[i] + l);
-          nn += v * v;
-        }
-        return sqrt(nn);
-      };
-      double hi = lo + gnorm / radius + 1.0;
-      while (norm_p(hi) > radius) hi = lo + 2.0 * (hi - lo);
-      double aa = lo, bb = hi;
-      for (int it = 0; it < 400; ++it) {
-        const double mid = 0.5 * (aa + bb);
-        if (mid == aa || mid == bb) break;
-        if (norm_p(mid) > radius) aa = mid;
-        else bb = mid;
-      }
-      lamb = bb;
-    }
-    // step in the eigenbasis, predicted gain and norm
-    double gp = 0, pBp = 0, nn = 0;
-    for (int i = 0; i < kN; ++i) {
-      double yi;
-      if (hard && fabs(lam[i] - lmin) <= 1e-12 * fmax(1.0, fabs(lmin))) yi = 0.0;
-      else yi = gt[i] / (lam[i] + lamb);
-      y[i] = yi;
-    }
-    if (hard) {
-      // orient the lowest eigenvector so its largest-magnitude entry is positive
-      int am = 0;
-      for (int i = 1; i < kN; ++i)
-        if (fabs(V[i][imin]) > fabs(V[am][imin])) am = i;
-      y[imin] = V[am][imin] < 0 ? -tau_hard : tau_hard;
-    }
-    for (int i = 0; i < kN; ++i) {
-      gp += gt[i] * y[i];
-      pBp += lam[i] * y[i] * y[i];
-      nn += y[i] * y[i];
-    }
-    const double pr = gp - 0.5 * pBp;
+      if (fabs(V[i][imin]) > fabs(V[am][imin])) am = i;
+    yl = V[am][imin] < 0 ? -tau_hard : tau_hard;
+  }
+  const double gp = wave_sum<double>(gt_l * yl), pBp = wave_sum<double>(lam_l * yl * yl), nn = wave_sum<double>(yl * yl);
+  if (own) y[lane] = yl;
+  const double pr = gp - 0.5 * pBp;
+  const bool go = pr > a.ftol * fmax(1.0, fabs(L));
+  if (lane == 0) {
     a.pred[s] = pr;
     a.pnorm[s] = sqrt(nn);
-    if (!(pr > a.ftol * fmax(1.0, fabs(L)))) {
-      a.status[s] = CEL_ST_CONVERGED;
-      a.trial_active[s] = 0;
-      ok_flag = 0;
-    } else {
-      a.trial_active[s] = 1;
-      ok_flag = 1;
-    }
+    if (!go) a.status[s] = CEL_ST_CONVERGED;
+    a.trial_active[s] = go ? 1 : 0;
   }
   __syncthreads();
-  if (!ok_flag) return;
+  if (!go) return;
   if (lane < kThetaN) {
     double v = a.theta[(int64_t)s * kThetaN + lane];
     if (lane < kN) {
