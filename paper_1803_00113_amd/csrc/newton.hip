@@ -19,6 +19,7 @@
 // gain <= ftol max(1, |L_s|), or radius < radius_min.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -40,89 +41,104 @@ constexpr int kLd = kN + 1;   // padded LDS row
 // KL, the normal KL of log r, the colour bound -log sum_j w_j exp(-D_j), and minus the log
 // prior densities of the radius, profile and axis point masses), times sc, added into B
 // (27 rows of stride LD).
-// KL = KL_a(eta) + KL_radius + KL_profile + KL_axis + (1 - a) K_0 + a K_1.
+// KL = KL_a(eta) + KL_radius + KL_profile + KL_axis + (1 - a) K_0 + a K_1; every loop
+// over parameters is unrolled so that all work arrays stay in registers.
 template <int LD>
 __device__ void kl_hessian_add(const DPrior& pr, const double* th, double (*B)[LD], double sc) {
   const double eta = th[2], a = sigmoid(eta);
   const double aa = a * (1.0 - a);
-  double K[2], dK[2][kN];
+  double K[2];
+#pragma unroll
   for (int i = 0; i < 2; ++i) {
-    for (int k = 0; k < kN; ++k) dK[i][k] = 0.0;
     const double rm = th[3 + i], lrv = th[5 + i], rv = exp(lrv);
     const double R1 = pr.r[i][0], R2 = pr.r[i][1];
     const double q = i == 0 ? 1.0 - a : a;
+    const double sg = i == 0 ? -aa : aa;   // d^2 KL / d eta d theta_k = sg dK_i/dtheta_k
     K[i] = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
-    dK[i][3 + i] = (rm - R1) / R2;
-    dK[i][5 + i] = -0.5 + rv / (2.0 * R2);
+    const double dm = (rm - R1) / R2, dv = -0.5 + rv / (2.0 * R2);
     B[3 + i][3 + i] += sc * (q / R2);
     B[5 + i][5 + i] += sc * (q * rv / (2.0 * R2));
-    // colour bound
+    B[2][3 + i] += sc * (sg * dm);
+    B[3 + i][2] += sc * (sg * dm);
+    B[2][5 + i] += sc * (sg * dv);
+    B[5 + i][2] += sc * (sg * dv);
+    // colour bound F = -log sum_j w_j exp(-D_j) in the 8 variables (means, log variances):
+    // grad F = sum_j xi_j dD_j;  hess F = sum_j xi_j (d2D_j - dD_j dD_j^T) + gradF gradF^T
     double cm[4], cv[4], lcv = 0;
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
       cm[k] = th[7 + 4 * i + k];
       cv[k] = exp(th[15 + 4 * i + k]);
       lcv += th[15 + 4 * i + k];
     }
-    double D[CEL_N_COLOUR_COMPONENTS], mx = -1e300;
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+    // D_j recomputed in each pass: keeps the component loops rolled and the 8x8 block in
+    // registers
+    auto Dj = [&](int j) {
       double tr = 0, maha = 0;
+#pragma unroll
       for (int k = 0; k < 4; ++k) {
         tr += pr.c_prec[i][j][k][k] * cv[k];
         double row = 0;
+#pragma unroll
         for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
         maha += (pr.c_mean[i][j][k] - cm[k]) * row;
       }
-      D[j] = 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - lcv);
-      mx = fmax(mx, pr.c_logw[i][j] - D[j]);
-    }
+      return 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - lcv);
+    };
+    double mx = -1e300;
+#pragma unroll 1
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) mx = fmax(mx, pr.c_logw[i][j] - Dj(j));
     double z = 0;
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - D[j] - mx);
+#pragma unroll 1
+    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - Dj(j) - mx);
     K[i] += -(mx + log(z));
-    // grad F = sum xi dD;  hess F = sum xi (d2D - dD dD^T) + gradF gradF^T  (8 variables)
-    double gF[8] = {0, 0, 0, 0, 0, 0, 0, 0}, hF[8][8];
-    for (int u = 0; u < 8; ++u)
+    double gF[8], hF[8][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      gF[u] = 0.0;
+#pragma unroll
       for (int w = 0; w < 8; ++w) hF[u][w] = 0.0;
+    }
+#pragma unroll 1
     for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
-      const double xi = exp(pr.c_logw[i][j] - D[j] - mx) / z;
-      if (xi == 0.0) continue;
+      const double xi = exp(pr.c_logw[i][j] - Dj(j) - mx) / z;
       double dD[8];
+#pragma unroll
       for (int k = 0; k < 4; ++k) {
         double row = 0;
+#pragma unroll
         for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
         dD[k] = row;
         dD[4 + k] = 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
       }
+#pragma unroll
       for (int u = 0; u < 8; ++u) {
         gF[u] += xi * dD[u];
+#pragma unroll
         for (int w = 0; w < 8; ++w) hF[u][w] -= xi * dD[u] * dD[w];
       }
+#pragma unroll
       for (int k = 0; k < 4; ++k) {
+#pragma unroll
         for (int l = 0; l < 4; ++l) hF[k][l] += xi * pr.c_prec[i][j][k][l];
         hF[4 + k][4 + k] += xi * 0.5 * pr.c_prec[i][j][k][k] * cv[k];
       }
     }
-    for (int u = 0; u < 8; ++u)
-      for (int w = 0; w < 8; ++w) hF[u][w] += gF[u] * gF[w];
-    int idx[8];
-    for (int k = 0; k < 4; ++k) {
-      idx[k] = 7 + 4 * i + k;
-      idx[4 + k] = 15 + 4 * i + k;
-    }
+#pragma unroll
     for (int u = 0; u < 8; ++u) {
-      dK[i][idx[u]] += gF[u];
-      for (int w = 0; w < 8; ++w) B[idx[u]][idx[w]] += sc * (q * hF[u][w]);
+      const int iu = u < 4 ? 7 + 4 * i + u : 15 + 4 * i + (u - 4);
+      B[2][iu] += sc * (sg * gF[u]);
+      B[iu][2] += sc * (sg * gF[u]);
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        const int iw = w < 4 ? 7 + 4 * i + w : 15 + 4 * i + (w - 4);
+        B[iu][iw] += sc * (q * (hF[u][w] + gF[u] * gF[w]));
+      }
     }
   }
   // type weight: dKL/deta = a(1-a) [eta - logit A + K1 - K0]
   const double t = eta - pr.logit_a + K[1] - K[0];
   B[2][2] += sc * (aa * (1.0 - 2.0 * a) * t + aa);
-  for (int k = 0; k < kN; ++k) {
-    const double c = aa * (dK[1][k] - dK[0][k]);
-    if (c != 0.0 && k != 2) {
-      B[2][k] += sc * (c);
-      B[k][2] += sc * (c);
-    }
-  }
   // point masses
   B[24][24] += sc * (1.0 / pr.radius[1]);
   {
@@ -678,11 +694,10 @@ __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
 struct TrArgs {
   const int32_t* job_src;     // sources of this launch
   int32_t n_jobs;
-  int32_t S;
   const uint8_t* active;
-  const double* v_grad;       // [variants][S][32]
-  const double* v_local;      // [variants][S]
-  double fd_step;
+  const double* v_grad;       // gradient at the iterate [S][32]
+  const double* v_local;      // L_s at the iterate [S]
+  const double* hess;         // Hessian of L_s [S][27][27]
   const double* theta;
   const double* radius;
   const double* npix;         // active pixels per source
@@ -692,26 +707,46 @@ struct TrArgs {
   double* pred;               // out: predicted gain
   double* pnorm;              // out: |p|
   int32_t* status;            // out: CONVERGED / NONFINITE for sources not tried
-  const DPrior* prior;
-  const double* hess;         // analytic pixel Hessians [S][27][27] (null: central differences)
 };
 
-constexpr int kJ = kN + 1;   // Jacobi dimension: the 27 parameters and one decoupled index
-constexpr int kJP = kJ / 2;    // rotations per round
+// Hessian of L_s from central differences of the pixel gradient (variants 1..54 hold the
+// gradients at theta_s +/- h e_k), symmetrised, minus the analytic KL Hessian (the tight
+// colour-prior mixture makes the KL's higher derivatives too large for differencing).
+struct FdHessArgs {
+  const int32_t* job_src;
+  int32_t n_jobs, S;
+  const uint8_t* active;
+  const double* v_grad;       // [variants][S][32]
+  double fd_step;
+  const double* theta;
+  const DPrior* prior;
+  double* hess;               // out [S][27][27]
+};
 
-// Round-robin (circle) schedule of parallel Jacobi: in round r (0..26) indices 0..26 on a
-// circle pair up as (r + m, r - m) mod 27, m = 1..13, and index r meets the spare index 27.
-// Every unordered pair meets exactly once per sweep of 27 rounds.
-__device__ __forceinline__ void rr_pair(int r, int m, int& p, int& q) {
-  if (m == 0) {
-    p = r;
-    q = kN;
-  } else {
-    const int u = (r + m) % kN, v = (r - m + kN) % kN;
-    p = min(u, v);
-    q = max(u, v);
+__global__ __launch_bounds__(64) void k_fd_hessian(FdHessArgs a) {
+  const int s = a.job_src ? a.job_src[blockIdx.x] : (int)blockIdx.x;
+  if (a.active && !a.active[s]) return;
+  const int lane = threadIdx.x;
+  __shared__ double H[kN][kLd];
+  __shared__ double th[kN];
+  const int64_t vs = (int64_t)a.S * kThetaN;
+  const double h2 = 2.0 * a.fd_step;
+  for (int idx = lane; idx < kN * kN; idx += 64) {
+    const int i = idx / kN, k = idx % kN;
+    const double hik = (a.v_grad[(int64_t)(1 + k) * vs + (int64_t)s * kThetaN + i] -
+                        a.v_grad[(int64_t)(1 + kN + k) * vs + (int64_t)s * kThetaN + i]) / h2;
+    const double hki = (a.v_grad[(int64_t)(1 + i) * vs + (int64_t)s * kThetaN + k] -
+                        a.v_grad[(int64_t)(1 + kN + i) * vs + (int64_t)s * kThetaN + k]) / h2;
+    H[i][k] = 0.5 * (hik + hki);
   }
+  if (lane < kN) th[lane] = a.theta[(int64_t)s * kThetaN + lane];
+  __syncthreads();
+  if (lane == 0) kl_hessian_add<kLd>(*a.prior, th, H, -1.0);
+  __syncthreads();
+  for (int idx = lane; idx < kN * kN; idx += 64) a.hess[(int64_t)s * kN * kN + idx] = H[idx / kN][idx % kN];
 }
+
+constexpr int kJ = kN + 1;   // Jacobi columns: the 27 parameters and one zero column
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -719,62 +754,48 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Eigen-decomposition for the trust-region subproblem: one-sided (Hestenes) Jacobi on
+// W = B + c I, c = 1.001 |B|_F (positive definite, so its singular vectors are B's
+// eigenvectors and its singular values the shifted eigenvalues).  Lane k holds column k of
+// W in registers; in round r of a sweep the lanes pair up by the round-robin (circle)
+// schedule -- columns (r + m, r - m) mod 27 for m = 1..13, column r with the zero column 27
+// -- exchange columns with one shuffle per entry, and orthogonalise each pair by the
+// rotation that diagonalises its 2x2 Gram block.  Sweeps stop when a whole sweep finds
+// every pair orthogonal to 1e-15; then lambda_k = |w_k| - c and v_k = w_k / |w_k|.
 __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
   const int s = a.job_src ? a.job_src[blockIdx.x] : (int)blockIdx.x;
+  const int tid = threadIdx.x, lane = tid;
   if (a.active && !a.active[s]) {
-    if (threadIdx.x == 0) a.trial_active[s] = 0;
+    if (tid == 0) a.trial_active[s] = 0;
     return;
   }
-  __shared__ double B[kJ][kJ + 1];
-  __shared__ double V[kN][kJ + 1];
-  __shared__ double g[kN], lam[kN], y[kN], gt[kN], th[kN];
-  __shared__ double rc[kJP], rs[kJP];
-  __shared__ int rp[kJP], rq[kJP];
-  const int lane = threadIdx.x;
-  const int64_t vs = (int64_t)a.S * kThetaN;
-  const double h2 = 2.0 * a.fd_step;
+  __shared__ double B[kN][kLd];
+  __shared__ double V[kN][kLd];
+  __shared__ double g[kN], lam[kN], y[kN], gt[kN];
+  __shared__ int verdict;   // 0 continue, 1 non-finite, 2 converged
   const double L = a.v_local[s];
-  // B = -H_pixels (exact, or central differences of the pixel gradient), padded with a
-  // zero row and column; V = I
-  for (int idx = lane; idx < kJ * kJ; idx += 64) {
-    const int i = idx / kJ, k = idx % kJ;
-    double b = 0.0;
-    if (i < kN && k < kN)
-      b = -(a.hess ? a.hess[(int64_t)s * kN * kN + i * kN + k]
-                   : (a.v_grad[(int64_t)(1 + k) * vs + (int64_t)s * kThetaN + i] -
-                      a.v_grad[(int64_t)(1 + kN + k) * vs + (int64_t)s * kThetaN + i]) / h2);
-    B[i][k] = b;
-    if (i < kN) V[i][k] = (i == k) ? 1.0 : 0.0;
-  }
-  if (lane < kN) {
-    g[lane] = a.v_grad[(int64_t)s * kThetaN + lane];
-    th[lane] = a.theta[(int64_t)s * kThetaN + lane];
-  }
-  __syncthreads();
-  // symmetrise: each unordered pair handled by one thread
-  for (int idx = lane; idx < kN * kN; idx += 64) {
+  const double radius = a.radius[s];
+  // B = -H (the Hessian of L_s, pixel and KL parts), symmetrised
+  for (int idx = tid; idx < kN * kN; idx += 64) {
     const int i = idx / kN, k = idx % kN;
-    if (i < k) {
-      const double v = 0.5 * (B[i][k] + B[k][i]);
-      B[i][k] = v;
-      B[k][i] = v;
-    }
+    B[i][k] = -0.5 * (a.hess[(int64_t)s * kN * kN + i * kN + k] + a.hess[(int64_t)s * kN * kN + k * kN + i]);
   }
-  __syncthreads();
-  // B = -(H_pixels - H_KL): the KL part analytically
-  if (lane == 0) kl_hessian_add<kJ + 1>(*a.prior, th, B, 1.0);
+  if (tid < kN) g[tid] = a.v_grad[(int64_t)s * kThetaN + tid];
   __syncthreads();
   // finiteness and the gradient test (wave reductions: every lane holds the same result)
-  double bad = 0.0, gm = 0.0;
-  for (int idx = lane; idx < kN * kN; idx += 64)
-    if (!isfinite(B[idx / kN][idx % kN])) bad = 1.0;
+  double bad = 0.0, gm = 0.0, fro = 0.0;
+  for (int idx = lane; idx < kN * kN; idx += 64) {
+    const double b = B[idx / kN][idx % kN];
+    if (!isfinite(b)) bad = 1.0;
+    fro += b * b;
+  }
   if (lane < kN) {
     if (!isfinite(g[lane])) bad = 1.0;
     gm = fabs(g[lane]);
   }
   bad = wave_max(bad);
   const double gmax = wave_max(gm);
-  const double radius = a.radius[s];
+  fro = wave_sum<double>(fro);
   if (bad != 0.0 || !isfinite(L) || !isfinite(radius)) {
     if (lane == 0) {
       a.status[s] = CEL_ST_NONFINITE;
@@ -789,69 +810,56 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
     }
     return;
   }
-  // parallel cyclic Jacobi: per round, 14 disjoint symmetric Schur rotations J (Golub & Van
-  // Loan) applied at once, B <- J^T B J, V <- V J
+  const double cs = sqrt(fro) * 1.001 + 1e-300;
+  double w[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) w[i] = lane < kN ? B[i][lane] + (i == lane ? cs : 0.0) : 0.0;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int idx = lane; idx < kN * kN; idx += 64) {
-      const int i = idx / kN, k = idx % kN;
-      const double v = B[i][k] * B[i][k];
-      tot += v;
-      if (i != k) off += v;
-    }
-    off = wave_sum<double>(off);
-    tot = wave_sum<double>(tot);
-    if (!(off > 1e-30 * tot) || off == 0.0) break;
+    double rotated = 0.0;
     for (int r = 0; r < kN; ++r) {
-      if (lane < kJP) {
-        int p, q;
-        rr_pair(r, lane, p, q);
-        const double apq = B[p][q];
-        double c = 1.0, sn = 0.0;
-        if (apq != 0.0) {
-          const double tau = (B[q][q] - B[p][p]) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sn = t * c;
-        }
-        rc[lane] = c;
-        rs[lane] = sn;
-        rp[lane] = p;
-        rq[lane] = q;
+      const int pt = lane > kN ? lane : lane == kN ? r : lane == r ? kN : ((2 * r - lane) % kN + kN) % kN;
+      double pw[kN], al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int i = 0; i < kN; ++i) {
+        pw[i] = __shfl(w[i], pt, 64);
+        al = fma(w[i], w[i], al);
+        be = fma(pw[i], pw[i], be);
+        ga = fma(w[i], pw[i], ga);
       }
-      __syncthreads();
-      for (int t = lane; t < kJ * kJP; t += 64) {   // columns: B <- B J, V <- V J
-        const int i = t / kJP, m = t % kJP;
-        const int p = rp[m], q = rq[m];
-        const double c = rc[m], sn = rs[m];
-        const double bp = B[i][p], bq = B[i][q];
-        B[i][p] = c * bp - sn * bq;
-        B[i][q] = sn * bp + c * bq;
-        if (i < kN) {
-          const double vp = V[i][p], vq = V[i][q];
-          V[i][p] = c * vp - sn * vq;
-          V[i][q] = sn * vp + c * vq;
-        }
+      const bool lowside = lane < pt;
+      const double alo = lowside ? al : be, ahi = lowside ? be : al;
+      double c = 1.0, sn = 0.0;
+      if (fabs(ga) > 1e-15 * sqrt(alo * ahi)) {
+        const double zeta = (ahi - alo) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        c = 1.0 / sqrt(1.0 + t * t);
+        sn = c * t;
+        rotated = 1.0;
       }
-      __syncthreads();
-      for (int t = lane; t < kJ * kJP; t += 64) {   // rows: B <- J^T B
-        const int k = t / kJP, m = t % kJP;
-        const int p = rp[m], q = rq[m];
-        const double c = rc[m], sn = rs[m];
-        const double bp = B[p][k], bq = B[q][k];
-        B[p][k] = c * bp - sn * bq;
-        B[q][k] = sn * bp + c * bq;
-      }
-      __syncthreads();
+      const double cp = lowside ? -sn : sn;
+#pragma unroll
+      for (int i = 0; i < kN; ++i) w[i] = fma(c, w[i], cp * pw[i]);
     }
+    if (wave_max(rotated) == 0.0) break;
   }
   if (lane < kN) {
-    lam[lane] = B[lane][lane];
-    double acc = 0;   // gt = V^T g
-    for (int i = 0; i < kN; ++i) acc += V[i][lane] * g[i];
+    double nn = 0.0;
+#pragma unroll
+    for (int i = 0; i < kN; ++i) nn = fma(w[i], w[i], nn);
+    const double sig = sqrt(nn), inv = 1.0 / sig;
+    double acc = 0.0;   // gt = V^T g
+#pragma unroll
+    for (int i = 0; i < kN; ++i) {
+      const double v = w[i] * inv;
+      V[i][lane] = v;
+      acc = fma(v, g[i], acc);
+    }
+    lam[lane] = sig - cs;
     gt[lane] = acc;
   }
   __syncthreads();
+  bool go = false;
+  {
   // the trust-region subproblem in the eigenbasis; scalar logic runs identically on every
   // lane, sums over the 27 eigenvalues are wave reductions
   const bool own = lane < kN;
@@ -864,44 +872,62 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
       lmin = lam[i];
       imin = i;
     }
-  auto norm_p = [&](double l) {
-    const double v = own ? gt_l / (lam_l + l) : 0.0;
+  const bool low_l = own && fabs(lam_l - lmin) <= 1e-12 * fmax(1.0, fabs(lmin));
+  // shifted eigenvalues d_i = lam_i + lo >= 0 (exact zero at the lowest): the multiplier is
+  // lo + mu, and |p|^2 = sum gt_i^2 / (d_i + mu)^2 keeps its precision near the pole
+  const double lo = fmax(0.0, -lmin);
+  const double dl = own ? lam_l + lo : 0.0;
+  auto norm_mu = [&](double m) {
+    const double v = own ? gt_l / (dl + m) : 0.0;
     return sqrt(wave_sum<double>(v * v));
   };
-  const bool low_l = own && fabs(lam_l - lmin) <= 1e-12 * fmax(1.0, fabs(lmin));
-  double lamb = -1.0;   // chosen multiplier (< 0: not yet found)
+  double mu = -1.0;   // chosen shifted multiplier (< 0: not yet found)
   bool hard = false;
-  if (lmin > 0 && norm_p(0.0) <= radius) lamb = 0.0;
-  const double lo = fmax(0.0, -lmin);
+  if (lmin > 0 && norm_mu(0.0) <= radius) mu = 0.0;
   double tau_hard = 0.0;
-  if (lamb < 0) {
+  if (mu < 0) {
     const double notorth = wave_max((low_l && fabs(gt_l) > 1e-12 * fmax(gnorm, 1e-300)) ? 1.0 : 0.0);
     if (notorth == 0.0) {
-      const double v = (own && !low_l) ? gt_l / (lam_l + lo) : 0.0;
+      const double v = (own && !low_l) ? gt_l / dl : 0.0;
       const double nr = wave_sum<double>(v * v);
       if (sqrt(nr) <= radius) {
         hard = true;
-        lamb = lo;
+        mu = 0.0;
         tau_hard = sqrt(fmax(radius * radius - nr, 0.0));
       }
     }
   }
-  if (lamb < 0) {
-    double hi = lo + gnorm / radius + 1.0;
-    while (norm_p(hi) > radius) hi = lo + 2.0 * (hi - lo);
-    double aa = lo, bb = hi;
-    for (int it = 0; it < 400; ++it) {
-      const double mid = 0.5 * (aa + bb);
-      if (mid == aa || mid == bb) break;
-      if (norm_p(mid) > radius) aa = mid;
-      else bb = mid;
+  if (mu < 0) {
+    // boundary multiplier: |p| = radius for mu in (0, inf).  Safeguarded Newton on
+    // 1/radius - 1/|p|, convex and decreasing in mu (Nocedal & Wright, Algorithm 4.3, in
+    // the eigenbasis: |q|^2 = sum gt_i^2 / (d_i + mu)^3), inside a bracket [aa, bb] with
+    // |p(aa)| > radius >= |p(bb)|, bisecting when a step leaves it; 4-13 steps to
+    // |p| = radius (1 + O(eps)).
+    double hi = gnorm / radius + 1.0;
+    while (norm_mu(hi) > radius) hi *= 2.0;
+    double aa = 0.0, bb = hi;
+    const double glow = wave_max(low_l ? fabs(gt_l) : 0.0);
+    double mc = lmin > 0 ? 0.0 : 0.5 * glow / radius;   // left of the root
+    if (!(mc >= aa && mc < bb) || (lmin <= 0 && !(mc > 0.0))) mc = 0.5 * (aa + bb);
+    for (int it = 0; it < 200 && mu < 0; ++it) {
+      const double v = own ? 1.0 / (dl + mc) : 0.0;
+      const double pv = gt_l * v;
+      const double s1 = wave_sum<double>(pv * pv), s2 = wave_sum<double>(pv * pv * v);
+      const double np = sqrt(s1);
+      if (np > radius) aa = mc;
+      else bb = mc;
+      double nx = mc + (s1 / s2) * (np - radius) / radius;
+      if (!(nx > aa && nx < bb)) nx = 0.5 * (aa + bb);
+      if (fabs(np - radius) <= 4.0 * DBL_EPSILON * radius || nx == mc) mu = mc;   // converged
+      else if (bb - aa <= 4.0 * DBL_EPSILON * bb) mu = bb;                        // bracket closed
+      mc = nx;
     }
-    lamb = bb;
+    if (mu < 0) mu = bb;
   }
   // step in the eigenbasis (hard case: completed along the lowest eigenvector, oriented so
   // that its largest-magnitude entry is positive), predicted gain and norm
   double yl = 0.0;
-  if (own) yl = (hard && low_l) ? 0.0 : gt_l / (lam_l + lamb);
+  if (own) yl = (hard && low_l) ? 0.0 : gt_l / (dl + mu);
   if (hard && lane == imin) {
     int am = 0;
     for (int i = 1; i < kN; ++i)
@@ -911,23 +937,25 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
   const double gp = wave_sum<double>(gt_l * yl), pBp = wave_sum<double>(lam_l * yl * yl), nn = wave_sum<double>(yl * yl);
   if (own) y[lane] = yl;
   const double pr = gp - 0.5 * pBp;
-  const bool go = pr > a.ftol * fmax(1.0, fabs(L));
+  go = pr > a.ftol * fmax(1.0, fabs(L));
   if (lane == 0) {
     a.pred[s] = pr;
     a.pnorm[s] = sqrt(nn);
     if (!go) a.status[s] = CEL_ST_CONVERGED;
     a.trial_active[s] = go ? 1 : 0;
+    verdict = go ? 0 : 2;
+  }
   }
   __syncthreads();
-  if (!go) return;
-  if (lane < kThetaN) {
-    double v = a.theta[(int64_t)s * kThetaN + lane];
-    if (lane < kN) {
+  if (verdict) return;
+  if (tid < kThetaN) {
+    double v = a.theta[(int64_t)s * kThetaN + tid];
+    if (tid < kN) {
       double step = 0;
-      for (int i = 0; i < kN; ++i) step += V[lane][i] * y[i];
+      for (int i = 0; i < kN; ++i) step += V[tid][i] * y[i];
       v += step;
     }
-    a.theta_trial[(int64_t)s * kThetaN + lane] = v;
+    a.theta_trial[(int64_t)s * kThetaN + tid] = v;
   }
 }
 
@@ -1077,25 +1105,39 @@ static hipError_t enqueue_newton_class(cel_plan* p, double* theta, double* radiu
   hipError_t e;
   const bool analytic = !p->opt.hessian_fd;
   if (analytic) {
-    // tables and maps at the iterate, then the exact pixel Hessians with the gradients
+    // tables and maps at the iterate, then the exact Hessians with the gradients
     e = prep_base(p, theta, sm, fp64);
     if (e == hipSuccess)
       e = enqueue_hessian(p, theta, p->d_class_tasks[cls], (int)p->class_tasks[cls].size(), p->d_class_src[cls], nsrc,
-                          active, false, p->v_local, p->v_grad, p->d_hess, sm);
+                          active, true, p->v_local, p->v_grad, p->d_hess, sm);
   } else {
-    // gradients at the iterate and at the 54 central-difference points
+    // gradients at the iterate and at the 54 central-difference points, then the Hessians
     e = eval_any(p, theta, nullptr, 0, 2 * kParamN + 1, true, cls, active, sm, true, fp64);
+    if (e == hipSuccess) {
+      FdHessArgs fa;
+      std::memset(&fa, 0, sizeof(fa));
+      fa.job_src = p->d_class_src[cls];
+      fa.n_jobs = nsrc;
+      fa.S = p->S;
+      fa.active = active;
+      fa.v_grad = p->v_grad;
+      fa.fd_step = p->opt.fd_step;
+      fa.theta = theta;
+      fa.prior = p->d_prior;
+      fa.hess = p->d_hess;
+      hipLaunchKernelGGL(k_fd_hessian, dim3(nsrc), dim3(64), 0, sm, fa);
+      e = hipGetLastError();
+    }
   }
   if (e != hipSuccess) return e;
   TrArgs ta;
   std::memset(&ta, 0, sizeof(ta));
   ta.job_src = p->d_class_src[cls];
   ta.n_jobs = nsrc;
-  ta.S = p->S;
   ta.active = active;
   ta.v_grad = p->v_grad;
   ta.v_local = p->v_local;
-  ta.fd_step = p->opt.fd_step;
+  ta.hess = p->d_hess;
   ta.theta = theta;
   ta.radius = radius;
   ta.npix = p->d_npix;
@@ -1107,8 +1149,6 @@ static hipError_t enqueue_newton_class(cel_plan* p, double* theta, double* radiu
   ta.pred = p->d_pred;
   ta.pnorm = p->d_step_norm;
   ta.status = status;
-  ta.prior = p->d_prior;
-  ta.hess = analytic ? p->d_hess : nullptr;
   hipLaunchKernelGGL(k_trsolve, dim3(nsrc), dim3(64), 0, sm, ta);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // objective at the trial points
