@@ -526,7 +526,7 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
       (st = track_upload(p, &p->d_prof, prof1)) || (st = track_upload(p, &p->d_htau_f, p->htau_fh)) ||
       (st = track_upload(p, &p->d_htau_d, p->htau_dh)) || (st = track_upload(p, &d_user_off, user_off)) ||
       (st = track_upload(p, &d_knots, knots)) || (st = track(p, &p->d_xs, (size_t)std::max<int64_t>(p->n_units, 1))) ||
-      (st = track(p, &p->d_pixconst, (size_t)2 * std::max(P, 1))) || (st = track(p, &p->d_total, 1)) ||
+      (st = track(p, &p->d_pixconst, (size_t)2 * std::max(P, 1))) || (st = track(p, &p->d_skymin, (size_t)std::max(P, 1))) || (st = track(p, &p->d_total, 1)) ||
       (st = ensure_variants(p, 1, p->opt.pixel_fp64 != 0))) {
     plan_release(p);
     return st;
@@ -551,7 +551,7 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
     return st;
   }
   hipError_t e = launch_pixels(p->d_patches, p->d_images, d_knots, pr->pixels, d_user_off, p->d_xs, p->d_xs64, P, sm);
-  if (e == hipSuccess) e = launch_pixconst(p->d_patches, p->d_nbr, p->d_xs, p->d_pixconst, P, sm);
+  if (e == hipSuccess) e = launch_pixconst(p->d_patches, p->d_nbr, p->d_xs, p->d_pixconst, p->d_skymin, P, sm);
   if (e == hipSuccess) e = hipStreamSynchronize(sm);
   if (e != hipSuccess) {
     plan_release(p);
@@ -609,6 +609,7 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   pa.n_patches = p->P;
   pa.trial_variant = p->trial_variant;
   pa.fd = p->fd_mode;
+  pa.sky_min = p->d_skymin;
   phase_mark(p, 0, sm);
   if (prep_base) {   // variant 0 of every source and its moment maps (neighbours read these)
     pa.variant0 = 0;
@@ -699,6 +700,7 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
   pa.n_patches = p->P;
   pa.trial_variant = p->trial_variant;
   pa.fd = p->fd_mode;
+  pa.sky_min = p->d_skymin;
   hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
   if (e == hipSuccess) e = launch_maps_t<T>(p, tables, sm);
   FusedArgs<T> fa;
@@ -765,6 +767,7 @@ static hipError_t prep_base_t(cel_plan* p, const double* theta, hipStream_t sm) 
   pa.n_patches = p->P;
   pa.trial_variant = p->trial_variant;
   pa.fd = p->fd_mode;
+  pa.sky_min = p->d_skymin;
   hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
   if (e == hipSuccess) e = launch_maps_t<T>(p, tables, sm);
   return e;

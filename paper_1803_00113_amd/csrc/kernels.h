@@ -19,6 +19,7 @@ struct PrepArgs {
   const uint8_t* active;       // per source (null = all)
   int32_t trial_variant;       // variant evaluated at theta_trial
   int32_t fd;                  // variants 1..54 are central-difference points
+  const double* sky_min;       // per patch: smallest sky value (component cut)
 };
 
 struct FinalizeArgs {
@@ -57,7 +58,7 @@ hipError_t launch_finalize(const FinalizeArgs& a, int n_variants, hipStream_t st
 hipError_t launch_total(const double* own, int n, double* out, hipStream_t st);
 hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const double* knots, const float* pixels,
                          const int64_t* user_off, float2* xs, double2* xs64, int n_patches, hipStream_t st);
-hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, double* out,
+hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, double* out, double* sky_min,
                            int n_patches, hipStream_t st);
 
 }  // namespace celmi

@@ -69,22 +69,27 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
   const double t10 = a10 * sig[0] + a11 * sig[1], t11 = a10 * sig[1] + a11 * sig[2];
   const double Sxx = t00 * a00 + t01 * a01, Sxy = t00 * a10 + t01 * a11, Syy = t10 * a10 + t11 * a11;
   const int K = im.n_psf;
-  if (lane == 0) {
-    // flux moments given the type (equation conditional): log l ~ N(m, v)
-    const double aa = sigmoid(th[2]);
-    const double w[2] = {1.0 - aa, aa};
-    double L[2], kk[2], ee[2];
-    for (int i = 0; i < 2; ++i) {
-      double m = th[3 + i], var = exp(th[5 + i]);
-      for (int c = 0; c < 4; ++c) {
-        const double W = c_W[im.band][c];
-        m += W * th[7 + 4 * i + c];
-        var += W * W * exp(th[15 + 4 * i + c]);
-      }
-      L[i] = im.iota * exp(m + 0.5 * var);
-      ee[i] = expm1(var);
-      kk[i] = w[i] * L[i] * L[i] * ee[i];
+  // flux moments given the type (equation conditional): log l ~ N(m, v) (every lane: the
+  // component cuts below scale with them)
+  const double aa = sigmoid(th[2]);
+  const double w[2] = {1.0 - aa, aa};
+  double L[2], kk[2], ee[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    double m = th[3 + i], var = exp(th[5 + i]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double W = c_W[im.band][c];
+      m += W * th[7 + 4 * i + c];
+      var += W * W * exp(th[15 + 4 * i + c]);
     }
+    L[i] = im.iota * exp(m + 0.5 * var);
+    ee[i] = expm1(var);
+    kk[i] = w[i] * L[i] * L[i] * ee[i];
+  }
+  const double smin = a.sky_min ? a.sky_min[pi_] : 0.0;
+  const double cut_gal = density_cut_log2<T>(L[0], smin), cut_star = density_cut_log2<T>(L[1], smin);
+  if (lane == 0) {
     tb->hdr[8] = (T)ee[0];
     tb->hdr[9] = (T)ee[1];
     tb->hdr[0] = (T)L[0];
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
         r[4] = (T)(cxx / det);
         const double lw = im.psf[k][0] > 0 ? log2(im.psf[k][0]) - kLog2TwoPi - 0.5 * log2(det) : kNegHuge;
         r[5] = (T)lw;
-        tb->rc2s[k] = (T)cut_radius2(lw, cxx, cxy, cyy);
+        tb->rc2s[k] = (T)cut_radius2(lw, cxx, cxy, cyy, cut_star);
       } else {
         r[0] = r[1] = r[2] = r[3] = r[4] = (T)0;
         r[5] = (T)kNegHuge;
@@ -135,7 +140,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
         r[2] = (T)(cxx / det);
         const double lw = wt > 0 ? log2(wt) - kLog2TwoPi - 0.5 * log2(det) : kNegHuge;
         r[3] = (T)lw;
-        tb->rc2[k][j] = (T)cut_radius2(lw, cxx, cxy, cyy);
+        tb->rc2[k][j] = (T)cut_radius2(lw, cxx, cxy, cyy, cut_gal);
         const double Pxx = cyy / det, Pxy = -cxy / det, Pyy = cxx / det, h = 0.5 * tau * tau;
         T* q = tb->gt[k][j];
         q[0] = (T)tau;
@@ -638,13 +643,15 @@ __global__ __launch_bounds__(256) void k_pixels(const DPatch* __restrict__ patch
 
 // sum over the patch of C(x) = x log x - x - log x! (all pixels, and owned pixels only)
 __global__ __launch_bounds__(256) void k_pixconst(const DPatch* __restrict__ patches, const int32_t* __restrict__ nbr_idx,
-                                                  const float2* __restrict__ xs, double* __restrict__ out) {
-  __shared__ double sh[2][256];
+                                                  const float2* __restrict__ xs, double* __restrict__ out,
+                                                  double* __restrict__ sky_min) {
+  __shared__ double sh[3][256];
   const DPatch P = patches[blockIdx.x];
   const int n = P.w * P.h;
-  double all = 0, own = 0;
+  double all = 0, own = 0, smin = INFINITY;
   for (int i = threadIdx.x; i < n; i += 256) {
     const double x = xs[P.off + i].x;
+    smin = fmin(smin, (double)xs[P.off + i].y);
     const double c = x > 0 ? x * log(x) - x - lgamma(x + 1.0) : 0.0;
     all += c;
     const int col = P.x0 + i % P.w, row = P.y0 + i / P.w;
@@ -657,17 +664,20 @@ __global__ __launch_bounds__(256) void k_pixconst(const DPatch* __restrict__ pat
   }
   sh[0][threadIdx.x] = all;
   sh[1][threadIdx.x] = own;
+  sh[2][threadIdx.x] = smin;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) {
       sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
       sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+      sh[2][threadIdx.x] = fmin(sh[2][threadIdx.x], sh[2][threadIdx.x + w]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     out[2 * blockIdx.x] = sh[0][0];
     out[2 * blockIdx.x + 1] = sh[1][0];
+    sky_min[blockIdx.x] = sh[2][0];
   }
 }
 
@@ -744,10 +754,11 @@ hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const d
   return hipGetLastError();
 }
 
-hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, double* out, int n_patches,
+hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, double* out, double* sky_min,
+                           int n_patches,
                            hipStream_t st) {
   if (n_patches <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pixconst, dim3(n_patches), dim3(256), 0, st, patches, nbr_idx, xs, out);
+  hipLaunchKernelGGL(k_pixconst, dim3(n_patches), dim3(256), 0, st, patches, nbr_idx, xs, out, sky_min);
   return hipGetLastError();
 }
 

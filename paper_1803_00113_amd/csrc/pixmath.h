@@ -20,14 +20,30 @@ template <> __device__ __forceinline__ double flog<double>(double x) { return lo
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLog2TwoPi = 2.6514961294723187980;   // log2(2 pi)
 constexpr double kNegHuge = -1.0e30;
-constexpr double kCutLog2 = -60.0;   // components below 2^-60 over a wavefront's pixels are skipped
+// Component cut (reading of the kernels' truncation): a mixture component is skipped over a
+// wavefront's pixel box when its contribution to the expected count there, flux times
+// density, stays below 2^-kRelCut of the patch's smallest sky value -- far below the
+// resolution of the rate in the kernel's precision (2^-24 in float32, 2^-53 in float64).
+template <typename T>
+constexpr double rel_cut_log2() {
+  return sizeof(T) == 8 ? 60.0 : 30.0;
+}
 
-// squared radius beyond which 2^(lw - log2(e)/2 d^T C^{-1} d) < 2^kCutLog2
-__device__ __forceinline__ double cut_radius2(double lw, double cxx, double cxy, double cyy) {
-  const double room = lw - kCutLog2;
+// squared radius beyond which 2^(lw - log2(e)/2 d^T C^{-1} d) < 2^cut (-1: never above it)
+__device__ __forceinline__ double cut_radius2(double lw, double cxx, double cxy, double cyy, double cut) {
+  const double room = lw - cut;
   if (!(room > 0)) return -1.0;
   const double lmax = 0.5 * (cxx + cyy) + sqrt(0.25 * (cxx - cyy) * (cxx - cyy) + cxy * cxy);
   return room / (0.5 * kLog2e / lmax);
+}
+
+// log2 threshold on a component's density for a source of expected flux L on a patch whose
+// sky is at least sky_min; -inf (keep everything) when either is not a positive finite
+// number, so that non-finite parameters still propagate to the objective
+template <typename T>
+__device__ __forceinline__ double density_cut_log2(double L, double sky_min) {
+  const double c = log2(sky_min) - log2(L) - rel_cut_log2<T>();
+  return (L > 0 && sky_min > 0 && isfinite(c)) ? c : -INFINITY;
 }
 
 // log l_b = log r + W[b] . c,  c_k = ln(l_{k+1} / l_k), reference band r = index 2

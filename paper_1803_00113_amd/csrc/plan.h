@@ -49,6 +49,7 @@ struct cel_plan {
   float2* d_maps = nullptr;     // (E_s, V_s) of each patch's source at the base parameters
   double2* d_maps64 = nullptr;
   double* d_pixconst = nullptr;
+  double* d_skymin = nullptr;     // per patch: smallest sky value
   double* d_total = nullptr;
   std::vector<int32_t*> d_class_patches, d_class_tasks, d_class_src;
   // per-variant scratch
