@@ -171,7 +171,7 @@ def hessian_leg(log, prob, reps=5):
     return out
 
 
-def serve_leg(log, rates=(20.0, 50.0, 100.0, 200.0), n_requests=40, pool=8):
+def serve_leg(log, rates=(20.0, 50.0, 100.0, 200.0), n_requests=200, pool=8):
     """Region requests of 1-200 sources (patch side 16-96, 5 bands) arriving as a Poisson
     process; each request takes 10 Newton rounds.  Arrivals cycle through `pool` generated
     regions."""

@@ -58,6 +58,12 @@ typedef int32_t cel_status;
 #define CEL_ST_CONVERGED 3     /* convergence test met, theta unchanged                  */
 #define CEL_ST_NONFINITE 4     /* objective or gradient not finite, theta unchanged      */
 
+/* conditions found on the device, accumulated per context (cel_last_device_error) */
+#define CEL_DEVERR_NONFINITE_OBJECTIVE 1  /* some L_s evaluated to a non-finite value      */
+#define CEL_DEVERR_NONFINITE_STEP 2       /* a Newton step met non-finite theta, gradient
+                                             or Hessian (that source: CEL_ST_NONFINITE)  */
+#define CEL_DEVERR_NONFINITE_HESSIAN 4    /* cel_elbo_hessian produced a non-finite entry  */
+
 #define CEL_N_THETA 32
 #define CEL_N_PARAM 27
 #define CEL_MAX_PSF 4
@@ -138,9 +144,16 @@ typedef struct cel_plan cel_plan;
 
 const char* cel_strerror(cel_status s);
 
-/* Create a context on HIP device `hip_device`.  opt may be NULL (defaults). */
+/* Create a context on HIP device `hip_device`.  opt may be NULL (defaults).  Plans made
+ * from a context must be freed before it is destroyed. */
 cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_options* opt);
 void cel_destroy(cel_ctx* ctx);
+
+/* Conditions the kernels of this context's plans found since the last call (a bitwise OR
+ * of CEL_DEVERR_*; 0 = none), then cleared.  Device-detected conditions never abort a
+ * batch: the affected sources carry their own status.  Call after synchronising the
+ * streams the work ran on; the read itself is a synchronous copy.  code: HOST int32. */
+cel_status cel_last_device_error(cel_ctx* ctx, int32_t* code);
 
 /* Validate a problem and build a plan: patch overlap lists, the source overlap graph and
  * its greedy colouring (ascending id, smallest free colour), work items sorted by cost,
@@ -198,6 +211,9 @@ typedef struct {
   int32_t n_sweeps;              /* block coordinate ascent passes (default 3)           */
   int32_t max_newton_iters;      /* per colour class per sweep (default 50)              */
   int32_t use_graph;             /* 1: replay a captured HIP graph per colour class      */
+  int32_t start_colour;          /* resume: first pass starts at this colour class; 0 =
+                                    a fresh pass (radii reset, statuses cleared)         */
+  int32_t max_classes;           /* stop after this many colour classes (0 = no limit)  */
 } cel_sweep_opts;
 
 typedef struct {
@@ -205,14 +221,22 @@ typedef struct {
   int32_t n_colours;
   int64_t n_newton_steps;        /* batched steps taken                                  */
   double seconds;                /* wall time of the call                                */
+  int32_t sweeps_done;           /* passes completed by this call                        */
+  int32_t next_colour;           /* cursor: the colour class a resumed call starts at
+                                    (0 when the last pass was completed)                 */
 } cel_sweep_report;
 
 /* Block coordinate ascent (Sections 4.3-4.4): for each sweep and each colour class in
  * ascending colour, Newton steps on the whole class (all members at once: they do not
  * overlap) until every member has converged or max_newton_iters steps were taken.  The
  * trust radius of every source starts at radius0 at each sweep.  theta DEVICE in/out;
- * radius DEVICE float64 [S] out; status DEVICE int32 [S] out (last status per source);
- * report HOST (filled after an internal stream synchronisation). */
+ * radius DEVICE float64 [S] in/out; status DEVICE int32 [S] in/out (last status per
+ * source); report HOST (filled after an internal stream synchronisation).
+ * Checkpoint / resume: with max_classes = k the call stops after k colour classes and
+ * reports the cursor; (theta, radius, status) and a second call with start_colour =
+ * next_colour and n_sweeps = the passes still due (the interrupted one included) continue
+ * exactly as one uninterrupted call.  opts NULL: defaults.  CEL_EINVAL if start_colour is
+ * outside [0, n_colours) (n_colours > 0) or a count is negative. */
 cel_status cel_sweep(cel_ctx* ctx, const cel_plan* plan, double* theta, double* radius, int32_t* status,
                      const cel_sweep_opts* opts, cel_sweep_report* report, void* stream);
 

@@ -17,6 +17,7 @@ N_PARAM = 27
 
 CEL_OK, CEL_EINVAL, CEL_ENOMEM, CEL_EHIP, CEL_EUNSUPPORTED = 0, -1, -2, -3, -4
 ST_SKIPPED, ST_ACCEPTED, ST_REJECTED, ST_CONVERGED, ST_NONFINITE = 0, 1, 2, 3, 4
+DEVERR_NONFINITE_OBJECTIVE, DEVERR_NONFINITE_STEP, DEVERR_NONFINITE_HESSIAN = 1, 2, 4
 
 
 class CelImage(C.Structure):
@@ -59,12 +60,13 @@ class CelOptions(C.Structure):
 
 
 class CelSweepOpts(C.Structure):
-    _fields_ = [("n_sweeps", C.c_int32), ("max_newton_iters", C.c_int32), ("use_graph", C.c_int32)]
+    _fields_ = [("n_sweeps", C.c_int32), ("max_newton_iters", C.c_int32), ("use_graph", C.c_int32),
+                ("start_colour", C.c_int32), ("max_classes", C.c_int32)]
 
 
 class CelSweepReport(C.Structure):
     _fields_ = [("elbo_total", C.c_double), ("n_colours", C.c_int32), ("n_newton_steps", C.c_int64),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("sweeps_done", C.c_int32), ("next_colour", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -88,6 +90,7 @@ _sig = {
     "cel_newton_step": (C.c_int32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, _vp, _vp]),
     "cel_phase_times": (C.c_int32, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "cel_sweep": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(CelSweepOpts), C.POINTER(CelSweepReport), _vp]),
+    "cel_last_device_error": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
 }
 EXPORTED = tuple(_sig)
 for _name, (_res, _args) in _sig.items():

@@ -264,16 +264,60 @@ def newton_step(plan: Plan, theta, radius, mask=None):
     return st, loc
 
 
-def sweep(plan: Plan, theta, n_sweeps=3, max_newton_iters=50, use_graph=True):
-    """cel_sweep: theta updated in place.  Returns (radius, status, report dict)."""
+def sweep(plan: Plan, theta, n_sweeps=3, max_newton_iters=50, use_graph=True, radius=None, status=None,
+          start_colour=0, max_classes=0):
+    """cel_sweep: theta updated in place.  Returns (radius, status, report dict).
+
+    Checkpoint / resume: with max_classes = k the call stops after k colour classes;
+    report["next_colour"] and report["sweeps_done"] are the cursor.  Pass the returned
+    radius and status back with start_colour = next_colour and the passes still due to
+    continue exactly as one uninterrupted call."""
     if not (isinstance(theta, torch.Tensor) and theta.is_cuda and theta.dtype == torch.float64
             and theta.is_contiguous() and theta.shape == (plan.S, F.N_THETA)):
         raise ValueError("theta must be a contiguous cuda float64 tensor [S,32]")
-    radius = plan._out(plan.S)
-    st = torch.empty(plan.S, dtype=torch.int32, device=plan.ctx.device)
-    o = F.CelSweepOpts(int(n_sweeps), int(max_newton_iters), int(bool(use_graph)))
+    if start_colour and (radius is None or status is None):
+        raise ValueError("a resumed sweep needs the radius and status of the interrupted one")
+    radius = plan._out(plan.S) if radius is None else radius
+    st = torch.zeros(plan.S, dtype=torch.int32, device=plan.ctx.device) if status is None else status
+    for t, dt in ((radius, torch.float64), (st, torch.int32)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.shape == (plan.S,)):
+            raise ValueError("radius / status must be contiguous cuda tensors [S] (float64 / int32)")
+    o = F.CelSweepOpts(int(n_sweeps), int(max_newton_iters), int(bool(use_graph)), int(start_colour), int(max_classes))
     rep = F.CelSweepReport()
     F.check("cel_sweep", F.lib.cel_sweep(plan.ctx.h, plan.h, _ptr(theta), _ptr(radius), _ptr(st), C.byref(o),
                                          C.byref(rep), _stream(plan.ctx.device)))
     return radius, st, dict(elbo=rep.elbo_total, n_colours=rep.n_colours, n_newton_steps=rep.n_newton_steps,
-                            seconds=rep.seconds)
+                            seconds=rep.seconds, sweeps_done=rep.sweeps_done, next_colour=rep.next_colour)
+
+
+def last_device_error(ctx: Context):
+    """cel_last_device_error: CEL_DEVERR_* bits found since the last call (then cleared).
+    Synchronises the context's device first."""
+    torch.cuda.synchronize(ctx.device)
+    code = C.c_int32()
+    F.check("cel_last_device_error", F.lib.cel_last_device_error(ctx.h, C.byref(code)))
+    return int(code.value)
+
+
+def save_state(path, theta, radius=None, status=None, cursor=None):
+    """Checkpoint the caller-owned optimisation state to an .npz file (host copies)."""
+    import numpy as _np
+    arrs = dict(theta=theta.detach().cpu().numpy())
+    if radius is not None:
+        arrs["radius"] = radius.detach().cpu().numpy()
+    if status is not None:
+        arrs["status"] = status.detach().cpu().numpy()
+    if cursor is not None:
+        arrs["cursor"] = _np.asarray([cursor.get("sweeps_done", 0), cursor.get("next_colour", 0)], _np.int64)
+    _np.savez(path, **arrs)
+
+
+def load_state(path, device):
+    """Inverse of save_state: (theta, radius or None, status or None, cursor dict or None)."""
+    import numpy as _np
+    with _np.load(path, allow_pickle=False) as z:
+        th = torch.as_tensor(z["theta"]).to(device).contiguous()
+        r = torch.as_tensor(z["radius"]).to(device).contiguous() if "radius" in z else None
+        st = torch.as_tensor(z["status"]).to(device).contiguous() if "status" in z else None
+        cur = dict(sweeps_done=int(z["cursor"][0]), next_colour=int(z["cursor"][1])) if "cursor" in z else None
+    return th, r, st, cur

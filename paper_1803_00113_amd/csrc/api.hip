@@ -308,14 +308,36 @@ extern "C" cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_op
   resolve_fd_step(o);
   if (!(o.pixels_per_lane == 1 || o.pixels_per_lane == 2 || o.pixels_per_lane == 4)) return CEL_EINVAL;
   if (o.chunk_pixels < 64 || o.chunk_pixels % 64 != 0 || o.chunk_pixels > (1 << 20)) return CEL_EINVAL;
+  if (hipSetDevice(hip_device) != hipSuccess) return CEL_EHIP;
+  int32_t* err = nullptr;
+  if (hipMalloc((void**)&err, sizeof(int32_t)) != hipSuccess) return CEL_ENOMEM;
+  if (hipMemset(err, 0, sizeof(int32_t)) != hipSuccess) {
+    (void)hipFree(err);
+    return CEL_EHIP;
+  }
   cel_ctx* c = new cel_ctx;
   c->device = hip_device;
   c->opt = o;
+  c->d_err = err;
   *out = c;
   return CEL_OK;
 }
 
-extern "C" void cel_destroy(cel_ctx* ctx) { delete ctx; }
+extern "C" void cel_destroy(cel_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->d_err && hipSetDevice(ctx->device) == hipSuccess) (void)hipFree(ctx->d_err);
+  delete ctx;
+}
+
+extern "C" cel_status cel_last_device_error(cel_ctx* ctx, int32_t* code) {
+  if (!ctx || !code) return CEL_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CEL_EHIP;
+  int32_t v = 0;
+  if (hipMemcpy(&v, ctx->d_err, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return CEL_EHIP;
+  if (hipMemset(ctx->d_err, 0, sizeof(int32_t)) != hipSuccess) return CEL_EHIP;
+  *code = v;
+  return CEL_OK;
+}
 
 extern "C" void cel_plan_free(cel_plan* plan) {
   if (!plan) return;
@@ -333,6 +355,7 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   cel_plan* p = new cel_plan;
   p->device = ctx->device;
   p->opt = ctx->opt;
+  p->d_err = ctx->d_err;
   const int S = pr->n_sources, N = pr->n_images, P = pr->n_patches;
   p->S = S;
   p->N = N;
@@ -668,6 +691,7 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   fz.patch_ptr = p->d_patch_ptr;
   fz.patches = p->d_patches;
   fz.pix_const = p->d_pixconst;
+  fz.err = p->d_err;
   fz.images = p->d_images;
   fz.prior = p->d_prior;
   fz.want_grad = grad ? 1 : 0;
@@ -727,6 +751,7 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
   fz.patch_ptr = p->d_patch_ptr;
   fz.patches = p->d_patches;
   fz.pix_const = p->d_pixconst;
+  fz.err = p->d_err;
   fz.images = p->d_images;
   fz.prior = p->d_prior;
   fz.want_grad = 1;

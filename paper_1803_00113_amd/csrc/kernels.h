@@ -45,6 +45,7 @@ struct FinalizeArgs {
   int64_t out_variant_stride;  // = S
   int32_t trial_variant;
   int32_t fd;
+  int32_t* err;                // device condition word (CEL_DEVERR_*), may be null
 };
 
 template <typename T>

@@ -185,14 +185,14 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
       yy[i] = dy[i] * dy[i];
     }
     const T d2 = box_dist2<T>(mx, my, box);
-    if (d2 <= tb->rc2s[k]) {
+    if (!(d2 > tb->rc2s[k])) {
       const T pxx = tb->star[k][2] * hl, pxy = tb->star[k][3] * hl, pyy = tb->star[k][4] * hl, lw = tb->star[k][5];
 #pragma unroll
       for (int i = 0; i < PPL; ++i) f1[i] += fexp2<T>(fma(pxx, xx[i], fma(pxy, xy[i], fma(pyy, yy[i], lw))));
     }
 #pragma unroll
     for (int j = 0; j < NEXP; ++j) {
-      if (!(d2 <= tb->rc2[k][j])) continue;
+      if (d2 > tb->rc2[k][j]) continue;
       const T pxx = tb->gal[k][j][0] * hl, pxy = tb->gal[k][j][1] * hl, pyy = tb->gal[k][j][2] * hl,
               lw = tb->gal[k][j][3];
 #pragma unroll
@@ -200,7 +200,7 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
     }
 #pragma unroll
     for (int j = 0; j < NDEV; ++j) {
-      if (!(d2 <= tb->rc2[k][kMaxProf + j])) continue;
+      if (d2 > tb->rc2[k][kMaxProf + j]) continue;
       const T pxx = tb->gal[k][kMaxProf + j][0] * hl, pxy = tb->gal[k][kMaxProf + j][1] * hl,
               pyy = tb->gal[k][kMaxProf + j][2] * hl, lw = tb->gal[k][kMaxProf + j][3];
 #pragma unroll
@@ -270,17 +270,17 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
       dy[i] = py[i] - my;
     }
     const T d2 = box_dist2<T>(mx, my, box);
-    if (d2 <= tb->rc2s[k])
+    if (!(d2 > tb->rc2s[k]))
       comp_own<T, PPL, DERIV ? 1 : 0>(tb->star[k][2], tb->star[k][3], tb->star[k][4], tb->star[k][5], (T)0, dx, dy,
                                       o.f1, o.g1x, o.g1y, z, z, z);
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
-      if (d2 <= tb->rc2[k][j])
+      if (!(d2 > tb->rc2[k][j]))
         comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], htau[j], dx,
                               dy, o.fe, o.gex, o.gey, o.sexx, o.sexy, o.seyy);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
-      if (d2 <= tb->rc2[k][kMaxProf + j])
+      if (!(d2 > tb->rc2[k][kMaxProf + j]))
         comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
                               tb->gal[k][kMaxProf + j][3], htau[kMaxProf + j], dx, dy, o.fd, o.gdx, o.gdy, o.sdxx,
                               o.sdxy, o.sdyy);
@@ -582,6 +582,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
     g[25] += gpi * prof * (1.0 - prof);
   }
   const int64_t out = (int64_t)vv * a.out_variant_stride + s;
+  if (a.err && !isfinite(local)) atomicOr(a.err, CEL_DEVERR_NONFINITE_OBJECTIVE);
   if (a.local) a.local[out] = local;
   if (a.own) a.own[out] = own;
   if (a.want_grad && a.grad) {

@@ -245,7 +245,7 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
     const T mx = tb->star[k][0], my = tb->star[k][1];
     const T dx = px - mx, dy = py - my;
     const T d2 = box_dist2<T>(mx, my, box);
-    if (d2 <= tb->rc2s[k]) {
+    if (!(d2 > tb->rc2s[k])) {
       const T Pxx = tb->star[k][2], Pxy = tb->star[k][3], Pyy = tb->star[k][4], lw = tb->star[k][5];
       const T ux = fma(Pxx, dx, Pxy * dy), uy = fma(Pxy, dx, Pyy * dy);
       const T N = fexp2<T>(fma(fma(dx, ux, dy * uy), hl, lw));
@@ -258,12 +258,12 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
     }
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
-      if (d2 <= tb->rc2[k][j])
+      if (!(d2 > tb->rc2[k][j]))
         gal_hess<T>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], tb->gt[k][j], omp, dx,
                     dy, fe, gme, gse, hmm, hms, hss);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
-      if (d2 <= tb->rc2[k][kMaxProf + j])
+      if (!(d2 > tb->rc2[k][kMaxProf + j]))
         gal_hess<T>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
                     tb->gal[k][kMaxProf + j][3], tb->gt[k][kMaxProf + j], pi, dx, dy, fd, gmd, gsd, hmm, hms, hss);
   }
@@ -518,6 +518,7 @@ struct HessFinArgs {
   double* local;               // [S]
   double* grad;                // [S][32]
   double* hess;                // [S][27][27]
+  int32_t* err;                // device condition word (non-finite Hessian entries)
 };
 
 __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
@@ -687,8 +688,13 @@ __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
   __syncthreads();
   if (lane == 0 && a.local) a.local[s] = local - klv;
   if (a.grad && lane < kThetaN) a.grad[(int64_t)s * kThetaN + lane] = lane < kN ? gs[lane] : 0.0;
-  for (int idx = lane; idx < kN * kN; idx += 64)
-    a.hess[(int64_t)s * kN * kN + idx] = Hs[idx / kN][idx % kN];
+  bool fin = true;
+  for (int idx = lane; idx < kN * kN; idx += 64) {
+    const double h = Hs[idx / kN][idx % kN];
+    fin = fin && isfinite(h);
+    a.hess[(int64_t)s * kN * kN + idx] = h;
+  }
+  if (a.err && !fin) atomicOr(a.err, CEL_DEVERR_NONFINITE_HESSIAN);
 }
 
 struct TrArgs {
@@ -707,6 +713,7 @@ struct TrArgs {
   double* pred;               // out: predicted gain
   double* pnorm;              // out: |p|
   int32_t* status;            // out: CONVERGED / NONFINITE for sources not tried
+  int32_t* err;               // device condition word
 };
 
 // Hessian of L_s from central differences of the pixel gradient (variants 1..54 hold the
@@ -800,6 +807,7 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
     if (lane == 0) {
       a.status[s] = CEL_ST_NONFINITE;
       a.trial_active[s] = 0;
+      if (a.err) atomicOr(a.err, CEL_DEVERR_NONFINITE_STEP);
     }
     return;
   }
@@ -1092,6 +1100,7 @@ static hipError_t enqueue_hessian(cel_plan* p, const double* theta, const int32_
   fa.local = local;
   fa.grad = grad;
   fa.hess = hess;
+  fa.err = with_kl ? p->d_err : nullptr;   // the Newton path reports through the step status
   hipLaunchKernelGGL(k_hess_finalize, dim3(n_src), dim3(64), 0, sm, fa);
   return hipGetLastError();
 }
@@ -1149,6 +1158,7 @@ static hipError_t enqueue_newton_class(cel_plan* p, double* theta, double* radiu
   ta.pred = p->d_pred;
   ta.pnorm = p->d_step_norm;
   ta.status = status;
+  ta.err = p->d_err;
   hipLaunchKernelGGL(k_trsolve, dim3(nsrc), dim3(64), 0, sm, ta);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // objective at the trial points
@@ -1232,11 +1242,14 @@ extern "C" cel_status cel_sweep(cel_ctx* ctx, const cel_plan* cplan, double* the
   cel_plan* p = const_cast<cel_plan*>(cplan);
   if (p->S > 0 && (!theta || !radius || !status)) return CEL_EINVAL;
   cel_sweep_opts o;
+  std::memset(&o, 0, sizeof(o));
   o.n_sweeps = 3;
   o.max_newton_iters = 50;
   o.use_graph = 1;
   if (opts) {
-    if (opts->n_sweeps < 0 || opts->max_newton_iters < 0) return CEL_EINVAL;
+    if (opts->n_sweeps < 0 || opts->max_newton_iters < 0 || opts->max_classes < 0 || opts->start_colour < 0 ||
+        (opts->start_colour > 0 && opts->start_colour >= cplan->n_colours))
+      return CEL_EINVAL;
     o = *opts;
   }
   if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
@@ -1253,7 +1266,7 @@ extern "C" cel_status cel_sweep(cel_ctx* ctx, const cel_plan* cplan, double* the
   int64_t steps = 0;
   hipError_t e = hipSuccess;
   const int S = p->S;
-  if (S > 0) {
+  if (S > 0 && o.start_colour == 0) {   // a fresh pass: every status starts as skipped
     hipLaunchKernelGGL(k_set_active, dim3((S + 255) / 256), dim3(256), 0, sm, p->d_mask, p->d_colour, S, -1);
     e = hipGetLastError();
     if (e == hipSuccess)
@@ -1265,10 +1278,21 @@ extern "C" cel_status cel_sweep(cel_ctx* ctx, const cel_plan* cplan, double* the
     p->graphs.assign(p->n_colours, {});
   }
   const int check_every = 4;
-  for (int sw = 0; sw < o.n_sweeps && e == hipSuccess && S > 0; ++sw) {
-    hipLaunchKernelGGL(k_fill_radius, dim3((S + 255) / 256), dim3(256), 0, sm, radius, S, p->opt.radius0);
-    if ((e = hipGetLastError()) != hipSuccess) break;
-    for (int c = 0; c < p->n_colours && e == hipSuccess; ++c) {
+  int classes = 0, sweeps_done = 0, next_colour = 0;
+  bool stopped = false;
+  for (int sw = 0; sw < o.n_sweeps && e == hipSuccess && S > 0 && !stopped; ++sw) {
+    const int c0 = sw == 0 ? o.start_colour : 0;
+    if (c0 == 0) {   // trust radii restart at each pass
+      hipLaunchKernelGGL(k_fill_radius, dim3((S + 255) / 256), dim3(256), 0, sm, radius, S, p->opt.radius0);
+      if ((e = hipGetLastError()) != hipSuccess) break;
+    }
+    for (int c = c0; c < p->n_colours && e == hipSuccess; ++c) {
+      if (o.max_classes > 0 && classes == o.max_classes) {
+        stopped = true;
+        next_colour = c;
+        break;
+      }
+      ++classes;
       const int nsrc = (int)p->class_src[c].size();
       hipLaunchKernelGGL(k_set_active, dim3((S + 255) / 256), dim3(256), 0, sm, p->d_mask, p->d_colour, S, c);
       if ((e = hipGetLastError()) != hipSuccess) break;
@@ -1310,6 +1334,7 @@ extern "C" cel_status cel_sweep(cel_ctx* ctx, const cel_plan* cplan, double* the
         }
       }
     }
+    if (!stopped && e == hipSuccess) ++sweeps_done;
   }
   if (e == hipSuccess && S > 0) e = launch_total_after_eval(p, theta, sm);
   double tot = 0;
@@ -1321,6 +1346,8 @@ extern "C" cel_status cel_sweep(cel_ctx* ctx, const cel_plan* cplan, double* the
     report->n_colours = p->n_colours;
     report->n_newton_steps = steps;
     report->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    report->sweeps_done = sweeps_done;
+    report->next_colour = next_colour;
   }
   return e == hipSuccess ? CEL_OK : CEL_EHIP;
 }

@@ -29,11 +29,13 @@ constexpr double rel_cut_log2() {
   return sizeof(T) == 8 ? 60.0 : 30.0;
 }
 
-// squared radius beyond which 2^(lw - log2(e)/2 d^T C^{-1} d) < 2^cut (-1: never above it)
+// squared radius beyond which 2^(lw - log2(e)/2 d^T C^{-1} d) < 2^cut (-1: never above it;
+// +inf when the component is not finite, so that NaN parameters reach the rate)
 __device__ __forceinline__ double cut_radius2(double lw, double cxx, double cxy, double cyy, double cut) {
   const double room = lw - cut;
-  if (!(room > 0)) return -1.0;
   const double lmax = 0.5 * (cxx + cyy) + sqrt(0.25 * (cxx - cyy) * (cxx - cyy) + cxy * cxy);
+  if (isnan(room) || !isfinite(lmax)) return INFINITY;
+  if (!(room > 0)) return -1.0;
   return room / (0.5 * kLog2e / lmax);
 }
 

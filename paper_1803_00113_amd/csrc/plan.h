@@ -10,6 +10,7 @@
 struct cel_ctx {
   int device;
   cel_options opt;
+  int32_t* d_err = nullptr;       // device condition word (CEL_DEVERR_*), shared by the plans
 };
 
 struct cel_plan {
@@ -50,6 +51,7 @@ struct cel_plan {
   double2* d_maps64 = nullptr;
   double* d_pixconst = nullptr;
   double* d_skymin = nullptr;     // per patch: smallest sky value
+  int32_t* d_err = nullptr;       // the context's condition word
   double* d_total = nullptr;
   std::vector<int32_t*> d_class_patches, d_class_tasks, d_class_src;
   // per-variant scratch

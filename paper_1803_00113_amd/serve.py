@@ -12,7 +12,9 @@ in device memory.  At every device step:
   3. one trust-radius Newton round runs, in one batched cel_newton_step, on every resident
      request's current colour class (a request cycles through its classes);
   4. requests that have completed their rounds leave: their parameters and objective are
-     copied to the host and the latency (arrival to result on the host) is recorded.
+     copied to the host and the latency (arrival to result on the host) is recorded;
+     cancelled requests leave without a result (a request may be cancelled while pending
+     or after a given number of rounds).
 Work of different requests shares launches; a request's results do not depend on which
 others are resident (every per-source reduction has a fixed order).
 """
@@ -95,6 +97,8 @@ class Request:
     prob: object
     arrival: float                     # seconds since the loop started
     rounds: int = 10
+    cancel_after_rounds: int = None    # cancel once this many rounds are done (None: never)
+    cancelled: bool = False
     # device state
     theta: torch.Tensor = None
     radius: torch.Tensor = None
@@ -118,6 +122,7 @@ class Stats:
     steps: int = 0
     deferred_admissions: int = 0
     rebuilds: int = 0
+    cancelled: int = 0
     units_evaluated: int = 0
     wall: float = 0.0
 
@@ -127,6 +132,7 @@ class Stats:
                     mean_ms=float(lat.mean() * 1e3), completed=len(self.latencies),
                     req_per_s=len(self.latencies) / max(self.wall, 1e-9), steps=self.steps,
                     deferred_admissions=self.deferred_admissions, rebuilds=self.rebuilds,
+                    cancelled=self.cancelled,
                     units_per_s=self.units_evaluated / max(self.wall, 1e-9), wall_s=self.wall)
 
 
@@ -154,6 +160,11 @@ class Server:
         r.rounds = self.rounds
         r.units = int(np.sum(p.patch_w.astype(np.int64) * p.patch_h))
 
+    def _cancel(self, r):
+        r.cancelled = True
+        r.theta = r.radius = r.pixels = None
+        self.stats.cancelled += 1
+
     def _rebuild(self):
         self.plan = None
         if not self.resident:
@@ -171,8 +182,21 @@ class Server:
 
     def step(self, now, pending):
         """Admit what fits from `pending` (arrived requests, oldest first), run one Newton
-        round for every resident request, retire finished ones.  Returns retired requests."""
+        round for every resident request, retire finished and cancelled ones.  Returns the
+        retired requests."""
         changed = False
+        # cancellations: pending requests are dropped, resident ones leave the plan
+        cancelled = [r for r in pending if r.cancel_after_rounds is not None and r.cancel_after_rounds <= 0]
+        for r in cancelled:
+            pending.remove(r)
+        gone = [r for r in self.resident
+                if r.cancel_after_rounds is not None and r.done_rounds >= r.cancel_after_rounds]
+        if gone:
+            self.resident = [r for r in self.resident if r not in gone]
+            changed = True
+        cancelled += gone
+        for r in cancelled:
+            self._cancel(r)
         used = sum(r.footprint for r in self.resident)
         while pending:
             r = pending[0]
@@ -189,7 +213,7 @@ class Server:
             self._rebuild()
             self.dirty = False
         if not self.resident:
-            return []
+            return cancelled
         S = self.plan.S
         theta = torch.cat([r.theta for r in self.resident])
         radius = torch.cat([r.radius for r in self.resident])
@@ -222,7 +246,7 @@ class Server:
                 r.finished = t_done
             self.resident = keep
             self.dirty = True
-        return finished
+        return finished + cancelled
 
     def run(self, requests, realtime=True):
         """Serve `requests` (each with .arrival seconds from start).  Returns the stats
@@ -241,7 +265,8 @@ class Server:
                 continue
             fin = self.step(now, pending)
             for r in fin:
-                self.stats.latencies.append((r.finished - t0) - r.arrival if realtime else r.finished - t0)
+                if not r.cancelled:
+                    self.stats.latencies.append((r.finished - t0) - r.arrival if realtime else r.finished - t0)
                 done += 1
         torch.cuda.synchronize(self.dev)
         self.stats.wall = time.perf_counter() - t0

@@ -128,3 +128,31 @@ def test_sweep_graph_equals_eager_and_matches_oracle():
     assert abs(res[0][3]["elbo"] - o_rep["elbo"]) <= 1e-5 * abs(o_rep["elbo"])
     # the GPU's final point, evaluated by the oracle, is as good as the oracle's own
     assert E.elbo(m, th)[0].item() >= o_rep["elbo"] - 1e-5 * abs(o_rep["elbo"])
+
+
+def test_sweep_checkpoint_resume_identical(tmp_path):
+    """Checkpoint / resume: a sweep stopped after a few colour classes, its state saved to
+    disk and reloaded, then resumed at the cursor, ends bitwise where one uninterrupted
+    sweep ends."""
+    say("case: sweep checkpoint / resume")
+    prob = gen.crop_patches(gen.subset(gen.config2(n_sources=20), images=[0, 5]), 20)
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    assert plan.n_colours >= 2
+    th_a = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    r_a, st_a, rep_a = api.sweep(plan, th_a, n_sweeps=2, max_newton_iters=20)
+    th_b = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    k = plan.n_colours + 1          # stop inside the second pass
+    r_b, st_b, rep_b = api.sweep(plan, th_b, n_sweeps=2, max_newton_iters=20, max_classes=k)
+    say(f"  stopped after {k} classes: {rep_b}")
+    assert rep_b["sweeps_done"] == 1 and rep_b["next_colour"] == 1
+    path = tmp_path / "state.npz"
+    api.save_state(path, th_b, r_b, st_b, rep_b)
+    th_c, r_c, st_c, cur = api.load_state(path, "cuda")
+    assert torch.equal(th_c, th_b) and torch.equal(r_c, r_b) and torch.equal(st_c, st_b)
+    _, _, rep_c = api.sweep(plan, th_c, n_sweeps=2 - cur["sweeps_done"], max_newton_iters=20,
+                            radius=r_c, status=st_c, start_colour=cur["next_colour"])
+    torch.cuda.synchronize()
+    assert torch.equal(th_c, th_a) and torch.equal(r_c, r_a) and torch.equal(st_c, st_a)
+    assert rep_c["elbo"] == rep_a["elbo"] and rep_c["next_colour"] == 0
+    assert rep_b["n_newton_steps"] + rep_c["n_newton_steps"] == rep_a["n_newton_steps"]

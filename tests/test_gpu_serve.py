@@ -57,3 +57,21 @@ def test_realtime_poisson_arrivals():
     stats = srv.run(reqs)
     say(f"  {stats}")
     assert stats["completed"] == 12 and stats["p99_ms"] >= stats["p50_ms"] > 0
+
+
+def test_cancellation_leaves_others_unchanged():
+    say("case: serving cancellation")
+    reqs = requests(5)
+    alone = {r.rid: serve.solo(r.prob, rounds=4) for r in reqs}
+    reqs[1].cancel_after_rounds = 2     # leaves while resident
+    reqs[3].cancel_after_rounds = 0     # cancelled before admission
+    srv = serve.Server(0, rounds=4)
+    stats = srv.run(reqs, realtime=False)
+    say(f"  {stats}")
+    assert stats["completed"] == 3 and stats["cancelled"] == 2
+    for r in reqs:
+        if r.rid in (1, 3):
+            assert r.cancelled and r.result_theta is None
+        else:
+            assert not r.cancelled
+            assert np.array_equal(r.result_theta, alone[r.rid].result_theta), r.rid
