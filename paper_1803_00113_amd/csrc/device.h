@@ -42,6 +42,11 @@ enum Slot {
 // hdr[8..9]: e0, e1 = expm1(variance of log l given the type) (for the analytic Hessian)
 // gt[k][j]: tau, tau^2, then tau^2/2 tr(E1 P E2 P) for the S-parameter pairs (xx,xx),
 //           (xx,xy), (xx,yy), (xy,xy), (xy,yy), (yy,yy)
+// hdr[10..11]: the source centre mu in patch-local pixels
+// sq[k], gq[k][j]: (-log2(e)/2 (P_xx, P_xy, P_yy), log2 weight) -- the exponent of a
+//   component at offset d from its centre is q0 dx^2 + q1 (2 dx dy) + q2 dy^2 + q3
+//   (values-only evaluation: neighbour maps, Hessian)
+// off[k]: centre of PSF component k minus mu (the PSF mean offset)
 template <typename T>
 struct alignas(16) Table {
   T hdr[16];
@@ -50,6 +55,9 @@ struct alignas(16) Table {
   T rc2s[kMaxPsf];
   T rc2[kMaxPsf][2 * kMaxProf];
   T gt[kMaxPsf][2 * kMaxProf][8];
+  T sq[kMaxPsf][4];
+  T gq[kMaxPsf][2 * kMaxProf][4];
+  T off[kMaxPsf][2];
 };
 
 struct DPatch {

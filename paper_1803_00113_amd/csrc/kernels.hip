@@ -100,6 +100,8 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
     tb->hdr[5] = (T)kk[1];
     tb->hdr[6] = (T)(w[0] * w[1]);
     tb->hdr[7] = (T)sigmoid(th[25]);
+    tb->hdr[10] = (T)mux;
+    tb->hdr[11] = (T)muy;
   }
   // components: 4 star slots then 4 x 16 galaxy slots
   for (int c = lane; c < kMaxPsf + kMaxPsf * 2 * kMaxProf; c += 64) {
@@ -117,10 +119,20 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
         const double lw = im.psf[k][0] > 0 ? log2(im.psf[k][0]) - kLog2TwoPi - 0.5 * log2(det) : kNegHuge;
         r[5] = (T)lw;
         tb->rc2s[k] = (T)cut_radius2(lw, cxx, cxy, cyy, cut_star);
+        const double hl = -0.5 * kLog2e;
+        tb->sq[k][0] = (T)(hl * cyy / det);
+        tb->sq[k][1] = (T)(hl * -cxy / det);
+        tb->sq[k][2] = (T)(hl * cxx / det);
+        tb->sq[k][3] = (T)lw;
+        tb->off[k][0] = (T)im.psf[k][1];
+        tb->off[k][1] = (T)im.psf[k][2];
       } else {
         r[0] = r[1] = r[2] = r[3] = r[4] = (T)0;
         r[5] = (T)kNegHuge;
         tb->rc2s[k] = (T)-1;
+        tb->sq[k][0] = tb->sq[k][1] = tb->sq[k][2] = (T)0;
+        tb->sq[k][3] = (T)kNegHuge;
+        tb->off[k][0] = tb->off[k][1] = (T)0;
       }
       r[6] = r[7] = (T)0;
     } else {
@@ -141,6 +153,11 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
         const double lw = wt > 0 ? log2(wt) - kLog2TwoPi - 0.5 * log2(det) : kNegHuge;
         r[3] = (T)lw;
         tb->rc2[k][j] = (T)cut_radius2(lw, cxx, cxy, cyy, cut_gal);
+        const double hl = -0.5 * kLog2e;
+        tb->gq[k][j][0] = (T)(hl * cyy / det);
+        tb->gq[k][j][1] = (T)(hl * -cxy / det);
+        tb->gq[k][j][2] = (T)(hl * cxx / det);
+        tb->gq[k][j][3] = (T)lw;
         const double Pxx = cyy / det, Pxy = -cxy / det, Pyy = cxx / det, h = 0.5 * tau * tau;
         T* q = tb->gt[k][j];
         q[0] = (T)tau;
@@ -156,6 +173,8 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
         r[3] = (T)kNegHuge;
         tb->rc2[k][j] = (T)-1;
         for (int e = 0; e < 8; ++e) tb->gt[k][j][e] = (T)0;
+        for (int e = 0; e < 3; ++e) tb->gq[k][j][e] = (T)0;
+        tb->gq[k][j][3] = (T)kNegHuge;
       }
     }
   }
@@ -172,7 +191,6 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
   T fe[PPL], fd[PPL];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) fe[i] = fd[i] = f1[i] = (T)0;
-  const T hl = (T)(-0.5 * kLog2e);
   for (int k = 0; k < K; ++k) {
     const T mx = tb->star[k][0], my = tb->star[k][1];
     T dx[PPL], dy[PPL], xx[PPL], xy[PPL], yy[PPL];
@@ -186,25 +204,21 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
     }
     const T d2 = box_dist2<T>(mx, my, box);
     if (!(d2 > tb->rc2s[k])) {
-      const T pxx = tb->star[k][2] * hl, pxy = tb->star[k][3] * hl, pyy = tb->star[k][4] * hl, lw = tb->star[k][5];
 #pragma unroll
-      for (int i = 0; i < PPL; ++i) f1[i] += fexp2<T>(fma(pxx, xx[i], fma(pxy, xy[i], fma(pyy, yy[i], lw))));
+      for (int i = 0; i < PPL; ++i) f1[i] += comp_value<T>(tb->sq[k], xx[i], xy[i], yy[i]);
     }
 #pragma unroll
     for (int j = 0; j < NEXP; ++j) {
       if (d2 > tb->rc2[k][j]) continue;
-      const T pxx = tb->gal[k][j][0] * hl, pxy = tb->gal[k][j][1] * hl, pyy = tb->gal[k][j][2] * hl,
-              lw = tb->gal[k][j][3];
 #pragma unroll
-      for (int i = 0; i < PPL; ++i) fe[i] += fexp2<T>(fma(pxx, xx[i], fma(pxy, xy[i], fma(pyy, yy[i], lw))));
+      for (int i = 0; i < PPL; ++i) fe[i] += comp_value<T>(tb->gq[k][j], xx[i], xy[i], yy[i]);
     }
 #pragma unroll
     for (int j = 0; j < NDEV; ++j) {
       if (d2 > tb->rc2[k][kMaxProf + j]) continue;
-      const T pxx = tb->gal[k][kMaxProf + j][0] * hl, pxy = tb->gal[k][kMaxProf + j][1] * hl,
-              pyy = tb->gal[k][kMaxProf + j][2] * hl, lw = tb->gal[k][kMaxProf + j][3];
 #pragma unroll
-      for (int i = 0; i < PPL; ++i) fd[i] += fexp2<T>(fma(pxx, xx[i], fma(pxy, xy[i], fma(pyy, yy[i], lw))));
+      for (int i = 0; i < PPL; ++i)
+        fd[i] += comp_value<T>(tb->gq[k][kMaxProf + j], xx[i], xy[i], yy[i]);
     }
   }
   const T pi = tb->hdr[7];

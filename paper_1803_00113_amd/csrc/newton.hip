@@ -191,13 +191,11 @@ struct PixH {
 // one galaxy component of one profile: value, first derivatives (per profile) and the
 // profile-weighted second derivatives in (mu, S)
 template <typename T>
-__device__ __forceinline__ void gal_hess(T Pxx, T Pxy, T Pyy, T lw, const T* gt, T wP, T dx, T dy, T& f, T* gm,
-                                         T* gs, T* hmm, T* hms, T* hss) {
-  const T hl = (T)(-0.5 * kLog2e);
+__device__ __forceinline__ void gal_hess(const T* q, T Pxx, T Pxy, T Pyy, T lw, const T* gt, T wP, T dx, T dy, T xx,
+                                         T xy, T yy, T& f, T* gm, T* gs, T* hmm, T* hms, T* hss) {
   const T ux = fma(Pxx, dx, Pxy * dy);
   const T uy = fma(Pxy, dx, Pyy * dy);
-  const T q = fma(dx, ux, dy * uy);
-  const T N = fexp2<T>(fma(q, hl, lw));
+  const T N = comp_value<T>(q, xx, xy, yy);
   const T qxx = fma(ux, ux, -Pxx), qxy = fma(ux, uy, -Pxy), qyy = fma(uy, uy, -Pyy);
   const T tau = gt[0], tau2 = gt[1];
   const T Nh = (T)0.5 * tau * N;
@@ -236,7 +234,6 @@ __device__ __forceinline__ void gal_hess(T Pxx, T Pxy, T Pyy, T lw, const T* gt,
 template <typename T, int NEXP, int NDEV>
 __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, int K, T px, T py, const T* box,
                                               PixH<T>& o) {
-  const T hl = (T)(-0.5 * kLog2e);
   T fe = 0, fd = 0, gme[2] = {0, 0}, gmd[2] = {0, 0}, gse[3] = {0, 0, 0}, gsd[3] = {0, 0, 0};
   T hmm[3] = {0, 0, 0}, hms[6] = {0, 0, 0, 0, 0, 0}, hss[6] = {0, 0, 0, 0, 0, 0};
   T f1 = 0, g1x = 0, g1y = 0, h1[3] = {0, 0, 0};
@@ -244,11 +241,12 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
   for (int k = 0; k < K; ++k) {
     const T mx = tb->star[k][0], my = tb->star[k][1];
     const T dx = px - mx, dy = py - my;
+    const T xx = dx * dx, xy = (T)2 * dx * dy, yy = dy * dy;
     const T d2 = box_dist2<T>(mx, my, box);
     if (!(d2 > tb->rc2s[k])) {
-      const T Pxx = tb->star[k][2], Pxy = tb->star[k][3], Pyy = tb->star[k][4], lw = tb->star[k][5];
+      const T Pxx = tb->star[k][2], Pxy = tb->star[k][3], Pyy = tb->star[k][4];
       const T ux = fma(Pxx, dx, Pxy * dy), uy = fma(Pxy, dx, Pyy * dy);
-      const T N = fexp2<T>(fma(fma(dx, ux, dy * uy), hl, lw));
+      const T N = comp_value<T>(tb->sq[k], xx, xy, yy);
       f1 += N;
       g1x = fma(N, ux, g1x);
       g1y = fma(N, uy, g1y);
@@ -259,13 +257,14 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
       if (!(d2 > tb->rc2[k][j]))
-        gal_hess<T>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], tb->gt[k][j], omp, dx,
-                    dy, fe, gme, gse, hmm, hms, hss);
+        gal_hess<T>(tb->gq[k][j], tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3],
+                    tb->gt[k][j], omp, dx, dy, xx, xy, yy, fe, gme, gse, hmm, hms, hss);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
       if (!(d2 > tb->rc2[k][kMaxProf + j]))
-        gal_hess<T>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
-                    tb->gal[k][kMaxProf + j][3], tb->gt[k][kMaxProf + j], pi, dx, dy, fd, gmd, gsd, hmm, hms, hss);
+        gal_hess<T>(tb->gq[k][kMaxProf + j], tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1],
+                    tb->gal[k][kMaxProf + j][2], tb->gal[k][kMaxProf + j][3], tb->gt[k][kMaxProf + j], pi, dx, dy, xx,
+                    xy, yy, fd, gmd, gsd, hmm, hms, hss);
   }
   o.f1 = f1;
   o.g1[0] = g1x;
@@ -752,8 +751,6 @@ __global__ __launch_bounds__(64) void k_fd_hessian(FdHessArgs a) {
   __syncthreads();
   for (int idx = lane; idx < kN * kN; idx += 64) a.hess[(int64_t)s * kN * kN + idx] = H[idx / kN][idx % kN];
 }
-
-constexpr int kJ = kN + 1;   // Jacobi columns: the 27 parameters and one zero column
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll

@@ -29,6 +29,17 @@ constexpr double rel_cut_log2() {
   return sizeof(T) == 8 ? 60.0 : 30.0;
 }
 
+// Value of one mixture component at offset (dx, dy) from its centre, given the monomials
+// xx = dx^2, xy = 2 dx dy, yy = dy^2 and its record q = (q0, q1, q2, log2 weight):
+// 2^(q0 xx + q1 xy + q2 yy + lw) -- the form for values alone (neighbour maps, Hessian);
+// the pixel kernel, which needs u = P d for the derivatives anyway, forms the exponent
+// from u (the same value up to rounding).
+template <typename T>
+__device__ __forceinline__ T comp_value(const T* __restrict__ q, T xx, T xy, T yy) {
+  return fexp2<T>(fma(q[0], xx, fma(q[1], xy, fma(q[2], yy, q[3]))));
+}
+
+
 // squared radius beyond which 2^(lw - log2(e)/2 d^T C^{-1} d) < 2^cut (-1: never above it;
 // +inf when the component is not finite, so that NaN parameters reach the rate)
 __device__ __forceinline__ double cut_radius2(double lw, double cxx, double cxy, double cyy, double cut) {
