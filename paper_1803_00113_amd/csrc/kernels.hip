@@ -305,7 +305,8 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
 // patches at the base parameters, read by the pixel kernel for overlapping neighbours.
 template <typename T, int PPL, int NEXP, int NDEV>
 __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
-  const int t = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+  const int pos = xcd_position((int)blockIdx.x, (int)gridDim.x);
+  const int t = a.order ? a.order[pos] : pos;
   const DTask task = a.tasks[t];
   const DPatch P = a.patches[task.patch];
   const Table<T>* __restrict__ tb = reinterpret_cast<const Table<T>*>(a.base) + task.patch;
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
 template <typename T, int PPL, bool GRAD, int NEXP, int NDEV>
 __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restrict__ htau) {
   const int v = a.variant0 + blockIdx.y;
-  const int wi = a.order_offset + blockIdx.x;
+  const int wi = a.order_offset + xcd_position((int)blockIdx.x, (int)gridDim.x);
   const int t = a.order ? a.order[wi] : wi;
   const DTask task = a.tasks[t];
   const DPatch P = a.patches[task.patch];

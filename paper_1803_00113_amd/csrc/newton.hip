@@ -314,7 +314,8 @@ struct HessArgs {
 
 template <typename T, int NEXP, int NDEV>
 __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
-  const int t = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+  const int pos = xcd_position((int)blockIdx.x, (int)gridDim.x);
+  const int t = a.order ? a.order[pos] : pos;
   const DTask task = a.tasks[t];
   const DPatch P = a.patches[task.patch];
   if (a.active && !a.active[P.src]) return;

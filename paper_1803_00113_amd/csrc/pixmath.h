@@ -20,6 +20,22 @@ template <> __device__ __forceinline__ double flog<double>(double x) { return lo
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLog2TwoPi = 2.6514961294723187980;   // log2(2 pi)
 constexpr double kNegHuge = -1.0e30;
+// Block -> position in a cost-sorted work list, XCD-aware.  Workgroups are dispatched to
+// the 8 XCDs in turn (block b on XCD b mod 8), each XCD with its own L2.  Consecutive
+// positions of the list (the chunks of one patch, sorted next to each other) are handed to
+// one XCD in groups of kXcdGroup, so they share its L2 (tables, neighbour maps); the list
+// order across groups, and so the large-first balance, is kept.  A tail that does not fill
+// whole groups maps to itself.
+constexpr int kXcds = 8;
+constexpr int kXcdGroup = 4;
+__device__ __forceinline__ int xcd_position(int b, int n) {
+  constexpr int span = kXcds * kXcdGroup;
+  const int full = (n / span) * span;
+  if (b >= full) return b;
+  const int xcd = b % kXcds, slot = b / kXcds;
+  return ((slot / kXcdGroup) * kXcds + xcd) * kXcdGroup + slot % kXcdGroup;
+}
+
 // Component cut (reading of the kernels' truncation): a mixture component is skipped over a
 // wavefront's pixel box when its contribution to the expected count there, flux times
 // density, stays below 2^-kRelCut of the patch's smallest sky value -- far below the
