@@ -67,26 +67,6 @@ static void resolve_fd_step(cel_options& o) {
   if (!(o.fd_step > 0)) o.fd_step = (o.pixel_fp64 || o.hessian_fp64) ? 1e-3 : 1e-2;
 }
 
-template <typename X>
-static cel_status dalloc(X** p, size_t n) {
-  *p = nullptr;
-  if (n == 0) n = 1;
-  if (hipMalloc((void**)p, n * sizeof(X)) != hipSuccess) {
-    *p = nullptr;
-    return CEL_ENOMEM;
-  }
-  return CEL_OK;
-}
-
-template <typename X>
-static cel_status upload(X** p, const std::vector<X>& v) {
-  cel_status st = dalloc(p, v.size());
-  if (st) return st;
-  if (!v.empty() && hipMemcpy(*p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice) != hipSuccess)
-    return CEL_EHIP;
-  return CEL_OK;
-}
-
 static bool finite(double x) { return std::isfinite(x); }
 
 // inverse and log-determinant of a symmetric positive definite 4x4 matrix (Cholesky)
@@ -191,20 +171,97 @@ static cel_status validate(const cel_problem* pr) {
   return CEL_OK;
 }
 
+constexpr size_t kCacheCap = (size_t)8 << 30;   // device bytes a context keeps for reuse
+
+cel_status ctx_alloc(cel_ctx* c, size_t bytes, void** ptr, size_t* got) {
+  bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+  *ptr = nullptr;
+  if (c) {
+    auto it = c->cache.lower_bound(bytes);
+    if (it != c->cache.end() && it->first <= bytes + bytes / 4 + 65536) {
+      *ptr = it->second;
+      *got = it->first;
+      c->cache_bytes -= it->first;
+      c->cache.erase(it);
+      return CEL_OK;
+    }
+  }
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    *ptr = nullptr;
+    // drop the cache and try once more
+    if (c && !c->cache.empty()) {
+      (void)hipDeviceSynchronize();
+      for (auto& kv : c->cache) (void)hipFree(kv.second);
+      c->cache.clear();
+      c->cache_bytes = 0;
+      if (hipMalloc(ptr, bytes) == hipSuccess) {
+        *got = bytes;
+        return CEL_OK;
+      }
+    }
+    *ptr = nullptr;
+    return CEL_ENOMEM;
+  }
+  *got = bytes;
+  return CEL_OK;
+}
+
+void ctx_release(cel_ctx* c) {
+  if (!c || --c->refs > 0) return;
+  if (hipSetDevice(c->device) == hipSuccess) {
+    (void)hipDeviceSynchronize();
+    for (auto& kv : c->cache) (void)hipFree(kv.second);
+    for (HostKit& k : c->kits) {
+      if (k.mask_copied) (void)hipEventDestroy(k.mask_copied);
+      if (k.own_stream) (void)hipStreamDestroy(k.own_stream);
+      if (k.h_mask) (void)hipHostFree(k.h_mask);
+      if (k.h_counter) (void)hipHostFree(k.h_counter);
+      if (k.h_total) (void)hipHostFree(k.h_total);
+    }
+    if (c->d_err) (void)hipFree(c->d_err);
+  }
+  delete c;
+}
+
 void plan_release(cel_plan* p) {
   if (!p) return;
+  // work of this plan may still be in flight on the caller's streams: finish it before
+  // its memory is reused (one synchronisation instead of one per freed block)
+  if (!p->allocs.empty() || p->mask_copied) (void)hipDeviceSynchronize();
   for (auto& g : p->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
-  if (p->mask_copied) (void)hipEventDestroy(p->mask_copied);
-  if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
-  if (p->h_mask) (void)hipHostFree(p->h_mask);
-  if (p->h_counter) (void)hipHostFree(p->h_counter);
-  if (p->h_total) (void)hipHostFree(p->h_total);
-  for (void* ptr : p->allocs) (void)hipFree(ptr);
+  cel_ctx* c = p->ctx;
+  if (p->mask_copied) {
+    HostKit k;
+    k.h_mask = p->h_mask;
+    k.mask_cap = p->mask_cap;
+    k.h_counter = p->h_counter;
+    k.h_total = p->h_total;
+    k.mask_copied = p->mask_copied;
+    k.own_stream = p->own_stream;
+    if (c) {
+      c->kits.push_back(k);
+    } else {
+      (void)hipEventDestroy(k.mask_copied);
+      if (k.own_stream) (void)hipStreamDestroy(k.own_stream);
+      if (k.h_mask) (void)hipHostFree(k.h_mask);
+      if (k.h_counter) (void)hipHostFree(k.h_counter);
+      if (k.h_total) (void)hipHostFree(k.h_total);
+    }
+  }
+  for (auto& b : p->allocs) {
+    if (c && c->cache_bytes + b.bytes <= kCacheCap) {
+      c->cache.emplace(b.bytes, b.ptr);
+      c->cache_bytes += b.bytes;
+    } else {
+      (void)hipFree(b.ptr);
+    }
+  }
   for (auto& r : p->ev_rec)
     for (hipEvent_t e : r) p->ev_pool.push_back(e);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
+  ctx_release(c);
 }
 
 void phase_mark(cel_plan* p, int k, hipStream_t sm) {
@@ -228,16 +285,21 @@ void phase_mark(cel_plan* p, int k, hipStream_t sm) {
 
 template <typename X>
 static cel_status track(cel_plan* p, X** ptr, size_t n) {
-  cel_status st = dalloc(ptr, n);
-  if (!st) p->allocs.push_back((void*)*ptr);
+  void* q = nullptr;
+  size_t got = 0;
+  cel_status st = ctx_alloc(p->ctx, std::max<size_t>(n, 1) * sizeof(X), &q, &got);
+  *ptr = static_cast<X*>(q);
+  if (!st) p->allocs.push_back({q, got});
   return st;
 }
 
 template <typename X>
 static cel_status track_upload(cel_plan* p, X** ptr, const std::vector<X>& v) {
-  cel_status st = upload(ptr, v);
-  if (*ptr) p->allocs.push_back((void*)*ptr);
-  return st;
+  cel_status st = track(p, ptr, v.size());
+  if (st) return st;
+  if (!v.empty() && hipMemcpy(*ptr, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice) != hipSuccess)
+    return CEL_EHIP;
+  return CEL_OK;
 }
 
 // grow the per-variant scratch (tables, slots, per-source outputs) to hold nv variants
@@ -280,11 +342,30 @@ cel_status ensure_newton(cel_plan* p) {
       (st = track(p, &p->d_hess, S1 * kParamN * kParamN)))
     return st;
   if (hipMemset(p->d_trial_active, 0, S1) != hipSuccess) return CEL_EHIP;
-  if (hipHostMalloc((void**)&p->h_mask, S1, 0) != hipSuccess) return CEL_ENOMEM;
-  if (hipHostMalloc((void**)&p->h_counter, sizeof(int32_t), 0) != hipSuccess) return CEL_ENOMEM;
-  if (hipHostMalloc((void**)&p->h_total, sizeof(double), 0) != hipSuccess) return CEL_ENOMEM;
-  if (hipEventCreate(&p->mask_copied) != hipSuccess) return CEL_EHIP;
-  if (hipStreamCreate(&p->own_stream) != hipSuccess) return CEL_EHIP;
+  // pinned words, event and stream: a kit from a freed plan when one is there
+  HostKit k;
+  cel_ctx* c = p->ctx;
+  if (c && !c->kits.empty()) {
+    k = c->kits.back();
+    c->kits.pop_back();
+  }
+  if (k.mask_cap < S1) {
+    if (k.h_mask) (void)hipHostFree(k.h_mask);
+    k.h_mask = nullptr;
+    k.mask_cap = 0;
+    if (hipHostMalloc((void**)&k.h_mask, S1, 0) != hipSuccess) return CEL_ENOMEM;
+    k.mask_cap = S1;
+  }
+  if (!k.h_counter && hipHostMalloc((void**)&k.h_counter, sizeof(int32_t), 0) != hipSuccess) return CEL_ENOMEM;
+  if (!k.h_total && hipHostMalloc((void**)&k.h_total, sizeof(double), 0) != hipSuccess) return CEL_ENOMEM;
+  if (!k.mask_copied && hipEventCreate(&k.mask_copied) != hipSuccess) return CEL_EHIP;
+  if (!k.own_stream && hipStreamCreate(&k.own_stream) != hipSuccess) return CEL_EHIP;
+  p->h_mask = k.h_mask;
+  p->mask_cap = k.mask_cap;
+  p->h_counter = k.h_counter;
+  p->h_total = k.h_total;
+  p->mask_copied = k.mask_copied;
+  p->own_stream = k.own_stream;
   p->newton_ready = true;
   return CEL_OK;
 }
@@ -323,11 +404,7 @@ extern "C" cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_op
   return CEL_OK;
 }
 
-extern "C" void cel_destroy(cel_ctx* ctx) {
-  if (!ctx) return;
-  if (ctx->d_err && hipSetDevice(ctx->device) == hipSuccess) (void)hipFree(ctx->d_err);
-  delete ctx;
-}
+extern "C" void cel_destroy(cel_ctx* ctx) { ctx_release(ctx); }
 
 extern "C" cel_status cel_last_device_error(cel_ctx* ctx, int32_t* code) {
   if (!ctx || !code) return CEL_EINVAL;
@@ -356,6 +433,8 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   p->device = ctx->device;
   p->opt = ctx->opt;
   p->d_err = ctx->d_err;
+  p->ctx = ctx;
+  ++ctx->refs;
   const int S = pr->n_sources, N = pr->n_images, P = pr->n_patches;
   p->S = S;
   p->N = N;

@@ -3,14 +3,34 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <map>
 #include <vector>
 
 #include "device.h"
 
+// Pinned host words, event and stream of a plan's Newton calls (reused across plans).
+struct HostKit {
+  uint8_t* h_mask = nullptr;
+  size_t mask_cap = 0;
+  int32_t* h_counter = nullptr;
+  double* h_total = nullptr;
+  hipEvent_t mask_copied = nullptr;
+  hipStream_t own_stream = nullptr;
+};
+
+// A context owns the condition word and caches the device blocks and host kits of freed
+// plans, so that building a plan again (a serving loop rebuilds its merged plan whenever
+// the resident set changes) neither allocates nor frees device memory -- hipFree would
+// synchronise the device every time.  It lives until its handle and every plan made from
+// it are released.
 struct cel_ctx {
   int device;
   cel_options opt;
   int32_t* d_err = nullptr;       // device condition word (CEL_DEVERR_*), shared by the plans
+  int refs = 1;                   // the caller's handle + one per live plan
+  std::multimap<size_t, void*> cache;   // free device blocks by size
+  size_t cache_bytes = 0;
+  std::vector<HostKit> kits;
 };
 
 struct cel_plan {
@@ -91,7 +111,13 @@ struct cel_plan {
   int trial_variant = celmi::kVariants - 1;
   double* d_hslots = nullptr;     // analytic Hessian partial sums [n_tasks][80]
   double* d_hess = nullptr;       // per-source pixel Hessians [S][27][27]
-  std::vector<void*> allocs;
+  struct Block {
+    void* ptr;
+    size_t bytes;
+  };
+  std::vector<Block> allocs;
+  cel_ctx* ctx = nullptr;
+  size_t mask_cap = 0;
   // measurement: events per recorded evaluation (start, tables, maps, pixels, end)
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::array<hipEvent_t, 5>> ev_rec;
@@ -100,6 +126,9 @@ struct cel_plan {
 namespace celmi {
 cel_options default_options();
 void plan_release(cel_plan* p);
+void ctx_release(cel_ctx* c);
+// a device block of at least `bytes` from the context's cache, else newly allocated
+cel_status ctx_alloc(cel_ctx* c, size_t bytes, void** ptr, size_t* got);
 cel_status ensure_variants(cel_plan* p, int nv, bool fp64);
 hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv, bool grad, int cls,
                     const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64);
