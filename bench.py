@@ -282,7 +282,7 @@ def main():
                     algorithmic_flop_per_launch=flops, covering_pairs=pairs,
                     algorithmic_bytes_per_launch=bytes_fused,
                     achieved_hbm_GBps=round(bytes_fused / (kernel_ms * 1e-3) / 1e9, 1),
-                    map_kernel=dict(kernel="k_maps<float, 2 px/lane>", kernel_ms=round(maps_ms, 4),
+                    map_kernel=dict(kernel="k_maps<float, 8 px/lane>", kernel_ms=round(maps_ms, 4),
                                     achieved=round(units * FLOP_MAP / (maps_ms * 1e-3) / 1e12, 3),
                                     algorithmic_flop_per_launch=units * FLOP_MAP),
                     phases_ms=[round(x / nb, 4) for x in ms_phase])

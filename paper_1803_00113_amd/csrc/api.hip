@@ -687,7 +687,7 @@ static hipError_t launch_maps_t(cel_plan* p, const Table<T>* tables, hipStream_t
   ma.maps = sizeof(T) == 8 ? (void*)p->d_maps64 : (void*)p->d_maps;
   ma.img_npsf = p->d_npsf;
   // the value-only pass keeps 4 pixels per lane: more independent exponentials per wavefront
-  return launch_maps<T>(ma, p->nexp, p->ndev, 4, (int)p->map_order_h.size(), sm);
+  return launch_maps<T>(ma, p->nexp, p->ndev, 8, (int)p->map_order_h.size(), sm);
 }
 
 // Enqueue prep + fused + finalize for `nv` variants starting at variant v0 over either all

@@ -203,22 +203,31 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
       yy[i] = dy[i] * dy[i];
     }
     const T d2 = box_dist2<T>(mx, my, box);
+    // this PSF component's records and cut radii, read before any is used (one wait for
+    // all of them instead of one per component)
+    T rc[NEXP + NDEV], qv[NEXP + NDEV][4];
+#pragma unroll
+    for (int j = 0; j < NEXP + NDEV; ++j) {
+      const int c = j < NEXP ? j : kMaxProf + (j - NEXP);
+      rc[j] = tb->rc2[k][c];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) qv[j][e] = tb->gq[k][c][e];
+    }
     if (!(d2 > tb->rc2s[k])) {
 #pragma unroll
       for (int i = 0; i < PPL; ++i) f1[i] += comp_value<T>(tb->sq[k], xx[i], xy[i], yy[i]);
     }
 #pragma unroll
     for (int j = 0; j < NEXP; ++j) {
-      if (d2 > tb->rc2[k][j]) continue;
+      if (d2 > rc[j]) continue;
 #pragma unroll
-      for (int i = 0; i < PPL; ++i) fe[i] += comp_value<T>(tb->gq[k][j], xx[i], xy[i], yy[i]);
+      for (int i = 0; i < PPL; ++i) fe[i] += comp_value<T>(qv[j], xx[i], xy[i], yy[i]);
     }
 #pragma unroll
     for (int j = 0; j < NDEV; ++j) {
-      if (d2 > tb->rc2[k][kMaxProf + j]) continue;
+      if (d2 > rc[NEXP + j]) continue;
 #pragma unroll
-      for (int i = 0; i < PPL; ++i)
-        fd[i] += comp_value<T>(tb->gq[k][kMaxProf + j], xx[i], xy[i], yy[i]);
+      for (int i = 0; i < PPL; ++i) fd[i] += comp_value<T>(qv[NEXP + j], xx[i], xy[i], yy[i]);
     }
   }
   const T pi = tb->hdr[7];
@@ -746,6 +755,9 @@ hipError_t launch_maps(const MapArgs& a, int nexp, int ndev, int ppl, int n_item
   } else if (ppl == 4) {
     if (std_prof) hipLaunchKernelGGL((k_maps<T, 4, 6, 8>), dim3(n_items), dim3(64), 0, st, a);
     else hipLaunchKernelGGL((k_maps<T, 4, 8, 8>), dim3(n_items), dim3(64), 0, st, a);
+  } else if (ppl == 8) {
+    if (std_prof) hipLaunchKernelGGL((k_maps<T, 8, 6, 8>), dim3(n_items), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_maps<T, 8, 8, 8>), dim3(n_items), dim3(64), 0, st, a);
   } else {
     return hipErrorInvalidValue;
   }
