@@ -194,24 +194,39 @@ def serve_leg(log, rates=(20.0, 50.0, 100.0, 200.0), n_requests=200, pool=8):
     return out
 
 
-def cpu_baseline(prob, seconds):
+def cpu_baseline(prob, seconds, single_thread_seconds=5.0):
     """The float64 reference timed on the host's cores on the first sources of the same
-    workload until `seconds` have elapsed (local objective + gradient of each source)."""
+    workload until `seconds` have elapsed (local objective + gradient of each source), and
+    the same on one thread for `single_thread_seconds`."""
     import torch
     from oracle import elbo as E
     m = E.Model(prob)
-    t0 = time.perf_counter()
-    units, n = 0, 0
-    for s in range(prob.n_sources):
-        E.local_value_grad(m, prob.theta0, s)
-        units += int(sum(prob.patch_w[p] * prob.patch_h[p] for p in m.patches_of[s]))
-        n += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=units / dt, unit="active-pixel evals/s", cores=int(torch.get_num_threads()), kind="oracle",
-                sample=f"local ELBO + gradient of the first {n} of {prob.n_sources} sources ({units} active "
-                       f"pixels, {dt:.1f} s), float64 PyTorch CPU")
+
+    def timed(limit):
+        t0 = time.perf_counter()
+        units, n = 0, 0
+        for s in range(prob.n_sources):
+            E.local_value_grad(m, prob.theta0, s)
+            units += int(sum(prob.patch_w[p] * prob.patch_h[p] for p in m.patches_of[s]))
+            n += 1
+            if time.perf_counter() - t0 > limit:
+                break
+        return units, n, time.perf_counter() - t0
+
+    threads = int(torch.get_num_threads())
+    units, n, dt = timed(seconds)
+    out = dict(value=units / dt, unit="active-pixel evals/s", cores=threads, kind="oracle",
+               sample=f"local ELBO + gradient of the first {n} of {prob.n_sources} sources ({units} active "
+                      f"pixels, {dt:.1f} s), float64 PyTorch CPU, {threads} threads")
+    if single_thread_seconds > 0:
+        torch.set_num_threads(1)
+        try:
+            u1, n1, dt1 = timed(single_thread_seconds)
+        finally:
+            torch.set_num_threads(threads)
+        out["single_thread_value"] = u1 / dt1
+        out["single_thread_sample"] = f"first {n1} sources ({u1} active pixels, {dt1:.1f} s), 1 thread"
+    return out
 
 
 def main():
