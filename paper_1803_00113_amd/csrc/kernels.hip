@@ -282,6 +282,7 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
     o.fe[i] = o.gex[i] = o.gey[i] = o.sexx[i] = o.sexy[i] = o.seyy[i] = (T)0;
     o.fd[i] = o.gdx[i] = o.gdy[i] = o.sdxx[i] = o.sdxy[i] = o.sdyy[i] = (T)0;
   }
+  __builtin_assume(K >= 1);   // images have 1..kMaxPsf PSF components (checked at prepare)
   for (int k = 0; k < K; ++k) {
     const T mx = tb->star[k][0], my = tb->star[k][1];
     T dx[PPL], dy[PPL], z[PPL];
@@ -367,27 +368,41 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
   const Table<T>* __restrict__ tb = a.own + (int64_t)v * a.variant_stride + task.patch;
   const int K = a.img_npsf[P.img];
   const int lane = threadIdx.x;
-  const float inv_w = 1.0f / (float)P.w;
   const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
   const T k0 = tb->hdr[4], k1 = tb->hdr[5], w01 = tb->hdr[6], pi = tb->hdr[7];
-  double acc[13];
+  // objective sums in FP64 per lane.  The 11 gradient sums are kept per lane in the pixel
+  // precision over at most kFlush pixel groups, then summed over the wavefront in FP64 into
+  // the work item's slot row (so a lane's partial sum never spans more than kFlush * PPL
+  // pixels, whatever the chunk size)
+  constexpr int kFlush = 4;
+  double acc_t = 0.0, acc_own = 0.0;
+  T part[S_T];
 #pragma unroll
-  for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+  for (int q = 0; q < S_T; ++q) part[q] = (T)0;
+  double* out = a.slots + (int64_t)blockIdx.y * a.slot_variant_stride + (int64_t)t * kSlots;
+  // patch-local coordinates of this lane's pixels, advanced by 64*PPL pixels per group:
+  // one integer division at the start, then a carry
+  const int step = 64 * PPL;
+  const int step_rows = step / P.w, step_cols = step - step_rows * P.w;
+  T px[PPL], py[PPL];
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const int idx = task.pix_begin + i * 64 + lane;
+    const int row = idx / P.w;
+    px[i] = (T)(idx - row * P.w);
+    py[i] = (T)row;
+  }
+  const T wT = (T)P.w, srT = (T)step_rows, scT = (T)step_cols;
+  int group = 0;
 
-  for (int base = task.pix_begin; base < task.pix_end; base += 64 * PPL) {
-    T px[PPL], py[PPL], xv[PPL], sky[PPL];
+  for (int base = task.pix_begin; base < task.pix_end; base += step, ++group) {
+    T xv[PPL], sky[PPL];
     bool valid[PPL];
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
       int idx = base + i * 64 + lane;
       valid[i] = idx < task.pix_end;
       if (!valid[i]) idx = task.pix_begin;
-      int row = (int)(((float)idx + 0.5f) * inv_w);
-      int col = idx - row * P.w;
-      if (col < 0) { row -= 1; col += P.w; }
-      else if (col >= P.w) { row += 1; col -= P.w; }
-      px[i] = (T)col;
-      py[i] = (T)row;
       if constexpr (sizeof(T) == 8) {
         const double2 xs = reinterpret_cast<const double2*>(a.xs)[P.off + idx];
         xv[i] = (T)xs.x;
@@ -402,7 +417,7 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
     T f0[PPL], f1[PPL];
     OwnPix<T, PPL> o;
     T box[4];
-    run_box<T>(base, min(base + 64 * PPL, task.pix_end), P.w, box);
+    run_box<T>(base, min(base + step, task.pix_end), P.w, box);
     eval_own<T, PPL, NEXP, NDEV, GRAD>(tb, htau, K, px, py, box, o);
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
@@ -449,12 +464,12 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
       const T x = xv[i];
-      const T invE = (T)1 / E[i];
+      const T invE = frcp<T>(E[i]);
       const T xr = x * invE * invE;
-      T Tm = (x > (T)0 ? x * flog<T>(E[i] / x) : (T)0) - (E[i] - x) - (T)0.5 * xr * V[i];
+      T Tm = (x > (T)0 ? x_log_ratio<T>(x, E[i]) : (T)0) - (E[i] - x) - (T)0.5 * xr * V[i];
       if (!valid[i]) Tm = (T)0;
-      acc[S_T] += (double)Tm;
-      acc[S_T_OWN] += own[i] ? (double)Tm : 0.0;
+      acc_t += (double)Tm;
+      acc_own += own[i] ? (double)Tm : 0.0;
       if (GRAD) {
         T cE = fma(xr * invE, V[i], (x - E[i]) * invE);
         T cV = (T)-0.5 * xr;
@@ -466,26 +481,47 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
         const T s0xx = pi * o.sdxx[i] + omp * o.sexx[i];
         const T s0xy = (T)2 * (pi * o.sdxy[i] + omp * o.sexy[i]);
         const T s0yy = pi * o.sdyy[i] + omp * o.seyy[i];
-        acc[S_CE_F0] += (double)(cE * f0[i]);
-        acc[S_CE_F1] += (double)(cE * f1[i]);
-        acc[S_CV_F00] += (double)(cV * f0[i] * f0[i]);
-        acc[S_CV_F11] += (double)(cV * f1[i] * f1[i]);
-        acc[S_CV_F01] += (double)(cV * f0[i] * f1[i]);
-        acc[S_MU_X] += (double)fma(rho0, g0x, rho1 * o.g1x[i]);
-        acc[S_MU_Y] += (double)fma(rho0, g0y, rho1 * o.g1y[i]);
-        acc[S_S_XX] += (double)(rho0 * s0xx);
-        acc[S_S_XY] += (double)(rho0 * s0xy);
-        acc[S_S_YY] += (double)(rho0 * s0yy);
-        acc[S_PI] += (double)(rho0 * (o.fd[i] - o.fe[i]));
+        const T cVf0 = cV * f0[i], cVf1 = cV * f1[i];
+        part[S_CE_F0] = fma(cE, f0[i], part[S_CE_F0]);
+        part[S_CE_F1] = fma(cE, f1[i], part[S_CE_F1]);
+        part[S_CV_F00] = fma(cVf0, f0[i], part[S_CV_F00]);
+        part[S_CV_F11] = fma(cVf1, f1[i], part[S_CV_F11]);
+        part[S_CV_F01] = fma(cVf0, f1[i], part[S_CV_F01]);
+        part[S_MU_X] = fma(rho0, g0x, fma(rho1, o.g1x[i], part[S_MU_X]));
+        part[S_MU_Y] = fma(rho0, g0y, fma(rho1, o.g1y[i], part[S_MU_Y]));
+        part[S_S_XX] = fma(rho0, s0xx, part[S_S_XX]);
+        part[S_S_XY] = fma(rho0, s0xy, part[S_S_XY]);
+        part[S_S_YY] = fma(rho0, s0yy, part[S_S_YY]);
+        part[S_PI] = fma(rho0, o.fd[i] - o.fe[i], part[S_PI]);
       }
     }
-  }
-  double* out = a.slots + (int64_t)blockIdx.y * a.slot_variant_stride + (int64_t)t * kSlots;
+    if (GRAD && (group % kFlush == kFlush - 1 || base + step >= task.pix_end)) {
+      const bool first = group < kFlush;
 #pragma unroll
-  for (int q = 0; q < 13; ++q) {
-    if (!GRAD && q != S_T && q != S_T_OWN) continue;
-    const double s = wave_sum<T>(acc[q]);
-    if (lane == 0) out[q] = s;
+      for (int q = 0; q < S_T; ++q) {
+        const double s = wave_sum<T>((double)part[q]);
+        if (lane == 0) out[q] = first ? s : out[q] + s;
+        part[q] = (T)0;
+      }
+    }
+    // next group: advance each lane's coordinates by step pixels
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      T c = px[i] + scT, r = py[i] + srT;
+      if (c >= wT) {
+        c -= wT;
+        r += (T)1;
+      }
+      px[i] = c;
+      py[i] = r;
+    }
+  }
+  const double s_t = wave_sum<T>(acc_t), s_own = wave_sum<T>(acc_own);
+  if (lane == 0) {
+    out[S_T] = s_t;
+    out[S_T_OWN] = s_own;
+    if (GRAD && task.pix_begin >= task.pix_end)
+      for (int q = 0; q < S_T; ++q) out[q] = 0.0;
   }
 }
 

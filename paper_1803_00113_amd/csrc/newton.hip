@@ -375,9 +375,9 @@ __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
     const T k0 = w0 * L0 * L0 * e0, k1 = w1 * L1 * L1 * e1;
     const T Vs = fma(k0 * f0, f0, fma(k1 * f1, f1, w01 * d * d));
     const T E = Eb + Es, V = Vb + Vs, x = xv;
-    const T invE = (T)1 / E;
+    const T invE = frcp<T>(E);
     const T xr = x * invE * invE;
-    T Tm = (x > (T)0 ? x * flog<T>(E / x) : (T)0) - (E - x) - (T)0.5 * xr * V;
+    T Tm = (x > (T)0 ? x_log_ratio<T>(x, E) : (T)0) - (E - x) - (T)0.5 * xr * V;
     T cE = fma(xr * invE, V, (x - E) * invE);
     T cV = (T)-0.5 * xr;
     T TEE = -xr - (T)3 * xr * V * invE * invE;

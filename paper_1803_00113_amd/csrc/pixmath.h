@@ -13,9 +13,28 @@ namespace celmi {
 template <typename T> __device__ __forceinline__ T fexp2(T x);
 template <> __device__ __forceinline__ float fexp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
 template <> __device__ __forceinline__ double fexp2<double>(double x) { return exp2(x); }
-template <typename T> __device__ __forceinline__ T flog(T x);
-template <> __device__ __forceinline__ float flog<float>(float x) { return logf(x); }
-template <> __device__ __forceinline__ double flog<double>(double x) { return log(x); }
+
+constexpr double kLn2 = 0.69314718055994530942;
+
+// x log(E/x) for a count x > 0 and a rate E > 0: the part of the centred Poisson term that
+// cancels against E - x, so the quotient must be accurate to the last bit or two.  float:
+// the quotient from the hardware reciprocal with one residual correction (within an ulp of
+// E/x for normal operands), the logarithm from the hardware log2 (operands here are
+// normal: x >= 1, E at least the patch's smallest sky value); double: library division
+// and logarithm.
+template <typename T> __device__ __forceinline__ T x_log_ratio(T x, T E);
+template <> __device__ __forceinline__ float x_log_ratio<float>(float x, float E) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  float q = E * r;
+  q = fmaf(fmaf(-x, q, E), r, q);
+  return x * (__builtin_amdgcn_logf(q) * (float)kLn2);
+}
+template <> __device__ __forceinline__ double x_log_ratio<double>(double x, double E) { return x * log(E / x); }
+
+// 1/E for the adjoint coefficients (float: hardware reciprocal, within 1 ulp)
+template <typename T> __device__ __forceinline__ T frcp(T E);
+template <> __device__ __forceinline__ float frcp<float>(float E) { return __builtin_amdgcn_rcpf(E); }
+template <> __device__ __forceinline__ double frcp<double>(double E) { return 1.0 / E; }
 
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLog2TwoPi = 2.6514961294723187980;   // log2(2 pi)
