@@ -416,8 +416,9 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
     // own source
     T f0[PPL], f1[PPL];
     OwnPix<T, PPL> o;
-    T box[4];
-    run_box<T>(base, min(base + step, task.pix_end), P.w, box);
+    int ibox[4];
+    run_box<int>(base, min(base + step, task.pix_end), P.w, ibox);
+    const T box[4] = {(T)ibox[0], (T)ibox[1], (T)ibox[2], (T)ibox[3]};
     eval_own<T, PPL, NEXP, NDEV, GRAD>(tb, htau, K, px, py, box, o);
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
@@ -435,17 +436,26 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
       own[i] = true;
     }
     // neighbours whose patch in this image covers the pixel (Section 2.2.3: the rate sums
-    // over sources): their moments E_t, V_t at the pixel come from the per-patch maps
+    // over sources): their moments E_t, V_t at the pixel come from the per-patch maps.  A
+    // neighbour whose rectangle misses the wavefront's pixel box is skipped as a whole.
+    int ix[PPL], iy[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      ix[i] = (int)px[i];
+      iy[i] = (int)py[i];
+    }
     for (int nb = P.nbr_begin; nb < P.nbr_end; ++nb) {
       const DPatch Q = a.patches[a.nbr_idx[nb]];
       const int ox = P.x0 - Q.x0, oy = P.y0 - Q.y0;
+      if (ibox[0] + ox >= Q.w || ibox[1] + ox < 0 || ibox[2] + oy >= Q.h || ibox[3] + oy < 0) continue;
       const bool lower = Q.src < P.src;
+      const int64_t qoff = Q.off;
 #pragma unroll
       for (int i = 0; i < PPL; ++i) {
-        const int cx = (int)px[i] + ox, cy = (int)py[i] + oy;
-        const bool in = valid[i] && cx >= 0 && cx < Q.w && cy >= 0 && cy < Q.h;
+        const int cx = ix[i] + ox, cy = iy[i] + oy;
+        const bool in = valid[i] && (unsigned)cx < (unsigned)Q.w && (unsigned)cy < (unsigned)Q.h;
         if (in) {
-          const int64_t at = Q.off + (int64_t)cy * Q.w + cx;
+          const int64_t at = qoff + (cy * Q.w + cx);
           if constexpr (sizeof(T) == 8) {
             const double2 ev = reinterpret_cast<const double2*>(a.maps)[at];
             E[i] += (T)ev.x;
@@ -622,11 +632,12 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
     for (int k = 0; k < 3; ++k) gS[k] = wave_sum<double>(gS[k]);
     gpi = wave_sum<double>(gpi);
   }
-  if (lane != 0) return;
   // the central-difference variants (1..54) carry the pixel part of the gradient only: the
   // KL part of the Hessian is taken analytically by the trust-region kernel
   const bool fd_variant = a.fd && v >= 1 && v <= 2 * kParamN;
-  double kl = kl_source(*a.prior, th, g, fd_variant ? 0.0 : 1.0);   // subtracts the KL gradient
+  // KL by the whole wavefront; subtracts the KL gradient
+  const double kl = kl_source_wave(*a.prior, th, g, fd_variant ? 0.0 : 1.0, lane);
+  if (lane != 0) return;
   local -= kl;
   own -= kl;
   if (a.want_grad) {

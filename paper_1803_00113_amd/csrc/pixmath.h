@@ -130,11 +130,123 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Colour bound of type i (Section 4.2.3 at its optimal weights): the value
+// -log sum_j w_j exp(-D_j) and its gradient, with respect to the colour means (gm) and the
+// log colour variances (gv), summed over the prior components j (weights xi_j).
+__device__ inline double colour_bound(const DPrior& pr, const double* th, int i, double* gm, double* gv) {
+  double cm[4], cv[4], lcv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    cm[k] = th[7 + 4 * i + k];
+    lcv[k] = th[15 + 4 * i + k];
+    cv[k] = exp(lcv[k]);
+    gm[k] = gv[k] = 0.0;
+  }
+  double D[CEL_N_COLOUR_COMPONENTS], mx = -1e300;
+  const double sum_lcv = lcv[0] + lcv[1] + lcv[2] + lcv[3];
+#pragma unroll
+  for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+    double tr = 0, maha = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      tr += pr.c_prec[i][j][k][k] * cv[k];
+      double row = 0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
+      maha += (pr.c_mean[i][j][k] - cm[k]) * row;
+    }
+    D[j] = 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - sum_lcv);
+    const double e = pr.c_logw[i][j] - D[j];
+    if (e > mx) mx = e;
+  }
+  double z = 0;
+#pragma unroll
+  for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - D[j] - mx);
+#pragma unroll
+  for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+    const double xi = exp(pr.c_logw[i][j] - D[j] - mx) / z;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double row = 0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
+      gm[k] += xi * row;
+      gv[k] += xi * 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
+    }
+  }
+  return -(mx + log(z));
+}
+
+// The same colour bounds computed by a whole wavefront (all 64 lanes active): lane 8 i + j
+// takes prior component j of type i (lanes 16..63 repeat lanes 0..15), the maximum,
+// normaliser and gradient sums are combined by fixed butterflies within each group of 8
+// lanes, and every lane receives both types' results.
+__device__ inline void colour_bound_wave(const DPrior& pr, const double* th, int lane, double* kc, double (*gm)[4],
+                                         double (*gv)[4]) {
+  static_assert(CEL_N_COLOUR_COMPONENTS == 8, "one lane per prior colour component, groups of 8");
+  const int i = (lane >> 3) & 1, j = lane & 7;
+  double cm[4], cv[4], lcv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {   // selects, not a lane-dependent index into th
+    cm[k] = i ? th[11 + k] : th[7 + k];
+    lcv[k] = i ? th[19 + k] : th[15 + k];
+    cv[k] = exp(lcv[k]);
+  }
+  const double sum_lcv = lcv[0] + lcv[1] + lcv[2] + lcv[3];
+  double tr = 0, maha = 0, row[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    tr += pr.c_prec[i][j][k][k] * cv[k];
+    double r = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) r += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
+    row[k] = r;
+    maha += (cm[k] - pr.c_mean[i][j][k]) * r;
+  }
+  const double e = pr.c_logw[i][j] - 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - sum_lcv);
+  double mx = e;
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  const double ex = exp(e - mx);
+  double z = ex;
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) z += __shfl_xor(z, off, 64);
+  const double xi = ex / z;
+  double part[9];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    part[k] = xi * row[k];
+    part[4 + k] = xi * 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
+  }
+  part[8] = -(mx + log(z));
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) part[q] += __shfl_xor(part[q], off, 64);
+  }
+  // this lane's group holds type i; the other type comes from the group 8 lanes away
+  double other[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) other[q] = __shfl_xor(part[q], 8, 64);
+  const bool first = i == 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    gm[0][k] = first ? part[k] : other[k];
+    gm[1][k] = first ? other[k] : part[k];
+    gv[0][k] = first ? part[4 + k] : other[4 + k];
+    gv[1][k] = first ? other[4 + k] : part[4 + k];
+  }
+  kc[0] = first ? part[8] : other[8];
+  kc[1] = first ? other[8] : part[8];
+}
+
 // KL(q(z_s) || p(z_s)) and its gradient in the unconstrained coordinates (equations eq:kl,
 // kleq; Supplement A with the readings: flux KL is the normal KL of log r with variances;
 // colour KL is the bound of Section 4.2.3 at its optimal weights; point-mass terms are
-// minus the log prior density; direction and angle terms are constants and dropped).
-__device__ inline double kl_source(const DPrior& pr, const double* th, double* g, double gs) {
+// minus the log prior density; direction and angle terms are constants and dropped), given
+// the colour bounds kc and their gradients.  Subtracts gs times the gradient from g.
+__device__ inline double kl_assemble(const DPrior& pr, const double* th, double* g, double gs, const double* kc,
+                                     const double (*gm)[4], const double (*gv)[4]) {
   const double eta = th[2];
   const double a = sigmoid(eta);
   const double log_a = -softplus(-eta), log_1ma = -softplus(eta);
@@ -146,51 +258,15 @@ __device__ inline double kl_source(const DPrior& pr, const double* th, double* g
   for (int i = 0; i < 2; ++i) {
     const double rm = th[3 + i], lrv = th[5 + i], rv = exp(lrv);
     const double R1 = pr.r[i][0], R2 = pr.r[i][1];
-    double kr = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
+    const double kr = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
     g[3 + i] -= gs * q[i] * (rm - R1) / R2;
     g[5 + i] -= gs * q[i] * (-0.5 + rv / (2.0 * R2));
-    // colour bound: -log sum_j w_j exp(-D_j); gradient sum_j xi_j dD_j
-    double cm[4], cv[4], lcv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      cm[k] = th[7 + 4 * i + k];
-      lcv[k] = th[15 + 4 * i + k];
-      cv[k] = exp(lcv[k]);
+      g[7 + 4 * i + k] -= gs * q[i] * gm[i][k];
+      g[15 + 4 * i + k] -= gs * q[i] * gv[i][k];
     }
-    double D[CEL_N_COLOUR_COMPONENTS], mx = -1e300;
-    double sum_lcv = lcv[0] + lcv[1] + lcv[2] + lcv[3];
-#pragma unroll
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
-      double tr = 0, maha = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        tr += pr.c_prec[i][j][k][k] * cv[k];
-        double row = 0;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
-        maha += (pr.c_mean[i][j][k] - cm[k]) * row;
-      }
-      D[j] = 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - sum_lcv);
-      const double e = pr.c_logw[i][j] - D[j];
-      if (e > mx) mx = e;
-    }
-    double z = 0;
-#pragma unroll
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - D[j] - mx);
-    const double kc = -(mx + log(z));
-#pragma unroll
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
-      const double xi = exp(pr.c_logw[i][j] - D[j] - mx) / z;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double row = 0;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
-        g[7 + 4 * i + k] -= gs * q[i] * xi * row;
-        g[15 + 4 * i + k] -= gs * q[i] * xi * 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
-      }
-    }
-    part[i] = kr + kc;
+    part[i] = kr + kc[i];
     kl += q[i] * part[i];
   }
   dk_da += part[1] - part[0];
@@ -211,6 +287,22 @@ __device__ inline double kl_source(const DPrior& pr, const double* th, double* g
     g[26] -= gs * (-(pr.axis[0] - 1.0) * (1.0 - p) + (pr.axis[1] - 1.0) * p);
   }
   return kl;
+}
+
+// KL and gradient by one lane
+__device__ inline double kl_source(const DPrior& pr, const double* th, double* g, double gs) {
+  double kc[2], gm[2][4], gv[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) kc[i] = colour_bound(pr, th, i, gm[i], gv[i]);
+  return kl_assemble(pr, th, g, gs, kc, gm, gv);
+}
+
+// KL and gradient by a whole wavefront (all lanes active; every lane gets the value and
+// applies the gradient to its own g)
+__device__ inline double kl_source_wave(const DPrior& pr, const double* th, double* g, double gs, int lane) {
+  double kc[2], gm[2][4], gv[2][4];
+  colour_bound_wave(pr, th, lane, kc, gm, gv);
+  return kl_assemble(pr, th, g, gs, kc, gm, gv);
 }
 
 }  // namespace celmi
