@@ -61,34 +61,62 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
   // position in patch-local pixel coordinates: mu = A u + b - (x0, y0)
   const double mux = im.A[0][0] * th[0] + im.A[0][1] * th[1] + im.b[0] - P.x0;
   const double muy = im.A[1][0] * th[0] + im.A[1][1] * th[1] + im.b[1] - P.y0;
+  // The source's exponentials are taken one per lane and broadcast, so that the exp code
+  // runs once per wavefront instead of once per value: lanes 0-1 the flux variances, 2-9
+  // the colour variances, 10 the radius, 11-13 exp(-x) of the type, axis and profile
+  // logits (sigmoid(x) = 1 / (1 + exp(-x))).
+  double earg = 0.0;
+#pragma unroll
+  for (int l = 0; l < 14; ++l) {
+    const double x = l < 2 ? th[5 + l] : l < 10 ? th[15 + (l - 2)] : l == 10 ? th[24] : l == 11 ? -th[2]
+                     : l == 12 ? -th[26] : -th[25];
+    earg = lane == l ? x : earg;
+  }
+  double eval = exp(earg);
+  if (lane >= 11 && lane <= 13) eval = 1.0 / (1.0 + eval);
+  double ex[14];
+#pragma unroll
+  for (int l = 0; l < 14; ++l) ex[l] = __shfl(eval, l, 64);
   double sig[3];
-  galaxy_cov(th[23], exp(th[24]), sigmoid(th[26]), sig);
+  galaxy_cov(th[23], ex[10], ex[12], sig);
   // pixel-frame galaxy covariance S = A Sigma A^T
   const double a00 = im.A[0][0], a01 = im.A[0][1], a10 = im.A[1][0], a11 = im.A[1][1];
   const double t00 = a00 * sig[0] + a01 * sig[1], t01 = a00 * sig[1] + a01 * sig[2];
   const double t10 = a10 * sig[0] + a11 * sig[1], t11 = a10 * sig[1] + a11 * sig[2];
   const double Sxx = t00 * a00 + t01 * a01, Sxy = t00 * a10 + t01 * a11, Syy = t10 * a10 + t11 * a11;
   const int K = im.n_psf;
-  // flux moments given the type (equation conditional): log l ~ N(m, v) (every lane: the
-  // component cuts below scale with them)
-  const double aa = sigmoid(th[2]);
+  // flux moments given the type (equation conditional): log l ~ N(m, v)
+  const double aa = ex[11];
   const double w[2] = {1.0 - aa, aa};
-  double L[2], kk[2], ee[2];
+  double m[2], var[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    double m = th[3 + i], var = exp(th[5 + i]);
+    m[i] = th[3 + i];
+    var[i] = ex[i];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double W = c_W[im.band][c];
-      m += W * th[7 + 4 * i + c];
-      var += W * W * exp(th[15 + 4 * i + c]);
+      m[i] += W * th[7 + 4 * i + c];
+      var[i] += W * W * ex[2 + 4 * i + c];
     }
-    L[i] = im.iota * exp(m + 0.5 * var);
-    ee[i] = expm1(var);
+  }
+  // lanes 0-1: exp(m + v/2); lanes 2-3: expm1(v); then broadcast
+  const int li = lane & 1;
+  const double mi = li ? m[1] : m[0], vi = li ? var[1] : var[0];
+  const double ev2 = lane < 2 ? exp(mi + 0.5 * vi) : expm1(vi);
+  double L[2], kk[2], ee[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    L[i] = im.iota * __shfl(ev2, i, 64);
+    ee[i] = __shfl(ev2, 2 + i, 64);
     kk[i] = w[i] * L[i] * L[i] * ee[i];
   }
+  // component cuts below scale with the flux: log2 of L0, L1 and the sky minimum, one per lane
   const double smin = a.sky_min ? a.sky_min[pi_] : 0.0;
-  const double cut_gal = density_cut_log2<T>(L[0], smin), cut_star = density_cut_log2<T>(L[1], smin);
+  const double larg = lane == 0 ? L[0] : lane == 1 ? L[1] : smin;
+  const double lg = log2(larg);
+  const double cut_gal = density_cut_log2<T>(L[0], smin, __shfl(lg, 0, 64), __shfl(lg, 2, 64));
+  const double cut_star = density_cut_log2<T>(L[1], smin, __shfl(lg, 1, 64), __shfl(lg, 2, 64));
   if (lane == 0) {
     tb->hdr[8] = (T)ee[0];
     tb->hdr[9] = (T)ee[1];
@@ -99,83 +127,72 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
     tb->hdr[4] = (T)kk[0];
     tb->hdr[5] = (T)kk[1];
     tb->hdr[6] = (T)(w[0] * w[1]);
-    tb->hdr[7] = (T)sigmoid(th[25]);
+    tb->hdr[7] = (T)ex[13];
     tb->hdr[10] = (T)mux;
     tb->hdr[11] = (T)muy;
   }
   // components: 4 star slots then 4 x 16 galaxy slots
   for (int c = lane; c < kMaxPsf + kMaxPsf * 2 * kMaxProf; c += 64) {
-    if (c < kMaxPsf) {
-      const int k = c;
+    // a star slot (c < kMaxPsf) or a galaxy slot: the same 2x2 algebra, one code path
+    const bool star = c < kMaxPsf;
+    const int g = c - kMaxPsf;
+    const int k = star ? c : g / (2 * kMaxProf), j = star ? 0 : g % (2 * kMaxProf);
+    const bool isdev = j >= kMaxProf;
+    const int jj = isdev ? j - kMaxProf : j;
+    const int nj = isdev ? a.prof->n_dev : a.prof->n_exp;
+    const bool used = k < K && (star || jj < nj);
+    double tau = 0.0, Pxx = 0.0, Pxy = 0.0, Pyy = 0.0, lw = kNegHuge, rc2 = -1.0;
+    if (used) {   // (an iteration whose slots are all unused skips the math)
+      const int pj = isdev ? a.prof->n_exp + jj : jj;
+      tau = star ? 0.0 : a.prof->tau[pj];
+      const double alpha = star ? 1.0 : a.prof->alpha[pj];
+      const double cxx = im.psf[k][3] + tau * Sxx, cxy = im.psf[k][4] + tau * Sxy, cyy = im.psf[k][5] + tau * Syy;
+      const double det = cxx * cyy - cxy * cxy, rdet = 1.0 / det;
+      const double wt = im.psf[k][0] * alpha;
+      Pxx = cyy * rdet;
+      Pxy = -cxy * rdet;
+      Pyy = cxx * rdet;
+      // log2 of weight / (2 pi sqrt(det))
+      lw = wt > 0 ? log2(wt * sqrt(rdet)) - kLog2TwoPi : kNegHuge;
+      rc2 = cut_radius2(lw, cxx, cxy, cyy, star ? cut_star : cut_gal);
+    }
+    const double hl = -0.5 * kLog2e;
+    const T qv[4] = {(T)(hl * Pxx), (T)(hl * Pxy), (T)(hl * Pyy), (T)lw};
+    const T pv[3] = {(T)Pxx, (T)Pxy, (T)Pyy};
+    if (star) {
       T* r = tb->star[k];
-      if (k < K) {
-        const double cxx = im.psf[k][3], cxy = im.psf[k][4], cyy = im.psf[k][5];
-        const double det = cxx * cyy - cxy * cxy;
-        r[0] = (T)(mux + im.psf[k][1]);
-        r[1] = (T)(muy + im.psf[k][2]);
-        r[2] = (T)(cyy / det);
-        r[3] = (T)(-cxy / det);
-        r[4] = (T)(cxx / det);
-        const double lw = im.psf[k][0] > 0 ? log2(im.psf[k][0]) - kLog2TwoPi - 0.5 * log2(det) : kNegHuge;
-        r[5] = (T)lw;
-        tb->rc2s[k] = (T)cut_radius2(lw, cxx, cxy, cyy, cut_star);
-        const double hl = -0.5 * kLog2e;
-        tb->sq[k][0] = (T)(hl * cyy / det);
-        tb->sq[k][1] = (T)(hl * -cxy / det);
-        tb->sq[k][2] = (T)(hl * cxx / det);
-        tb->sq[k][3] = (T)lw;
-        tb->off[k][0] = (T)im.psf[k][1];
-        tb->off[k][1] = (T)im.psf[k][2];
-      } else {
-        r[0] = r[1] = r[2] = r[3] = r[4] = (T)0;
-        r[5] = (T)kNegHuge;
-        tb->rc2s[k] = (T)-1;
-        tb->sq[k][0] = tb->sq[k][1] = tb->sq[k][2] = (T)0;
-        tb->sq[k][3] = (T)kNegHuge;
-        tb->off[k][0] = tb->off[k][1] = (T)0;
-      }
+      const double ox = used ? im.psf[k][1] : 0.0, oy = used ? im.psf[k][2] : 0.0;
+      r[0] = (T)(used ? mux + ox : 0.0);
+      r[1] = (T)(used ? muy + oy : 0.0);
+      r[2] = pv[0];
+      r[3] = pv[1];
+      r[4] = pv[2];
+      r[5] = (T)lw;
       r[6] = r[7] = (T)0;
+      tb->rc2s[k] = (T)rc2;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tb->sq[k][e] = qv[e];
+      tb->off[k][0] = (T)ox;
+      tb->off[k][1] = (T)oy;
     } else {
-      const int k = (c - kMaxPsf) / (2 * kMaxProf), j = (c - kMaxPsf) % (2 * kMaxProf);
       T* r = tb->gal[k][j];
-      const bool isdev = j >= kMaxProf;
-      const int jj = isdev ? j - kMaxProf : j;
-      const int nj = isdev ? a.prof->n_dev : a.prof->n_exp;
-      if (k < K && jj < nj) {
-        const double tau = a.prof->tau[isdev ? a.prof->n_exp + jj : jj];
-        const double alpha = a.prof->alpha[isdev ? a.prof->n_exp + jj : jj];
-        const double cxx = im.psf[k][3] + tau * Sxx, cxy = im.psf[k][4] + tau * Sxy, cyy = im.psf[k][5] + tau * Syy;
-        const double det = cxx * cyy - cxy * cxy;
-        const double wt = im.psf[k][0] * alpha;
-        r[0] = (T)(cyy / det);
-        r[1] = (T)(-cxy / det);
-        r[2] = (T)(cxx / det);
-        const double lw = wt > 0 ? log2(wt) - kLog2TwoPi - 0.5 * log2(det) : kNegHuge;
-        r[3] = (T)lw;
-        tb->rc2[k][j] = (T)cut_radius2(lw, cxx, cxy, cyy, cut_gal);
-        const double hl = -0.5 * kLog2e;
-        tb->gq[k][j][0] = (T)(hl * cyy / det);
-        tb->gq[k][j][1] = (T)(hl * -cxy / det);
-        tb->gq[k][j][2] = (T)(hl * cxx / det);
-        tb->gq[k][j][3] = (T)lw;
-        const double Pxx = cyy / det, Pxy = -cxy / det, Pyy = cxx / det, h = 0.5 * tau * tau;
-        T* q = tb->gt[k][j];
-        q[0] = (T)tau;
-        q[1] = (T)(tau * tau);
-        q[2] = (T)(h * Pxx * Pxx);
-        q[3] = (T)(h * 2.0 * Pxx * Pxy);
-        q[4] = (T)(h * Pxy * Pxy);
-        q[5] = (T)(h * (2.0 * Pxy * Pxy + 2.0 * Pxx * Pyy));
-        q[6] = (T)(h * 2.0 * Pxy * Pyy);
-        q[7] = (T)(h * Pyy * Pyy);
-      } else {
-        r[0] = r[1] = r[2] = (T)0;
-        r[3] = (T)kNegHuge;
-        tb->rc2[k][j] = (T)-1;
-        for (int e = 0; e < 8; ++e) tb->gt[k][j][e] = (T)0;
-        for (int e = 0; e < 3; ++e) tb->gq[k][j][e] = (T)0;
-        tb->gq[k][j][3] = (T)kNegHuge;
-      }
+      r[0] = pv[0];
+      r[1] = pv[1];
+      r[2] = pv[2];
+      r[3] = (T)lw;
+      tb->rc2[k][j] = (T)rc2;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tb->gq[k][j][e] = qv[e];
+      const double h = 0.5 * tau * tau;
+      T* q = tb->gt[k][j];
+      q[0] = (T)tau;
+      q[1] = (T)(tau * tau);
+      q[2] = (T)(h * Pxx * Pxx);
+      q[3] = (T)(h * 2.0 * Pxx * Pxy);
+      q[4] = (T)(h * Pxy * Pxy);
+      q[5] = (T)(h * (2.0 * Pxy * Pxy + 2.0 * Pxx * Pyy));
+      q[6] = (T)(h * 2.0 * Pxy * Pyy);
+      q[7] = (T)(h * Pyy * Pyy);
     }
   }
 }

@@ -82,15 +82,15 @@ __device__ __forceinline__ double cut_radius2(double lw, double cxx, double cxy,
   const double lmax = 0.5 * (cxx + cyy) + sqrt(0.25 * (cxx - cyy) * (cxx - cyy) + cxy * cxy);
   if (isnan(room) || !isfinite(lmax)) return INFINITY;
   if (!(room > 0)) return -1.0;
-  return room / (0.5 * kLog2e / lmax);
+  return room * lmax * (2.0 / kLog2e);
 }
 
 // log2 threshold on a component's density for a source of expected flux L on a patch whose
 // sky is at least sky_min; -inf (keep everything) when either is not a positive finite
 // number, so that non-finite parameters still propagate to the objective
 template <typename T>
-__device__ __forceinline__ double density_cut_log2(double L, double sky_min) {
-  const double c = log2(sky_min) - log2(L) - rel_cut_log2<T>();
+__device__ __forceinline__ double density_cut_log2(double L, double sky_min, double log2_L, double log2_sky_min) {
+  const double c = log2_sky_min - log2_L - rel_cut_log2<T>();
   return (L > 0 && sky_min > 0 && isfinite(c)) ? c : -INFINITY;
 }
 
