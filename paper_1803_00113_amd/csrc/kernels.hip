@@ -339,37 +339,45 @@ __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
   const Table<T>* __restrict__ tb = reinterpret_cast<const Table<T>*>(a.base) + task.patch;
   const int K = a.img_npsf[P.img];
   const int lane = threadIdx.x;
-  const float inv_w = 1.0f / (float)P.w;
   const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
   const T k0 = tb->hdr[4], k1 = tb->hdr[5], w01 = tb->hdr[6];
-  for (int base = task.pix_begin; base < task.pix_end; base += 64 * PPL) {
-    T px[PPL], py[PPL];
-    int idxs[PPL];
+  // patch-local coordinates of this lane's pixels, advanced by a carry per group
+  const int step = 64 * PPL;
+  const int step_rows = step / P.w, step_cols = step - step_rows * P.w;
+  const T wT = (T)P.w, srT = (T)step_rows, scT = (T)step_cols;
+  T px[PPL], py[PPL];
 #pragma unroll
-    for (int i = 0; i < PPL; ++i) {
-      int idx = base + i * 64 + lane;
-      idxs[i] = idx;
-      if (idx >= task.pix_end) idx = task.pix_begin;
-      int row = (int)(((float)idx + 0.5f) * inv_w);
-      int col = idx - row * P.w;
-      if (col < 0) { row -= 1; col += P.w; }
-      else if (col >= P.w) { row += 1; col -= P.w; }
-      px[i] = (T)col;
-      py[i] = (T)row;
-    }
+  for (int i = 0; i < PPL; ++i) {
+    const int idx = task.pix_begin + i * 64 + lane;
+    const int row = idx / P.w;
+    px[i] = (T)(idx - row * P.w);
+    py[i] = (T)row;
+  }
+  for (int base = task.pix_begin; base < task.pix_end; base += step) {
     T f0[PPL], f1[PPL], box[4];
-    run_box<T>(base, min(base + 64 * PPL, task.pix_end), P.w, box);
+    run_box<T>(base, min(base + step, task.pix_end), P.w, box);
     eval_values<T, PPL, NEXP, NDEV>(tb, K, px, py, box, f0, f1);
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
-      if (idxs[i] >= task.pix_end) continue;
+      const int idx = base + i * 64 + lane;
+      if (idx >= task.pix_end) continue;
       const T a0 = L0 * f0[i], a1 = L1 * f1[i], d = a0 - a1;
       const T Es = w0 * a0 + w1 * a1;
       const T Vs = fma(k0 * f0[i], f0[i], fma(k1 * f1[i], f1[i], w01 * d * d));
       if constexpr (sizeof(T) == 8)
-        reinterpret_cast<double2*>(a.maps)[P.off + idxs[i]] = make_double2(Es, Vs);
+        reinterpret_cast<double2*>(a.maps)[P.off + idx] = make_double2(Es, Vs);
       else
-        reinterpret_cast<float2*>(a.maps)[P.off + idxs[i]] = make_float2(Es, Vs);
+        reinterpret_cast<float2*>(a.maps)[P.off + idx] = make_float2(Es, Vs);
+    }
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      T c = px[i] + scT, r = py[i] + srT;
+      if (c >= wT) {
+        c -= wT;
+        r += (T)1;
+      }
+      px[i] = c;
+      py[i] = r;
     }
   }
 }
