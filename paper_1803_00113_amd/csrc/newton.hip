@@ -38,119 +38,126 @@ constexpr int kLd = kN + 1;   // padded LDS row
 
 
 // Hessian of KL_s in the unconstrained coordinates (the same KL as the objective: the type
-// KL, the normal KL of log r, the colour bound -log sum_j w_j exp(-D_j), and minus the log
-// prior densities of the radius, profile and axis point masses), times sc, added into B
-// (27 rows of stride LD).
-// KL = KL_a(eta) + KL_radius + KL_profile + KL_axis + (1 - a) K_0 + a K_1; every loop
-// over parameters is unrolled so that all work arrays stay in registers.
+// KL, the normal KL of log r, the colour bound F = -log sum_j w_j exp(-D_j), and minus the
+// log prior densities of the radius, profile and axis point masses), times sc, added into
+// B (27 rows of stride LD).  KL = KL_a(eta) + KL_radius + KL_profile + KL_axis
+// + (1 - a) K_0 + a K_1; grad F = sum_j xi_j dD_j and
+// hess F = sum_j xi_j (d2D_j - dD_j dD_j^T) + grad F grad F^T in the 8 colour variables.
+// Computed by a whole wavefront (all 64 lanes active, B in LDS): lane
+// 8 i + j takes prior colour component j of type i -- its weight xi_j, dD_j and d2D_j --
+// and the sums over j of xi_j (d2D_j - dD_j dD_j^T) and xi_j dD_j are formed through LDS
+// in fixed order (work: 16 x 44 and 2 x 44 doubles); lanes then add the two 8 x 8 colour
+// blocks and lane 0 the remaining terms.  Ends after a barrier.
+constexpr int kKlw = 44;   // 36 upper-triangle entries of the 8 x 8 block + 8 gradient entries
 template <int LD>
-__device__ void kl_hessian_add(const DPrior& pr, const double* th, double (*B)[LD], double sc) {
-  const double eta = th[2], a = sigmoid(eta);
-  const double aa = a * (1.0 - a);
-  double K[2];
+__device__ void kl_hessian_wave(const DPrior& pr, const double* th, double (*B)[LD], double sc, int lane,
+                                double (*work)[kKlw], double (*sums)[kKlw]) {
+  static_assert(CEL_N_COLOUR_COMPONENTS == 8, "one lane per prior colour component, groups of 8");
+  const int i = (lane >> 3) & 1, j = lane & 7;
+  double cm[4], cv[4], lcv = 0;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const double rm = th[3 + i], lrv = th[5 + i], rv = exp(lrv);
-    const double R1 = pr.r[i][0], R2 = pr.r[i][1];
-    const double q = i == 0 ? 1.0 - a : a;
-    const double sg = i == 0 ? -aa : aa;   // d^2 KL / d eta d theta_k = sg dK_i/dtheta_k
-    K[i] = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5;
-    const double dm = (rm - R1) / R2, dv = -0.5 + rv / (2.0 * R2);
-    B[3 + i][3 + i] += sc * (q / R2);
-    B[5 + i][5 + i] += sc * (q * rv / (2.0 * R2));
-    B[2][3 + i] += sc * (sg * dm);
-    B[3 + i][2] += sc * (sg * dm);
-    B[2][5 + i] += sc * (sg * dv);
-    B[5 + i][2] += sc * (sg * dv);
-    // colour bound F = -log sum_j w_j exp(-D_j) in the 8 variables (means, log variances):
-    // grad F = sum_j xi_j dD_j;  hess F = sum_j xi_j (d2D_j - dD_j dD_j^T) + gradF gradF^T
-    double cm[4], cv[4], lcv = 0;
+  for (int k = 0; k < 4; ++k) {   // selects, not a lane-dependent index into th
+    cm[k] = i ? th[11 + k] : th[7 + k];
+    const double l = i ? th[19 + k] : th[15 + k];
+    cv[k] = exp(l);
+    lcv += l;
+  }
+  double tr = 0, maha = 0, dD[8];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      cm[k] = th[7 + 4 * i + k];
-      cv[k] = exp(th[15 + 4 * i + k]);
-      lcv += th[15 + 4 * i + k];
-    }
-    // D_j recomputed in each pass: keeps the component loops rolled and the 8x8 block in
-    // registers
-    auto Dj = [&](int j) {
-      double tr = 0, maha = 0;
+  for (int k = 0; k < 4; ++k) {
+    tr += pr.c_prec[i][j][k][k] * cv[k];
+    double r = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        tr += pr.c_prec[i][j][k][k] * cv[k];
-        double row = 0;
+    for (int l = 0; l < 4; ++l) r += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
+    dD[k] = r;
+    dD[4 + k] = 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
+    maha += (cm[k] - pr.c_mean[i][j][k]) * r;
+  }
+  const double e = pr.c_logw[i][j] - 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - lcv);
+  double mx = e;
 #pragma unroll
-        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
-        maha += (pr.c_mean[i][j][k] - cm[k]) * row;
+  for (int off = 1; off < 8; off <<= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  const double ex = exp(e - mx);
+  double z = ex;
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) z += __shfl_xor(z, off, 64);
+  const double xi = ex / z;
+  const double kc = -(mx + log(z));   // the colour bound of type i
+  if (lane < 16) {
+    int n = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int w = u; w < 8; ++w) {
+        double d2 = 0.0;
+        if (u < 4 && w < 4) d2 = pr.c_prec[i][j][u][w];
+        else if (u == w) d2 = 0.5 * pr.c_prec[i][j][u - 4][u - 4] * cv[u - 4];
+        work[lane][n++] = xi * (d2 - dD[u] * dD[w]);
       }
-      return 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - lcv);
-    };
-    double mx = -1e300;
-#pragma unroll 1
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) mx = fmax(mx, pr.c_logw[i][j] - Dj(j));
-    double z = 0;
-#pragma unroll 1
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - Dj(j) - mx);
-    K[i] += -(mx + log(z));
-    double gF[8], hF[8][8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      gF[u] = 0.0;
+    for (int u = 0; u < 8; ++u) work[lane][36 + u] = xi * dD[u];
+  }
+  __syncthreads();
+  for (int e2 = lane; e2 < 2 * kKlw; e2 += 64) {
+    const int ii = e2 / kKlw, q = e2 % kKlw;
+    double acc = 0;
+    for (int jj = 0; jj < 8; ++jj) acc += work[8 * ii + jj][q];
+    sums[ii][q] = acc;
+  }
+  __syncthreads();
+  const double eta = th[2], a = sigmoid(eta), aa = a * (1.0 - a);
+  // colour blocks: entry (u, w) of type ii, lanes 0..63 twice
+  for (int e2 = lane; e2 < 2 * 64; e2 += 64) {
+    const int ii = e2 / 64, u = (e2 % 64) / 8, w = e2 % 8;
+    const int lo = u < w ? u : w, hi = u < w ? w : u;
+    const int n = lo * 8 - lo * (lo - 1) / 2 + (hi - lo);
+    const double q = ii == 0 ? 1.0 - a : a;
+    const double hf = sums[ii][n] + sums[ii][36 + u] * sums[ii][36 + w];
+    const int iu = u < 4 ? 7 + 4 * ii + u : 15 + 4 * ii + (u - 4);
+    const int iw = w < 4 ? 7 + 4 * ii + w : 15 + 4 * ii + (w - 4);
+    B[iu][iw] += sc * (q * hf);
+  }
+  const double kc1 = __shfl(kc, 8, 64);
+  if (lane == 0) {
+    double K[2];
+    const double kcs[2] = {kc, kc1};
 #pragma unroll
-      for (int w = 0; w < 8; ++w) hF[u][w] = 0.0;
-    }
-#pragma unroll 1
-    for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
-      const double xi = exp(pr.c_logw[i][j] - Dj(j) - mx) / z;
-      double dD[8];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double row = 0;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
-        dD[k] = row;
-        dD[4 + k] = 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
-      }
+    for (int ii = 0; ii < 2; ++ii) {
+      const double rm = th[3 + ii], lrv = th[5 + ii], rv = exp(lrv);
+      const double R1 = pr.r[ii][0], R2 = pr.r[ii][1];
+      const double q = ii == 0 ? 1.0 - a : a;
+      const double sg = ii == 0 ? -aa : aa;   // d^2 KL / d eta d theta_k = sg dK_i/dtheta_k
+      K[ii] = 0.5 * (log(R2) - lrv) + (rv + (rm - R1) * (rm - R1)) / (2.0 * R2) - 0.5 + kcs[ii];
+      const double dm = (rm - R1) / R2, dv = -0.5 + rv / (2.0 * R2);
+      B[3 + ii][3 + ii] += sc * (q / R2);
+      B[5 + ii][5 + ii] += sc * (q * rv / (2.0 * R2));
+      B[2][3 + ii] += sc * (sg * dm);
+      B[3 + ii][2] += sc * (sg * dm);
+      B[2][5 + ii] += sc * (sg * dv);
+      B[5 + ii][2] += sc * (sg * dv);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        gF[u] += xi * dD[u];
-#pragma unroll
-        for (int w = 0; w < 8; ++w) hF[u][w] -= xi * dD[u] * dD[w];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int l = 0; l < 4; ++l) hF[k][l] += xi * pr.c_prec[i][j][k][l];
-        hF[4 + k][4 + k] += xi * 0.5 * pr.c_prec[i][j][k][k] * cv[k];
+        const int iu = u < 4 ? 7 + 4 * ii + u : 15 + 4 * ii + (u - 4);
+        B[2][iu] += sc * (sg * sums[ii][36 + u]);
+        B[iu][2] += sc * (sg * sums[ii][36 + u]);
       }
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int iu = u < 4 ? 7 + 4 * i + u : 15 + 4 * i + (u - 4);
-      B[2][iu] += sc * (sg * gF[u]);
-      B[iu][2] += sc * (sg * gF[u]);
-#pragma unroll
-      for (int w = 0; w < 8; ++w) {
-        const int iw = w < 4 ? 7 + 4 * i + w : 15 + 4 * i + (w - 4);
-        B[iu][iw] += sc * (q * (hF[u][w] + gF[u] * gF[w]));
-      }
+    // type weight: dKL/deta = a(1-a) [eta - logit A + K1 - K0]
+    const double t = eta - pr.logit_a + K[1] - K[0];
+    B[2][2] += sc * (aa * (1.0 - 2.0 * a) * t + aa);
+    // point masses
+    B[24][24] += sc * (1.0 / pr.radius[1]);
+    {
+      const double p = sigmoid(th[25]);
+      B[25][25] += sc * ((pr.profile[0] + pr.profile[1] - 2.0) * p * (1.0 - p));
+    }
+    {
+      const double p = sigmoid(th[26]);
+      B[26][26] += sc * ((pr.axis[0] + pr.axis[1] - 2.0) * p * (1.0 - p));
     }
   }
-  // type weight: dKL/deta = a(1-a) [eta - logit A + K1 - K0]
-  const double t = eta - pr.logit_a + K[1] - K[0];
-  B[2][2] += sc * (aa * (1.0 - 2.0 * a) * t + aa);
-  // point masses
-  B[24][24] += sc * (1.0 / pr.radius[1]);
-  {
-    const double p = sigmoid(th[25]);
-    B[25][25] += sc * ((pr.profile[0] + pr.profile[1] - 2.0) * p * (1.0 - p));
-  }
-  {
-    const double p = sigmoid(th[26]);
-    B[26][26] += sc * ((pr.axis[0] + pr.axis[1] - 2.0) * p * (1.0 - p));
-  }
+  __syncthreads();
 }
-
 
 // ----------------------------------------------------------------------------------------
 // Analytic Hessian of the pixel part of L_s (Section 4.3 uses a dense Newton Hessian).
@@ -521,169 +528,228 @@ struct HessFinArgs {
   int32_t* err;                // device condition word (non-finite Hessian entries)
 };
 
+// Sparsity of J = dr/dtheta (r: the 11 primitive coordinates, theta: the 27 parameters):
+// column k has jcount(k) nonzero rows jrow(k, e) -- the centre rows for the position, the
+// flux rows m_i / v_i for the flux and colour parameters, the three S rows for the angle,
+// radius and axis, and one row each for the type and profile logits.
+__device__ __forceinline__ int jcount(int k) { return k < 2 ? 2 : (k == 23 || k == 24 || k == 26) ? 3 : 1; }
+__device__ __forceinline__ int jrow(int k, int e) {
+  if (k < 2) return 5 + e;
+  if (k == 2) return 0;
+  if (k < 5) return 1 + 2 * (k - 3);
+  if (k < 7) return 2 + 2 * (k - 5);
+  if (k < 15) return 1 + 2 * ((k - 7) / 4);
+  if (k < 23) return 2 + 2 * ((k - 15) / 4);
+  if (k == 25) return 10;
+  return 7 + e;
+}
+
 __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
   const int s = a.job_src ? a.job_src[blockIdx.x] : (int)blockIdx.x;
   if (a.active && !a.active[s]) return;
   const int lane = threadIdx.x;
-  __shared__ double sm[kHSlots];
-  __shared__ double Qy[kPrim][kPrim], Jy[kPrim][kPrim], Ty[kPrim][kPrim], Qr[kPrim][kPrim], Gr[kPrim];
-  __shared__ double J[kPrim][kN], T1[kPrim][kN];
+  // slot sums and flux moments of up to kPB patches, gathered together (one memory and one
+  // exp latency per batch instead of per patch)
+  constexpr int kPB = 16, kHU = 2 + kPrim + kHQ;
+  __shared__ double smb[kPB][kHU], Lfb[kPB][2], evb[kPB][2];
+  __shared__ double Qr[kPrim][kPrim], Gr[kPrim];
+  // column k of dr/dtheta: rows jr[k][e] with values jv[k][e] (zero past jcount(k)); dg the
+  // diagonal and sblk the S-block second-derivative terms
+  __shared__ double jv[kN][3], dg[kN], sblk[3][3];
+  __shared__ int jr[kN][3];
   __shared__ double Hs[kN][kLd], gs[kThetaN];
   __shared__ double th[kN], sd1[3][3], sd2[3][3][3];
-  __shared__ double Lf[2], ev[2], rv[2], cvv[2][4];
+  __shared__ double rv[2], cvv[2][4];
   if (lane < kN) th[lane] = a.theta[(int64_t)s * kThetaN + lane];
-  for (int idx = lane; idx < kN * kN; idx += 64) Hs[idx / kN][idx % kN] = 0.0;
   if (lane < kThetaN) gs[lane] = 0.0;
   __syncthreads();
   if (lane == 0) sigma_derivs(th[23], th[24], th[26], sd1, sd2);
+  if (lane < kN) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) jr[lane][e] = e < jcount(lane) ? jrow(lane, e) : jrow(lane, 0);
+  }
+  // flux and colour variances, one per lane
+  if (lane >= 1 && lane < 11) {
+    const int l = lane - 1;
+    const double e = exp(l < 2 ? th[5 + l] : th[15 + (l - 2)]);
+    if (l < 2) rv[l] = e;
+    else cvv[(l - 2) / 4][(l - 2) % 4] = e;
+  }
+  __syncthreads();
+  // this lane's Hessian entries idx = lane + 64 m accumulate in registers over the patches
+  constexpr int kHPer = (kN * kN + 63) / 64;
+  double hacc[kHPer];
+#pragma unroll
+  for (int m = 0; m < kHPer; ++m) hacc[m] = 0.0;
   double local = 0.0;
   const double aa = sigmoid(th[2]), pi = sigmoid(th[25]);
-  for (int p = a.patch_ptr[s]; p < a.patch_ptr[s + 1]; ++p) {
-    const DPatch P = a.patches[p];
-    const cel_image& im = a.images[P.img];
-    for (int l = lane; l < 2 + kPrim + kHQ; l += 64) {
+  const int p0 = a.patch_ptr[s], p1 = a.patch_ptr[s + 1];
+  for (int pb = p0; pb < p1; pb += kPB) {
+    const int nb = min(kPB, p1 - pb);
+    for (int e = lane; e < nb * kHU; e += 64) {
+      const int q = e / kHU, l = e % kHU;
+      const DPatch P = a.patches[pb + q];
       double acc = 0;
       for (int t = P.task_begin; t < P.task_end; ++t) acc += a.hslots[(int64_t)t * kHSlots + l];
-      sm[l] = acc;
+      smb[q][l] = acc;
     }
-    // flux moments of this band: L_i, e_i (as functions of m_i, v_i)
-    if (lane < 2) {
-      const int i = lane;
-      double m = th[3 + i];
-      const double r = exp(th[5 + i]);
-      double var = r;
+    // flux moments of each patch's band: L_i = iota exp(m_i + v_i / 2) and e_i = exp(v_i),
+    // lane 4 q + 2 w + i
+    if (lane < 4 * nb) {
+      const int q = lane >> 2, i = lane & 1, w = (lane >> 1) & 1;
+      const cel_image& imq = a.images[a.patches[pb + q].img];
+      double m = th[3 + i], var = rv[i];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const double W = c_W[im.band][c];
-        const double cv = exp(th[15 + 4 * i + c]);
+        const double W = c_W[imq.band][c];
         m += W * th[7 + 4 * i + c];
-        var += W * W * cv;
-        cvv[i][c] = cv;
+        var += W * W * cvv[i][c];
       }
-      rv[i] = r;
-      Lf[i] = im.iota * exp(m + 0.5 * var);
-      ev[i] = exp(var);
+      const double ex = exp(w == 0 ? m + 0.5 * var : var);
+      if (w == 0) Lfb[q][i] = imq.iota * ex;
+      else evb[q][i] = ex;
     }
     __syncthreads();
-    local += sm[0] + a.pix_const[2 * p];
-    // stage 1: y = (a, L0, L1, e0, e1, z) -> r = (a, m0, v0, m1, v1, z); Jy[u][r] = dy_u/dr
-    for (int idx = lane; idx < kPrim * kPrim; idx += 64) {
-      const int u = idx / kPrim, r = idx % kPrim;
-      Qy[u][r] = sm[2 + kPrim + (u <= r ? qidx(u, r) : qidx(r, u))];
-      double j = (u == r) ? 1.0 : 0.0;
-      if (u == 1 || u == 2) {
-        const int i = u - 1;
-        j = (r == 1 + 2 * i) ? Lf[i] : (r == 2 + 2 * i) ? 0.5 * Lf[i] : 0.0;
-      } else if (u == 3 || u == 4) {
-        const int i = u - 3;
-        j = (r == 2 + 2 * i) ? ev[i] : 0.0;
-      }
-      Jy[u][r] = j;
-    }
-    // stage 2 Jacobian J[r][theta] = dr/dtheta
-    for (int idx = lane; idx < kPrim * kN; idx += 64) {
-      const int r = idx / kN, k = idx % kN;
-      double j = 0.0;
-      if (r == 0) {
-        j = k == 2 ? aa * (1.0 - aa) : 0.0;
-      } else if (r <= 4) {
-        const int i = (r - 1) / 2;
-        if (r == 1 + 2 * i) {   // m_i
-          if (k == 3 + i) j = 1.0;
-          else if (k >= 7 + 4 * i && k < 11 + 4 * i) j = c_W[im.band][k - 7 - 4 * i];
-        } else {                // v_i
-          if (k == 5 + i) j = rv[i];
-          else if (k >= 15 + 4 * i && k < 19 + 4 * i) {
-            const double W = c_W[im.band][k - 15 - 4 * i];
-            j = W * W * cvv[i][k - 15 - 4 * i];
+    for (int q = 0; q < nb; ++q) {
+      const int p = pb + q;
+      const DPatch P = a.patches[p];
+      const cel_image& im = a.images[P.img];
+      const double* sm = smb[q];
+      const double* Lf = Lfb[q];
+      const double* ev = evb[q];
+      local += sm[0] + a.pix_const[2 * p];
+      // stage 1: y = (a, L0, L1, e0, e1, z) -> r = (a, m0, v0, m1, v1, z).  Each r is reached
+      // from at most two y: a <- a; m_i <- L_i (dL/dm = L); v_i <- L_i (L/2) and e_i (e^v);
+      // z <- z.  Qr = Jy^T Qy Jy + sum_u g_u d2y_u/dr2, Gr = Jy^T g.  Written without
+      // branches: the second source of an r that has one is given weight 0.
+      auto ysrc = [&](int r, int* u, double* j) {
+        const bool flux = r >= 1 && r <= 4;
+        const int i = (r - 1) >> 1;
+        const bool var = flux && ((r & 1) == 0);
+        const double L = i ? Lf[1] : Lf[0], e = i ? ev[1] : ev[0];
+        u[0] = flux ? 1 + i : r;
+        j[0] = flux ? (var ? 0.5 * L : L) : 1.0;
+        u[1] = var ? 3 + i : u[0];
+        j[1] = var ? e : 0.0;
+      };
+      for (int idx = lane; idx < kPrim * kPrim; idx += 64) {
+        const int r = idx / kPrim, r2 = idx % kPrim;
+        int ua[2], ub[2];
+        double ja[2], jb[2];
+        ysrc(r, ua, ja);
+        ysrc(r2, ub, jb);
+        double v = 0;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            const int u = ua[x], w = ub[y];
+            v += ja[x] * sm[2 + kPrim + (u <= w ? qidx(u, w) : qidx(w, u))] * jb[y];
           }
+        // second derivatives of y in r: L_i: mm = L, mv = L/2, vv = L/4; e_i: vv = e^v
+        if (r >= 1 && r <= 4 && r2 >= 1 && r2 <= 4 && ((r - 1) >> 1) == ((r2 - 1) >> 1)) {
+          const int i = (r - 1) >> 1;
+          const double gL = sm[3 + i], ge = sm[5 + i];
+          const double L = i ? Lf[1] : Lf[0], e = i ? ev[1] : ev[0];
+          const int nv = ((r & 1) == 0) + ((r2 & 1) == 0);   // how many of r, r2 are v_i
+          v += gL * L * (nv == 0 ? 1.0 : nv == 1 ? 0.5 : 0.25) + (nv == 2 ? ge * e : 0.0);
         }
-      } else if (r <= 6) {      // pixel-frame centre
-        if (k < 2) j = im.A[r - 5][k];
-      } else if (r <= 9) {      // S = A Sigma A^T in (angle, log radius, logit axis)
-        const int t = k == 23 ? 0 : k == 24 ? 1 : k == 26 ? 2 : -1;
-        if (t >= 0) {
-          double sv[3];
-          conj_A(im.A, sd1[t], sv);
-          j = sv[r - 7];
-        }
-      } else {
-        j = k == 25 ? pi * (1.0 - pi) : 0.0;
+        Qr[r][r2] = v;
       }
-      J[r][k] = j;
-    }
-    __syncthreads();
-    for (int idx = lane; idx < kPrim * kPrim; idx += 64) {
-      const int u = idx / kPrim, r = idx % kPrim;
-      double v = 0;
-      for (int w = 0; w < kPrim; ++w) v += Qy[u][w] * Jy[w][r];
-      Ty[u][r] = v;
-    }
-    __syncthreads();
-    for (int idx = lane; idx < kPrim * kPrim; idx += 64) {
-      const int r = idx / kPrim, r2 = idx % kPrim;
-      double v = 0;
-      for (int u = 0; u < kPrim; ++u) v += Jy[u][r] * Ty[u][r2];
-      // second derivatives of y in r: L_i: mm = L, mv = L/2, vv = L/4; e_i: vv = e^v
-      for (int i = 0; i < 2; ++i) {
-        const int im_ = 1 + 2 * i, iv = 2 + 2 * i;
-        const double gL = sm[2 + 1 + i], ge = sm[2 + 3 + i];
-        if (r == im_ && r2 == im_) v += gL * Lf[i];
-        if ((r == im_ && r2 == iv) || (r == iv && r2 == im_)) v += gL * 0.5 * Lf[i];
-        if (r == iv && r2 == iv) v += gL * 0.25 * Lf[i] + ge * ev[i];
+      if (lane < kPrim) {
+        int ua[2];
+        double ja[2];
+        ysrc(lane, ua, ja);
+        Gr[lane] = ja[0] * sm[2 + ua[0]] + ja[1] * sm[2 + ua[1]];
       }
-      Qr[r][r2] = v;
-    }
-    if (lane < kPrim) {
-      double v = 0;
-      for (int u = 0; u < kPrim; ++u) v += Jy[u][lane] * sm[2 + u];
-      Gr[lane] = v;
-    }
-    __syncthreads();
-    // T1 = Qr J
-    for (int idx = lane; idx < kPrim * kN; idx += 64) {
-      const int r = idx / kN, k = idx % kN;
-      double v = 0;
-      for (int r2 = 0; r2 < kPrim; ++r2) v += Qr[r][r2] * J[r2][k];
-      T1[r][k] = v;
-    }
-    __syncthreads();
-    // H += J^T T1 + sum_r Gr[r] d2r/dtheta2;  g += J^T Gr
-    for (int idx = lane; idx < kN * kN; idx += 64) {
-      const int i = idx / kN, k = idx % kN;
-      double v = 0;
-      for (int r = 0; r < kPrim; ++r) v += J[r][i] * T1[r][k];
-      if (i == k) {
-        if (i == 2) v += Gr[0] * aa * (1.0 - aa) * (1.0 - 2.0 * aa);
-        if (i == 5 || i == 6) v += Gr[2 + 2 * (i - 5)] * rv[i - 5];
-        if (i >= 15 && i < 23) {
-          const int ii = (i - 15) / 4, c = (i - 15) % 4;
-          const double W = c_W[im.band][c];
-          v += Gr[2 + 2 * ii] * W * W * cvv[ii][c];
-        }
-        if (i == 25) v += Gr[10] * pi * (1.0 - pi) * (1.0 - 2.0 * pi);
+      __syncthreads();   // Gr is read below
+      // stage 2: the nonzero values of column k of J = dr/dtheta (zero-padded to 3), all
+      // candidates formed and one selected
+      if (lane < kN) {
+        const int k = lane;
+        const double A00 = im.A[0][0], A01 = im.A[0][1], A10 = im.A[1][0], A11 = im.A[1][1];
+        const int c = (k - 7) & 3, ti = (k - 15) >> 2;
+        const double W = c_W[im.band][c];
+        const int t = k == 23 ? 0 : k == 24 ? 1 : 2;
+        double sv[3];
+        conj_A(im.A, sd1[t], sv);
+        const bool sk = k == 23 || k == 24 || k == 26;
+        double v0 = 0.0;
+        v0 = k == 0 ? A00 : k == 1 ? A01 : v0;
+        v0 = k == 2 ? aa * (1.0 - aa) : v0;
+        v0 = (k == 3 || k == 4) ? 1.0 : v0;
+        v0 = (k == 5 || k == 6) ? rv[k == 6] : v0;
+        v0 = (k >= 7 && k < 15) ? W : v0;
+        v0 = (k >= 15 && k < 23) ? W * W * cvv[ti & 1][c] : v0;
+        v0 = k == 25 ? pi * (1.0 - pi) : v0;
+        v0 = sk ? sv[0] : v0;
+        jv[k][0] = v0;
+        jv[k][1] = k == 0 ? A10 : k == 1 ? A11 : sk ? sv[1] : 0.0;
+        jv[k][2] = sk ? sv[2] : 0.0;
+        // the diagonal second-derivative terms sum_r Gr[r] d2r/dtheta_k^2 (outside the S block)
+        double dgk = 0.0;
+        dgk = k == 2 ? Gr[0] * aa * (1.0 - aa) * (1.0 - 2.0 * aa) : dgk;
+        dgk = (k == 5 || k == 6) ? Gr[2 + 2 * (k - 5)] * rv[k == 6] : dgk;
+        dgk = (k >= 15 && k < 23) ? Gr[2 + 2 * (ti & 1)] * W * W * cvv[ti & 1][c] : dgk;
+        dgk = k == 25 ? Gr[10] * pi * (1.0 - pi) * (1.0 - 2.0 * pi) : dgk;
+        dg[k] = dgk;
       }
-      const int ti = i == 23 ? 0 : i == 24 ? 1 : i == 26 ? 2 : -1;
-      const int tk = k == 23 ? 0 : k == 24 ? 1 : k == 26 ? 2 : -1;
-      if (ti >= 0 && tk >= 0) {
+      // S block (angle, radius, axis): sum_r Gr[r] d2S_r/dt dt'
+      if (lane >= 32 && lane < 41) {
+        const int ti = (lane - 32) / 3, tk = (lane - 32) % 3;
         double sv[3];
         conj_A(im.A, sd2[ti][tk], sv);
-        v += Gr[7] * sv[0] + Gr[8] * sv[1] + Gr[9] * sv[2];
+        sblk[ti][tk] = Gr[7] * sv[0] + Gr[8] * sv[1] + Gr[9] * sv[2];
       }
-      Hs[i][k] += v;
+      __syncthreads();
+      // H += J^T Qr J + the second-derivative terms, 3 x 3 terms per entry (zero-padded
+      // columns; the rows of column k are jr[k][e])
+#pragma unroll
+      for (int m = 0; m < kHPer; ++m) {
+        const int idx = lane + 64 * m;
+        if (idx >= kN * kN) break;
+        const int i = idx / kN, k = idx % kN;
+        double v = 0;
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+          const int r = jr[i][x];
+          double tt = 0;
+#pragma unroll
+          for (int y = 0; y < 3; ++y) tt += Qr[r][jr[k][y]] * jv[k][y];
+          v += jv[i][x] * tt;
+        }
+        if (i == k) v += dg[i];
+        const int si = i == 23 ? 0 : i == 24 ? 1 : i == 26 ? 2 : -1;
+        const int sk = k == 23 ? 0 : k == 24 ? 1 : k == 26 ? 2 : -1;
+        if (si >= 0 && sk >= 0) v += sblk[si][sk];
+        hacc[m] += v;
+      }
+      if (lane < kN) gs[lane] += jv[lane][0] * Gr[jr[lane][0]] + jv[lane][1] * Gr[jr[lane][1]] + jv[lane][2] * Gr[jr[lane][2]];
+      __syncthreads();
     }
-    if (lane < kN) {
-      double v = 0;
-      for (int r = 0; r < kPrim; ++r) v += J[r][lane] * Gr[r];
-      gs[lane] += v;
-    }
-    __syncthreads();
   }
+#pragma unroll
+  for (int m = 0; m < kHPer; ++m) {
+    const int idx = lane + 64 * m;
+    if (idx < kN * kN) Hs[idx / kN][idx % kN] = hacc[m];
+  }
+  __syncthreads();
   // KL: value, gradient and (optionally) Hessian
   __shared__ double klv;
-  if (lane == 0) {
-    klv = kl_source(*a.prior, th, gs, 1.0);   // subtracts grad KL from gs
-    if (a.with_kl) kl_hessian_add<kLd>(*a.prior, th, Hs, -1.0);
+  {
+    double gk[kThetaN];
+#pragma unroll
+    for (int k = 0; k < kThetaN; ++k) gk[k] = 0.0;
+    const double kv = kl_source_wave(*a.prior, th, gk, 1.0, lane);   // every lane: gk = -grad KL
+    if (lane == 0) {
+      klv = kv;
+#pragma unroll
+      for (int k = 0; k < kN; ++k) gs[k] += gk[k];
+    }
+  }
+  if (a.with_kl) {
+    __shared__ double klw[16][kKlw], kls[2][kKlw];
+    kl_hessian_wave<kLd>(*a.prior, th, Hs, -1.0, lane, klw, kls);
   }
   __syncthreads();
   if (lane == 0 && a.local) a.local[s] = local - klv;
@@ -748,8 +814,8 @@ __global__ __launch_bounds__(64) void k_fd_hessian(FdHessArgs a) {
   }
   if (lane < kN) th[lane] = a.theta[(int64_t)s * kThetaN + lane];
   __syncthreads();
-  if (lane == 0) kl_hessian_add<kLd>(*a.prior, th, H, -1.0);
-  __syncthreads();
+  __shared__ double klw[16][kKlw], kls[2][kKlw];
+  kl_hessian_wave<kLd>(*a.prior, th, H, -1.0, lane, klw, kls);
   for (int idx = lane; idx < kN * kN; idx += 64) a.hess[(int64_t)s * kN * kN + idx] = H[idx / kN][idx % kN];
 }
 

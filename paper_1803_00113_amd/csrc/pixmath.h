@@ -130,54 +130,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Colour bound of type i (Section 4.2.3 at its optimal weights): the value
-// -log sum_j w_j exp(-D_j) and its gradient, with respect to the colour means (gm) and the
-// log colour variances (gv), summed over the prior components j (weights xi_j).
-__device__ inline double colour_bound(const DPrior& pr, const double* th, int i, double* gm, double* gv) {
-  double cm[4], cv[4], lcv[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    cm[k] = th[7 + 4 * i + k];
-    lcv[k] = th[15 + 4 * i + k];
-    cv[k] = exp(lcv[k]);
-    gm[k] = gv[k] = 0.0;
-  }
-  double D[CEL_N_COLOUR_COMPONENTS], mx = -1e300;
-  const double sum_lcv = lcv[0] + lcv[1] + lcv[2] + lcv[3];
-#pragma unroll
-  for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
-    double tr = 0, maha = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      tr += pr.c_prec[i][j][k][k] * cv[k];
-      double row = 0;
-#pragma unroll
-      for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (pr.c_mean[i][j][l] - cm[l]);
-      maha += (pr.c_mean[i][j][k] - cm[k]) * row;
-    }
-    D[j] = 0.5 * (tr + maha - 4.0 + pr.c_logdet[i][j] - sum_lcv);
-    const double e = pr.c_logw[i][j] - D[j];
-    if (e > mx) mx = e;
-  }
-  double z = 0;
-#pragma unroll
-  for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) z += exp(pr.c_logw[i][j] - D[j] - mx);
-#pragma unroll
-  for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
-    const double xi = exp(pr.c_logw[i][j] - D[j] - mx) / z;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      double row = 0;
-#pragma unroll
-      for (int l = 0; l < 4; ++l) row += pr.c_prec[i][j][k][l] * (cm[l] - pr.c_mean[i][j][l]);
-      gm[k] += xi * row;
-      gv[k] += xi * 0.5 * (pr.c_prec[i][j][k][k] * cv[k] - 1.0);
-    }
-  }
-  return -(mx + log(z));
-}
-
-// The same colour bounds computed by a whole wavefront (all 64 lanes active): lane 8 i + j
+// Colour bounds of both types (Section 4.2.3 at their optimal weights): the values
+// -log sum_j w_j exp(-D_j) and their gradients with respect to the colour means (gm) and
+// log colour variances (gv), summed over the prior components j with weights xi_j,
+// computed by a whole wavefront (all 64 lanes active): lane 8 i + j
 // takes prior component j of type i (lanes 16..63 repeat lanes 0..15), the maximum,
 // normaliser and gradient sums are combined by fixed butterflies within each group of 8
 // lanes, and every lane receives both types' results.
@@ -287,14 +243,6 @@ __device__ inline double kl_assemble(const DPrior& pr, const double* th, double*
     g[26] -= gs * (-(pr.axis[0] - 1.0) * (1.0 - p) + (pr.axis[1] - 1.0) * p);
   }
   return kl;
-}
-
-// KL and gradient by one lane
-__device__ inline double kl_source(const DPrior& pr, const double* th, double* g, double gs) {
-  double kc[2], gm[2][4], gv[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) kc[i] = colour_bound(pr, th, i, gm[i], gv[i]);
-  return kl_assemble(pr, th, g, gs, kc, gm, gv);
 }
 
 // KL and gradient by a whole wavefront (all lanes active; every lane gets the value and
