@@ -881,6 +881,31 @@ hipError_t prep_base(cel_plan* p, const double* theta, hipStream_t sm, bool fp64
   return fp64 ? prep_base_t<double>(p, theta, sm) : prep_base_t<float>(p, theta, sm);
 }
 
+template <typename T>
+static hipError_t prep_class_t(cel_plan* p, const double* theta, int cls, const uint8_t* active, hipStream_t sm) {
+  const int np = (int)p->class_patches[cls].size();
+  if (np == 0) return hipSuccess;
+  PrepArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.theta = theta;
+  pa.fd_step = p->opt.fd_step;
+  pa.patch_list = p->d_class_patches[cls];
+  pa.patches = p->d_patches;
+  pa.images = p->d_images;
+  pa.prof = p->d_prof;
+  pa.tables = sizeof(T) == 8 ? (void*)p->tables_d : (void*)p->tables_f;
+  pa.n_patches = p->P;
+  pa.active = active;
+  pa.trial_variant = p->trial_variant;
+  pa.fd = p->fd_mode;
+  pa.sky_min = p->d_skymin;
+  return launch_prep_tables<T>(pa, np, 1, sm);
+}
+
+hipError_t prep_class(cel_plan* p, const double* theta, int cls, const uint8_t* active, hipStream_t sm, bool fp64) {
+  return fp64 ? prep_class_t<double>(p, theta, cls, active, sm) : prep_class_t<float>(p, theta, cls, active, sm);
+}
+
 template hipError_t enqueue_eval<float>(cel_plan*, const double*, const double*, int, int, bool, int,
                                         const uint8_t*, hipStream_t, bool);
 template hipError_t enqueue_eval<double>(cel_plan*, const double*, const double*, int, int, bool, int,

@@ -1169,17 +1169,21 @@ static hipError_t enqueue_hessian(cel_plan* p, const double* theta, const int32_
   return hipGetLastError();
 }
 
-// One Newton iteration of colour class `cls` on the sources flagged in `active`.
+// One Newton iteration of colour class `cls` on the sources flagged in `active`.  With
+// maps_current the neighbour moment maps are taken as they are (none of the class's
+// neighbours has moved since they were made: the sweep refreshes them once per class) and
+// only the class's own tables are rebuilt.
 static hipError_t enqueue_newton_class(cel_plan* p, double* theta, double* radius, uint8_t* active, int cls,
-                                       int32_t* status, double* out_local, bool clear_done, hipStream_t sm) {
+                                       int32_t* status, double* out_local, bool clear_done, hipStream_t sm,
+                                       bool maps_current = false) {
   const bool fp64 = p->opt.pixel_fp64 || p->opt.hessian_fp64;
   const int nsrc = (int)p->class_src[cls].size();
   if (nsrc == 0) return hipSuccess;
   hipError_t e;
   const bool analytic = !p->opt.hessian_fd;
   if (analytic) {
-    // tables and maps at the iterate, then the exact Hessians with the gradients
-    e = prep_base(p, theta, sm, fp64);
+    // tables (and maps) at the iterate, then the exact Hessians with the gradients
+    e = maps_current ? prep_class(p, theta, cls, active, sm, fp64) : prep_base(p, theta, sm, fp64);
     if (e == hipSuccess)
       e = enqueue_hessian(p, theta, p->d_class_tasks[cls], (int)p->class_tasks[cls].size(), p->d_class_src[cls], nsrc,
                           active, true, p->v_local, p->v_grad, p->d_hess, sm);
@@ -1360,6 +1364,10 @@ extern "C" cel_status cel_sweep(cel_ctx* ctx, const cel_plan* cplan, double* the
       const int nsrc = (int)p->class_src[c].size();
       hipLaunchKernelGGL(k_set_active, dim3((S + 255) / 256), dim3(256), 0, sm, p->d_mask, p->d_colour, S, c);
       if ((e = hipGetLastError()) != hipSuccess) break;
+      // the neighbours of this class keep their parameters during its iterations: their
+      // moment maps are made once here (analytic Hessian path)
+      const bool maps_once = !p->opt.hessian_fd;
+      if (maps_once && (e = prep_base(p, theta, sm, p->opt.pixel_fp64 || p->opt.hessian_fp64)) != hipSuccess) break;
       hipGraphExec_t exec = nullptr;
       if (o.use_graph) {
         auto& G = p->graphs[c];
@@ -1369,7 +1377,7 @@ extern "C" cel_status cel_sweep(cel_ctx* ctx, const cel_plan* cplan, double* the
           hipGraph_t graph;
           e = hipStreamBeginCapture(sm, hipStreamCaptureModeThreadLocal);
           if (e != hipSuccess) break;
-          hipError_t e2 = enqueue_newton_class(p, theta, radius, p->d_mask, c, status, nullptr, true, sm);
+          hipError_t e2 = enqueue_newton_class(p, theta, radius, p->d_mask, c, status, nullptr, true, sm, maps_once);
           e = hipStreamEndCapture(sm, &graph);
           if (e2 != hipSuccess) e = e2;
           if (e != hipSuccess) break;
@@ -1385,7 +1393,7 @@ extern "C" cel_status cel_sweep(cel_ctx* ctx, const cel_plan* cplan, double* the
       }
       for (int it = 0; it < o.max_newton_iters && e == hipSuccess; ++it) {
         if (exec) e = hipGraphLaunch(exec, sm);
-        else e = enqueue_newton_class(p, theta, radius, p->d_mask, c, status, nullptr, true, sm);
+        else e = enqueue_newton_class(p, theta, radius, p->d_mask, c, status, nullptr, true, sm, maps_once);
         ++steps;
         if (e != hipSuccess) break;
         if ((it + 1) % check_every == 0 || it + 1 == o.max_newton_iters) {
