@@ -33,6 +33,7 @@
 namespace celmi {
 
 constexpr int kN = kParamN;   // 27
+static_assert(kN % 3 == 0, "the Jacobi dot products run in three chains");
 constexpr int kLd = kN + 1;   // padded LDS row
 
 
@@ -888,16 +889,33 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
   for (int i = 0; i < kN; ++i) w[i] = lane < kN ? B[i][lane] + (i == lane ? cs : 0.0) : 0.0;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double rotated = 0.0;
+    // squared column norm, exact at the start of a sweep and carried through its rotations
+    // (|c w + cp pw|^2 = c^2 al + cp^2 be + 2 c cp ga)
+    double al = 0.0;
+    {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < kN; i += 3) {
+        a0 = fma(w[i], w[i], a0);
+        a1 = fma(w[i + 1], w[i + 1], a1);
+        a2 = fma(w[i + 2], w[i + 2], a2);
+      }
+      al = a0 + a1 + a2;
+    }
     for (int r = 0; r < kN; ++r) {
       const int pt = lane > kN ? lane : lane == kN ? r : lane == r ? kN : ((2 * r - lane) % kN + kN) % kN;
-      double pw[kN], al = 0.0, be = 0.0, ga = 0.0;
+      double pw[kN];
+      const double be = __shfl(al, pt, 64);
+      double g0 = 0.0, g1 = 0.0, g2 = 0.0;   // three chains for the dot product
 #pragma unroll
-      for (int i = 0; i < kN; ++i) {
-        pw[i] = __shfl(w[i], pt, 64);
-        al = fma(w[i], w[i], al);
-        be = fma(pw[i], pw[i], be);
-        ga = fma(w[i], pw[i], ga);
+      for (int i = 0; i < kN; ++i) pw[i] = __shfl(w[i], pt, 64);
+#pragma unroll
+      for (int i = 0; i < kN; i += 3) {
+        g0 = fma(w[i], pw[i], g0);
+        g1 = fma(w[i + 1], pw[i + 1], g1);
+        g2 = fma(w[i + 2], pw[i + 2], g2);
       }
+      const double ga = g0 + g1 + g2;
       const bool lowside = lane < pt;
       const double alo = lowside ? al : be, ahi = lowside ? be : al;
       double c = 1.0, sn = 0.0;
@@ -911,6 +929,7 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
       const double cp = lowside ? -sn : sn;
 #pragma unroll
       for (int i = 0; i < kN; ++i) w[i] = fma(c, w[i], cp * pw[i]);
+      al = c * c * al + cp * cp * be + 2.0 * c * cp * ga;
     }
     if (wave_max(rotated) == 0.0) break;
   }
