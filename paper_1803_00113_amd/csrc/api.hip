@@ -686,7 +686,7 @@ static hipError_t launch_maps_t(cel_plan* p, const Table<T>* tables, hipStream_t
   ma.base = tables;
   ma.maps = sizeof(T) == 8 ? (void*)p->d_maps64 : (void*)p->d_maps;
   ma.img_npsf = p->d_npsf;
-  // the value-only pass keeps 4 pixels per lane: more independent exponentials per wavefront
+  // the value-only pass keeps 8 pixels per lane: more independent exponentials per wavefront
   return launch_maps<T>(ma, p->nexp, p->ndev, 8, (int)p->map_order_h.size(), sm);
 }
 
@@ -695,7 +695,8 @@ static hipError_t launch_maps_t(cel_plan* p, const Table<T>* tables, hipStream_t
 // plan's per-variant arrays.
 template <typename T>
 static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv,
-                               bool grad, int cls, const uint8_t* active, hipStream_t sm, bool prep_base) {
+                               bool grad, int cls, const uint8_t* active, hipStream_t sm, bool prep_base,
+                               double* local_out, double* grad_out) {
   Table<T>* tables = reinterpret_cast<Table<T>*>(sizeof(T) == 8 ? (void*)p->tables_d : (void*)p->tables_f);
   const T* htau = sizeof(T) == 8 ? (const T*)p->d_htau_d : (const T*)p->d_htau_f;
   hipError_t e = hipSuccess;
@@ -774,9 +775,10 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   fz.images = p->d_images;
   fz.prior = p->d_prior;
   fz.want_grad = grad ? 1 : 0;
-  fz.local = p->v_local + (int64_t)v0 * p->S;
+  const bool direct = v0 == 0 && nv == 1;
+  fz.local = direct && local_out ? local_out : p->v_local + (int64_t)v0 * p->S;
   fz.own = p->v_own + (int64_t)v0 * p->S;
-  fz.grad = p->v_grad + (int64_t)v0 * p->S * kThetaN;
+  fz.grad = direct && grad_out ? grad_out : p->v_grad + (int64_t)v0 * p->S * kThetaN;
   fz.out_variant_stride = p->S;
   fz.trial_variant = p->trial_variant;
   fz.fd = p->fd_mode;
@@ -906,15 +908,13 @@ hipError_t prep_class(cel_plan* p, const double* theta, int cls, const uint8_t* 
   return fp64 ? prep_class_t<double>(p, theta, cls, active, sm) : prep_class_t<float>(p, theta, cls, active, sm);
 }
 
-template hipError_t enqueue_eval<float>(cel_plan*, const double*, const double*, int, int, bool, int,
-                                        const uint8_t*, hipStream_t, bool);
-template hipError_t enqueue_eval<double>(cel_plan*, const double*, const double*, int, int, bool, int,
-                                         const uint8_t*, hipStream_t, bool);
-
 hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv, bool grad, int cls,
-                    const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64) {
-  return fp64 ? enqueue_eval<double>(p, theta, theta_trial, v0, nv, grad, cls, active, sm, prep_base)
-              : enqueue_eval<float>(p, theta, theta_trial, v0, nv, grad, cls, active, sm, prep_base);
+                    const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64, double* local_out,
+                    double* grad_out) {
+  return fp64 ? enqueue_eval<double>(p, theta, theta_trial, v0, nv, grad, cls, active, sm, prep_base, local_out,
+                                     grad_out)
+              : enqueue_eval<float>(p, theta, theta_trial, v0, nv, grad, cls, active, sm, prep_base, local_out,
+                                    grad_out);
 }
 
 }  // namespace celmi
@@ -929,14 +929,12 @@ static cel_status eval_common(cel_ctx* ctx, const cel_plan* cplan, const double*
   cel_status st = ensure_variants(p, 1, fp64);
   if (st) return st;
   p->marking = true;
-  hipError_t e = eval_any(p, theta, nullptr, 0, 1, want_grad, -1, nullptr, sm, true, fp64);
+  // the finalisation writes the caller's local objectives and gradients directly
+  hipError_t e = eval_any(p, theta, nullptr, 0, 1, want_grad, -1, nullptr, sm, true, fp64, elbo_local,
+                          want_grad ? grad : nullptr);
   if (e == hipSuccess && elbo_total) e = launch_total(p->v_own, p->S, elbo_total, sm);
   phase_mark(p, 4, sm);
   p->marking = false;
-  if (e == hipSuccess && elbo_local && p->S > 0)
-    e = hipMemcpyAsync(elbo_local, p->v_local, sizeof(double) * p->S, hipMemcpyDeviceToDevice, sm);
-  if (e == hipSuccess && grad && p->S > 0)
-    e = hipMemcpyAsync(grad, p->v_grad, sizeof(double) * p->S * kThetaN, hipMemcpyDeviceToDevice, sm);
   return e == hipSuccess ? CEL_OK : CEL_EHIP;
 }
 

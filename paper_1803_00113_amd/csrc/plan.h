@@ -130,8 +130,11 @@ void ctx_release(cel_ctx* c);
 // a device block of at least `bytes` from the context's cache, else newly allocated
 cel_status ctx_alloc(cel_ctx* c, size_t bytes, void** ptr, size_t* got);
 cel_status ensure_variants(cel_plan* p, int nv, bool fp64);
+// (local_out / grad_out: where variant 0's local objectives and gradients go when nv == 1;
+// null = the plan's per-variant arrays)
 hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv, bool grad, int cls,
-                    const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64);
+                    const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64, double* local_out = nullptr,
+                    double* grad_out = nullptr);
 hipError_t plain_eval(cel_plan* p, const double* theta, hipStream_t sm, bool fp64);
 // component tables at the iterate for every patch and the neighbour moment maps
 hipError_t prep_base(cel_plan* p, const double* theta, hipStream_t sm, bool fp64);
