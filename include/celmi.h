@@ -47,7 +47,7 @@ extern "C" {
 typedef int32_t cel_status;
 #define CEL_OK 0
 #define CEL_EINVAL (-1)        /* invalid argument (null pointer, bad size, bad table)   */
-#define CEL_ENOMEM (-2)        /* device allocation failed (only in cel_prepare)         */
+#define CEL_ENOMEM (-2)        /* device or pinned host allocation failed (cel_prepare)  */
 #define CEL_EHIP (-3)          /* a HIP runtime call failed                              */
 #define CEL_EUNSUPPORTED (-4)  /* a size beyond the library's compiled limits            */
 

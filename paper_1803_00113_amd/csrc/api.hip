@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -219,6 +220,7 @@ void ctx_release(cel_ctx* c) {
       if (k.h_total) (void)hipHostFree(k.h_total);
     }
     if (c->d_err) (void)hipFree(c->d_err);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
   }
   delete c;
 }
@@ -298,6 +300,51 @@ static cel_status track_upload(cel_plan* p, X** ptr, const std::vector<X>& v) {
   cel_status st = track(p, ptr, v.size());
   if (st) return st;
   if (!v.empty() && hipMemcpy(*ptr, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice) != hipSuccess)
+    return CEL_EHIP;
+  return CEL_OK;
+}
+
+// Host arrays copied to the device in one transfer: each gets its own 256-byte aligned
+// slice of one tracked block (one synchronous copy instead of one per array).
+struct UploadPack {
+  struct Item {
+    std::function<void(char*)> set;
+    const void* src;
+    size_t bytes, off;
+  };
+  std::vector<Item> items;
+  size_t total = 0;
+  template <typename X>
+  void add(X** dst, const std::vector<X>& v) {
+    const size_t off = (total + 255) & ~(size_t)255, bytes = v.size() * sizeof(X);
+    items.push_back({[dst](char* q) { *dst = reinterpret_cast<X*>(q); }, v.data(), bytes, off});
+    total = off + std::max<size_t>(bytes, 1);
+  }
+};
+
+static cel_status upload_pack(cel_plan* p, UploadPack& pk, hipStream_t sm) {
+  char* base = nullptr;
+  cel_status st = track(p, &base, pk.total);
+  if (st) return st;
+  // staged through the context's pinned buffer (grown when a larger plan needs it)
+  cel_ctx* c = p->ctx;
+  if (c->stage_cap < pk.total) {
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    c->h_stage = nullptr;
+    c->stage_cap = 0;
+    const size_t cap = std::max<size_t>(pk.total + pk.total / 4, (size_t)1 << 20);
+    if (hipHostMalloc((void**)&c->h_stage, cap) != hipSuccess) {
+      c->h_stage = nullptr;
+      return CEL_ENOMEM;
+    }
+    c->stage_cap = cap;
+  }
+  for (auto& it : pk.items) {
+    if (it.bytes) std::memcpy(c->h_stage + it.off, it.src, it.bytes);
+    it.set(base + it.off);
+  }
+  if (hipMemcpyAsync(base, c->h_stage, pk.total, hipMemcpyHostToDevice, sm) != hipSuccess ||
+      hipStreamSynchronize(sm) != hipSuccess)
     return CEL_EHIP;
   return CEL_OK;
 }
@@ -505,9 +552,20 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
     p->n_colours = std::max(p->n_colours, c + 1);
   }
   // work items: runs of chunk pixels per patch (patch-major), launch order by cost
+  // Cost of a work item: pixels x (1 + neighbour patches / 2), kept as the integer
+  // pixels x (2 + neighbour patches); the order is by decreasing cost, ties by item id
+  // (keys: inverted cost above the id).
   const int CH = p->opt.chunk_pixels;
+  int64_t n_items = 0;
+  for (int i = 0; i < P; ++i) n_items += ((int64_t)p->patches_h[i].w * p->patches_h[i].h + CH - 1) / CH;
+  if (n_items > (int64_t)1 << 30) {
+    plan_release(p);
+    return CEL_EUNSUPPORTED;
+  }
   p->tasks_h.clear();
-  std::vector<double> cost;
+  p->tasks_h.reserve(n_items);
+  std::vector<uint64_t> keys;
+  keys.reserve(n_items);
   for (int i = 0; i < P; ++i) {
     DPatch& d = p->patches_h[i];
     const int n = d.w * d.h;
@@ -518,19 +576,28 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
       t.pix_begin = b;
       t.pix_end = std::min(n, b + CH);
       t.pad = 0;
+      const uint64_t c = (uint64_t)(t.pix_end - t.pix_begin) * (uint64_t)(2 + (d.nbr_end - d.nbr_begin));
+      const uint64_t inv = 0xffffffffull - std::min<uint64_t>(c, 0xffffffffull);
+      keys.push_back((inv << 32) | (uint64_t)p->tasks_h.size());
       p->tasks_h.push_back(t);
-      cost.push_back((double)(t.pix_end - t.pix_begin) * (1.0 + 0.5 * (d.nbr_end - d.nbr_begin)));
     }
     d.task_end = (int)p->tasks_h.size();
   }
   p->n_tasks = (int64_t)p->tasks_h.size();
-  if (p->n_tasks > (int64_t)1 << 30) {
-    plan_release(p);
-    return CEL_EUNSUPPORTED;
+  // stable LSD radix sort on the inverted cost (the ids are generated in ascending order)
+  {
+    std::vector<uint64_t> tmp(keys.size());
+    for (int pass = 0; pass < 4; ++pass) {
+      const int shift = 32 + 8 * pass;
+      size_t count[257] = {0};
+      for (uint64_t k : keys) ++count[((k >> shift) & 0xff) + 1];
+      for (int b = 0; b < 256; ++b) count[b + 1] += count[b];
+      for (uint64_t k : keys) tmp[count[(k >> shift) & 0xff]++] = k;
+      keys.swap(tmp);
+    }
   }
   p->order_h.resize(p->n_tasks);
-  std::iota(p->order_h.begin(), p->order_h.end(), 0);
-  std::stable_sort(p->order_h.begin(), p->order_h.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  for (int64_t i = 0; i < p->n_tasks; ++i) p->order_h[i] = (int32_t)(keys[i] & 0xffffffffull);
   // the moment maps are read only where another source's patch overlaps: keep the work
   // items whose pixel rows meet a neighbour's rectangle
   p->map_order_h.clear();
@@ -620,30 +687,35 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   std::vector<DProfiles> prof1(1, p->prof_h);
   int64_t* d_user_off = nullptr;
   double* d_knots = nullptr;
-  std::vector<int32_t> colour32(p->colour.begin(), p->colour.end());
-  if ((st = track_upload(p, &p->d_patches, p->patches_h)) || (st = track_upload(p, &p->d_images, imgs)) ||
-      (st = track_upload(p, &p->d_nbr, p->nbr_idx_h)) || (st = track_upload(p, &p->d_tasks, p->tasks_h)) ||
-      (st = track_upload(p, &p->d_order, p->order_h)) || (st = track_upload(p, &p->d_map_order, p->map_order_h)) || (st = track_upload(p, &p->d_patch_ptr, p->patch_ptr_h)) ||
-      (st = track_upload(p, &p->d_npsf, npsf)) || (st = track_upload(p, &p->d_prior, prior1)) ||
-      (st = track_upload(p, &p->d_prof, prof1)) || (st = track_upload(p, &p->d_htau_f, p->htau_fh)) ||
-      (st = track_upload(p, &p->d_htau_d, p->htau_dh)) || (st = track_upload(p, &d_user_off, user_off)) ||
-      (st = track_upload(p, &d_knots, knots)) || (st = track(p, &p->d_xs, (size_t)std::max<int64_t>(p->n_units, 1))) ||
-      (st = track(p, &p->d_pixconst, (size_t)2 * std::max(P, 1))) || (st = track(p, &p->d_skymin, (size_t)std::max(P, 1))) || (st = track(p, &p->d_total, 1)) ||
-      (st = ensure_variants(p, 1, p->opt.pixel_fp64 != 0))) {
-    plan_release(p);
-    return st;
-  }
-  // class lists on the device
+  // the plan's tables and lists, the per-colour lists included, in one transfer
+  UploadPack pk;
+  pk.add(&p->d_patches, p->patches_h);
+  pk.add(&p->d_images, imgs);
+  pk.add(&p->d_nbr, p->nbr_idx_h);
+  pk.add(&p->d_tasks, p->tasks_h);
+  pk.add(&p->d_order, p->order_h);
+  pk.add(&p->d_map_order, p->map_order_h);
+  pk.add(&p->d_patch_ptr, p->patch_ptr_h);
+  pk.add(&p->d_npsf, npsf);
+  pk.add(&p->d_prior, prior1);
+  pk.add(&p->d_prof, prof1);
+  pk.add(&p->d_htau_f, p->htau_fh);
+  pk.add(&p->d_htau_d, p->htau_dh);
+  pk.add(&d_user_off, user_off);
+  pk.add(&d_knots, knots);
   p->d_class_patches.assign(p->n_colours, nullptr);
   p->d_class_tasks.assign(p->n_colours, nullptr);
   p->d_class_src.assign(p->n_colours, nullptr);
   for (int c = 0; c < p->n_colours; ++c) {
-    if ((st = track_upload(p, &p->d_class_patches[c], p->class_patches[c])) ||
-        (st = track_upload(p, &p->d_class_tasks[c], p->class_tasks[c])) ||
-        (st = track_upload(p, &p->d_class_src[c], p->class_src[c]))) {
-      plan_release(p);
-      return st;
-    }
+    pk.add(&p->d_class_patches[c], p->class_patches[c]);
+    pk.add(&p->d_class_tasks[c], p->class_tasks[c]);
+    pk.add(&p->d_class_src[c], p->class_src[c]);
+  }
+  if ((st = upload_pack(p, pk, sm)) || (st = track(p, &p->d_xs, (size_t)std::max<int64_t>(p->n_units, 1))) ||
+      (st = track(p, &p->d_pixconst, (size_t)2 * std::max(P, 1))) || (st = track(p, &p->d_skymin, (size_t)std::max(P, 1))) || (st = track(p, &p->d_total, 1)) ||
+      (st = ensure_variants(p, 1, p->opt.pixel_fp64 != 0))) {
+    plan_release(p);
+    return st;
   }
   if ((st = track(p, &p->d_maps, (size_t)std::max<int64_t>(p->n_units, 1))) ||
       ((p->opt.pixel_fp64 || p->opt.hessian_fp64) &&

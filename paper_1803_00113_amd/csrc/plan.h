@@ -31,6 +31,8 @@ struct cel_ctx {
   std::multimap<size_t, void*> cache;   // free device blocks by size
   size_t cache_bytes = 0;
   std::vector<HostKit> kits;
+  char* h_stage = nullptr;        // pinned staging buffer for plan uploads
+  size_t stage_cap = 0;
 };
 
 struct cel_plan {
