@@ -21,7 +21,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work, counted from the method as computed ("Roofline"):
+# Algorithmic work, counted from the method as computed:
 # pixel kernel, per active pixel: the own source's 3 PSF x (1 star + 14 galaxy) Gaussian
 # components with their mu / S / profile derivatives, the delta-method pixel term and the
 # adjoint accumulation; per (pixel, covering neighbour) pair: adding its moments.

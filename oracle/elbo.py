@@ -14,7 +14,7 @@ Follows the paper's model and objective step by step:
     (Section 2.1.2, equation hsi), convolved analytically with a Gaussian-mixture PSF
     (Section 2.2.3)
 
-Readings of garbled or silent passages (each is listed in the design doc):
+Readings of garbled or silent passages:
   colours c_b = ln(l_{b+1}/l_b) with r the reference band; log-normal and normal second
   parameters are variances; e_profile weights the de Vaucouleurs profile; Sigma_s taken
   literally as R^T diag(r^2, axis^2 r^2) R with R = [[cos,-sin],[sin,cos]]; angle in

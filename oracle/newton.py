@@ -7,7 +7,7 @@ Euclidean-ball trust region (the subproblem of Nocedal & Wright, Numerical Optim
 ch. 4), with a dense Hessian.  Section 4.4: sources that do not overlap can be optimised
 in parallel with the same result as serially, so blocks are grouped by a colouring of the
 overlap graph.  The paper prints no trust-region constants; the ones below are this
-implementation's reading (listed in the design doc):
+implementation's reading:
   initial radius 1, maximum radius 100, accept if rho > 0.1, shrink to 0.25*|p| if
   rho < 0.25, double (capped) if rho > 0.75 and the step reached the boundary;
   converged when |g|_inf <= gtol * max(1, |L_s| / n_pix), or the model's predicted gain

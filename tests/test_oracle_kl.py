@@ -1,5 +1,5 @@
 """Pins of the oracle's KL divergence (equations eq:kl, kleq; Supplement A, with the
-readings listed in the design doc) against scipy densities, numerical integration, Monte Carlo
+oracle's stated readings) against scipy densities, numerical integration, Monte Carlo
 and brute-force minimisation over the free weights of the colour bound."""
 import math
 
