@@ -66,24 +66,16 @@ def host_tables(prob):
     """cel_image / cel_patch arrays and prior / profile structs of a problem."""
     N = int(len(prob.img_band))
     P = int(len(prob.patch_src))
-    images = (F.CelImage * max(N, 1))()
-    for n in range(N):
-        im = images[n]
-        im.band = int(prob.img_band[n])
-        im.H = int(prob.img_H[n])
-        im.W = int(prob.img_W[n])
-        im.n_psf = int(prob.img_npsf[n])
-        for k in range(F.MAX_PSF):
-            for q in range(6):
-                im.psf[k][q] = float(prob.img_psf[n, k, q])
-        for i in range(2):
-            for j in range(2):
-                im.A[i][j] = float(prob.img_A[n, i, j])
-            im.b[i] = float(prob.img_b[n, i])
-        im.iota = float(prob.img_iota[n])
-        im.sky_qh = int(prob.img_sky_qh[n])
-        im.sky_qw = int(prob.img_sky_qw[n])
-        im.sky_off = int(prob.img_sky_off[n])
+    # cel_image records filled column by column (numpy mirrors the C struct's layout)
+    images = np.zeros(max(N, 1), dtype=np.dtype(F.CelImage))
+    if N:
+        im = images[:N]
+        im["band"], im["H"], im["W"] = prob.img_band, prob.img_H, prob.img_W
+        im["n_psf"] = prob.img_npsf
+        psf = np.asarray(prob.img_psf, dtype=np.float64)
+        im["psf"][:, :psf.shape[1], :] = psf[:, :F.MAX_PSF, :]
+        im["A"], im["b"], im["iota"] = prob.img_A, prob.img_b, prob.img_iota
+        im["sky_qh"], im["sky_qw"], im["sky_off"] = prob.img_sky_qh, prob.img_sky_qw, prob.img_sky_off
     patches = np.zeros(max(P, 1), dtype=np.dtype([("src", "<i4"), ("img", "<i4"), ("x0", "<i4"), ("y0", "<i4"),
                                                    ("w", "<i4"), ("h", "<i4"), ("pix_off", "<i8")]))
     patches = patches[:P] if P else patches[:0]
@@ -144,7 +136,7 @@ class Plan:
         cp.n_sources = int(prob.n_sources)
         cp.n_images = int(len(prob.img_band))
         cp.n_patches = int(len(prob.patch_src))
-        cp.images = C.cast(images, C.POINTER(F.CelImage))
+        cp.images = images.ctypes.data_as(C.POINTER(F.CelImage))
         cp.sky_knots = knots.ctypes.data_as(C.POINTER(C.c_double))
         cp.n_sky_knots = int(knots.size)
         cp.patches = patches.ctypes.data_as(C.POINTER(F.CelPatch))

@@ -377,14 +377,10 @@ cel_status ensure_newton(cel_plan* p) {
   if (p->newton_ready) return CEL_OK;
   cel_status st;
   const size_t S1 = std::max(p->S, 1);
-  std::vector<double> npix(S1, 0.0);
-  for (int i = 0; i < p->P; ++i) npix[p->patches_h[i].src] += (double)p->patches_h[i].w * p->patches_h[i].h;
-  std::vector<int32_t> col(S1, 0);
-  for (int s = 0; s < p->S; ++s) col[s] = p->colour[s];
+  // (the per-source pixel counts and colours were uploaded with the plan)
   if ((st = track(p, &p->d_theta_trial, S1 * kThetaN)) || (st = track(p, &p->d_pred, S1)) ||
       (st = track(p, &p->d_step_norm, S1)) || (st = track(p, &p->d_trial_active, S1)) ||
       (st = track(p, &p->d_mask, S1)) || (st = track(p, &p->d_counter, 1)) ||
-      (st = track_upload(p, &p->d_npix, npix)) || (st = track_upload(p, &p->d_colour, col)) ||
       (st = track(p, &p->d_hslots, (size_t)std::max<int64_t>(p->n_tasks, 1) * 80)) ||
       (st = track(p, &p->d_hess, S1 * kParamN * kParamN)))
     return st;
@@ -703,6 +699,13 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   pk.add(&p->d_htau_d, p->htau_dh);
   pk.add(&d_user_off, user_off);
   pk.add(&d_knots, knots);
+  // per-source active pixel counts and colours (read by the Newton steps)
+  std::vector<double> npix(std::max(S, 1), 0.0);
+  for (int i = 0; i < P; ++i) npix[p->patches_h[i].src] += (double)p->patches_h[i].w * p->patches_h[i].h;
+  std::vector<int32_t> col(std::max(S, 1), 0);
+  for (int s = 0; s < S; ++s) col[s] = p->colour[s];
+  pk.add(&p->d_npix, npix);
+  pk.add(&p->d_colour, col);
   p->d_class_patches.assign(p->n_colours, nullptr);
   p->d_class_tasks.assign(p->n_colours, nullptr);
   p->d_class_src.assign(p->n_colours, nullptr);

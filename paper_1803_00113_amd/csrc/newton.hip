@@ -200,7 +200,7 @@ struct PixH {
 // profile-weighted second derivatives in (mu, S)
 template <typename T>
 __device__ __forceinline__ void gal_hess(const T* q, T Pxx, T Pxy, T Pyy, T lw, const T* gt, T wP, T dx, T dy, T xx,
-                                         T xy, T yy, T& f, T* gm, T* gs, T* hmm, T* hms, T* hss) {
+                                         T xy, T yy, T& f, T* gm, T* gs, T* hmm, T* hms, T* hmsb, T* hss, T* hssb) {
   const T ux = fma(Pxx, dx, Pxy * dy);
   const T uy = fma(Pxy, dx, Pyy * dy);
   const T N = comp_value<T>(q, xx, xy, yy);
@@ -223,20 +223,29 @@ __device__ __forceinline__ void gal_hess(const T* q, T Pxx, T Pxy, T Pyy, T lw, 
   const T vxy_x = fma(Pxx, uy, Pxy * ux), vxy_y = fma(Pxy, uy, Pyy * ux);
   const T vyy_x = uy * Pxy, vyy_y = uy * Pyy;
   const T w0e = Nxx * wP, w1e = Nxy * wP, w2e = Nyy * wP;
-  hms[0] += fma(w0e, ux, -Ntw * vxx_x);
-  hms[3] += fma(w0e, uy, -Ntw * vxx_y);
-  hms[1] += fma(w1e, ux, -Ntw * vxy_x);
-  hms[4] += fma(w1e, uy, -Ntw * vxy_y);
-  hms[2] += fma(w2e, ux, -Ntw * vyy_x);
-  hms[5] += fma(w2e, uy, -Ntw * vyy_y);
+  // two accumulators per entry (the terms in N u and in N P), so that each term is one fma
+  hms[0] = fma(w0e, ux, hms[0]);
+  hms[3] = fma(w0e, uy, hms[3]);
+  hms[1] = fma(w1e, ux, hms[1]);
+  hms[4] = fma(w1e, uy, hms[4]);
+  hms[2] = fma(w2e, ux, hms[2]);
+  hms[5] = fma(w2e, uy, hms[5]);
+  hmsb[0] = fma(Ntw, vxx_x, hmsb[0]);
+  hmsb[3] = fma(Ntw, vxx_y, hmsb[3]);
+  hmsb[1] = fma(Ntw, vxy_x, hmsb[1]);
+  hmsb[4] = fma(Ntw, vxy_y, hmsb[4]);
+  hmsb[2] = fma(Ntw, vyy_x, hmsb[2]);
+  hmsb[5] = fma(Ntw, vyy_y, hmsb[5]);
   const T q1 = (T)2 * qxy;
   const T Nwt2 = Nw * tau2;
-  hss[0] += fma(Nwt2, (T)0.25 * qxx * qxx - ux * vxx_x, Nw * gt[2]);
-  hss[1] += fma(Nwt2, (T)0.25 * qxx * q1 - ux * vxy_x, Nw * gt[3]);
-  hss[2] += fma(Nwt2, (T)0.25 * qxx * qyy - ux * vyy_x, Nw * gt[4]);
-  hss[3] += fma(Nwt2, (T)0.25 * q1 * q1 - fma(uy, vxy_x, ux * vxy_y), Nw * gt[5]);
-  hss[4] += fma(Nwt2, (T)0.25 * q1 * qyy - uy * vxy_y, Nw * gt[6]);
-  hss[5] += fma(Nwt2, (T)0.25 * qyy * qyy - uy * vyy_y, Nw * gt[7]);
+  hss[0] = fma(Nwt2, (T)0.25 * qxx * qxx - ux * vxx_x, hss[0]);
+  hss[1] = fma(Nwt2, (T)0.25 * qxx * q1 - ux * vxy_x, hss[1]);
+  hss[2] = fma(Nwt2, (T)0.25 * qxx * qyy - ux * vyy_x, hss[2]);
+  hss[3] = fma(Nwt2, (T)0.25 * q1 * q1 - fma(uy, vxy_x, ux * vxy_y), hss[3]);
+  hss[4] = fma(Nwt2, (T)0.25 * q1 * qyy - uy * vxy_y, hss[4]);
+  hss[5] = fma(Nwt2, (T)0.25 * qyy * qyy - uy * vyy_y, hss[5]);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) hssb[e] = fma(Nw, gt[2 + e], hssb[e]);
 }
 
 template <typename T, int NEXP, int NDEV>
@@ -244,6 +253,7 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
                                               PixH<T>& o) {
   T fe = 0, fd = 0, gme[2] = {0, 0}, gmd[2] = {0, 0}, gse[3] = {0, 0, 0}, gsd[3] = {0, 0, 0};
   T hmm[3] = {0, 0, 0}, hms[6] = {0, 0, 0, 0, 0, 0}, hss[6] = {0, 0, 0, 0, 0, 0};
+  T hmsb[6] = {0, 0, 0, 0, 0, 0}, hssb[6] = {0, 0, 0, 0, 0, 0};
   T f1 = 0, g1x = 0, g1y = 0, h1[3] = {0, 0, 0};
   const T pi = tb->hdr[7], omp = (T)1 - pi;
   for (int k = 0; k < K; ++k) {
@@ -266,13 +276,18 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
     for (int j = 0; j < NEXP; ++j)
       if (!(d2 > tb->rc2[k][j]))
         gal_hess<T>(tb->gq[k][j], tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3],
-                    tb->gt[k][j], omp, dx, dy, xx, xy, yy, fe, gme, gse, hmm, hms, hss);
+                    tb->gt[k][j], omp, dx, dy, xx, xy, yy, fe, gme, gse, hmm, hms, hmsb, hss, hssb);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
       if (!(d2 > tb->rc2[k][kMaxProf + j]))
         gal_hess<T>(tb->gq[k][kMaxProf + j], tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1],
                     tb->gal[k][kMaxProf + j][2], tb->gal[k][kMaxProf + j][3], tb->gt[k][kMaxProf + j], pi, dx, dy, xx,
-                    xy, yy, fd, gmd, gsd, hmm, hms, hss);
+                    xy, yy, fd, gmd, gsd, hmm, hms, hmsb, hss, hssb);
+  }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    hms[e] -= hmsb[e];
+    hss[e] += hssb[e];
   }
   o.f1 = f1;
   o.g1[0] = g1x;
@@ -416,12 +431,19 @@ __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
       Eu[5 + j] = w0 * L0 * o.g0[j] + w1 * L1 * g1z[j];
       Vu[5 + j] = (T)2 * (k0 * f0 * o.g0[j] + k1 * f1 * g1z[j] + w01 * d * dz[j]);
     }
+    // T_EE E_u E_v + T_EV (E_u V_v + V_u E_v) = E_u a_v + c_u E_v with a = T_EE E + T_EV V,
+    // c = T_EV V
+    T av[kPrim], cu[kPrim];
 #pragma unroll
     for (int u = 0; u < kPrim; ++u) {
       G[u] = fma(cE, Eu[u], fma(cV, Vu[u], G[u]));
-      const T te = TEE * Eu[u], tv = TEV * Vu[u], tu = TEV * Eu[u];
+      av[u] = fma(TEE, Eu[u], TEV * Vu[u]);
+      cu[u] = TEV * Vu[u];
+    }
 #pragma unroll
-      for (int v = u; v < kPrim; ++v) Q[qidx(u, v)] += fma(te, Eu[v], fma(tu, Vu[v], tv * Eu[v]));
+    for (int u = 0; u < kPrim; ++u) {
+#pragma unroll
+      for (int v = u; v < kPrim; ++v) Q[qidx(u, v)] = fma(Eu[u], av[v], fma(cu[u], Eu[v], Q[qidx(u, v)]));
     }
     // second derivatives of E_s and V_s
     Q[qidx(0, 0)] += cV * (T)-2 * d * d;
@@ -844,7 +866,7 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
   __shared__ double B[kN][kLd];
   __shared__ double V[kN][kLd];
   __shared__ double g[kN], lam[kN], y[kN], gt[kN];
-  __shared__ int verdict;   // 0 continue, 1 non-finite, 2 converged
+  __shared__ int outcome;   // 0 continue, 1 non-finite, 2 converged
   const double L = a.v_local[s];
   const double radius = a.radius[s];
   // B = -H (the Hessian of L_s, pixel and KL parts), symmetrised
@@ -1034,11 +1056,11 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
     a.pnorm[s] = sqrt(nn);
     if (!go) a.status[s] = CEL_ST_CONVERGED;
     a.trial_active[s] = go ? 1 : 0;
-    verdict = go ? 0 : 2;
+    outcome = go ? 0 : 2;
   }
   }
   __syncthreads();
-  if (verdict) return;
+  if (outcome) return;
   if (tid < kThetaN) {
     double v = a.theta[(int64_t)s * kThetaN + tid];
     if (tid < kN) {

@@ -6,15 +6,18 @@ in device memory.  At every device step:
   1. requests that have arrived are admitted, oldest first, while the estimated device
      footprint of the resident set stays within the HBM budget (a request that does not
      fit waits; it is never failed for lack of memory);
-  2. if the resident set changed, the resident requests are merged into one plan (their
+  2. if a request was admitted, the resident requests are merged into one plan (their
      pixel arrays are concatenated on the device; sources of different requests never
-     overlap, so the merged colouring restricted to a request equals its own);
+     overlap, so the merged colouring restricted to a request equals its own), and their
+     parameters and trust radii into one device array each;
   3. one trust-radius Newton round runs, in one batched cel_newton_step, on every resident
      request's current colour class (a request cycles through its classes);
   4. requests that have completed their rounds leave: their parameters and objective are
      copied to the host and the latency (arrival to result on the host) is recorded;
      cancelled requests leave without a result (a request may be cancelled while pending
-     or after a given number of rounds).
+     or after a given number of rounds).  A request that leaves stays in the merged plan,
+     masked out, until the next admission rebuilds it (or until such requests hold more
+     than half of the plan's sources), so that leaving costs no rebuild.
 Work of different requests shares launches; a request's results do not depend on which
 others are resident (every per-source reduction has a fixed order).
 """
@@ -114,6 +117,7 @@ class Request:
     footprint: int = 0
     units: int = 0
     offset: int = 0
+    in_plan: bool = False             # laid out in the current merged plan
 
 
 @dataclass
@@ -147,6 +151,8 @@ class Server:
         self.rounds = int(rounds)
         self.resident: list[Request] = []
         self.plan = None
+        self.theta = self.radius = None   # merged state of the requests laid out in the plan
+        self.in_plan: list[Request] = []
         self.dirty = False
         self.stats = Stats()
 
@@ -166,19 +172,40 @@ class Server:
         self.stats.cancelled += 1
 
     def _rebuild(self):
+        # the state of requests already in the plan comes from the merged arrays
+        for r in self.resident:
+            if r.in_plan:
+                sl = slice(r.offset, r.offset + r.prob.n_sources)
+                r.theta, r.radius = self.theta[sl], self.radius[sl]
         self.plan = None
+        self.theta = self.radius = None
+        self.in_plan = []
         if not self.resident:
             return
         merged = merge([r.prob for r in self.resident])
-        pixels = torch.cat([r.pixels for r in self.resident]) if self.resident else None
+        pixels = torch.cat([r.pixels for r in self.resident])
         self.plan = api.Plan(self.ctx, merged, pixels_device=pixels)
         off = 0
         for r in self.resident:
             r.colours = self.plan.colours[off:off + r.prob.n_sources]
             r.n_colours = int(r.colours.max()) + 1 if r.prob.n_sources else 1
             r.offset = off
+            r.in_plan = True
             off += r.prob.n_sources
+        self.theta = torch.cat([r.theta for r in self.resident]).contiguous()
+        self.radius = torch.cat([r.radius for r in self.resident]).contiguous()
+        for r in self.resident:
+            r.theta = r.radius = None
+        self.in_plan = list(self.resident)
         self.stats.rebuilds += 1
+
+    def _leave(self, gone):
+        """Requests leaving the resident set stay in the plan, masked out; a rebuild is
+        asked for once they hold more than half of its sources."""
+        self.resident = [r for r in self.resident if r not in gone]
+        idle = sum(r.prob.n_sources for r in self.in_plan if r not in self.resident)
+        if self.plan is not None and 2 * idle > self.plan.S:
+            self.dirty = True
 
     def step(self, now, pending):
         """Admit what fits from `pending` (arrived requests, oldest first), run one Newton
@@ -192,11 +219,12 @@ class Server:
         gone = [r for r in self.resident
                 if r.cancel_after_rounds is not None and r.done_rounds >= r.cancel_after_rounds]
         if gone:
-            self.resident = [r for r in self.resident if r not in gone]
-            changed = True
+            self._leave(gone)
         cancelled += gone
         for r in cancelled:
             self._cancel(r)
+        # (requests that left but stay in the plan do not count: an admission rebuilds the
+        # plan without them, after the old one is released)
         used = sum(r.footprint for r in self.resident)
         while pending:
             r = pending[0]
@@ -215,37 +243,31 @@ class Server:
         if not self.resident:
             return cancelled
         S = self.plan.S
-        theta = torch.cat([r.theta for r in self.resident])
-        radius = torch.cat([r.radius for r in self.resident])
         mask = np.zeros(S, bool)
         for r in self.resident:
             c = r.done_rounds % r.n_colours
             mask[r.offset:r.offset + r.prob.n_sources] = r.colours == c
-        status, local = api.newton_step(self.plan, theta, radius, mask)
+        status, local = api.newton_step(self.plan, self.theta, self.radius, mask)
         self.stats.steps += 1
         self.stats.units_evaluated += sum(r.units for r in self.resident)
-        finished, keep = [], []
+        finished = []
         for r in self.resident:
-            sl = slice(r.offset, r.offset + r.prob.n_sources)
-            r.theta = theta[sl].clone()
-            r.radius = radius[sl].clone()
             r.done_rounds += 1
             if r.done_rounds >= r.rounds:
                 finished.append(r)
-            else:
-                keep.append(r)
         if finished:
+            theta_h = self.theta.cpu().numpy()
             tot_local = local.cpu().numpy()
             st = status.cpu().numpy()
             t_done = time.perf_counter()
             for r in finished:
                 sl = slice(r.offset, r.offset + r.prob.n_sources)
-                r.result_theta = r.theta.cpu().numpy()
+                r.result_theta = theta_h[sl].copy()
                 r.result_local = tot_local[sl]
                 r.result_status = st[sl]
                 r.finished = t_done
-            self.resident = keep
-            self.dirty = True
+                r.pixels = None
+            self._leave(finished)
         return finished + cancelled
 
     def run(self, requests, realtime=True):

@@ -50,3 +50,85 @@ def test_merge_rejects_different_priors():
     assert not serve.same_model(a, b)
     with pytest.raises(ValueError):
         serve.merge([a, b])
+
+
+class _FakeBackend:
+    """Stands in for the library in the serving loop's bookkeeping test: a 'plan' with one
+    colour, and a Newton step that adds 1 to every masked source's parameters."""
+
+    def __init__(self):
+        self.plans = 0
+
+    def install(self, monkeypatch, serve):
+        import torch
+        fake = self
+
+        class Ctx:
+            def __init__(self, device, **kw):
+                self.device = torch.device("cpu")
+
+        class Plan:
+            def __init__(self, ctx, merged, pixels_device=None):
+                fake.plans += 1
+                self.S = merged.n_sources
+                self.colours = np.zeros(self.S, np.int32)
+
+        def newton_step(plan, theta, radius, mask):
+            m = torch.as_tensor(mask)
+            theta[m] += 1.0
+            status = m.to(torch.int32)
+            local = torch.where(m, theta[:, 0], torch.full_like(theta[:, 0], float("nan")))
+            return status, local
+
+        monkeypatch.setattr(serve.api, "Context", Ctx)
+        monkeypatch.setattr(serve.api, "Plan", Plan)
+        monkeypatch.setattr(serve.api, "newton_step", newton_step)
+        monkeypatch.setattr(serve.torch.cuda, "synchronize", lambda *a, **k: None)
+
+
+def test_server_bookkeeping(monkeypatch):
+    """Every finished request carries exactly its own rounds of updates; leaving (finishing
+    or cancelling) costs no plan rebuild, admissions do; idle requests are dropped from the
+    plan once they hold more than half of its sources."""
+    from paper_1803_00113_amd import serve
+    fake = _FakeBackend()
+    fake.install(monkeypatch, serve)
+    probs = [gen.crop_patches(gen.config5_request(300 + i, n_sources=2 + i), 16) for i in range(6)]
+    reqs = [serve.Request(i, p, arrival=0.0) for i, p in enumerate(probs)]
+    reqs[2].cancel_after_rounds = 1
+    fp = sorted(serve.footprint_bytes(p) for p in probs)
+    srv = serve.Server(0, hbm_budget_bytes=fp[-1] + fp[-2], rounds=3)
+    stats = srv.run(reqs, realtime=False)
+    assert stats["completed"] == 5 and stats["cancelled"] == 1
+    for r in reqs:
+        if r.cancelled:
+            assert r.result_theta is None
+            continue
+        want = np.array(r.prob.theta0, np.float64)
+        for _ in range(3):
+            want = want + 1.0
+        assert np.array_equal(r.result_theta, want), r.rid
+        assert np.array_equal(r.result_status, np.ones(r.prob.n_sources, np.int32))
+    # one plan per admission event, none for leaving
+    assert fake.plans == stats["rebuilds"] and stats["rebuilds"] <= stats["steps"]
+    admissions = stats["rebuilds"]
+    assert admissions < 6 + 1
+
+
+def test_server_drops_idle_majority(monkeypatch):
+    """A request that leaves while holding most of the plan's sources triggers one rebuild
+    without it; the remaining request's updates are unaffected."""
+    from paper_1803_00113_amd import serve
+    fake = _FakeBackend()
+    fake.install(monkeypatch, serve)
+    big = serve.Request(0, gen.crop_patches(gen.config5_request(401, n_sources=8), 16), arrival=0.0)
+    small = serve.Request(1, gen.crop_patches(gen.config5_request(402, n_sources=2), 16), arrival=0.0)
+    big.cancel_after_rounds = 1
+    srv = serve.Server(0, rounds=3)
+    stats = srv.run([big, small], realtime=False)
+    assert stats["completed"] == 1 and stats["cancelled"] == 1
+    assert stats["rebuilds"] == 2 and fake.plans == 2
+    want = np.array(small.prob.theta0, np.float64)
+    for _ in range(3):
+        want = want + 1.0
+    assert np.array_equal(small.result_theta, want)
