@@ -248,6 +248,17 @@ cel_status cel_sweep(cel_ctx* ctx, const cel_plan* plan, double* theta, double* 
  * record.  CEL_EINVAL if timing was not enabled. */
 cel_status cel_phase_times(cel_plan* plan, double* ms, int64_t* n_calls, int32_t reset);
 
+/* Launch tuning of the pixel pass (the paper's thread-level execution study and its remark
+ * that sources of varying size make SIMD across sources hard): times the ELBO-and-gradient
+ * evaluation at theta with 1, 2 and 4 pixels per lane (one warm-up and three timed calls
+ * each, on `stream`, synchronised) and keeps the fastest in the plan; later evaluations,
+ * Newton steps and sweeps of the plan use it (captured sweep graphs are dropped).  Outputs
+ * of a plan are deterministic once its setting is fixed; different settings sum partial
+ * results in different groupings (last-bit differences).  theta: DEVICE [S][32].
+ * pixels_per_lane: HOST int32 out (may be NULL).  Writes no caller buffer but
+ * pixels_per_lane; the plan's internal scratch holds the last timed evaluation. */
+cel_status cel_tune(cel_ctx* ctx, cel_plan* plan, const double* theta, int32_t* pixels_per_lane, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

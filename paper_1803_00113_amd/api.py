@@ -182,6 +182,14 @@ class Plan:
         F.check("cel_phase_times", F.lib.cel_phase_times(self.h, ms, C.byref(n), int(bool(reset))))
         return list(ms), int(n.value)
 
+    def tune(self, theta):
+        """cel_tune: times the evaluation at theta with 1, 2 and 4 pixels per lane, keeps the
+        fastest for this plan and returns it."""
+        th = self._theta(theta)
+        ppl = C.c_int32()
+        F.check("cel_tune", F.lib.cel_tune(self.ctx.h, self.h, _ptr(th), C.byref(ppl), _stream(self.ctx.device)))
+        return int(ppl.value)
+
     def _out(self, *shape):
         return torch.empty(shape, dtype=torch.float64, device=self.ctx.device)
 

@@ -1043,6 +1043,56 @@ extern "C" cel_status cel_elbo_grad_plain(cel_ctx* ctx, const cel_plan* cplan, c
   return e == hipSuccess ? CEL_OK : CEL_EHIP;
 }
 
+extern "C" cel_status cel_tune(cel_ctx* ctx, cel_plan* p, const double* theta, int32_t* pixels_per_lane,
+                                void* stream) {
+  if (!ctx || !p || (!theta && p->S > 0)) return CEL_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
+  const int keep = p->opt.pixels_per_lane;
+  if (p->S == 0) {
+    if (pixels_per_lane) *pixels_per_lane = keep;
+    return CEL_OK;
+  }
+  hipStream_t sm = (hipStream_t)stream;
+  const bool fp64 = p->opt.pixel_fp64 != 0;
+  cel_status st = ensure_variants(p, 1, fp64);
+  if (st) return st;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    return CEL_EHIP;
+  }
+  const bool marking = p->marking;
+  p->marking = false;
+  int best = keep;
+  float best_ms = INFINITY;
+  hipError_t e = hipSuccess;
+  for (int c : {1, 2, 4}) {
+    p->opt.pixels_per_lane = c;
+    e = eval_any(p, theta, nullptr, 0, 1, true, -1, nullptr, sm, true, fp64);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(ev[0], sm);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = eval_any(p, theta, nullptr, 0, 1, true, -1, nullptr, sm, true, fp64);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], sm);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (e != hipSuccess) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  p->marking = marking;
+  p->opt.pixels_per_lane = e == hipSuccess ? best : keep;
+  // sweep graphs captured with the previous setting are rebuilt on their next use
+  for (auto& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
+  if (pixels_per_lane) *pixels_per_lane = p->opt.pixels_per_lane;
+  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+}
+
 extern "C" cel_status cel_phase_times(cel_plan* p, double* ms, int64_t* n_calls, int32_t reset) {
   if (!p || !p->opt.timing) return CEL_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;

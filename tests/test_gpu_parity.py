@@ -101,6 +101,23 @@ def test_small_batched_fp32(small2, chunk):
     say(f"  max grad rel err {err:.2e}")
 
 
+def test_tuned_plan_matches_a_plan_built_with_its_setting(small2):
+    """cel_tune keeps one of 1, 2, 4 pixels per lane; the tuned plan's outputs equal, bit for
+    bit, those of a plan created with that setting, and stay within the oracle's tolerance."""
+    say("case: small config2 launch tuning")
+    prob, (o_tot, o_loc, o_g) = small2
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    ppl = plan.tune(prob.theta0)
+    say(f"  tuned pixels per lane: {ppl}")
+    assert ppl in (1, 2, 4)
+    t1, l1, g1 = api.elbo_grad(plan, prob.theta0)
+    _, t2, l2, g2 = run(prob, pixels_per_lane=ppl)
+    torch.cuda.synchronize()
+    assert t1.item() == t2 and np.array_equal(l1.cpu().numpy(), l2) and np.array_equal(g1.cpu().numpy(), g2)
+    check(prob, t2, l2, g2, o_tot, o_loc, o_g)
+
+
 def test_small_batched_fp64(small2):
     say("case: small config2 fp64")
     prob, (o_tot, o_loc, o_g) = small2
