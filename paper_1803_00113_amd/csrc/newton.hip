@@ -33,7 +33,7 @@
 namespace celmi {
 
 constexpr int kN = kParamN;   // 27
-static_assert(kN % 3 == 0, "the Jacobi dot products run in three chains");
+static_assert(((kN + 1) / 2) % 2 == 0, "the Jacobi half-columns hold an even number of rows");
 constexpr int kLd = kN + 1;   // padded LDS row
 
 
@@ -906,39 +906,47 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
     return;
   }
   const double cs = sqrt(fro) * 1.001 + 1e-300;
-  double w[kN];
+  // Lane 32 h + c holds rows 14 h .. 14 h + 13 of column c (c < 27; column 27 is the idle
+  // partner of the odd-size round-robin), so a round exchanges and rotates 14 entries per
+  // lane; sums over a column add the two halves (lanes c and c + 32).
+  constexpr int kH = (kN + 1) / 2;
+  const int half = lane >> 5, col = lane & 31;
+  auto hsum = [&](double v) { return v + __shfl_xor(v, 32, 64); };
+  double w[kH];
 #pragma unroll
-  for (int i = 0; i < kN; ++i) w[i] = lane < kN ? B[i][lane] + (i == lane ? cs : 0.0) : 0.0;
+  for (int i = 0; i < kH; ++i) {
+    const int row = half * kH + i;
+    w[i] = (col < kN && row < kN) ? B[row][col] + (row == col ? cs : 0.0) : 0.0;
+  }
   for (int sweep = 0; sweep < 40; ++sweep) {
     double rotated = 0.0;
     // squared column norm, exact at the start of a sweep and carried through its rotations
     // (|c w + cp pw|^2 = c^2 al + cp^2 be + 2 c cp ga)
-    double al = 0.0;
+    double al;
     {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-      for (int i = 0; i < kN; i += 3) {
+      for (int i = 0; i < kH; i += 2) {
         a0 = fma(w[i], w[i], a0);
         a1 = fma(w[i + 1], w[i + 1], a1);
-        a2 = fma(w[i + 2], w[i + 2], a2);
       }
-      al = a0 + a1 + a2;
+      al = hsum(a0 + a1);
     }
     for (int r = 0; r < kN; ++r) {
-      const int pt = lane > kN ? lane : lane == kN ? r : lane == r ? kN : ((2 * r - lane) % kN + kN) % kN;
-      double pw[kN];
+      const int pc = col > kN ? col : col == kN ? r : col == r ? kN : ((2 * r - col) % kN + kN) % kN;
+      const int pt = half * 32 + pc;
+      double pw[kH];
       const double be = __shfl(al, pt, 64);
-      double g0 = 0.0, g1 = 0.0, g2 = 0.0;   // three chains for the dot product
 #pragma unroll
-      for (int i = 0; i < kN; ++i) pw[i] = __shfl(w[i], pt, 64);
+      for (int i = 0; i < kH; ++i) pw[i] = __shfl(w[i], pt, 64);
+      double g0 = 0.0, g1 = 0.0;   // two chains for the dot product
 #pragma unroll
-      for (int i = 0; i < kN; i += 3) {
+      for (int i = 0; i < kH; i += 2) {
         g0 = fma(w[i], pw[i], g0);
         g1 = fma(w[i + 1], pw[i + 1], g1);
-        g2 = fma(w[i + 2], pw[i + 2], g2);
       }
-      const double ga = g0 + g1 + g2;
-      const bool lowside = lane < pt;
+      const double ga = hsum(g0 + g1);
+      const bool lowside = col < pc;
       const double alo = lowside ? al : be, ahi = lowside ? be : al;
       double c = 1.0, sn = 0.0;
       if (fabs(ga) > 1e-15 * sqrt(alo * ahi)) {
@@ -950,25 +958,31 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
       }
       const double cp = lowside ? -sn : sn;
 #pragma unroll
-      for (int i = 0; i < kN; ++i) w[i] = fma(c, w[i], cp * pw[i]);
+      for (int i = 0; i < kH; ++i) w[i] = fma(c, w[i], cp * pw[i]);
       al = c * c * al + cp * cp * be + 2.0 * c * cp * ga;
     }
     if (wave_max(rotated) == 0.0) break;
   }
-  if (lane < kN) {
+  {
     double nn = 0.0;
 #pragma unroll
-    for (int i = 0; i < kN; ++i) nn = fma(w[i], w[i], nn);
-    const double sig = sqrt(nn), inv = 1.0 / sig;
+    for (int i = 0; i < kH; ++i) nn = fma(w[i], w[i], nn);
+    const double sig = sqrt(hsum(nn)), inv = 1.0 / sig;
     double acc = 0.0;   // gt = V^T g
 #pragma unroll
-    for (int i = 0; i < kN; ++i) {
-      const double v = w[i] * inv;
-      V[i][lane] = v;
-      acc = fma(v, g[i], acc);
+    for (int i = 0; i < kH; ++i) {
+      const int row = half * kH + i;
+      if (col < kN && row < kN) {
+        const double v = w[i] * inv;
+        V[row][col] = v;
+        acc = fma(v, g[row], acc);
+      }
     }
-    lam[lane] = sig - cs;
-    gt[lane] = acc;
+    acc = hsum(acc);
+    if (col < kN && half == 0) {
+      lam[col] = sig - cs;
+      gt[col] = acc;
+    }
   }
   __syncthreads();
   bool go = false;
