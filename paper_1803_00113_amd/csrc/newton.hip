@@ -256,6 +256,7 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
   T hmsb[6] = {0, 0, 0, 0, 0, 0}, hssb[6] = {0, 0, 0, 0, 0, 0};
   T f1 = 0, g1x = 0, g1y = 0, h1[3] = {0, 0, 0};
   const T pi = tb->hdr[7], omp = (T)1 - pi;
+  __builtin_assume(K >= 1);   // images have 1..kMaxPsf PSF components (checked at prepare)
   for (int k = 0; k < K; ++k) {
     const T mx = tb->star[k][0], my = tb->star[k][1];
     const T dx = px - mx, dy = py - my;
@@ -345,7 +346,6 @@ __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
   const Table<T>* __restrict__ tb = reinterpret_cast<const Table<T>*>(a.tables) + task.patch;
   const int K = a.img_npsf[P.img];
   const int lane = threadIdx.x;
-  const float inv_w = 1.0f / (float)P.w;
   const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
   const T e0 = tb->hdr[8], e1 = tb->hdr[9];
   const T w01 = w0 * w1, aa = w1, oma2 = (T)1 - (T)2 * aa;
@@ -355,14 +355,14 @@ __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
   for (int u = 0; u < kPrim; ++u) G[u] = 0;
 #pragma unroll
   for (int u = 0; u < kHQ; ++u) Q[u] = 0;
+  // this lane's patch-local pixel coordinates, advanced by 64 pixels per pass with a carry
+  const int step_rows = 64 / P.w, step_cols = 64 - step_rows * P.w;
+  int row = (task.pix_begin + lane) / P.w;
+  int col = task.pix_begin + lane - row * P.w;
   for (int base = task.pix_begin; base < task.pix_end; base += 64) {
     int idx = base + lane;
     const bool valid = idx < task.pix_end;
     if (!valid) idx = task.pix_begin;
-    int row = (int)(((float)idx + 0.5f) * inv_w);
-    int col = idx - row * P.w;
-    if (col < 0) { row -= 1; col += P.w; }
-    else if (col >= P.w) { row += 1; col -= P.w; }
     T xv, sky;
     if constexpr (sizeof(T) == 8) {
       const double2 xs = reinterpret_cast<const double2*>(a.xs)[P.off + idx];
@@ -371,17 +371,21 @@ __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
       const float2 xs = reinterpret_cast<const float2*>(a.xs)[P.off + idx];
       xv = xs.x; sky = xs.y;
     }
-    T box[4];
-    run_box<T>(base, min(base + 64, task.pix_end), P.w, box);
+    int ibox[4];
+    run_box<int>(base, min(base + 64, task.pix_end), P.w, ibox);
+    const T box[4] = {(T)ibox[0], (T)ibox[1], (T)ibox[2], (T)ibox[3]};
     PixH<T> o;
     eval_own_hess<T, NEXP, NDEV>(tb, K, (T)col, (T)row, box, o);
     T Eb = sky, Vb = 0;
     bool own = true;
     for (int nb = P.nbr_begin; nb < P.nbr_end; ++nb) {
       const DPatch Qp = a.patches[a.nbr_idx[nb]];
-      const int cx = col + P.x0 - Qp.x0, cy = row + P.y0 - Qp.y0;
-      if (valid && cx >= 0 && cx < Qp.w && cy >= 0 && cy < Qp.h) {
-        const int64_t at = Qp.off + (int64_t)cy * Qp.w + cx;
+      const int ox = P.x0 - Qp.x0, oy = P.y0 - Qp.y0;
+      // a neighbour whose rectangle misses this pass's pixel box is skipped as a whole
+      if (ibox[0] + ox >= Qp.w || ibox[1] + ox < 0 || ibox[2] + oy >= Qp.h || ibox[3] + oy < 0) continue;
+      const int cx = col + ox, cy = row + oy;
+      if (valid && (unsigned)cx < (unsigned)Qp.w && (unsigned)cy < (unsigned)Qp.h) {
+        const int64_t at = Qp.off + (cy * Qp.w + cx);
         if constexpr (sizeof(T) == 8) {
           const double2 ev = reinterpret_cast<const double2*>(a.maps)[at];
           Eb += ev.x; Vb += ev.y;
@@ -477,6 +481,12 @@ __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
                               w01 * (dz[i] * dz[j] + d * (L0 * h0ij - L1 * h1ij)));
         Q[qidx(5 + i, 5 + j)] += fma(cE, Euv, cV * Vuv);
       }
+    }
+    col += step_cols;
+    row += step_rows;
+    if (col >= P.w) {
+      col -= P.w;
+      row += 1;
     }
   }
   double* out = a.hslots + (int64_t)t * kHSlots;
