@@ -1356,10 +1356,15 @@ extern "C" cel_status cel_newton_step(cel_ctx* ctx, const cel_plan* cplan, doubl
   std::memcpy(p->h_mask, m.data(), p->S);
   hipError_t e = hipMemcpyAsync(p->d_mask, p->h_mask, p->S, hipMemcpyHostToDevice, sm);
   if (e == hipSuccess) e = hipEventRecord(p->mask_copied, sm);
+  // The stepped sources never overlap one another, so no class steps a neighbour of another
+  // class's stepped source: the tables and neighbour maps made once at the iterate serve
+  // every class (each class then rebuilds only its own tables).
+  const bool maps_once = !p->opt.hessian_fd;
+  if (maps_once && e == hipSuccess) e = prep_base(p, theta, sm, p->opt.pixel_fp64 || p->opt.hessian_fp64);
   for (int c = 0; c < p->n_colours && e == hipSuccess; ++c) {
     bool any = false;
     for (int s : p->class_src[c]) any = any || m[s];
-    if (any) e = enqueue_newton_class(p, theta, radius, p->d_mask, c, step_status, elbo_local, false, sm);
+    if (any) e = enqueue_newton_class(p, theta, radius, p->d_mask, c, step_status, elbo_local, false, sm, maps_once);
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_skipped, dim3((p->S + 255) / 256), dim3(256), 0, sm, p->d_mask, p->S, step_status,
