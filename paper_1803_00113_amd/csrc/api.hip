@@ -216,6 +216,7 @@ void ctx_release(cel_ctx* c) {
       if (k.mask_copied) (void)hipEventDestroy(k.mask_copied);
       if (k.own_stream) (void)hipStreamDestroy(k.own_stream);
       if (k.h_mask) (void)hipHostFree(k.h_mask);
+      if (k.h_lists) (void)hipHostFree(k.h_lists);
       if (k.h_counter) (void)hipHostFree(k.h_counter);
       if (k.h_total) (void)hipHostFree(k.h_total);
     }
@@ -237,6 +238,8 @@ void plan_release(cel_plan* p) {
     HostKit k;
     k.h_mask = p->h_mask;
     k.mask_cap = p->mask_cap;
+    k.h_lists = p->h_lists;
+    k.lists_cap = p->lists_cap;
     k.h_counter = p->h_counter;
     k.h_total = p->h_total;
     k.mask_copied = p->mask_copied;
@@ -247,6 +250,7 @@ void plan_release(cel_plan* p) {
       (void)hipEventDestroy(k.mask_copied);
       if (k.own_stream) (void)hipStreamDestroy(k.own_stream);
       if (k.h_mask) (void)hipHostFree(k.h_mask);
+      if (k.h_lists) (void)hipHostFree(k.h_lists);
       if (k.h_counter) (void)hipHostFree(k.h_counter);
       if (k.h_total) (void)hipHostFree(k.h_total);
     }
@@ -382,6 +386,8 @@ cel_status ensure_newton(cel_plan* p) {
       (st = track(p, &p->d_step_norm, S1)) || (st = track(p, &p->d_trial_active, S1)) ||
       (st = track(p, &p->d_mask, S1)) || (st = track(p, &p->d_counter, 1)) ||
       (st = track(p, &p->d_hslots, (size_t)std::max<int64_t>(p->n_tasks, 1) * 80)) ||
+      (st = track(p, &p->d_step_src, S1)) || (st = track(p, &p->d_step_patches, (size_t)std::max(p->P, 1))) ||
+      (st = track(p, &p->d_step_tasks, (size_t)std::max<int64_t>(p->n_tasks, 1))) ||
       (st = track(p, &p->d_hess, S1 * kParamN * kParamN)))
     return st;
   if (hipMemset(p->d_trial_active, 0, S1) != hipSuccess) return CEL_EHIP;
@@ -399,12 +405,32 @@ cel_status ensure_newton(cel_plan* p) {
     if (hipHostMalloc((void**)&k.h_mask, S1, 0) != hipSuccess) return CEL_ENOMEM;
     k.mask_cap = S1;
   }
+  const size_t lists = S1 + (size_t)std::max(p->P, 1) + (size_t)std::max<int64_t>(p->n_tasks, 1);
+  if (k.lists_cap < lists) {
+    if (k.h_lists) (void)hipHostFree(k.h_lists);
+    k.h_lists = nullptr;
+    k.lists_cap = 0;
+    if (hipHostMalloc((void**)&k.h_lists, lists * sizeof(int32_t), 0) != hipSuccess) return CEL_ENOMEM;
+    k.lists_cap = lists;
+  }
   if (!k.h_counter && hipHostMalloc((void**)&k.h_counter, sizeof(int32_t), 0) != hipSuccess) return CEL_ENOMEM;
   if (!k.h_total && hipHostMalloc((void**)&k.h_total, sizeof(double), 0) != hipSuccess) return CEL_ENOMEM;
   if (!k.mask_copied && hipEventCreate(&k.mask_copied) != hipSuccess) return CEL_EHIP;
   if (!k.own_stream && hipStreamCreate(&k.own_stream) != hipSuccess) return CEL_EHIP;
   p->h_mask = k.h_mask;
   p->mask_cap = k.mask_cap;
+  p->h_lists = k.h_lists;
+  p->lists_cap = k.lists_cap;
+  // the step class (entry n_colours of the class lists), filled by each cel_newton_step
+  p->class_src.resize(p->n_colours + 1);
+  p->class_patches.resize(p->n_colours + 1);
+  p->class_tasks.resize(p->n_colours + 1);
+  p->d_class_src.resize(p->n_colours + 1);
+  p->d_class_patches.resize(p->n_colours + 1);
+  p->d_class_tasks.resize(p->n_colours + 1);
+  p->d_class_src[p->n_colours] = p->d_step_src;
+  p->d_class_patches[p->n_colours] = p->d_step_patches;
+  p->d_class_tasks[p->n_colours] = p->d_step_tasks;
   p->h_counter = k.h_counter;
   p->h_total = k.h_total;
   p->mask_copied = k.mask_copied;

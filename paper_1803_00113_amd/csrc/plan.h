@@ -12,6 +12,8 @@
 struct HostKit {
   uint8_t* h_mask = nullptr;
   size_t mask_cap = 0;
+  int32_t* h_lists = nullptr;     // a Newton step's source, patch and work-item lists
+  size_t lists_cap = 0;
   int32_t* h_counter = nullptr;
   double* h_total = nullptr;
   hipEvent_t mask_copied = nullptr;
@@ -49,6 +51,8 @@ struct cel_plan {
   std::vector<std::vector<int>> adj;
   std::vector<int> colour;
   int n_colours = 0;
+  // per colour class c < n_colours: its sources, patches and work items (cost order); entry
+  // n_colours (Newton scratch) holds the sources stepped by one cel_newton_step call
   std::vector<std::vector<int32_t>> class_patches, class_tasks, class_src;
   celmi::DPrior prior_h;
   celmi::DProfiles prof_h;
@@ -95,6 +99,8 @@ struct cel_plan {
   uint8_t* d_mask = nullptr;
   int32_t* d_counter = nullptr;
   uint8_t* h_mask = nullptr;      // pinned
+  int32_t* h_lists = nullptr;     // pinned, S + P + n_tasks entries
+  size_t lists_cap = 0;
   int32_t* h_counter = nullptr;   // pinned
   double* h_total = nullptr;      // pinned
   hipEvent_t mask_copied = nullptr;
@@ -112,6 +118,9 @@ struct cel_plan {
   int fd_mode = 1;
   int trial_variant = celmi::kVariants - 1;
   double* d_hslots = nullptr;     // analytic Hessian partial sums [n_tasks][80]
+  int32_t* d_step_src = nullptr;      // a Newton step's sources, patches and work items
+  int32_t* d_step_patches = nullptr;
+  int32_t* d_step_tasks = nullptr;
   double* d_hess = nullptr;       // per-source pixel Hessians [S][27][27]
   struct Block {
     void* ptr;
