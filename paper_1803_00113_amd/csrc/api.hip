@@ -221,6 +221,7 @@ void ctx_release(cel_ctx* c) {
       if (k.h_total) (void)hipHostFree(k.h_total);
     }
     if (c->d_err) (void)hipFree(c->d_err);
+    if (c->d_ctable) (void)hipFree(c->d_ctable);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
   }
   delete c;
@@ -465,10 +466,21 @@ extern "C" cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_op
     (void)hipFree(err);
     return CEL_EHIP;
   }
+  double* table = nullptr;
+  if (hipMalloc((void**)&table, sizeof(double) * kCountTable) != hipSuccess) {
+    (void)hipFree(err);
+    return CEL_ENOMEM;
+  }
+  if (launch_count_table(table, nullptr) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
+    (void)hipFree(table);
+    (void)hipFree(err);
+    return CEL_EHIP;
+  }
   cel_ctx* c = new cel_ctx;
   c->device = hip_device;
   c->opt = o;
   c->d_err = err;
+  c->d_ctable = table;
   *out = c;
   return CEL_OK;
 }
@@ -754,7 +766,8 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
     return st;
   }
   hipError_t e = launch_pixels(p->d_patches, p->d_images, d_knots, pr->pixels, d_user_off, p->d_xs, p->d_xs64, P, sm);
-  if (e == hipSuccess) e = launch_pixconst(p->d_patches, p->d_nbr, p->d_xs, p->d_pixconst, p->d_skymin, P, sm);
+  if (e == hipSuccess)
+    e = launch_pixconst(p->d_patches, p->d_nbr, p->d_xs, ctx->d_ctable, p->d_pixconst, p->d_skymin, P, sm);
   if (e == hipSuccess) e = hipStreamSynchronize(sm);
   if (e != hipSuccess) {
     plan_release(p);

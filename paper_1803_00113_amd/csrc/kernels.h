@@ -59,7 +59,10 @@ hipError_t launch_finalize(const FinalizeArgs& a, int n_variants, hipStream_t st
 hipError_t launch_total(const double* own, int n, double* out, hipStream_t st);
 hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const double* knots, const float* pixels,
                          const int64_t* user_off, float2* xs, double2* xs64, int n_patches, hipStream_t st);
-hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, double* out, double* sky_min,
-                           int n_patches, hipStream_t st);
+// data constants x log x - x - log x! of the counts 0 .. kCountTable - 1 (once per context)
+constexpr int kCountTable = 4096;
+hipError_t launch_count_table(double* table, hipStream_t st);
+hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, const double* table,
+                           double* out, double* sky_min, int n_patches, hipStream_t st);
 
 }  // namespace celmi

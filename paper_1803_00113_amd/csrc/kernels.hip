@@ -714,8 +714,17 @@ __global__ __launch_bounds__(256) void k_pixels(const DPatch* __restrict__ patch
   const cel_image& im = images[P.img];
   const double* kn = knots + im.sky_off;
   const int n = P.w * P.h;
+  // patch-local coordinates of this thread's pixels, advanced by 256 pixels per pass
+  const int step_rows = 256 / P.w, step_cols = 256 - step_rows * P.w;
+  int prow = (int)threadIdx.x / P.w, pcol = (int)threadIdx.x - prow * P.w;
   for (int i = threadIdx.x; i < n; i += 256) {
-    const int row = P.y0 + i / P.w, col = P.x0 + i % P.w;
+    const int row = P.y0 + prow, col = P.x0 + pcol;
+    pcol += step_cols;
+    prow += step_rows;
+    if (pcol >= P.w) {
+      pcol -= P.w;
+      prow += 1;
+    }
     // bilinear interpolation on a knot grid spanning the image corners (Section 2.2.1)
     double fy = 0, fx = 0;
     int iy = 0, ix = 0;
@@ -739,19 +748,39 @@ __global__ __launch_bounds__(256) void k_pixels(const DPatch* __restrict__ patch
 }
 
 // sum over the patch of C(x) = x log x - x - log x! (all pixels, and owned pixels only)
+// data constant of a count: x log x - x - log x! (0 for x = 0)
+__device__ __forceinline__ double count_const(double x) { return x > 0 ? x * log(x) - x - lgamma(x + 1.0) : 0.0; }
+
+// the data constants of the counts 0 .. kCountTable - 1
+__global__ __launch_bounds__(256) void k_count_table(double* __restrict__ table) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < kCountTable) table[i] = count_const((double)i);
+}
+
 __global__ __launch_bounds__(256) void k_pixconst(const DPatch* __restrict__ patches, const int32_t* __restrict__ nbr_idx,
-                                                  const float2* __restrict__ xs, double* __restrict__ out,
-                                                  double* __restrict__ sky_min) {
+                                                  const float2* __restrict__ xs, const double* __restrict__ table,
+                                                  double* __restrict__ out, double* __restrict__ sky_min) {
   __shared__ double sh[3][256];
   const DPatch P = patches[blockIdx.x];
   const int n = P.w * P.h;
   double all = 0, own = 0, smin = INFINITY;
+  // patch-local coordinates of this thread's pixels, advanced by 256 pixels per pass
+  const int step_rows = 256 / P.w, step_cols = 256 - step_rows * P.w;
+  int prow = (int)threadIdx.x / P.w, pcol = (int)threadIdx.x - prow * P.w;
   for (int i = threadIdx.x; i < n; i += 256) {
-    const double x = xs[P.off + i].x;
-    smin = fmin(smin, (double)xs[P.off + i].y);
-    const double c = x > 0 ? x * log(x) - x - lgamma(x + 1.0) : 0.0;
+    const float2 v = xs[P.off + i];
+    const double x = v.x;
+    smin = fmin(smin, (double)v.y);
+    // integer counts below the table's size from the table (the same values)
+    const double c = (x >= 0 && x < (double)kCountTable && x == floor(x)) ? table[(int)x] : count_const(x);
     all += c;
-    const int col = P.x0 + i % P.w, row = P.y0 + i / P.w;
+    const int col = P.x0 + pcol, row = P.y0 + prow;
+    pcol += step_cols;
+    prow += step_rows;
+    if (pcol >= P.w) {
+      pcol -= P.w;
+      prow += 1;
+    }
     bool mine = true;
     for (int nb = P.nbr_begin; nb < P.nbr_end; ++nb) {
       const DPatch Q = patches[nbr_idx[nb]];
@@ -854,11 +883,15 @@ hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const d
   return hipGetLastError();
 }
 
-hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, double* out, double* sky_min,
-                           int n_patches,
-                           hipStream_t st) {
+hipError_t launch_count_table(double* table, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_table, dim3((kCountTable + 255) / 256), dim3(256), 0, st, table);
+  return hipGetLastError();
+}
+
+hipError_t launch_pixconst(const DPatch* patches, const int32_t* nbr_idx, const float2* xs, const double* table,
+                           double* out, double* sky_min, int n_patches, hipStream_t st) {
   if (n_patches <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pixconst, dim3(n_patches), dim3(256), 0, st, patches, nbr_idx, xs, out, sky_min);
+  hipLaunchKernelGGL(k_pixconst, dim3(n_patches), dim3(256), 0, st, patches, nbr_idx, xs, table, out, sky_min);
   return hipGetLastError();
 }
 

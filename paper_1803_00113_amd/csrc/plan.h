@@ -29,6 +29,7 @@ struct cel_ctx {
   int device;
   cel_options opt;
   int32_t* d_err = nullptr;       // device condition word (CEL_DEVERR_*), shared by the plans
+  double* d_ctable = nullptr;     // data constants of small counts (k_pixconst)
   int refs = 1;                   // the caller's handle + one per live plan
   std::multimap<size_t, void*> cache;   // free device blocks by size
   size_t cache_bytes = 0;
