@@ -196,7 +196,8 @@ cel_status cel_elbo_hessian(cel_ctx* ctx, const cel_plan* plan, const double* th
 
 /* One trust-region Newton step (Section 4.3) on every source with mask[s] != 0 (HOST
  * uint8 [S], NULL = all), all from the same iterate.  Masked sources must be pairwise
- * non-overlapping (checked against the plan: CEL_EINVAL otherwise).  Hessian exact (as
+ * non-overlapping (checked against the plan: CEL_EINVAL otherwise); with the exact Hessian
+ * they are stepped as one batch whatever their colour classes.  Hessian exact (as
  * cel_elbo_hessian), or with options.hessian_fd by central differences of the gradient
  * (pixel part; the KL part is always exact); the subproblem is solved
  * exactly (eigen-decomposition, boundary multiplier by a safeguarded secular-equation
