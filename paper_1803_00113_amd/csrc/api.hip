@@ -536,54 +536,66 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   }
   p->n_units = off;
   for (int s = 0; s < S; ++s) p->patch_ptr_h[s + 1] += p->patch_ptr_h[s];
-  // neighbour patches: same image, other source, intersecting rectangles (sweep over x0)
-  std::vector<std::vector<int>> nbr(P);
+  // neighbour patches: same image, other source, intersecting rectangles (sweep over x0);
+  // the pairs are counted per patch and scattered into the CSR list, then each patch's
+  // (short) list is sorted ascending
   {
-    std::vector<std::vector<int>> by_img(N);
-    for (int i = 0; i < P; ++i) by_img[p->patches_h[i].img].push_back(i);
-    for (int n = 0; n < N; ++n) {
-      auto& v = by_img[n];
-      std::sort(v.begin(), v.end(), [&](int a, int b) {
-        return p->patches_h[a].x0 < p->patches_h[b].x0 || (p->patches_h[a].x0 == p->patches_h[b].x0 && a < b);
-      });
-      for (size_t ia = 0; ia < v.size(); ++ia) {
-        const DPatch& A = p->patches_h[v[ia]];
-        for (size_t ib = ia + 1; ib < v.size(); ++ib) {
-          const DPatch& B = p->patches_h[v[ib]];
-          if (B.x0 >= A.x0 + A.w) break;
-          if (B.y0 < A.y0 + A.h && A.y0 < B.y0 + B.h && A.src != B.src) {
-            nbr[v[ia]].push_back(v[ib]);
-            nbr[v[ib]].push_back(v[ia]);
-          }
+    std::vector<int> order(P);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      const DPatch &A = p->patches_h[a], &B = p->patches_h[b];
+      return A.img != B.img ? A.img < B.img : A.x0 != B.x0 ? A.x0 < B.x0 : a < b;
+    });
+    std::vector<int2> pairs;
+    std::vector<int> deg(P + 1, 0);
+    for (int ia = 0; ia < P; ++ia) {
+      const DPatch& A = p->patches_h[order[ia]];
+      for (int ib = ia + 1; ib < P; ++ib) {
+        const DPatch& B = p->patches_h[order[ib]];
+        if (B.img != A.img || B.x0 >= A.x0 + A.w) break;
+        if (B.y0 < A.y0 + A.h && A.y0 < B.y0 + B.h && A.src != B.src) {
+          pairs.push_back(make_int2(order[ia], order[ib]));
+          ++deg[order[ia]];
+          ++deg[order[ib]];
         }
       }
     }
+    int e = 0;
+    for (int i = 0; i < P; ++i) {
+      p->patches_h[i].nbr_begin = p->patches_h[i].nbr_end = e;
+      e += deg[i];
+    }
+    p->nbr_idx_h.resize(e);
+    for (const int2& q : pairs) {
+      p->nbr_idx_h[p->patches_h[q.x].nbr_end++] = q.y;
+      p->nbr_idx_h[p->patches_h[q.y].nbr_end++] = q.x;
+    }
+    for (int i = 0; i < P; ++i)
+      std::sort(p->nbr_idx_h.begin() + p->patches_h[i].nbr_begin, p->nbr_idx_h.begin() + p->patches_h[i].nbr_end);
   }
-  p->nbr_idx_h.clear();
-  for (int i = 0; i < P; ++i) {
-    std::sort(nbr[i].begin(), nbr[i].end());
-    p->patches_h[i].nbr_begin = (int)p->nbr_idx_h.size();
-    for (int q : nbr[i]) p->nbr_idx_h.push_back(q);
-    p->patches_h[i].nbr_end = (int)p->nbr_idx_h.size();
-  }
-  // source overlap graph and greedy colouring (ascending id, smallest free colour)
+  // source overlap graph (neighbour patches' sources, without repeats) and greedy colouring
+  // (ascending id, smallest free colour)
   p->adj.assign(S, {});
   for (int i = 0; i < P; ++i)
-    for (int q : nbr[i]) p->adj[p->patches_h[i].src].push_back(p->patches_h[q].src);
+    for (int e = p->patches_h[i].nbr_begin; e < p->patches_h[i].nbr_end; ++e)
+      p->adj[p->patches_h[i].src].push_back(p->patches_h[p->nbr_idx_h[e]].src);
   for (auto& a : p->adj) {
     std::sort(a.begin(), a.end());
     a.erase(std::unique(a.begin(), a.end()), a.end());
   }
   p->colour.assign(S, -1);
   p->n_colours = 0;
-  for (int s = 0; s < S; ++s) {
-    std::vector<char> used(p->adj[s].size() + 1, 0);
-    for (int t : p->adj[s])
-      if (p->colour[t] >= 0 && p->colour[t] < (int)used.size()) used[p->colour[t]] = 1;
-    int c = 0;
-    while (used[c]) ++c;
-    p->colour[s] = c;
-    p->n_colours = std::max(p->n_colours, c + 1);
+  {
+    std::vector<char> used;
+    for (int s = 0; s < S; ++s) {
+      used.assign(p->adj[s].size() + 1, 0);
+      for (int t : p->adj[s])
+        if (p->colour[t] >= 0 && p->colour[t] < (int)used.size()) used[p->colour[t]] = 1;
+      int c = 0;
+      while (used[c]) ++c;
+      p->colour[s] = c;
+      p->n_colours = std::max(p->n_colours, c + 1);
+    }
   }
   // work items: runs of chunk pixels per patch (patch-major), launch order by cost
   // Cost of a work item: pixels x (1 + neighbour patches / 2), kept as the integer
