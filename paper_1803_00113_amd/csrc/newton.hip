@@ -200,7 +200,7 @@ struct PixH {
 // profile-weighted second derivatives in (mu, S)
 template <typename T>
 __device__ __forceinline__ void gal_hess(const T* q, T Pxx, T Pxy, T Pyy, T lw, const T* gt, T wP, T dx, T dy, T xx,
-                                         T xy, T yy, T& f, T* gm, T* gs, T* hmm, T* hms, T* hmsb, T* hss, T* hssb) {
+                                         T xy, T yy, T& f, T* gm, T* gs, T* hmm, T* hms, T* hss) {
   const T ux = fma(Pxx, dx, Pxy * dy);
   const T uy = fma(Pxy, dx, Pyy * dy);
   const T N = comp_value<T>(q, xx, xy, yy);
@@ -223,19 +223,20 @@ __device__ __forceinline__ void gal_hess(const T* q, T Pxx, T Pxy, T Pyy, T lw, 
   const T vxy_x = fma(Pxx, uy, Pxy * ux), vxy_y = fma(Pxy, uy, Pyy * ux);
   const T vyy_x = uy * Pxy, vyy_y = uy * Pyy;
   const T w0e = Nxx * wP, w1e = Nxy * wP, w2e = Nyy * wP;
-  // two accumulators per entry (the terms in N u and in N P), so that each term is one fma
+  // each term is one fma into the entry's accumulator (the sign of the terms in N P rides on
+  // the operand)
   hms[0] = fma(w0e, ux, hms[0]);
   hms[3] = fma(w0e, uy, hms[3]);
   hms[1] = fma(w1e, ux, hms[1]);
   hms[4] = fma(w1e, uy, hms[4]);
   hms[2] = fma(w2e, ux, hms[2]);
   hms[5] = fma(w2e, uy, hms[5]);
-  hmsb[0] = fma(Ntw, vxx_x, hmsb[0]);
-  hmsb[3] = fma(Ntw, vxx_y, hmsb[3]);
-  hmsb[1] = fma(Ntw, vxy_x, hmsb[1]);
-  hmsb[4] = fma(Ntw, vxy_y, hmsb[4]);
-  hmsb[2] = fma(Ntw, vyy_x, hmsb[2]);
-  hmsb[5] = fma(Ntw, vyy_y, hmsb[5]);
+  hms[0] = fma(-Ntw, vxx_x, hms[0]);
+  hms[3] = fma(-Ntw, vxx_y, hms[3]);
+  hms[1] = fma(-Ntw, vxy_x, hms[1]);
+  hms[4] = fma(-Ntw, vxy_y, hms[4]);
+  hms[2] = fma(-Ntw, vyy_x, hms[2]);
+  hms[5] = fma(-Ntw, vyy_y, hms[5]);
   const T q1 = (T)2 * qxy;
   const T Nwt2 = Nw * tau2;
   hss[0] = fma(Nwt2, (T)0.25 * qxx * qxx - ux * vxx_x, hss[0]);
@@ -245,7 +246,7 @@ __device__ __forceinline__ void gal_hess(const T* q, T Pxx, T Pxy, T Pyy, T lw, 
   hss[4] = fma(Nwt2, (T)0.25 * q1 * qyy - uy * vxy_y, hss[4]);
   hss[5] = fma(Nwt2, (T)0.25 * qyy * qyy - uy * vyy_y, hss[5]);
 #pragma unroll
-  for (int e = 0; e < 6; ++e) hssb[e] = fma(Nw, gt[2 + e], hssb[e]);
+  for (int e = 0; e < 6; ++e) hss[e] = fma(Nw, gt[2 + e], hss[e]);
 }
 
 template <typename T, int NEXP, int NDEV>
@@ -253,7 +254,6 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
                                               PixH<T>& o) {
   T fe = 0, fd = 0, gme[2] = {0, 0}, gmd[2] = {0, 0}, gse[3] = {0, 0, 0}, gsd[3] = {0, 0, 0};
   T hmm[3] = {0, 0, 0}, hms[6] = {0, 0, 0, 0, 0, 0}, hss[6] = {0, 0, 0, 0, 0, 0};
-  T hmsb[6] = {0, 0, 0, 0, 0, 0}, hssb[6] = {0, 0, 0, 0, 0, 0};
   T f1 = 0, g1x = 0, g1y = 0, h1[3] = {0, 0, 0};
   const T pi = tb->hdr[7], omp = (T)1 - pi;
   __builtin_assume(K >= 1);   // images have 1..kMaxPsf PSF components (checked at prepare)
@@ -277,18 +277,13 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
     for (int j = 0; j < NEXP; ++j)
       if (!(d2 > tb->rc2[k][j]))
         gal_hess<T>(tb->gq[k][j], tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3],
-                    tb->gt[k][j], omp, dx, dy, xx, xy, yy, fe, gme, gse, hmm, hms, hmsb, hss, hssb);
+                    tb->gt[k][j], omp, dx, dy, xx, xy, yy, fe, gme, gse, hmm, hms, hss);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
       if (!(d2 > tb->rc2[k][kMaxProf + j]))
         gal_hess<T>(tb->gq[k][kMaxProf + j], tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1],
                     tb->gal[k][kMaxProf + j][2], tb->gal[k][kMaxProf + j][3], tb->gt[k][kMaxProf + j], pi, dx, dy, xx,
-                    xy, yy, fd, gmd, gsd, hmm, hms, hmsb, hss, hssb);
-  }
-#pragma unroll
-  for (int e = 0; e < 6; ++e) {
-    hms[e] -= hmsb[e];
-    hss[e] += hssb[e];
+                    xy, yy, fd, gmd, gsd, hmm, hms, hss);
   }
   o.f1 = f1;
   o.g1[0] = g1x;
@@ -336,8 +331,11 @@ struct HessArgs {
   const int32_t* img_npsf;
 };
 
+// The float form is held to at most 168 VGPRs, three wavefronts per SIMD (its live set fits
+// there without spilling; at the two wavefronts that 194 VGPRs allowed the kernel stalled on
+// latency).  The double form keeps its natural allocation.
 template <typename T, int NEXP, int NDEV>
-__global__ __launch_bounds__(64) void k_hess(HessArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_hess(HessArgs a) {
   const int pos = xcd_position((int)blockIdx.x, (int)gridDim.x);
   const int t = a.order ? a.order[pos] : pos;
   const DTask task = a.tasks[t];
@@ -419,6 +417,18 @@ __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
       g1z[j] = j < 2 ? o.g1[j] : (T)0;
       dz[j] = L0 * o.g0[j] - L1 * g1z[j];
     }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+      for (int j = i; j < 6; ++j) {
+        const T h0ij = o.h0[zidx(i, j)];
+        const T h1ij = (i < 2 && j < 2) ? o.h1[i + j] : (T)0;
+        const T Euv = w0 * L0 * h0ij + w1 * L1 * h1ij;
+        const T Vuv = (T)2 * (k0 * (o.g0[i] * o.g0[j] + f0 * h0ij) + k1 * (g1z[i] * g1z[j] + f1 * h1ij) +
+                              w01 * (dz[i] * dz[j] + d * (L0 * h0ij - L1 * h1ij)));
+        Q[qidx(5 + i, 5 + j)] += fma(cE, Euv, cV * Vuv);
+      }
+    }
     T Eu[kPrim], Vu[kPrim];
     Eu[0] = -d;
     Eu[1] = w0 * f0;
@@ -447,7 +457,13 @@ __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
 #pragma unroll
     for (int u = 0; u < kPrim; ++u) {
 #pragma unroll
-      for (int v = u; v < kPrim; ++v) Q[qidx(u, v)] = fma(Eu[u], av[v], fma(cu[u], Eu[v], Q[qidx(u, v)]));
+      for (int v = u; v < kPrim; ++v) {
+        // E_u vanishes in the two amplitude-variance coordinates (u = 3, 4)
+        T q = Q[qidx(u, v)];
+        if (v != 3 && v != 4) q = fma(cu[u], Eu[v], q);
+        if (u != 3 && u != 4) q = fma(Eu[u], av[v], q);
+        Q[qidx(u, v)] = q;
+      }
     }
     // second derivatives of E_s and V_s
     Q[qidx(0, 0)] += cV * (T)-2 * d * d;
@@ -469,18 +485,6 @@ __global__ __launch_bounds__(64) void k_hess(HessArgs a) {
       Q[qidx(2, 5 + j)] += fma(cE, w1 * g1j, cV * ((T)4 * w1 * L1 * e1 * f1 * g1j - (T)2 * w01 * (dzj * f1 + d * g1j)));
       Q[qidx(3, 5 + j)] += cV * ((T)2 * w0 * L0 * L0 * f0 * g0j);
       Q[qidx(4, 5 + j)] += cV * ((T)2 * w1 * L1 * L1 * f1 * g1j);
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-#pragma unroll
-      for (int j = i; j < 6; ++j) {
-        const T h0ij = o.h0[zidx(i, j)];
-        const T h1ij = (i < 2 && j < 2) ? o.h1[i + j] : (T)0;
-        const T Euv = w0 * L0 * h0ij + w1 * L1 * h1ij;
-        const T Vuv = (T)2 * (k0 * (o.g0[i] * o.g0[j] + f0 * h0ij) + k1 * (g1z[i] * g1z[j] + f1 * h1ij) +
-                              w01 * (dz[i] * dz[j] + d * (L0 * h0ij - L1 * h1ij)));
-        Q[qidx(5 + i, 5 + j)] += fma(cE, Euv, cV * Vuv);
-      }
     }
     col += step_cols;
     row += step_rows;
