@@ -11,6 +11,8 @@ Modules:
              reverse-mode autodiff in float64
   newton  -- trust-region Newton block step, graph colouring and block coordinate ascent
              (Sections 4.3-4.4)
+  likelihood -- Poisson log-likelihood at point values of the latent variables, the
+             likelihood factor of the MCMC procedure's target (Sections 3 and 3.1)
 
 Parity status per function is listed in each function's docstring ("pinned by ..." or
 "parity unpinned").

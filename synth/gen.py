@@ -491,6 +491,42 @@ def config4(seed=SEED_BASE + 4, n_sources=600, H=2048, W=1489, n_epochs=3):
                      prior, profiles, theta0)
 
 
+def truth_point(prob):
+    """The true latent values of every source as a [S,16] float64 array of point values
+    (position, type 1 = star, log reference-band flux, four colours, angle, log half-light
+    radius, profile weight, axis ratio, then zeros): the layout of cel_loglik's z."""
+    t = prob.truth
+    z = np.zeros((prob.n_sources, 16))
+    z[:, 0:2] = t["u"]
+    z[:, 2] = t["star"].astype(np.float64)
+    z[:, 3] = np.log(t["flux"])
+    z[:, 4:8] = t["colours"]
+    z[:, 8] = t["angle"]
+    z[:, 9] = np.log(t["radius"])
+    z[:, 10] = t["profile"]
+    z[:, 11] = t["axis"]
+    return z
+
+
+def perturbed_points(z, n, seed):
+    """n seeded perturbations [n,S,16] of point values z [S,16] (candidate states of a
+    sampler): position +-0.4 px, log flux 0.2, colours 0.1, angle 0.3, log radius 0.2 (normal
+    sd), profile weight uniform on [0, 1], axis ratio uniform on [0.2, 1], the type
+    alternating over candidates and sources."""
+    rng = np.random.default_rng(seed)
+    S = z.shape[0]
+    out = np.repeat(np.asarray(z, dtype=np.float64)[None], n, 0).copy()
+    out[:, :, 0:2] += rng.normal(0, 0.4, (n, S, 2))
+    out[:, :, 2] = (np.arange(n)[:, None] + np.arange(S)[None, :]) % 2
+    out[:, :, 3] += rng.normal(0, 0.2, (n, S))
+    out[:, :, 4:8] += rng.normal(0, 0.1, (n, S, 4))
+    out[:, :, 8] += rng.normal(0, 0.3, (n, S))
+    out[:, :, 9] += rng.normal(0, 0.2, (n, S))
+    out[:, :, 10] = rng.uniform(0, 1, (n, S))
+    out[:, :, 11] = rng.uniform(0.2, 1, (n, S))
+    return out
+
+
 def make_config(k, **kw):
     return {1: config1, 2: config2, 3: config3, 4: config4}[k](**kw)
 
