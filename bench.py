@@ -171,6 +171,31 @@ def hessian_leg(log, prob, reps=5):
     return out
 
 
+def loglik_leg(log, prob, units, n_cand=56, reps=3):
+    """Point log-likelihood (the MCMC target's likelihood factor) of n_cand candidate states
+    of every source of the batched workload, the others at their true values: candidate
+    active-pixel evaluations per second."""
+    import torch
+    from paper_1803_00113_amd import api
+    from synth import gen
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    z = gen.truth_point(prob)
+    zf = torch.as_tensor(z, device="cuda").contiguous()
+    zc = torch.as_tensor(gen.perturbed_points(z, n_cand, gen.SEED_BASE + 7), device="cuda").contiguous()
+    api.loglik(plan, zf, zc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ll = api.loglik(plan, zf, zc)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    res = dict(candidates_per_source=n_cand, ms_per_call=1e3 * dt,
+               candidate_pixel_evals_per_s=n_cand * units / dt, finite=bool(torch.isfinite(ll).all()))
+    log(f"loglik: {res}")
+    return res
+
+
 def serve_leg(log, rates=(20.0, 50.0, 100.0, 200.0), n_requests=200, pool=8):
     """Region requests of 1-200 sources (patch side 16-96, 5 bands) arriving as a Poisson
     process; each request takes 10 Newton rounds.  Arrivals cycle through `pool` generated
@@ -243,6 +268,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-hessian", action="store_true")
+    ap.add_argument("--no-loglik", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -324,6 +350,7 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
 
     hess = None if args.no_hessian else hessian_leg(log, prob)
+    llk = None if args.no_loglik else loglik_leg(log, prob, units)
     sweep = None if args.no_sweep else sweep_leg(log)
     serving = None if args.no_serve else serve_leg(log)
 
@@ -342,7 +369,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "plain": plain, "batched_vs_plain": (value / plain["value"]) if plain else None,
         "p99_region_latency_ms": serving[0]["p99_ms"] if serving else None,
-        "serving": serving, "sweep": sweep, "hessian": hess,
+        "serving": serving, "sweep": sweep, "hessian": hess, "loglik": llk,
     }
     print(json.dumps(line), flush=True)
 

@@ -66,6 +66,7 @@ typedef int32_t cel_status;
 
 #define CEL_N_THETA 32
 #define CEL_N_PARAM 27
+#define CEL_Z_N 16             /* point values per source (cel_loglik)                   */
 #define CEL_MAX_PSF 4
 #define CEL_MAX_PROFILE 8
 #define CEL_N_COLOUR_COMPONENTS 8
@@ -248,6 +249,36 @@ cel_status cel_sweep(cel_ctx* ctx, const cel_plan* plan, double* theta, double* 
  * evaluations recorded (it synchronises on the recorded events).  reset != 0 clears the
  * record.  CEL_EINVAL if timing was not enabled. */
 cel_status cel_phase_times(cel_plan* plan, double* ms, int64_t* n_calls, int32_t reset);
+
+/* Exact Poisson log-likelihood at point values of the latent variables, batched over
+ * candidates: the quantity that the annealed importance sampler and slice sampling of the
+ * paper's MCMC procedure evaluate (Section 3, equation eqzs: source s is sampled with its
+ * neighbours' latent variables z_{-s} held fixed; Section 3.1: the target
+ * pi(w_s) = p(x | w_s, a_s, z_{-s}) p(w_s | a_s), whose likelihood factor this is).
+ *   ll[c][s] = sum over the active pixels of source s's patches of
+ *              x log(lambda) - lambda - log(x!),
+ *   lambda   = sky + sum over the sources t whose patch covers the pixel of l_t f_t
+ *              (Section 2.2.3), with source s at z_cand[c][s] and every other source at
+ *              z_fixed[t].
+ * Pixels outside source s's patches do not depend on z_s and are left out.
+ * Point values z[s*16 + k] (float64):
+ *   0-1  u (reference pixel frame)        | 2  type: 1 star, 0 galaxy (nonzero = star)
+ *   3    log r (reference-band flux)      | 4-7 colours c_1..c_4 (as in theta)
+ *   8    galaxy angle (radians)           | 9  log half-light radius (pixels)
+ *   10   profile weight e_profile, [0, 1] | 11 axis ratio e_axis, (0, 1]
+ *   12-15 unused
+ * z_fixed: DEVICE [S][16].  z_cand: DEVICE [n_cand][S][16] (rows of unselected sources are
+ * not read).  mask: HOST uint8 [S], selected sources (NULL = all); selected sources may
+ * overlap (each candidate sees the others at z_fixed).  ll: DEVICE float64 [n_cand][S] out;
+ * rows of unselected sources are not written; a candidate outside the support (profile
+ * weight or axis ratio out of range, a non-finite value) gets -infinity.
+ * Cost: the neighbour maps at z_fixed once, then one ELBO-only pixel pass per candidate over
+ * the selected sources' pixels (candidates are batched 56 at a time).  Pixel precision as
+ * the context's pixel_fp64 option; sums in FP64.  Asynchronous on `stream`; uses the plan's
+ * scratch (no two calls on one plan may overlap).
+ * CEL_EINVAL: null pointers, n_cand < 0.  CEL_ENOMEM: scratch allocation failed. */
+cel_status cel_loglik(cel_ctx* ctx, const cel_plan* plan, const double* z_fixed, int32_t n_cand,
+                      const double* z_cand, const uint8_t* mask, double* ll, void* stream);
 
 /* Launch tuning of the pixel pass (the paper's thread-level execution study and its remark
  * that sources of varying size make SIMD across sources hard): times the ELBO-and-gradient

@@ -14,6 +14,7 @@ MAX_PROFILE = 8
 N_COLOUR_COMPONENTS = 8
 N_THETA = 32
 N_PARAM = 27
+N_Z = 16
 
 CEL_OK, CEL_EINVAL, CEL_ENOMEM, CEL_EHIP, CEL_EUNSUPPORTED = 0, -1, -2, -3, -4
 ST_SKIPPED, ST_ACCEPTED, ST_REJECTED, ST_CONVERGED, ST_NONFINITE = 0, 1, 2, 3, 4
@@ -90,6 +91,7 @@ _sig = {
     "cel_newton_step": (C.c_int32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, _vp, _vp]),
     "cel_phase_times": (C.c_int32, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "cel_tune": (C.c_int32, [_vp, _vp, _vp, C.POINTER(C.c_int32), _vp]),
+    "cel_loglik": (C.c_int32, [_vp, _vp, _vp, C.c_int32, _vp, C.POINTER(C.c_uint8), _vp, _vp]),
     "cel_sweep": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(CelSweepOpts), C.POINTER(CelSweepReport), _vp]),
     "cel_last_device_error": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
 }

@@ -264,6 +264,26 @@ def newton_step(plan: Plan, theta, radius, mask=None):
     return st, loc
 
 
+def loglik(plan: Plan, z_fixed, z_cand, mask=None):
+    """cel_loglik: exact Poisson log-likelihood of each candidate point of each selected
+    source, the others at z_fixed.  z_fixed [S,16] and z_cand [C,S,16] device float64 tensors
+    (layout in include/celmi.h); mask: host bool/uint8 array [S] or None.  Returns ll [C,S]
+    (rows of unselected sources NaN)."""
+    for t, shape in ((z_fixed, (plan.S, F.N_Z)), (z_cand, None)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("z_fixed / z_cand must be contiguous cuda float64 tensors")
+        if shape is not None and tuple(t.shape) != shape:
+            raise ValueError("z_fixed must be [S,16]")
+    if z_cand.dim() != 3 or tuple(z_cand.shape[1:]) != (plan.S, F.N_Z):
+        raise ValueError("z_cand must be [C,S,16]")
+    n = int(z_cand.shape[0])
+    ll = torch.full((n, plan.S), float("nan"), dtype=torch.float64, device=plan.ctx.device)
+    keep, m = _mask(plan, mask)
+    F.check("cel_loglik", F.lib.cel_loglik(plan.ctx.h, plan.h, _ptr(z_fixed), n, _ptr(z_cand), m, _ptr(ll),
+                                           _stream(plan.ctx.device)))
+    return ll
+
+
 def sweep(plan: Plan, theta, n_sweeps=3, max_newton_iters=50, use_graph=True, radius=None, status=None,
           start_colour=0, max_classes=0):
     """cel_sweep: theta updated in place.  Returns (radius, status, report dict).

@@ -378,6 +378,42 @@ cel_status ensure_variants(cel_plan* p, int nv, bool fp64) {
   return CEL_OK;
 }
 
+hipError_t stage_selection(cel_plan* p, const std::vector<uint8_t>& m, bool as_class, hipStream_t sm) {
+  // the pinned buffers are reused: wait for the previous call's copies out of them
+  if (hipEventSynchronize(p->mask_copied) != hipSuccess) return hipErrorUnknown;
+  std::memcpy(p->h_mask, m.data(), p->S);
+  hipError_t e = hipMemcpyAsync(p->d_mask, p->h_mask, p->S, hipMemcpyHostToDevice, sm);
+  if (as_class) {
+    const int cls = p->n_colours;
+    auto& src = p->class_src[cls];
+    auto& pat = p->class_patches[cls];
+    auto& tsk = p->class_tasks[cls];
+    src.clear();
+    pat.clear();
+    tsk.clear();
+    for (int s = 0; s < p->S; ++s)
+      if (m[s]) {
+        src.push_back(s);
+        for (int i = p->patch_ptr_h[s]; i < p->patch_ptr_h[s + 1]; ++i) pat.push_back(i);
+      }
+    for (int t : p->order_h)
+      if (m[p->patches_h[p->tasks_h[t].patch].src]) tsk.push_back(t);
+    int32_t* h = p->h_lists;
+    std::memcpy(h, src.data(), src.size() * sizeof(int32_t));
+    std::memcpy(h + src.size(), pat.data(), pat.size() * sizeof(int32_t));
+    std::memcpy(h + src.size() + pat.size(), tsk.data(), tsk.size() * sizeof(int32_t));
+    if (e == hipSuccess && !src.empty())
+      e = hipMemcpyAsync(p->d_step_src, h, src.size() * sizeof(int32_t), hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess && !pat.empty())
+      e = hipMemcpyAsync(p->d_step_patches, h + src.size(), pat.size() * sizeof(int32_t), hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess && !tsk.empty())
+      e = hipMemcpyAsync(p->d_step_tasks, h + src.size() + pat.size(), tsk.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, sm);
+  }
+  if (e == hipSuccess) e = hipEventRecord(p->mask_copied, sm);
+  return e;
+}
+
 cel_status ensure_newton(cel_plan* p) {
   if (p->newton_ready) return CEL_OK;
   cel_status st;
@@ -822,7 +858,10 @@ static hipError_t launch_maps_t(cel_plan* p, const Table<T>* tables, hipStream_t
 template <typename T>
 static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv,
                                bool grad, int cls, const uint8_t* active, hipStream_t sm, bool prep_base,
-                               double* local_out, double* grad_out) {
+                               double* local_out, double* grad_out, int64_t theta_vstride = 0) {
+  // theta_vstride > 0: likelihood mode -- variant v's parameters at theta + v * theta_vstride,
+  // no differences, no KL, the pixel sums of variant v to local_out + v * S
+  const bool point = theta_vstride > 0;
   Table<T>* tables = reinterpret_cast<Table<T>*>(sizeof(T) == 8 ? (void*)p->tables_d : (void*)p->tables_f);
   const T* htau = sizeof(T) == 8 ? (const T*)p->d_htau_d : (const T*)p->d_htau_f;
   hipError_t e = hipSuccess;
@@ -837,8 +876,9 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   pa.tables = tables;
   pa.n_patches = p->P;
   pa.trial_variant = p->trial_variant;
-  pa.fd = p->fd_mode;
+  pa.fd = point ? 0 : p->fd_mode;
   pa.sky_min = p->d_skymin;
+  pa.theta_vstride = theta_vstride;
   phase_mark(p, 0, sm);
   if (prep_base) {   // variant 0 of every source and its moment maps (neighbours read these)
     pa.variant0 = 0;
@@ -901,13 +941,16 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   fz.images = p->d_images;
   fz.prior = p->d_prior;
   fz.want_grad = grad ? 1 : 0;
-  const bool direct = v0 == 0 && nv == 1;
+  const bool direct = (v0 == 0 && nv == 1) || point;
   fz.local = direct && local_out ? local_out : p->v_local + (int64_t)v0 * p->S;
   fz.own = p->v_own + (int64_t)v0 * p->S;
   fz.grad = direct && grad_out ? grad_out : p->v_grad + (int64_t)v0 * p->S * kThetaN;
   fz.out_variant_stride = p->S;
   fz.trial_variant = p->trial_variant;
-  fz.fd = p->fd_mode;
+  fz.fd = point ? 0 : p->fd_mode;
+  fz.theta_vstride = theta_vstride;
+  fz.no_kl = point ? 1 : 0;
+  if (point) fz.err = nullptr;   // a candidate's non-finite likelihood is a result, not a fault
   if (cls >= 0) {
     // jobs = members of the class
     fz.n_jobs = (int)p->class_src[cls].size();
@@ -1091,6 +1134,54 @@ extern "C" cel_status cel_elbo_grad_plain(cel_ctx* ctx, const cel_plan* cplan, c
     e = hipMemcpyAsync(elbo_local, p->v_local, sizeof(double) * p->S, hipMemcpyDeviceToDevice, sm);
   if (e == hipSuccess && grad && p->S > 0)
     e = hipMemcpyAsync(grad, p->v_grad, sizeof(double) * p->S * kThetaN, hipMemcpyDeviceToDevice, sm);
+  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+}
+
+// Exact Poisson log-likelihood at point values (Section 3.1's target p(x | w_s, a_s, z_{-s})):
+// the other sources at z_fixed give the neighbour maps once; each chunk of candidates is a
+// set of variants of the objective's pixel pass over the selected sources' work items.
+extern "C" cel_status cel_loglik(cel_ctx* ctx, const cel_plan* cplan, const double* z_fixed, int32_t n_cand,
+                                 const double* z_cand, const uint8_t* mask, double* ll, void* stream) {
+  if (!ctx || !cplan || n_cand < 0) return CEL_EINVAL;
+  cel_plan* p = const_cast<cel_plan*>(cplan);
+  if (p->S > 0 && n_cand > 0 && (!z_fixed || !z_cand || !ll)) return CEL_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
+  if (p->S == 0 || n_cand == 0) return CEL_OK;
+  hipStream_t sm = (hipStream_t)stream;
+  const bool fp64 = p->opt.pixel_fp64 != 0;
+  const int S = p->S;
+  const int chunk = std::min<int>(n_cand, kVariants);
+  cel_status st = ensure_variants(p, chunk, fp64);
+  if (st == CEL_OK) st = ensure_newton(p);
+  if (st == CEL_OK && p->pt_cap < chunk) {
+    if ((st = track(p, &p->d_pt_theta, (size_t)(chunk + 1) * S * kThetaN)) ||
+        (st = track(p, &p->d_pt_ok, (size_t)chunk * S)))
+      return st;
+    p->pt_cap = chunk;
+  }
+  if (st) return st;
+  std::vector<uint8_t> m(S, 1);
+  if (mask)
+    for (int s = 0; s < S; ++s) m[s] = mask[s] ? 1 : 0;
+  bool any = false;
+  for (int s = 0; s < S; ++s) any = any || m[s];
+  if (!any) return CEL_OK;
+  const int cls = p->n_colours;   // the selection, staged as the step class
+  hipError_t e = stage_selection(p, m, true, sm);
+  double* th_base = p->d_pt_theta;
+  double* th_cand = p->d_pt_theta + (int64_t)S * kThetaN;
+  const int64_t row = (int64_t)S * kThetaN;
+  if (e == hipSuccess) e = launch_point_theta(z_fixed, S, th_base, nullptr, sm);
+  if (e == hipSuccess) e = prep_base(p, th_base, sm, fp64);
+  for (int c0 = 0; c0 < n_cand && e == hipSuccess; c0 += chunk) {
+    const int nc = std::min(chunk, n_cand - c0);
+    e = launch_point_theta(z_cand + (int64_t)c0 * S * CEL_Z_N, (int64_t)nc * S, th_cand, p->d_pt_ok, sm);
+    if (e != hipSuccess) break;
+    double* out = ll + (int64_t)c0 * S;
+    e = fp64 ? enqueue_eval<double>(p, th_cand, nullptr, 0, nc, false, cls, nullptr, sm, false, out, nullptr, row)
+             : enqueue_eval<float>(p, th_cand, nullptr, 0, nc, false, cls, nullptr, sm, false, out, nullptr, row);
+    if (e == hipSuccess) e = launch_support_masked(p->d_pt_ok, p->d_mask, S, (int64_t)nc * S, out, sm);
+  }
   return e == hipSuccess ? CEL_OK : CEL_EHIP;
 }
 

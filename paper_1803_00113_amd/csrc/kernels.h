@@ -20,6 +20,7 @@ struct PrepArgs {
   int32_t trial_variant;       // variant evaluated at theta_trial
   int32_t fd;                  // variants 1..54 are central-difference points
   const double* sky_min;       // per patch: smallest sky value (component cut)
+  int64_t theta_vstride;       // > 0: variant v reads theta + v * theta_vstride (per-variant points)
 };
 
 struct FinalizeArgs {
@@ -46,6 +47,8 @@ struct FinalizeArgs {
   int32_t trial_variant;
   int32_t fd;
   int32_t* err;                // device condition word (CEL_DEVERR_*), may be null
+  int64_t theta_vstride;       // as in PrepArgs
+  int32_t no_kl;               // 1: the pixel sum alone (point likelihood), no KL
 };
 
 template <typename T>
@@ -59,6 +62,12 @@ hipError_t launch_finalize(const FinalizeArgs& a, int n_variants, hipStream_t st
 hipError_t launch_total(const double* own, int n, double* out, hipStream_t st);
 hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const double* knots, const float* pixels,
                          const int64_t* user_off, float2* xs, double2* xs64, int n_patches, hipStream_t st);
+// unconstrained parameters [n][32] that make the objective's pixel terms the exact Poisson
+// log-likelihood at point values z [n][CEL_Z_N] (type probability 0 or 1, zero variances);
+// ok[n] (may be null) records which rows lie in the support
+hipError_t launch_point_theta(const double* z, int64_t n, double* theta, uint8_t* ok, hipStream_t st);
+// ll[i] = -infinity where ok[i] == 0 and source i % S is selected (mask[S])
+hipError_t launch_support_masked(const uint8_t* ok, const uint8_t* mask, int S, int64_t n, double* ll, hipStream_t st);
 // data constants x log x - x - log x! of the counts 0 .. kCountTable - 1 (once per context)
 constexpr int kCountTable = 4096;
 hipError_t launch_count_table(double* table, hipStream_t st);

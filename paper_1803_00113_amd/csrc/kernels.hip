@@ -23,12 +23,13 @@
 
 namespace celmi {
 
-// Parameters of variant v of a source: base theta, +/- h along one coordinate, or trial.
-// (central differences only when fd != 0; the trial point is variant trial_v)
-__device__ __forceinline__ void load_theta(const double* theta, const double* theta_trial, int s, int v,
-                                           double h, double* th, int trial_v, int fd) {
+// Parameters of variant v of a source: base theta, +/- h along one coordinate, trial, or the
+// variant's own parameter array (vstride > 0).  (central differences only when fd != 0; the
+// trial point is variant trial_v)
+__device__ __forceinline__ void load_theta(const double* theta, const double* theta_trial, int64_t vstride, int s,
+                                           int v, double h, double* th, int trial_v, int fd) {
   const double* src = (v == trial_v && theta_trial) ? theta_trial + (int64_t)s * kThetaN
-                                                    : theta + (int64_t)s * kThetaN;
+                                                    : theta + (int64_t)v * vstride + (int64_t)s * kThetaN;
   // the perturbed coordinate is selected arithmetically so that th stays in registers
   const int kp = (fd && v >= 1 && v <= kParamN) ? v - 1 : -1;
   const int km = (fd && v > kParamN && v <= 2 * kParamN) ? v - 1 - kParamN : -1;
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
   if (a.active && !a.active[P.src]) return;
   const cel_image& im = a.images[P.img];
   double th[kThetaN];
-  load_theta(a.theta, a.theta_trial, P.src, v, a.fd_step, th, a.trial_variant, a.fd);
+  load_theta(a.theta, a.theta_trial, a.theta_vstride, P.src, v, a.fd_step, th, a.trial_variant, a.fd);
   Table<T>* tb = reinterpret_cast<Table<T>*>(a.tables) + (int64_t)v * a.n_patches + pi_;
   const int lane = threadIdx.x;
   // position in patch-local pixel coordinates: mu = A u + b - (x0, y0)
@@ -201,13 +202,16 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
 // k_fused: the per-pixel hot loop
 
 // Values of a source's star (f1) and galaxy (f0) light at PPL pixels (local coords of the
-// source's own patch).  Neighbour evaluation: no derivatives.
+// source's own patch).  Neighbour evaluation: no derivatives.  A type of weight exactly 0
+// (a point value of the type) is not evaluated (its components take the cut radius -1): its
+// light enters the moments only through that weight.
 template <typename T, int PPL, int NEXP, int NDEV>
 __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int K, const T* px, const T* py,
                                             const T* box, T* f0, T* f1) {
   T fe[PPL], fd[PPL];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) fe[i] = fd[i] = f1[i] = (T)0;
+  const bool use_gal = tb->hdr[2] != (T)0, use_star = tb->hdr[3] != (T)0;
   for (int k = 0; k < K; ++k) {
     const T mx = tb->star[k][0], my = tb->star[k][1];
     T dx[PPL], dy[PPL], xx[PPL], xy[PPL], yy[PPL];
@@ -226,11 +230,11 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
 #pragma unroll
     for (int j = 0; j < NEXP + NDEV; ++j) {
       const int c = j < NEXP ? j : kMaxProf + (j - NEXP);
-      rc[j] = tb->rc2[k][c];
+      rc[j] = use_gal ? tb->rc2[k][c] : (T)-1;
 #pragma unroll
       for (int e = 0; e < 4; ++e) qv[j][e] = tb->gq[k][c][e];
     }
-    if (!(d2 > tb->rc2s[k])) {
+    if (!(d2 > (use_star ? tb->rc2s[k] : (T)-1))) {
 #pragma unroll
       for (int i = 0; i < PPL; ++i) f1[i] += comp_value<T>(tb->sq[k], xx[i], xy[i], yy[i]);
     }
@@ -289,7 +293,9 @@ __device__ __forceinline__ void comp_own(T pxx, T pxy, T pyy, T lw, T htau, cons
 
 // The own source's values (and, with DERIV, partial derivatives).  The values are formed
 // by the same operations with or without DERIV, so the ELBO-only and the gradient paths
-// give bitwise-identical objectives.
+// give bitwise-identical objectives.  Without DERIV a type of weight exactly 0 (a point
+// value of the type) is not evaluated: its light enters the moments only through that
+// weight, so the objective is unchanged.
 template <typename T, int PPL, int NEXP, int NDEV, bool DERIV>
 __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const T* __restrict__ htau, int K,
                                          const T* px, const T* py, const T* box, OwnPix<T, PPL>& o) {
@@ -300,6 +306,7 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
     o.fd[i] = o.gdx[i] = o.gdy[i] = o.sdxx[i] = o.sdxy[i] = o.sdyy[i] = (T)0;
   }
   __builtin_assume(K >= 1);   // images have 1..kMaxPsf PSF components (checked at prepare)
+  const bool use_gal = DERIV || tb->hdr[2] != (T)0, use_star = DERIV || tb->hdr[3] != (T)0;
   for (int k = 0; k < K; ++k) {
     const T mx = tb->star[k][0], my = tb->star[k][1];
     T dx[PPL], dy[PPL], z[PPL];
@@ -311,17 +318,18 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
       dy[i] = py[i] - my;
     }
     const T d2 = box_dist2<T>(mx, my, box);
-    if (!(d2 > tb->rc2s[k]))
+    // (a type of weight 0 takes the cut radius -1: every component skipped)
+    if (!(d2 > (use_star ? tb->rc2s[k] : (T)-1)))
       comp_own<T, PPL, DERIV ? 1 : 0>(tb->star[k][2], tb->star[k][3], tb->star[k][4], tb->star[k][5], (T)0, dx, dy,
                                       o.f1, o.g1x, o.g1y, z, z, z);
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
-      if (!(d2 > tb->rc2[k][j]))
+      if (!(d2 > (use_gal ? tb->rc2[k][j] : (T)-1)))
         comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], htau[j], dx,
                               dy, o.fe, o.gex, o.gey, o.sexx, o.sexy, o.seyy);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
-      if (!(d2 > tb->rc2[k][kMaxProf + j]))
+      if (!(d2 > (use_gal ? tb->rc2[k][kMaxProf + j] : (T)-1)))
         comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
                               tb->gal[k][kMaxProf + j][3], htau[kMaxProf + j], dx, dy, o.fd, o.gdx, o.gdy, o.sdxx,
                               o.sdxy, o.sdyy);
@@ -573,7 +581,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   const int v = a.variant0 + vv;
   if (a.active && !a.active[s]) return;
   double th[kThetaN];
-  load_theta(a.theta, a.theta_trial, s, v, a.fd_step, th, a.trial_variant, a.fd);
+  load_theta(a.theta, a.theta_trial, a.theta_vstride, s, v, a.fd_step, th, a.trial_variant, a.fd);
   double g[kThetaN];
   #pragma unroll
   for (int k = 0; k < kThetaN; ++k) g[k] = 0.0;
@@ -661,7 +669,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   // KL part of the Hessian is taken analytically by the trust-region kernel
   const bool fd_variant = a.fd && v >= 1 && v <= 2 * kParamN;
   // KL by the whole wavefront; subtracts the KL gradient
-  const double kl = kl_source_wave(*a.prior, th, g, fd_variant ? 0.0 : 1.0, lane);
+  const double kl = a.no_kl ? 0.0 : kl_source_wave(*a.prior, th, g, fd_variant ? 0.0 : 1.0, lane);
   if (lane != 0) return;
   local -= kl;
   own -= kl;
@@ -880,6 +888,64 @@ hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const d
                          const int64_t* user_off, float2* xs, double2* xs64, int n_patches, hipStream_t st) {
   if (n_patches <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pixels, dim3(n_patches), dim3(256), 0, st, patches, images, knots, pixels, user_off, xs, xs64);
+  return hipGetLastError();
+}
+
+// Point values z of a source (type, log flux, colours, position, shape) as unconstrained
+// parameters whose variational distribution is the point mass at z (Section 3.1 evaluates
+// the likelihood at sampled z): the type logit at +/-infinity (q(star) exactly 1 or 0),
+// every variance exp(-infinity) = 0, both types' flux and colour means at the point's
+// values, the profile and axis logits of the point's weights.  With zero variances the
+// delta method's correction vanishes and the objective's pixel terms are the Poisson
+// log-likelihood at z.  A row outside the support (profile weight not in [0, 1], axis
+// ratio not in (0, 1], or a non-finite value) is marked in ok[] (null: not recorded).
+__global__ __launch_bounds__(256) void k_point_theta(const double* __restrict__ z, int64_t n,
+                                                     double* __restrict__ theta, uint8_t* __restrict__ ok) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double* zi = z + i * CEL_Z_N;
+  double* t = theta + i * kThetaN;
+  const double inf = __builtin_huge_val();
+  bool good = zi[10] >= 0.0 && zi[10] <= 1.0 && zi[11] > 0.0 && zi[11] <= 1.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) good = good && isfinite(zi[k]);
+  t[0] = zi[0];
+  t[1] = zi[1];
+  t[2] = zi[2] != 0.0 ? inf : -inf;
+  t[3] = t[4] = zi[3];
+  t[5] = t[6] = -inf;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    t[7 + c] = t[11 + c] = zi[4 + c];
+    t[15 + c] = t[19 + c] = -inf;
+  }
+  t[23] = zi[8];
+  t[24] = zi[9];
+  // logit(p) = log p - log(1 - p): -inf at 0, +inf at 1
+  t[25] = log(zi[10]) - log1p(-zi[10]);
+  t[26] = log(zi[11]) - log1p(-zi[11]);
+#pragma unroll
+  for (int k = kParamN; k < kThetaN; ++k) t[k] = 0.0;
+  if (ok) ok[i] = good ? 1 : 0;
+}
+
+// log-likelihood -infinity for the selected sources' candidates outside the support (ok[] of
+// k_point_theta; rows [candidate][source], S sources per candidate)
+__global__ __launch_bounds__(256) void k_support(const uint8_t* __restrict__ ok, const uint8_t* __restrict__ mask,
+                                                 int S, int64_t n, double* __restrict__ ll) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n && mask[i % S] && !ok[i]) ll[i] = -__builtin_huge_val();
+}
+
+hipError_t launch_point_theta(const double* z, int64_t n, double* theta, uint8_t* ok, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_point_theta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, z, n, theta, ok);
+  return hipGetLastError();
+}
+
+hipError_t launch_support_masked(const uint8_t* ok, const uint8_t* mask, int S, int64_t n, double* ll, hipStream_t st) {
+  if (n <= 0 || S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_support, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ok, mask, S, n, ll);
   return hipGetLastError();
 }
 

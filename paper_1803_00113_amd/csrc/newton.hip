@@ -1355,14 +1355,9 @@ extern "C" cel_status cel_newton_step(cel_ctx* ctx, const cel_plan* cplan, doubl
   cel_status st = newton_scratch(p);
   if (st) return st;
   if (p->S == 0) return CEL_OK;
-  // stage the mask through the plan's pinned buffer (wait for the previous copies first)
-  if (hipEventSynchronize(p->mask_copied) != hipSuccess) return CEL_EHIP;
-  std::memcpy(p->h_mask, m.data(), p->S);
-  hipError_t e = hipMemcpyAsync(p->d_mask, p->h_mask, p->S, hipMemcpyHostToDevice, sm);
   // The stepped sources never overlap one another, so none is a neighbour of another: the
   // tables and neighbour maps made once at the iterate serve all of them, and the sources
-  // of several colour classes are stepped as one batch (the step class: its source, patch
-  // and work-item lists go to the device with the mask).
+  // of several colour classes are stepped as one batch (the step class).
   std::vector<int> used;
   for (int c = 0; c < p->n_colours; ++c) {
     bool any = false;
@@ -1370,34 +1365,9 @@ extern "C" cel_status cel_newton_step(cel_ctx* ctx, const cel_plan* cplan, doubl
     if (any) used.push_back(c);
   }
   int cls = used.empty() ? -1 : used[0];
-  if (used.size() > 1 && !p->opt.hessian_fd) {
-    cls = p->n_colours;
-    auto& src = p->class_src[cls];
-    auto& pat = p->class_patches[cls];
-    auto& tsk = p->class_tasks[cls];
-    src.clear();
-    pat.clear();
-    tsk.clear();
-    for (int s = 0; s < p->S; ++s)
-      if (m[s]) {
-        src.push_back(s);
-        for (int i = p->patch_ptr_h[s]; i < p->patch_ptr_h[s + 1]; ++i) pat.push_back(i);
-      }
-    for (int t : p->order_h)
-      if (m[p->patches_h[p->tasks_h[t].patch].src]) tsk.push_back(t);
-    int32_t* h = p->h_lists;
-    std::memcpy(h, src.data(), src.size() * sizeof(int32_t));
-    std::memcpy(h + src.size(), pat.data(), pat.size() * sizeof(int32_t));
-    std::memcpy(h + src.size() + pat.size(), tsk.data(), tsk.size() * sizeof(int32_t));
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(p->d_step_src, h, src.size() * sizeof(int32_t), hipMemcpyHostToDevice, sm);
-    if (e == hipSuccess && !pat.empty())
-      e = hipMemcpyAsync(p->d_step_patches, h + src.size(), pat.size() * sizeof(int32_t), hipMemcpyHostToDevice, sm);
-    if (e == hipSuccess && !tsk.empty())
-      e = hipMemcpyAsync(p->d_step_tasks, h + src.size() + pat.size(), tsk.size() * sizeof(int32_t),
-                         hipMemcpyHostToDevice, sm);
-  }
-  if (e == hipSuccess) e = hipEventRecord(p->mask_copied, sm);
+  const bool union_class = used.size() > 1 && !p->opt.hessian_fd;
+  if (union_class) cls = p->n_colours;
+  hipError_t e = stage_selection(p, m, union_class, sm);
   const bool maps_once = !p->opt.hessian_fd;
   if (maps_once && e == hipSuccess && cls >= 0) e = prep_base(p, theta, sm, p->opt.pixel_fp64 || p->opt.hessian_fp64);
   if (cls == p->n_colours) {

@@ -123,6 +123,11 @@ struct cel_plan {
   int32_t* d_step_patches = nullptr;
   int32_t* d_step_tasks = nullptr;
   double* d_hess = nullptr;       // per-source pixel Hessians [S][27][27]
+  // point-likelihood scratch: parameters of the fixed point and of pt_cap candidates
+  // [(pt_cap + 1)][S][32], candidate support flags [pt_cap][S]
+  double* d_pt_theta = nullptr;
+  uint8_t* d_pt_ok = nullptr;
+  int pt_cap = 0;
   struct Block {
     void* ptr;
     size_t bytes;
@@ -156,6 +161,11 @@ hipError_t prep_class(cel_plan* p, const double* theta, int cls, const uint8_t* 
 // record a phase boundary event (k = 0..4) of the current evaluation when timing is on
 void phase_mark(cel_plan* p, int k, hipStream_t sm);
 cel_status ensure_newton(cel_plan* p);
+// Stage a selection of sources (m[s] != 0) for a batched call: the mask to p->d_mask and,
+// when as_class, the union of the selected sources as the step class (index n_colours) --
+// its source, patch and work-item lists -- through the plan's pinned buffers.  Waits for the
+// previous call's copies out of those buffers and records p->mask_copied after its own.
+hipError_t stage_selection(cel_plan* p, const std::vector<uint8_t>& m, bool as_class, hipStream_t sm);
 // global ELBO at theta into p->d_total (tables, ELBO-only pixel pass, finalisation, total)
 hipError_t launch_total_after_eval(cel_plan* p, const double* theta, hipStream_t sm);
 }  // namespace celmi
