@@ -21,9 +21,12 @@ Point values per source z[s] (16 float64):
 The light kernels are the variational oracle's (oracle.elbo.source_profiles, pinned there);
 pinned here by tests/test_oracle_likelihood.py: exact Poisson sums with scipy's pmf and
 normal densities for stars and for isotropic galaxies (with the overlapping neighbour), the
-zero-variance limit of the variational objective's pixel terms, and locality in z_{-s}.
+zero-variance limit of the variational objective's pixel terms, and locality in z_{-s}; the
+prior density by scipy's normal, multivariate normal and beta densities.
 """
 from __future__ import annotations
+
+import math
 
 import torch
 
@@ -90,3 +93,42 @@ def point_of_theta(theta, star):
     z[:, 10] = torch.sigmoid(th[:, 25])
     z[:, 11] = torch.sigmoid(th[:, 26])
     return z
+
+
+def log_prior(model, z_s):
+    """log p(w_s | a_s) at a point (the AIS start distribution pi_0 of Section 3.1), over the
+    coordinates of the point layout: the model's priors (Section 2.1) -- log r normal given
+    the type (the flux is log-normal), colours from the type's Gaussian mixture, and for a
+    galaxy log radius normal (log-normal radius), profile weight and axis ratio beta, angle
+    uniform on [0, pi) radians; the position's uniform prior is a constant and left out.
+    -inf outside the support (profile weight not in [0, 1], axis ratio not in (0, 1])."""
+    z = torch.as_tensor(z_s, dtype=DT)
+    prof, axis = float(z[10]), float(z[11])
+    if not (0.0 <= prof <= 1.0 and 0.0 < axis <= 1.0 and bool(torch.isfinite(z[:12]).all())):
+        return -math.inf
+    i = 1 if float(z[2]) != 0.0 else 0
+
+    def normal(x, mean, var):
+        return -0.5 * math.log(2 * math.pi * var) - (x - mean) ** 2 / (2 * var)
+
+    lp = normal(z[3], model.prior_r[i, 0], model.prior_r[i, 1])
+    c = z[4:8]
+    terms = []
+    for j in range(model.prior_cw.shape[1]):
+        w = model.prior_cw[i, j]
+        if w <= 0:
+            continue
+        cov = model.prior_ccov[i, j]
+        d = c - model.prior_cmean[i, j]
+        maha = d @ torch.linalg.solve(cov, d)
+        terms.append(torch.log(w) - 2.0 * math.log(2 * math.pi) - 0.5 * torch.logdet(cov) - 0.5 * maha)
+    lp = lp + torch.logsumexp(torch.stack(terms), 0)
+    if i == 0:
+        def beta(x, ab):
+            a, b = ab[0], ab[1]
+            lb = torch.lgamma(a) + torch.lgamma(b) - torch.lgamma(a + b)
+            return (a - 1) * torch.log(x) + (b - 1) * torch.log1p(-x) - lb
+
+        lp = lp + normal(z[9], model.prior_radius[0], model.prior_radius[1])
+        lp = lp + beta(z[10], model.prior_profile) + beta(z[11], model.prior_axis) - math.log(math.pi)
+    return float(lp)

@@ -151,3 +151,32 @@ def test_depends_on_neighbours_only_through_overlap():
     z3 = z.clone()
     z3[t, 3] += 0.5
     assert L.log_likelihood(m, z3, s, z3[s]) != base
+
+
+@pytest.mark.parametrize("star", [0, 1])
+def test_log_prior_against_scipy(c1, star):
+    """log p(w_s | a_s) over the point layout's coordinates (Section 2.1 priors): scipy's
+    normal density for log flux and log radius, its multivariate normal mixture for the
+    colours, its beta density for the profile weight and axis ratio, 1/pi for the angle;
+    -inf outside the support."""
+    prob, m = c1
+    z = gen.perturbed_points(gen.truth_point(prob), 5, 3)[:, 0]
+    z[:, 2] = star
+    i = star
+    for row in z:
+        lp = stats.norm(prob.prior_r[i, 0], math.sqrt(prob.prior_r[i, 1])).logpdf(row[3])
+        mix = sum(w * stats.multivariate_normal(mu, cov).pdf(row[4:8])
+                  for w, mu, cov in zip(prob.prior_cw[i], prob.prior_cmean[i], prob.prior_ccov[i]) if w > 0)
+        lp += math.log(mix)
+        if not star:
+            lp += stats.norm(prob.prior_radius[0], math.sqrt(prob.prior_radius[1])).logpdf(row[9])
+            lp += stats.beta(*prob.prior_profile).logpdf(row[10]) + stats.beta(*prob.prior_axis).logpdf(row[11])
+            lp -= math.log(math.pi)
+        got = L.log_prior(m, row)
+        assert abs(got - lp) <= 1e-10 * abs(lp), (got, lp)
+    bad = z[0].copy()
+    bad[11] = 0.0
+    assert L.log_prior(m, bad) == -math.inf
+    bad = z[0].copy()
+    bad[10] = 1.2
+    assert L.log_prior(m, bad) == -math.inf
