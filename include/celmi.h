@@ -280,6 +280,18 @@ cel_status cel_phase_times(cel_plan* plan, double* ms, int64_t* n_calls, int32_t
 cel_status cel_loglik(cel_ctx* ctx, const cel_plan* plan, const double* z_fixed, int32_t n_cand,
                       const double* z_cand, const uint8_t* mask, double* ll, void* stream);
 
+/* Log prior density log p(w | a) of n point values (the start distribution pi_0 of the
+ * annealed importance sampler, Section 3.1; the priors of Section 2.1), over the point
+ * layout's coordinates (see cel_loglik): log r ~ normal(prior mean, variance of the type),
+ * colours ~ the type's Gaussian mixture, and for a galaxy (z[2] == 0) log radius ~ normal,
+ * profile weight and axis ratio ~ beta, angle ~ uniform on [0, pi) radians.  The position's
+ * uniform prior is a constant and left out, as is the type's prior p(a).  Together with
+ * cel_loglik this gives the annealed target log pi_t = log p(w | a) + gamma_t ll.
+ * z: DEVICE float64 [n][16]; out: DEVICE float64 [n]; -infinity outside the support (as in
+ * cel_loglik).  Uses the plan's prior tables only; asynchronous on `stream`.
+ * CEL_EINVAL: null pointers with n > 0, n < 0. */
+cel_status cel_log_prior(cel_ctx* ctx, const cel_plan* plan, int64_t n, const double* z, double* out, void* stream);
+
 /* Launch tuning of the pixel pass (the paper's thread-level execution study and its remark
  * that sources of varying size make SIMD across sources hard): times the ELBO-and-gradient
  * evaluation at theta with 1, 2 and 4 pixels per lane (one warm-up and three timed calls

@@ -92,6 +92,7 @@ _sig = {
     "cel_phase_times": (C.c_int32, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "cel_tune": (C.c_int32, [_vp, _vp, _vp, C.POINTER(C.c_int32), _vp]),
     "cel_loglik": (C.c_int32, [_vp, _vp, _vp, C.c_int32, _vp, C.POINTER(C.c_uint8), _vp, _vp]),
+    "cel_log_prior": (C.c_int32, [_vp, _vp, C.c_int64, _vp, _vp, _vp]),
     "cel_sweep": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(CelSweepOpts), C.POINTER(CelSweepReport), _vp]),
     "cel_last_device_error": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
 }

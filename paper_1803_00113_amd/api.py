@@ -284,6 +284,18 @@ def loglik(plan: Plan, z_fixed, z_cand, mask=None):
     return ll
 
 
+def log_prior(plan: Plan, z):
+    """cel_log_prior: log p(w | a) of point values z [..., 16] (contiguous cuda float64);
+    returns a tensor of z's leading shape."""
+    if not (isinstance(z, torch.Tensor) and z.is_cuda and z.dtype == torch.float64 and z.is_contiguous()
+            and z.shape[-1] == F.N_Z):
+        raise ValueError("z must be a contiguous cuda float64 tensor [..., 16]")
+    out = torch.empty(z.shape[:-1], dtype=torch.float64, device=plan.ctx.device)
+    F.check("cel_log_prior", F.lib.cel_log_prior(plan.ctx.h, plan.h, int(out.numel()), _ptr(z), _ptr(out),
+                                                 _stream(plan.ctx.device)))
+    return out
+
+
 def sweep(plan: Plan, theta, n_sweeps=3, max_newton_iters=50, use_graph=True, radius=None, status=None,
           start_colour=0, max_classes=0):
     """cel_sweep: theta updated in place.  Returns (radius, status, report dict).

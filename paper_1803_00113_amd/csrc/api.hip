@@ -1185,6 +1185,14 @@ extern "C" cel_status cel_loglik(cel_ctx* ctx, const cel_plan* cplan, const doub
   return e == hipSuccess ? CEL_OK : CEL_EHIP;
 }
 
+extern "C" cel_status cel_log_prior(cel_ctx* ctx, const cel_plan* plan, int64_t n, const double* z, double* out,
+                                    void* stream) {
+  if (!ctx || !plan || n < 0 || (n > 0 && (!z || !out))) return CEL_EINVAL;
+  if (n == 0) return CEL_OK;
+  if (hipSetDevice(plan->device) != hipSuccess) return CEL_EHIP;
+  return launch_log_prior(plan->d_prior, z, n, out, (hipStream_t)stream) == hipSuccess ? CEL_OK : CEL_EHIP;
+}
+
 extern "C" cel_status cel_tune(cel_ctx* ctx, cel_plan* p, const double* theta, int32_t* pixels_per_lane,
                                 void* stream) {
   if (!ctx || !p || (!theta && p->S > 0)) return CEL_EINVAL;

@@ -66,6 +66,8 @@ hipError_t launch_pixels(const DPatch* patches, const cel_image* images, const d
 // log-likelihood at point values z [n][CEL_Z_N] (type probability 0 or 1, zero variances);
 // ok[n] (may be null) records which rows lie in the support
 hipError_t launch_point_theta(const double* z, int64_t n, double* theta, uint8_t* ok, hipStream_t st);
+// log p(w | a) of n point values z [n][CEL_Z_N] under the plan's prior tables
+hipError_t launch_log_prior(const DPrior* prior, const double* z, int64_t n, double* out, hipStream_t st);
 // ll[i] = -infinity where ok[i] == 0 and source i % S is selected (mask[S])
 hipError_t launch_support_masked(const uint8_t* ok, const uint8_t* mask, int S, int64_t n, double* ll, hipStream_t st);
 // data constants x log x - x - log x! of the counts 0 .. kCountTable - 1 (once per context)

@@ -937,6 +937,61 @@ __global__ __launch_bounds__(256) void k_support(const uint8_t* __restrict__ ok,
   if (i < n && mask[i % S] && !ok[i]) ll[i] = -__builtin_huge_val();
 }
 
+// log p(w_s | a_s) at point values (the start distribution of the annealed importance
+// sampler, Section 3.1), over the point layout's coordinates, from the model's priors
+// (Section 2.1): log r normal given the type, the colours from the type's Gaussian
+// mixture, and for a galaxy log radius normal, profile weight and axis ratio beta, the angle
+// uniform on [0, pi); the position's uniform prior is a constant and left out.  -infinity
+// outside the support.  One thread per point.
+__global__ __launch_bounds__(256) void k_log_prior(const DPrior* __restrict__ pr, const double* __restrict__ z,
+                                                   int64_t n, double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  const double* zi = z + r * CEL_Z_N;
+  bool good = zi[10] >= 0.0 && zi[10] <= 1.0 && zi[11] > 0.0 && zi[11] <= 1.0;
+  for (int k = 0; k < 12; ++k) good = good && isfinite(zi[k]);
+  if (!good) {
+    out[r] = -__builtin_huge_val();
+    return;
+  }
+  const int i = zi[2] != 0.0 ? 1 : 0;
+  const double kLogTwoPi = 1.8378770664093454836;
+  auto normal = [&](double x, double mean, double var) {
+    const double d = x - mean;
+    return -0.5 * (kLogTwoPi + log(var)) - 0.5 * d * d / var;
+  };
+  double lp = normal(zi[3], pr->r[i][0], pr->r[i][1]);
+  // colour mixture: log sum_j w_j N(c; m_j, C_j), largest term factored out
+  double t[CEL_N_COLOUR_COMPONENTS], tmax = -__builtin_huge_val();
+  for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) {
+    double maha = 0.0;
+    double d[4];
+    for (int a = 0; a < 4; ++a) d[a] = zi[4 + a] - pr->c_mean[i][j][a];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) maha += d[a] * pr->c_prec[i][j][a][b] * d[b];
+    const bool used = pr->c_logw[i][j] > -1e299;
+    t[j] = used ? pr->c_logw[i][j] - 2.0 * kLogTwoPi - 0.5 * pr->c_logdet[i][j] - 0.5 * maha : -__builtin_huge_val();
+    tmax = fmax(tmax, t[j]);
+  }
+  double sum = 0.0;
+  for (int j = 0; j < CEL_N_COLOUR_COMPONENTS; ++j) sum += exp(t[j] - tmax);
+  lp += tmax + log(sum);
+  if (i == 0) {
+    const double pa = pr->profile[0], pb = pr->profile[1], aa = pr->axis[0], ab = pr->axis[1];
+    lp += normal(zi[9], pr->radius[0], pr->radius[1]);
+    lp += (pa - 1.0) * log(zi[10]) + (pb - 1.0) * log1p(-zi[10]) - pr->lbeta_profile;
+    lp += (aa - 1.0) * log(zi[11]) + (ab - 1.0) * log1p(-zi[11]) - pr->lbeta_axis;
+    lp -= 1.1447298858494001741;   // log(pi): the angle's uniform density on [0, pi)
+  }
+  out[r] = lp;
+}
+
+hipError_t launch_log_prior(const DPrior* prior, const double* z, int64_t n, double* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_log_prior, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, prior, z, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_point_theta(const double* z, int64_t n, double* theta, uint8_t* ok, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_point_theta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, z, n, theta, ok);

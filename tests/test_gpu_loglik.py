@@ -106,3 +106,22 @@ def test_full_batched_workload_sampled():
     got = np.array([ll[c, s] for c, s in pairs])
     err = np.abs(got - want) / np.abs(want)
     assert np.all(err <= 1e-5), (err.max(), pairs[int(err.argmax())])
+
+
+def test_log_prior_matches_oracle():
+    """cel_log_prior (the annealed sampler's start density, Section 3.1) against the oracle
+    for stars, galaxies, the support's edges and points outside it (float64: 1e-12)."""
+    say("case: log prior, 2-source field, 40 points")
+    prob = gen.config1()
+    m = E.Model(prob)
+    z = gen.perturbed_points(gen.truth_point(prob), 20, 21).reshape(-1, 16)
+    z[0, 10], z[1, 10], z[2, 11] = 0.0, 1.0, 1.0
+    z[3, 11], z[4, 10], z[5, 3] = 0.0, -0.1, np.inf
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    got = api.log_prior(plan, torch.as_tensor(z).cuda().contiguous()).cpu().numpy()
+    want = np.array([L.log_prior(m, row) for row in z])
+    bad = ~np.isfinite(want)
+    assert np.array_equal(got[bad], want[bad]) and bad[3:6].all()
+    err = np.abs(got[~bad] - want[~bad]) / np.abs(want[~bad])
+    assert np.all(err <= 1e-12), err.max()
