@@ -203,8 +203,8 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
 
 // Values of a source's star (f1) and galaxy (f0) light at PPL pixels (local coords of the
 // source's own patch).  Neighbour evaluation: no derivatives.  A type of weight exactly 0
-// (a point value of the type) is not evaluated (its components take the cut radius -1): its
-// light enters the moments only through that weight.
+// (a point value of the type) is not evaluated: its light enters the moments only through
+// that weight.
 template <typename T, int PPL, int NEXP, int NDEV>
 __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int K, const T* px, const T* py,
                                             const T* box, T* f0, T* f1) {
@@ -230,23 +230,25 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
 #pragma unroll
     for (int j = 0; j < NEXP + NDEV; ++j) {
       const int c = j < NEXP ? j : kMaxProf + (j - NEXP);
-      rc[j] = use_gal ? tb->rc2[k][c] : (T)-1;
+      rc[j] = tb->rc2[k][c];
 #pragma unroll
       for (int e = 0; e < 4; ++e) qv[j][e] = tb->gq[k][c][e];
     }
-    if (!(d2 > (use_star ? tb->rc2s[k] : (T)-1))) {
+    // a type of weight 0 sees its components at infinite distance: all skipped
+    const T d2s = use_star ? d2 : (T)INFINITY, d2g = use_gal ? d2 : (T)INFINITY;
+    if (!(d2s > tb->rc2s[k])) {
 #pragma unroll
       for (int i = 0; i < PPL; ++i) f1[i] += comp_value<T>(tb->sq[k], xx[i], xy[i], yy[i]);
     }
 #pragma unroll
     for (int j = 0; j < NEXP; ++j) {
-      if (d2 > rc[j]) continue;
+      if (d2g > rc[j]) continue;
 #pragma unroll
       for (int i = 0; i < PPL; ++i) fe[i] += comp_value<T>(qv[j], xx[i], xy[i], yy[i]);
     }
 #pragma unroll
     for (int j = 0; j < NDEV; ++j) {
-      if (d2 > rc[NEXP + j]) continue;
+      if (d2g > rc[NEXP + j]) continue;
 #pragma unroll
       for (int i = 0; i < PPL; ++i) fd[i] += comp_value<T>(qv[NEXP + j], xx[i], xy[i], yy[i]);
     }
@@ -318,18 +320,19 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
       dy[i] = py[i] - my;
     }
     const T d2 = box_dist2<T>(mx, my, box);
-    // (a type of weight 0 takes the cut radius -1: every component skipped)
-    if (!(d2 > (use_star ? tb->rc2s[k] : (T)-1)))
+    // a type of weight 0 sees its components at infinite distance: all skipped
+    const T d2s = use_star ? d2 : (T)INFINITY, d2g = use_gal ? d2 : (T)INFINITY;
+    if (!(d2s > tb->rc2s[k]))
       comp_own<T, PPL, DERIV ? 1 : 0>(tb->star[k][2], tb->star[k][3], tb->star[k][4], tb->star[k][5], (T)0, dx, dy,
                                       o.f1, o.g1x, o.g1y, z, z, z);
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
-      if (!(d2 > (use_gal ? tb->rc2[k][j] : (T)-1)))
+      if (!(d2g > tb->rc2[k][j]))
         comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], htau[j], dx,
                               dy, o.fe, o.gex, o.gey, o.sexx, o.sexy, o.seyy);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
-      if (!(d2 > (use_gal ? tb->rc2[k][kMaxProf + j] : (T)-1)))
+      if (!(d2g > tb->rc2[k][kMaxProf + j]))
         comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
                               tb->gal[k][kMaxProf + j][3], htau[kMaxProf + j], dx, dy, o.fd, o.gdx, o.gdy, o.sdxx,
                               o.sdxy, o.sdyy);
