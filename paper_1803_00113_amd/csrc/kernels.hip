@@ -170,7 +170,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
       r[4] = pv[2];
       r[5] = (T)lw;
       r[6] = r[7] = (T)0;
-      tb->rc2s[k] = (T)rc2;
+      tb->rc2s[k] = (T)rc2 + (T)0;   // (+ 0: a -0 becomes +0, for the integer-ordered cut test)
 #pragma unroll
       for (int e = 0; e < 4; ++e) tb->sq[k][e] = qv[e];
       tb->off[k][0] = (T)ox;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
       r[1] = pv[1];
       r[2] = pv[2];
       r[3] = (T)lw;
-      tb->rc2[k][j] = (T)rc2;
+      tb->rc2[k][j] = (T)rc2 + (T)0;
 #pragma unroll
       for (int e = 0; e < 4; ++e) tb->gq[k][j][e] = qv[e];
       const double h = 0.5 * tau * tau;
@@ -235,20 +235,20 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
       for (int e = 0; e < 4; ++e) qv[j][e] = tb->gq[k][c][e];
     }
     // a type of weight 0 sees its components at infinite distance: all skipped
-    const T d2s = use_star ? d2 : (T)INFINITY, d2g = use_gal ? d2 : (T)INFINITY;
-    if (!(d2s > tb->rc2s[k])) {
+    const auto d2s = uniform_cut_key(use_star ? d2 : (T)INFINITY), d2g = uniform_cut_key(use_gal ? d2 : (T)INFINITY);
+    if (!(d2s > cut_key(tb->rc2s[k]))) {
 #pragma unroll
       for (int i = 0; i < PPL; ++i) f1[i] += comp_value<T>(tb->sq[k], xx[i], xy[i], yy[i]);
     }
 #pragma unroll
     for (int j = 0; j < NEXP; ++j) {
-      if (d2g > rc[j]) continue;
+      if (d2g > cut_key(rc[j])) continue;
 #pragma unroll
       for (int i = 0; i < PPL; ++i) fe[i] += comp_value<T>(qv[j], xx[i], xy[i], yy[i]);
     }
 #pragma unroll
     for (int j = 0; j < NDEV; ++j) {
-      if (d2g > rc[NEXP + j]) continue;
+      if (d2g > cut_key(rc[NEXP + j])) continue;
 #pragma unroll
       for (int i = 0; i < PPL; ++i) fd[i] += comp_value<T>(qv[NEXP + j], xx[i], xy[i], yy[i]);
     }
@@ -321,18 +321,18 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
     }
     const T d2 = box_dist2<T>(mx, my, box);
     // a type of weight 0 sees its components at infinite distance: all skipped
-    const T d2s = use_star ? d2 : (T)INFINITY, d2g = use_gal ? d2 : (T)INFINITY;
-    if (!(d2s > tb->rc2s[k]))
+    const auto d2s = uniform_cut_key(use_star ? d2 : (T)INFINITY), d2g = uniform_cut_key(use_gal ? d2 : (T)INFINITY);
+    if (!(d2s > cut_key(tb->rc2s[k])))
       comp_own<T, PPL, DERIV ? 1 : 0>(tb->star[k][2], tb->star[k][3], tb->star[k][4], tb->star[k][5], (T)0, dx, dy,
                                       o.f1, o.g1x, o.g1y, z, z, z);
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
-      if (!(d2g > tb->rc2[k][j]))
+      if (!(d2g > cut_key(tb->rc2[k][j])))
         comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], htau[j], dx,
                               dy, o.fe, o.gex, o.gey, o.sexx, o.sexy, o.seyy);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
-      if (!(d2g > tb->rc2[k][kMaxProf + j]))
+      if (!(d2g > cut_key(tb->rc2[k][kMaxProf + j])))
         comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
                               tb->gal[k][kMaxProf + j][3], htau[kMaxProf + j], dx, dy, o.fd, o.gdx, o.gdy, o.sdxx,
                               o.sdxy, o.sdyy);

@@ -104,6 +104,16 @@ __device__ __forceinline__ double softplus(double x) { return x > 0 ? x + log1p(
 
 
 // Squared distance from (mx, my) to the wavefront's pixel box [bx0, bx1] x [by0, by1].
+// The component cut compares a wavefront-uniform squared distance d2 (>= +0, possibly +inf)
+// with a stored squared cut radius that is never -0 or NaN (the tables are written so).  For
+// such values the order of IEEE floats is the signed order of their bit patterns, so the
+// float path takes each test as an integer compare of scalar registers instead of one vector
+// compare per component; the double path compares the values.
+__device__ __forceinline__ int cut_key(float x) { return __float_as_int(x); }
+__device__ __forceinline__ double cut_key(double x) { return x; }
+__device__ __forceinline__ int uniform_cut_key(float d2) { return __builtin_amdgcn_readfirstlane(__float_as_int(d2)); }
+__device__ __forceinline__ double uniform_cut_key(double d2) { return d2; }
+
 template <typename T>
 __device__ __forceinline__ T box_dist2(T mx, T my, const T* box) {
   const T ddx = fmax(fmax(box[0] - mx, mx - box[1]), (T)0);
