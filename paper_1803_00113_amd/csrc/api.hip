@@ -425,7 +425,8 @@ cel_status ensure_newton(cel_plan* p) {
       (st = track(p, &p->d_hslots, (size_t)std::max<int64_t>(p->n_tasks, 1) * 80)) ||
       (st = track(p, &p->d_step_src, S1)) || (st = track(p, &p->d_step_patches, (size_t)std::max(p->P, 1))) ||
       (st = track(p, &p->d_step_tasks, (size_t)std::max<int64_t>(p->n_tasks, 1))) ||
-      (st = track(p, &p->d_hess, S1 * kParamN * kParamN)))
+      (st = track(p, &p->d_hess, S1 * kParamN * kParamN)) ||
+      (st = track(p, &p->d_hpart, S1 * kHessParts * kHessPartN)))
     return st;
   if (hipMemset(p->d_trial_active, 0, S1) != hipSuccess) return CEL_EHIP;
   // pinned words, event and stream: a kit from a freed plan when one is there

@@ -563,7 +563,16 @@ struct HessFinArgs {
   double* grad;                // [S][32]
   double* hess;                // [S][27][27]
   int32_t* err;                // device condition word (non-finite Hessian entries)
+  double* part;                // [S][kHParts][kPartN] per-part sums: Hessian, gradient, local
 };
+
+// The pixel part of a source's Hessian is summed over its patches by kHParts wavefronts,
+// each taking a contiguous quarter of the patches (a single wavefront per source leaves
+// most SIMDs idle and waits on every latency alone); k_hess_combine adds the parts in a
+// fixed order and the KL terms.
+constexpr int kHParts = kHessParts;
+constexpr int kPartN = kHessPartN;   // Hessian, gradient, local, pad
+static_assert(kPartN >= kN * kN + kN + 1, "part record too small");
 
 // Sparsity of J = dr/dtheta (r: the 11 primitive coordinates, theta: the 27 parameters):
 // column k has jcount(k) nonzero rows jrow(k, e) -- the centre rows for the position, the
@@ -585,6 +594,7 @@ __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
   const int s = a.job_src ? a.job_src[blockIdx.x] : (int)blockIdx.x;
   if (a.active && !a.active[s]) return;
   const int lane = threadIdx.x;
+  const int w = blockIdx.y;
   // slot sums and flux moments of up to kPB patches, gathered together (one memory and one
   // exp latency per batch instead of per patch)
   constexpr int kPB = 16, kHU = 2 + kPrim + kHQ;
@@ -594,7 +604,7 @@ __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
   // diagonal and sblk the S-block second-derivative terms
   __shared__ double jv[kN][3], dg[kN], sblk[3][3];
   __shared__ int jr[kN][3];
-  __shared__ double Hs[kN][kLd], gs[kThetaN];
+  __shared__ double gs[kThetaN];
   __shared__ double th[kN], sd1[3][3], sd2[3][3][3];
   __shared__ double rv[2], cvv[2][4];
   if (lane < kN) th[lane] = a.theta[(int64_t)s * kThetaN + lane];
@@ -620,7 +630,9 @@ __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
   for (int m = 0; m < kHPer; ++m) hacc[m] = 0.0;
   double local = 0.0;
   const double aa = sigmoid(th[2]), pi = sigmoid(th[25]);
-  const int p0 = a.patch_ptr[s], p1 = a.patch_ptr[s + 1];
+  // this part's patches: a contiguous share of the source's
+  const int q0 = a.patch_ptr[s], nq = a.patch_ptr[s + 1] - q0, per = (nq + kHParts - 1) / kHParts;
+  const int p0 = q0 + min(nq, w * per), p1 = q0 + min(nq, (w + 1) * per);
   for (int pb = p0; pb < p1; pb += kPB) {
     const int nb = min(kPB, p1 - pb);
     for (int e = lane; e < nb * kHU; e += 64) {
@@ -765,11 +777,43 @@ __global__ __launch_bounds__(64) void k_hess_finalize(HessFinArgs a) {
       __syncthreads();
     }
   }
+  // this part's sums
+  double* out = a.part + ((int64_t)s * kHParts + w) * kPartN;
 #pragma unroll
   for (int m = 0; m < kHPer; ++m) {
     const int idx = lane + 64 * m;
-    if (idx < kN * kN) Hs[idx / kN][idx % kN] = hacc[m];
+    if (idx < kN * kN) out[idx] = hacc[m];
   }
+  __syncthreads();   // gs is complete
+  if (lane < kN) out[kN * kN + lane] = gs[lane];
+  if (lane == 0) out[kN * kN + kN] = local;   // (every lane holds the same sum)
+}
+
+// one wavefront per source: the parts' sums in a fixed order, then the KL value, gradient
+// and (with with_kl) Hessian, and the outputs
+__global__ __launch_bounds__(64) void k_hess_combine(HessFinArgs a) {
+  const int s = a.job_src ? a.job_src[blockIdx.x] : (int)blockIdx.x;
+  if (a.active && !a.active[s]) return;
+  const int lane = threadIdx.x;
+  __shared__ double Hs[kN][kLd], gs[kThetaN], th[kN];
+  if (lane < kN) th[lane] = a.theta[(int64_t)s * kThetaN + lane];
+  const double* part = a.part + (int64_t)s * kHParts * kPartN;
+  for (int idx = lane; idx < kN * kN; idx += 64) {
+    double h = 0.0;
+#pragma unroll
+    for (int w = 0; w < kHParts; ++w) h += part[w * kPartN + idx];
+    Hs[idx / kN][idx % kN] = h;
+  }
+  if (lane < kThetaN) {
+    double g = 0.0;
+    if (lane < kN)
+#pragma unroll
+      for (int w = 0; w < kHParts; ++w) g += part[w * kPartN + kN * kN + lane];
+    gs[lane] = g;
+  }
+  double local = 0.0;
+#pragma unroll
+  for (int w = 0; w < kHParts; ++w) local += part[w * kPartN + kN * kN + kN];
   __syncthreads();
   // KL: value, gradient and (optionally) Hessian
   __shared__ double klv;
@@ -1234,7 +1278,10 @@ static hipError_t enqueue_hessian(cel_plan* p, const double* theta, const int32_
   fa.grad = grad;
   fa.hess = hess;
   fa.err = with_kl ? p->d_err : nullptr;   // the Newton path reports through the step status
-  hipLaunchKernelGGL(k_hess_finalize, dim3(n_src), dim3(64), 0, sm, fa);
+  fa.part = p->d_hpart;
+  hipLaunchKernelGGL(k_hess_finalize, dim3(n_src, kHParts), dim3(64), 0, sm, fa);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hess_combine, dim3(n_src), dim3(64), 0, sm, fa);
   return hipGetLastError();
 }
 

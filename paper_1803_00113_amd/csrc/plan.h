@@ -123,6 +123,7 @@ struct cel_plan {
   int32_t* d_step_patches = nullptr;
   int32_t* d_step_tasks = nullptr;
   double* d_hess = nullptr;       // per-source pixel Hessians [S][27][27]
+  double* d_hpart = nullptr;      // per-source partial Hessian sums [S][kHessParts][kHessPartN]
   // point-likelihood scratch: parameters of the fixed point and of pt_cap candidates
   // [(pt_cap + 1)][S][32], candidate support flags [pt_cap][S]
   double* d_pt_theta = nullptr;
@@ -141,6 +142,10 @@ struct cel_plan {
 };
 
 namespace celmi {
+// the Hessian's patch sums are split over kHessParts wavefronts per source, each writing
+// a record of kHessPartN doubles (27 x 27 Hessian, 27 gradient entries, the local sum)
+constexpr int kHessParts = 4;
+constexpr int kHessPartN = 27 * 27 + 27 + 1 + 3;
 cel_options default_options();
 void plan_release(cel_plan* p);
 void ctx_release(cel_ctx* c);
