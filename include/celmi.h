@@ -273,7 +273,8 @@ cel_status cel_phase_times(cel_plan* plan, double* ms, int64_t* n_calls, int32_t
  * rows of unselected sources are not written; a candidate outside the support (profile
  * weight or axis ratio out of range, a non-finite value) gets -infinity.
  * Cost: the neighbour maps at z_fixed once, then one ELBO-only pixel pass per candidate over
- * the selected sources' pixels (candidates are batched 56 at a time).  Pixel precision as
+ * the selected sources' pixels (candidates are batched 56 at a time; the pass takes 4 pixels
+ * per lane whatever the plan's pixels-per-lane setting).  Pixel precision as
  * the context's pixel_fp64 option; sums in FP64.  Asynchronous on `stream`; uses the plan's
  * scratch (no two calls on one plan may overlap).
  * CEL_EINVAL: null pointers, n_cand < 0.  CEL_ENOMEM: scratch allocation failed. */

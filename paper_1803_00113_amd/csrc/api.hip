@@ -856,6 +856,8 @@ static hipError_t launch_maps_t(cel_plan* p, const Table<T>* tables, hipStream_t
 // Enqueue prep + fused + finalize for `nv` variants starting at variant v0 over either all
 // sources (cls < 0) or one colour class, with optional active mask.  Outputs go to the
 // plan's per-variant arrays.
+constexpr int kPointPixelsPerLane = 4;
+
 template <typename T>
 static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv,
                                bool grad, int cls, const uint8_t* active, hipStream_t sm, bool prep_base,
@@ -922,7 +924,11 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   fa.active = active;
   fa.variant0 = v0;
   fa.img_npsf = p->d_npsf;
-  e = launch_fused<T>(fa, htau, p->nexp, p->ndev, p->opt.pixels_per_lane, grad, n_items, nv, sm);
+  // the likelihood pass (values only, often one type per candidate) takes 4 pixels per lane
+  // whatever the plan's setting: more independent work per wavefront for thin candidates
+  // (10.2 ms per 56 x 1000 candidates against 12.1 at 2 and 10.8 at 8)
+  const int ppl = point ? kPointPixelsPerLane : p->opt.pixels_per_lane;
+  e = launch_fused<T>(fa, htau, p->nexp, p->ndev, ppl, grad, n_items, nv, sm);
   if (e != hipSuccess) return e;
   phase_mark(p, 3, sm);
   FinalizeArgs fz;
