@@ -125,3 +125,22 @@ def test_log_prior_matches_oracle():
     assert np.array_equal(got[bad], want[bad]) and bad[3:6].all()
     err = np.abs(got[~bad] - want[~bad]) / np.abs(want[~bad])
     assert np.all(err <= 1e-12), err.max()
+
+
+def test_degenerate_calls():
+    """No candidates, an empty selection, and a source whose candidate equals the fixed point
+    (the likelihood then equals the variational objective's pixel sum at the point)."""
+    say("case: loglik degenerate calls")
+    prob = gen.config1()
+    m = E.Model(prob)
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    zf = gen.truth_point(prob)
+    zf_d = torch.as_tensor(zf).cuda().contiguous()
+    empty = api.loglik(plan, zf_d, torch.zeros((0, prob.n_sources, 16), dtype=torch.float64, device="cuda"))
+    assert empty.shape == (0, prob.n_sources)
+    none = api.loglik(plan, zf_d, zf_d[None].clone(), mask=np.zeros(prob.n_sources, bool))
+    assert torch.isnan(none).all()
+    same = api.loglik(plan, zf_d, zf_d[None].clone()).cpu().numpy()[0]
+    want = np.array([L.log_likelihood(m, zf, s, zf[s]) for s in range(prob.n_sources)])
+    assert np.all(np.abs(same - want) <= 1e-5 * np.abs(want))
