@@ -160,7 +160,9 @@ cel_status cel_last_device_error(cel_ctx* ctx, int32_t* code);
  * its greedy colouring (ascending id, smallest free colour), work items sorted by cost,
  * and device copies of the tables; reads the pixels once (on `stream`, synchronised
  * before return) to form per-pixel (count, sky) pairs and the per-patch data constants
- * sum(x log x - x - log x!).  Owns all scratch of later calls.  Synchronous. */
+ * sum(x log x - x - log x!).  Owns all scratch of later calls.  Synchronous.
+ * CEL_EUNSUPPORTED beyond the compiled limits: 2^20 images, image width 2^20, 2^24 patches,
+ * 2^22 pixels per patch, 2^30 work items, 4 PSF components, 8 + 8 profile components. */
 cel_status cel_prepare(cel_ctx* ctx, const cel_problem* prob, cel_plan** out, void* stream);
 void cel_plan_free(cel_plan* plan);
 

@@ -112,10 +112,12 @@ static cel_status validate(const cel_problem* pr) {
   if (pr->n_patches > 0 && (!pr->patches || !pr->pixels)) return CEL_EINVAL;
   if (!pr->prior || !pr->profiles) return CEL_EINVAL;
   if (pr->n_sky_knots > 0 && !pr->sky_knots) return CEL_EINVAL;
+  // (the neighbour sweep packs image, column and patch id into one 64-bit key)
+  if (pr->n_images >= (1 << 20) || pr->n_patches >= (1 << 24)) return CEL_EUNSUPPORTED;
   for (int n = 0; n < pr->n_images; ++n) {
     const cel_image& im = pr->images[n];
     if (im.band < 0 || im.band > 4 || im.H < 1 || im.W < 1 || im.n_psf < 1) return CEL_EINVAL;
-    if (im.n_psf > kMaxPsf) return CEL_EUNSUPPORTED;
+    if (im.n_psf > kMaxPsf || im.W > (1 << 20)) return CEL_EUNSUPPORTED;
     for (int k = 0; k < im.n_psf; ++k) {
       const double* q = im.psf[k];
       for (int i = 0; i < 6; ++i)
@@ -577,23 +579,34 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   // the pairs are counted per patch and scattered into the CSR list, then each patch's
   // (short) list is sorted ascending
   {
-    std::vector<int> order(P);
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int a, int b) {
-      const DPatch &A = p->patches_h[a], &B = p->patches_h[b];
-      return A.img != B.img ? A.img < B.img : A.x0 != B.x0 ? A.x0 < B.x0 : a < b;
-    });
+    // (image, x0, id) order by one integer sort of packed keys (image < 2^20, x0 < 2^20 and
+    // id < 2^24, checked by validate), then the rectangles in that order, contiguous
+    struct Rect {
+      int32_t img, x0, x1, y0, y1, src, id;
+    };
+    std::vector<uint64_t> key(P);
+    for (int i = 0; i < P; ++i) {
+      const DPatch& d = p->patches_h[i];
+      key[i] = ((uint64_t)d.img << 44) | ((uint64_t)d.x0 << 24) | (uint64_t)i;
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<Rect> r(P);
+    for (int i = 0; i < P; ++i) {
+      const int id = (int)(key[i] & 0xffffffu);
+      const DPatch& d = p->patches_h[id];
+      r[i] = Rect{d.img, d.x0, d.x0 + d.w, d.y0, d.y0 + d.h, d.src, id};
+    }
     std::vector<int2> pairs;
     std::vector<int> deg(P + 1, 0);
     for (int ia = 0; ia < P; ++ia) {
-      const DPatch& A = p->patches_h[order[ia]];
+      const Rect& A = r[ia];
       for (int ib = ia + 1; ib < P; ++ib) {
-        const DPatch& B = p->patches_h[order[ib]];
-        if (B.img != A.img || B.x0 >= A.x0 + A.w) break;
-        if (B.y0 < A.y0 + A.h && A.y0 < B.y0 + B.h && A.src != B.src) {
-          pairs.push_back(make_int2(order[ia], order[ib]));
-          ++deg[order[ia]];
-          ++deg[order[ib]];
+        const Rect& B = r[ib];
+        if (B.img != A.img || B.x0 >= A.x1) break;
+        if (B.y0 < A.y1 && A.y0 < B.y1 && A.src != B.src) {
+          pairs.push_back(make_int2(A.id, B.id));
+          ++deg[A.id];
+          ++deg[B.id];
         }
       }
     }
