@@ -6,6 +6,10 @@ in device memory.  At every device step:
   1. requests that have arrived are admitted, oldest first, while the estimated device
      footprint of the resident set stays within the HBM budget (a request that does not
      fit waits; it is never failed for lack of memory);
+     Under a burst of arrivals, admissions are held while the last rebuild of the merged plan
+     is younger than `min_rebuild_interval_s` (a rebuild costs a few milliseconds of host
+     work, so that arrivals a few milliseconds apart share one; a lone arrival is admitted
+     at once);
   2. if a request was admitted, the resident requests are merged into one plan (their
      pixel arrays are concatenated on the device; sources of different requests never
      overlap, so the merged colouring restricted to a request equals its own), and their
@@ -125,6 +129,7 @@ class Stats:
     latencies: list = field(default_factory=list)
     steps: int = 0
     deferred_admissions: int = 0
+    held_admissions: int = 0      # steps whose arrivals waited for the rebuild interval
     rebuilds: int = 0
     cancelled: int = 0
     units_evaluated: int = 0
@@ -135,7 +140,8 @@ class Stats:
         return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
                     mean_ms=float(lat.mean() * 1e3), completed=len(self.latencies),
                     req_per_s=len(self.latencies) / max(self.wall, 1e-9), steps=self.steps,
-                    deferred_admissions=self.deferred_admissions, rebuilds=self.rebuilds,
+                    deferred_admissions=self.deferred_admissions, held_admissions=self.held_admissions,
+                    rebuilds=self.rebuilds,
                     cancelled=self.cancelled,
                     units_per_s=self.units_evaluated / max(self.wall, 1e-9), wall_s=self.wall)
 
@@ -143,7 +149,7 @@ class Stats:
 class Server:
     """Continuous-batching loop on one device."""
 
-    def __init__(self, device=0, hbm_budget_bytes=16 << 30, rounds=10, **ctx_opts):
+    def __init__(self, device=0, hbm_budget_bytes=16 << 30, rounds=10, min_rebuild_interval_s=0.01, **ctx_opts):
         self.ctx = api.Context(device, **ctx_opts)
         self.dev = self.ctx.device
         self.variants = VARIANTS_FD if ctx_opts.get("hessian_fd") else VARIANTS_EXACT
@@ -154,6 +160,8 @@ class Server:
         self.theta = self.radius = None   # merged state of the requests laid out in the plan
         self.in_plan: list[Request] = []
         self.dirty = False
+        self.min_rebuild_interval = float(min_rebuild_interval_s)
+        self.last_rebuild = -float("inf")
         self.stats = Stats()
 
     # -- admission and merging ---------------------------------------------------------------
@@ -226,7 +234,10 @@ class Server:
         # (requests that left but stay in the plan do not count: an admission rebuilds the
         # plan without them, after the old one is released)
         used = sum(r.footprint for r in self.resident)
-        while pending:
+        hold = bool(pending) and bool(self.resident) and now - self.last_rebuild < self.min_rebuild_interval
+        if hold:
+            self.stats.held_admissions += 1
+        while pending and not hold:
             r = pending[0]
             r.footprint = r.footprint or footprint_bytes(r.prob, self.variants)
             if used + r.footprint > self.budget and self.resident:
@@ -240,6 +251,7 @@ class Server:
         if changed or self.dirty:
             self._rebuild()
             self.dirty = False
+            self.last_rebuild = now
         if not self.resident:
             return cancelled
         S = self.plan.S
