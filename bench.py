@@ -203,6 +203,9 @@ def serve_leg(log, rates=(20.0, 50.0, 100.0, 200.0), n_requests=200, pool=8):
     from paper_1803_00113_amd import serve
     from synth import gen
     regions = [gen.config5_request(gen.SEED_BASE + 5 + 100 * i) for i in range(pool)]
+    # untimed warm-up: each region once through a server (first plan builds and launches)
+    warm = [serve.Request(i, regions[i], 0.001 * i, rounds=10) for i in range(pool)]
+    serve.Server(0, rounds=10).run(warm)
     out = []
     for rate in rates:
         rng = np.random.default_rng(int(rate))

@@ -6,10 +6,10 @@ in device memory.  At every device step:
   1. requests that have arrived are admitted, oldest first, while the estimated device
      footprint of the resident set stays within the HBM budget (a request that does not
      fit waits; it is never failed for lack of memory);
-     Under a burst of arrivals, admissions are held while the last rebuild of the merged plan
-     is younger than `min_rebuild_interval_s` (a rebuild costs a few milliseconds of host
-     work, so that arrivals a few milliseconds apart share one; a lone arrival is admitted
-     at once);
+     Under a burst of arrivals (the last two rebuilds less than two intervals apart),
+     admissions are held while the last rebuild of the merged plan is younger than
+     `min_rebuild_interval_s`: a rebuild costs a few milliseconds of host work, and arrivals
+     a few milliseconds apart then share one; outside bursts an arrival is admitted at once;
   2. if a request was admitted, the resident requests are merged into one plan (their
      pixel arrays are concatenated on the device; sources of different requests never
      overlap, so the merged colouring restricted to a request equals its own), and their
@@ -161,7 +161,7 @@ class Server:
         self.in_plan: list[Request] = []
         self.dirty = False
         self.min_rebuild_interval = float(min_rebuild_interval_s)
-        self.last_rebuild = -float("inf")
+        self.last_rebuild = self.prev_rebuild = -float("inf")
         self.stats = Stats()
 
     # -- admission and merging ---------------------------------------------------------------
@@ -234,7 +234,8 @@ class Server:
         # (requests that left but stay in the plan do not count: an admission rebuilds the
         # plan without them, after the old one is released)
         used = sum(r.footprint for r in self.resident)
-        hold = bool(pending) and bool(self.resident) and now - self.last_rebuild < self.min_rebuild_interval
+        burst = self.last_rebuild - self.prev_rebuild < 2 * self.min_rebuild_interval
+        hold = bool(pending) and bool(self.resident) and burst and now - self.last_rebuild < self.min_rebuild_interval
         if hold:
             self.stats.held_admissions += 1
         while pending and not hold:
@@ -251,7 +252,7 @@ class Server:
         if changed or self.dirty:
             self._rebuild()
             self.dirty = False
-            self.last_rebuild = now
+            self.prev_rebuild, self.last_rebuild = self.last_rebuild, now
         if not self.resident:
             return cancelled
         S = self.plan.S

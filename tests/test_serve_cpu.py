@@ -135,23 +135,27 @@ def test_server_drops_idle_majority(monkeypatch):
 
 
 def test_admissions_held_for_the_rebuild_interval(monkeypatch):
-    """Arrivals while the merged plan's last rebuild is younger than the interval wait for a
-    later step (and then share one rebuild); with nothing resident a request is admitted at
-    once.  Driven with explicit clock values."""
+    """In a burst (the last two rebuilds less than two intervals apart), arrivals while the
+    last rebuild is younger than the interval wait for a later step and then share one
+    rebuild; outside a burst, or with nothing resident, a request is admitted at once.
+    Driven with explicit clock values."""
     from paper_1803_00113_amd import serve
     fake = _FakeBackend()
     fake.install(monkeypatch, serve)
-    probs = [gen.crop_patches(gen.config5_request(500 + i, n_sources=2), 16) for i in range(3)]
+    probs = [gen.crop_patches(gen.config5_request(500 + i, n_sources=2), 16) for i in range(4)]
     reqs = [serve.Request(i, p, arrival=0.0) for i, p in enumerate(probs)]
     srv = serve.Server(0, rounds=50, min_rebuild_interval_s=0.010)
     pending = [reqs[0]]
     srv.step(0.000, pending)                      # empty server: admitted at once
     assert srv.stats.rebuilds == 1 and not pending
-    pending += [reqs[1], reqs[2]]
-    srv.step(0.004, pending)                      # 4 ms after the rebuild: held
-    srv.step(0.008, pending)
-    assert srv.stats.rebuilds == 1 and len(pending) == 2 and srv.stats.held_admissions == 2
-    srv.step(0.011, pending)                      # interval over: both admitted, one rebuild
-    assert srv.stats.rebuilds == 2 and not pending and len(srv.resident) == 3
-    # the request admitted first kept its rounds through the rebuild
-    assert reqs[0].done_rounds == 4 and reqs[1].done_rounds == 1
+    pending.append(reqs[1])
+    srv.step(0.004, pending)                      # no burst yet: admitted at once
+    assert srv.stats.rebuilds == 2 and not pending and srv.stats.held_admissions == 0
+    pending += [reqs[2], reqs[3]]
+    srv.step(0.008, pending)                      # burst, 4 ms after the rebuild: held
+    srv.step(0.012, pending)
+    assert srv.stats.rebuilds == 2 and len(pending) == 2 and srv.stats.held_admissions == 2
+    srv.step(0.015, pending)                      # interval over: both admitted, one rebuild
+    assert srv.stats.rebuilds == 3 and not pending and len(srv.resident) == 4
+    # requests admitted earlier kept their rounds through the rebuilds
+    assert reqs[0].done_rounds == 5 and reqs[1].done_rounds == 4 and reqs[2].done_rounds == 1
