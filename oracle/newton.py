@@ -108,12 +108,16 @@ def greedy_colouring(adj):
     return colour
 
 
-def newton_step_source(model, theta, s, radius, opts=None):
+def newton_step_source(model, theta, s, radius, opts=None, info=None):
     """One trust-region Newton step on source s with every other source fixed.
-    Returns (theta_s_new[32], radius_new, status, L_s at the returned point)."""
+    Returns (theta_s_new[32], radius_new, status, L_s at the returned point).  A dict passed
+    as `info` receives the step's local model: L, g, H (when formed), the subproblem's
+    solution p and its predicted gain."""
     o = dict(DEFAULTS, **(opts or {}))
     theta = np.asarray(theta, dtype=np.float64)
     L, g = E.local_value_grad(model, theta, s)
+    if info is not None:
+        info.update(L=L, g=g)
     ts = theta[s].copy()
     if not (np.isfinite(L) and np.all(np.isfinite(g)) and np.all(np.isfinite(ts))):
         return ts, radius, ST_NONFINITE, L
@@ -123,6 +127,8 @@ def newton_step_source(model, theta, s, radius, opts=None):
     H = E.local_hessian(model, theta, s)
     p, _, _ = tr_subproblem(g, H, radius)
     pred = float(g @ p + 0.5 * p @ H @ p)
+    if info is not None:
+        info.update(H=H, p=p, pred=pred)
     if pred <= o["ftol"] * max(1.0, abs(L)):
         return ts, radius, ST_CONVERGED, L
     trial = theta.copy()

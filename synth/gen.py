@@ -7,7 +7,8 @@ each source emits Poisson(iota * band flux) photons, each photon's sky offset is
 from the galaxy light kernel (a component of the profile mixture, then a scaled and
 rotated normal vector), mapped to the pixel frame by the image's affine WCS, blurred by
 a draw from the image's PSF mixture and binned to the nearest pixel centre; skyglow adds
-Poisson counts from a smooth (planar) rate field per image.  The problem arrays follow
+Poisson counts from a smooth rate field per image (a plane, optionally with an
+undulation, sampled on the image's sky knot grid).  The problem arrays follow
 the layout documented in include/celmi.h.
 
 Workloads (seed = 180300110 + k for workload k):
@@ -18,6 +19,8 @@ Workloads (seed = 180300110 + k for workload k):
   4 "field":   one 2048x1489 field, 5 bands x 3 epochs (offsets up to 20 px, small
                rotations), ~600 uniformly placed sources, 70% galaxies.
   5 "serving": region requests of 1-200 sources, side 16-96, 5 bands.
+  6 "skew":    a small blended field with general WCS, calibration, sky grid and PSF
+               (config_skew).
 """
 from __future__ import annotations
 
@@ -200,7 +203,7 @@ def render(rng, img, canvas, sources, profiles):
     y0, x0, h, w = canvas
     rows = np.arange(y0, y0 + h, dtype=np.float64)[:, None]
     cols = np.arange(x0, x0 + w, dtype=np.float64)[None, :]
-    sky = img["sky0"] + img["sky_gy"] * (rows - img["H"] / 2) + img["sky_gx"] * (cols - img["W"] / 2)
+    sky = sky_field(img, rows, cols)
     counts = rng.poisson(np.maximum(sky, 0.0)).astype(np.int64)
     A, b = img["A"], img["b"]
     for src in sources:
@@ -221,12 +224,26 @@ def render(rng, img, canvas, sources, profiles):
     return counts
 
 
+def sky_field(img, rows, cols):
+    """The image's true skyglow rate at pixel centres (rows, cols broadcast): a plane, plus,
+    when the image has one, a smooth undulation of relative amplitude sky_wave (a product of
+    sines over the frame), so that a knot grid samples a field with curvature."""
+    H, W = img["H"], img["W"]
+    sky = img["sky0"] + img["sky_gy"] * (rows - H / 2) + img["sky_gx"] * (cols - W / 2)
+    amp = img.get("sky_wave", 0.0)
+    if amp:
+        ph = img["sky_phase"]
+        sky = sky * (1.0 + amp * np.sin(2 * math.pi * (rows / H * img["sky_ky"] + ph[0]))
+                     * np.sin(2 * math.pi * (cols / W * img["sky_kx"] + ph[1])))
+    return sky
+
+
 def sky_knots_for(img, qh, qw):
-    """Knot values of the image's planar sky field on a qh x qw grid spanning the corners."""
+    """Knot values of the image's sky field on a qh x qw grid spanning the corners."""
     H, W = img["H"], img["W"]
     ky = np.linspace(0, H - 1, qh) if qh > 1 else np.array([(H - 1) / 2.0])
     kx = np.linspace(0, W - 1, qw) if qw > 1 else np.array([(W - 1) / 2.0])
-    return (img["sky0"] + img["sky_gy"] * (ky[:, None] - H / 2) + img["sky_gx"] * (kx[None, :] - W / 2))
+    return sky_field(img, ky[:, None], kx[None, :]) * np.ones((len(ky), len(kx)))
 
 
 # ----------------------------------------------------------------------------------------
@@ -333,13 +350,45 @@ def _assemble(name, images, sources, patch_rects, pixel_lists, prior, profiles, 
         truth=truth, name=name)
 
 
-def _image(rng, band, H, W, sky0, A=None, b=None, sky_grad=0.0, qh=2, qw=2, npsf=3, iota=1.0):
-    return dict(band=int(band), H=int(H), W=int(W), npsf=npsf, psf=make_psf(rng, npsf),
-                A=np.eye(2) if A is None else np.asarray(A, np.float64),
-                b=np.zeros(2) if b is None else np.asarray(b, np.float64),
-                iota=float(iota), sky0=float(sky0),
-                sky_gy=float(rng.uniform(-sky_grad, sky_grad)),
-                sky_gx=float(rng.uniform(-sky_grad, sky_grad)), qh=qh, qw=qw)
+def _image(rng, band, H, W, sky0, A=None, b=None, sky_grad=0.0, qh=2, qw=2, npsf=3, iota=1.0, psf=None,
+           sky_wave=0.0):
+    im = dict(band=int(band), H=int(H), W=int(W), npsf=npsf, psf=make_psf(rng, npsf) if psf is None else psf,
+              A=np.eye(2) if A is None else np.asarray(A, np.float64),
+              b=np.zeros(2) if b is None else np.asarray(b, np.float64),
+              iota=float(iota), sky0=float(sky0),
+              sky_gy=float(rng.uniform(-sky_grad, sky_grad)),
+              sky_gx=float(rng.uniform(-sky_grad, sky_grad)), qh=qh, qw=qw)
+    if sky_wave:
+        im.update(sky_wave=float(sky_wave), sky_ky=float(rng.uniform(0.7, 1.6)), sky_kx=float(rng.uniform(0.7, 1.6)),
+                  sky_phase=rng.uniform(0, 1, 2))
+    return im
+
+
+def make_psf_skewed(rng, npsf):
+    """A PSF mixture with off-centre components and correlated (tilted, elongated)
+    covariances: sigma 1-2.5 px along each principal axis, means within 0.6 px."""
+    w = rng.dirichlet(np.full(npsf, 2.0))
+    psf = np.zeros((MAX_PSF, 6))
+    for k in range(npsf):
+        s1, s2 = rng.uniform(1.0, 2.5, 2)
+        t = rng.uniform(0, math.pi)
+        c, sn = math.cos(t), math.sin(t)
+        cxx = s1 * s1 * c * c + s2 * s2 * sn * sn
+        cyy = s1 * s1 * sn * sn + s2 * s2 * c * c
+        cxy = (s1 * s1 - s2 * s2) * c * sn
+        mx, my = rng.uniform(-0.6, 0.6, 2)
+        psf[k] = [w[k], mx, my, cxx, cxy, cyy]
+    return psf
+
+
+def random_wcs(rng, scale=(0.85, 1.2), shear=0.15, angle=0.6):
+    """An affine map sky -> pixels with rotation, shear and unequal axis scales (A != A^T,
+    det > 0): A = R(phi) [[1, sh], [0, 1]] diag(sx, sy)."""
+    phi = rng.uniform(-angle, angle)
+    sh = rng.uniform(-shear, shear)
+    sx, sy = rng.uniform(*scale, 2)
+    R = np.array([[math.cos(phi), -math.sin(phi)], [math.sin(phi), math.cos(phi)]])
+    return R @ np.array([[1.0, sh], [0.0, 1.0]]) @ np.diag([sx, sy])
 
 
 def _grouped(name, seed, n_sources, side_lo, side_hi, n_epochs, flux_mode, max_group=5,
@@ -444,6 +493,48 @@ def config5_request(seed, n_sources=None):
     rng = np.random.default_rng(seed)
     n = int(n_sources if n_sources is not None else rng.integers(1, 201))
     return _grouped(f"request_{n}src_5b_side16-96", seed + 7, n, 16, 96, 1, "prior", prior_seed=SURVEY_PRIOR_SEED)
+
+
+def config_skew(seed=SEED_BASE + 6, n_groups=2, H=83, W=97, qh=4, qw=5):
+    """A small blended field on which every image differs from the plain workloads in the
+    ways they leave out: a WCS with rotation, shear and unequal scales and a sub-pixel
+    offset, a calibration iota in [0.4, 3] per image, a sky knot grid of qh x qw (>= 3 x 3)
+    sampling a field with curvature, PSF mixtures of 2-4 off-centre, tilted components;
+    rectangular patches of unequal sides, some cut by the image edge.  Sources sit in
+    overlapping groups of 2-3 (4 images: bands g and i, two epochs)."""
+    rng = np.random.default_rng(seed)
+    profiles = load_profiles()
+    prior = make_prior(rng)
+    images = []
+    for e in range(2):
+        for band in (1, 3):
+            npsf = int(rng.integers(2, 5))
+            images.append(_image(rng, band, H, W, rng.uniform(60, 150), A=random_wcs(rng),
+                                 b=rng.uniform(-3, 3, 2), sky_grad=0.05, qh=qh, qw=qw, npsf=npsf,
+                                 iota=rng.uniform(0.4, 3.0), psf=make_psf_skewed(rng, npsf), sky_wave=0.25))
+    # sky positions whose pixel positions stay inside every frame
+    sources = []
+    centres = [np.array([W * 0.3, H * 0.35]), np.array([W * 0.68, H * 0.62])][:n_groups]
+    for c in centres:
+        for _ in range(int(rng.integers(2, 4))):
+            u = c + rng.uniform(-5, 5, 2)
+            sources.append(draw_source(rng, prior, rng.random() < 0.4, u, flux=rng.uniform(2e3, 2e4)))
+    theta0 = [init_theta(rng, s_) for s_ in sources]
+    rects = []
+    for s_, src in enumerate(sources):
+        for n, img in enumerate(images):
+            pos = img["A"] @ src["u"] + img["b"]
+            w = int(rng.integers(14, 31))
+            h = int(rng.integers(14, 31))
+            x0 = int(round(pos[0])) - w // 2 + int(rng.integers(-2, 3))
+            y0 = int(round(pos[1])) - h // 2 + int(rng.integers(-2, 3))
+            x1, y1 = min(W, x0 + w), min(H, y0 + h)
+            x0, y0 = max(0, x0), max(0, y0)
+            rects.append((s_, n, x0, y0, x1 - x0, y1 - y0))
+    frames = [render(rng, images[n], (0, 0, H, W), sources, profiles) for n in range(len(images))]
+    pix = [frames[n][y0:y0 + h, x0:x0 + w] for (s_, n, x0, y0, w, h) in rects]
+    return _assemble(f"skew_{len(sources)}src_{H}x{W}_4img_sky{qh}x{qw}", images, sources, rects, pix,
+                     prior, profiles, theta0)
 
 
 def _extent_halfwidth(src, psf_sigma_max):

@@ -199,25 +199,3 @@ def test_invalid_problems_rejected():
     plan = api.Plan(ctx, prob)
     with pytest.raises(ValueError):
         api.elbo_grad(plan, np.zeros((3, 32)))
-
-
-@pytest.mark.parametrize("n_sample", [24])
-def test_config2_full_size_sampled(n_sample):
-    """Full batched workload (1000 sources, 5 bands x 2 epochs, ~1.7e7 active pixels) in the
-    launch configuration the benchmark times; sampled sources against the oracle's L_s and
-    gradient, and the global ELBO against the sum of the oracle's per-source owned terms is
-    checked through the elbo_local identity on the sample."""
-    say("case: config2 full size, sampled")
-    prob = gen.config2()
-    plan, tot, loc, g = run(prob)
-    m = E.Model(prob)
-    rng = np.random.default_rng(0)
-    sample = rng.choice(prob.n_sources, n_sample, replace=False)
-    o_loc = np.zeros(prob.n_sources)
-    o_g = np.zeros((prob.n_sources, 32))
-    for s in sample:
-        v, gs = E.local_value_grad(m, prob.theta0, int(s))
-        o_loc[s] = v
-        o_g[s, :27] = gs
-    check(prob, None, loc, g, None, o_loc, o_g, sources=sample)
-    assert np.isfinite(tot)
