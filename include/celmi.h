@@ -16,8 +16,10 @@
  *    caller and never retained past the call's stream work.  "HOST" pointers are read
  *    during the call only.
  *  - Calls are asynchronous on the given stream (0 = the null stream).  Outputs are valid
- *    once the caller synchronises that stream.  Nothing allocates during evaluation
- *    calls: scratch is sized by cel_prepare and owned by the plan.
+ *    once the caller synchronises that stream.  cel_elbo_eval and cel_elbo_grad allocate
+ *    nothing (their scratch is made by cel_prepare and owned by the plan); the Hessian,
+ *    Newton, sweep and likelihood calls allocate their own scratch at their first call on
+ *    a plan; cel_elbo_grad_static never allocates.
  *  - A context and its plans are not thread-safe; use one per host thread.
  *  - Results are deterministic: a fixed plan and inputs give bitwise-identical outputs,
  *    independent of launch configuration and of which other sources share a launch.
@@ -50,6 +52,8 @@ typedef int32_t cel_status;
 #define CEL_ENOMEM (-2)        /* device or pinned host allocation failed (cel_prepare)  */
 #define CEL_EHIP (-3)          /* a HIP runtime call failed                              */
 #define CEL_EUNSUPPORTED (-4)  /* a size beyond the library's compiled limits            */
+#define CEL_ESCRATCH (-5)      /* cel_elbo_grad_static: scratch need beyond the static
+                                  buffer (CEL_STATIC_SCRATCH_BYTES)                     */
 
 /* per-source status written by cel_newton_step / cel_sweep */
 #define CEL_ST_SKIPPED 0       /* not selected by the mask                               */
@@ -183,6 +187,23 @@ cel_status cel_elbo_eval(cel_ctx* ctx, const cel_plan* plan, const double* theta
  * (entries 27-31 written 0).  elbo_total / elbo_local as above (either may be NULL). */
 cel_status cel_elbo_grad(cel_ctx* ctx, const cel_plan* plan, const double* theta, double* elbo_total,
                          double* elbo_local, double* grad, void* stream);
+
+/* For callers that cannot allocate device memory at call time (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cel_elbo_grad with its
+ * per-call scratch (component tables, neighbour moment maps, slot rows, per-source sums)
+ * in one static device buffer of CEL_STATIC_SCRATCH_BYTES per device, held from the
+ * library's first cel_create on that device until the process ends, instead of the plan's
+ * own blocks.  It calls no allocating routine.  Same kernels and launch order as
+ * cel_elbo_grad, so the outputs are bitwise identical.  Arguments as cel_elbo_grad.
+ * Need in bytes (each part rounded up to 256): n_patches x 4656 (float64 pixels: 9312)
+ * + active pixels x 8 (16) + work items x 128 + sources x 272; CEL_ESCRATCH beyond the
+ * buffer (the 1000-source batched workload of 1.7e7 pixels needs 190 MB).  All calls on
+ * one device share the buffer: calls that overlap in time on one device (several streams,
+ * several host threads, several contexts) race and must be serialised by the caller; a
+ * call's outputs are complete once its stream is synchronised. */
+#define CEL_STATIC_SCRATCH_BYTES ((int64_t)256 << 20)
+cel_status cel_elbo_grad_static(cel_ctx* ctx, const cel_plan* plan, const double* theta, double* elbo_total,
+                                double* elbo_local, double* grad, void* stream);
 
 /* Same as cel_elbo_grad, one launch sequence per source ("plain" form, for comparison
  * with the batched form).  Slower by design; identical results. */

@@ -16,7 +16,8 @@ N_THETA = 32
 N_PARAM = 27
 N_Z = 16
 
-CEL_OK, CEL_EINVAL, CEL_ENOMEM, CEL_EHIP, CEL_EUNSUPPORTED = 0, -1, -2, -3, -4
+CEL_OK, CEL_EINVAL, CEL_ENOMEM, CEL_EHIP, CEL_EUNSUPPORTED, CEL_ESCRATCH = 0, -1, -2, -3, -4, -5
+STATIC_SCRATCH_BYTES = 256 << 20
 ST_SKIPPED, ST_ACCEPTED, ST_REJECTED, ST_CONVERGED, ST_NONFINITE = 0, 1, 2, 3, 4
 DEVERR_NONFINITE_OBJECTIVE, DEVERR_NONFINITE_STEP, DEVERR_NONFINITE_HESSIAN = 1, 2, 4
 
@@ -87,6 +88,7 @@ _sig = {
     "cel_elbo_eval": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cel_elbo_grad": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cel_elbo_grad_plain": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cel_elbo_grad_static": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cel_elbo_hessian": (C.c_int32, [_vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, _vp, _vp, _vp]),
     "cel_newton_step": (C.c_int32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, _vp, _vp]),
     "cel_phase_times": (C.c_int32, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),

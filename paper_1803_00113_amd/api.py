@@ -212,6 +212,18 @@ def elbo_grad(plan: Plan, theta):
     return tot, loc, g
 
 
+def elbo_grad_static(plan: Plan, theta, out=None):
+    """cel_elbo_grad_static: cel_elbo_grad with its scratch in the library's static device
+    buffer (no allocation inside the call).  out: optional (total [1], local [S], grad
+    [S,32]) float64 cuda tensors to write into (else they are allocated here, by torch,
+    before the call).  Returns (total, local, grad)."""
+    th = plan._theta(theta)
+    tot, loc, g = out if out is not None else (plan._out(1), plan._out(plan.S), plan._out(plan.S, F.N_THETA))
+    F.check("cel_elbo_grad_static", F.lib.cel_elbo_grad_static(plan.ctx.h, plan.h, _ptr(th), _ptr(tot), _ptr(loc),
+                                                               _ptr(g), _stream(plan.ctx.device)))
+    return tot, loc, g
+
+
 def elbo_grad_plain(plan: Plan, theta):
     """cel_elbo_grad_plain: one launch per source; same outputs as elbo_grad."""
     th = plan._theta(theta)

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -22,6 +23,7 @@ extern "C" const char* cel_strerror(cel_status s) {
     case CEL_ENOMEM: return "device allocation failed";
     case CEL_EHIP: return "HIP runtime error";
     case CEL_EUNSUPPORTED: return "unsupported size or option";
+    case CEL_ESCRATCH: return "the call needs more scratch than the static buffer holds (CEL_STATIC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }
@@ -488,6 +490,28 @@ hipError_t launch_total_after_eval(cel_plan* p, const double* theta, hipStream_t
 
 }  // namespace celmi
 
+// Scratch of cel_elbo_grad_static: one buffer per device for the life of the process, so
+// that the entry point allocates nothing.  Host code never uses the array's name as an
+// address: each device's copy is at the address hipGetSymbolAddress returns with that
+// device current (resolved once per device, at the first cel_create on it).
+static __device__ __align__(256) unsigned char scratch[CEL_STATIC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device: address of its copy of `scratch`, or null
+}  // namespace
+
+// the calling thread's current device must be `device`
+static cel_status resolve_static_scratch(int device, int n_devices) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() < n_devices) g_scratch_ptr.resize(n_devices, nullptr);
+  if (g_scratch_ptr[device]) return CEL_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CEL_EHIP;
+  g_scratch_ptr[device] = ptr;
+  return CEL_OK;
+}
+
 extern "C" cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_options* opt) {
   if (!out) return CEL_EINVAL;
   *out = nullptr;
@@ -499,6 +523,7 @@ extern "C" cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_op
   if (!(o.pixels_per_lane == 1 || o.pixels_per_lane == 2 || o.pixels_per_lane == 4)) return CEL_EINVAL;
   if (o.chunk_pixels < 64 || o.chunk_pixels % 64 != 0 || o.chunk_pixels > (1 << 20)) return CEL_EINVAL;
   if (hipSetDevice(hip_device) != hipSuccess) return CEL_EHIP;
+  if (resolve_static_scratch(hip_device, nd) != CEL_OK) return CEL_EHIP;
   int32_t* err = nullptr;
   if (hipMalloc((void**)&err, sizeof(int32_t)) != hipSuccess) return CEL_ENOMEM;
   if (hipMemset(err, 0, sizeof(int32_t)) != hipSuccess) {
@@ -1124,6 +1149,74 @@ static cel_status eval_common(cel_ctx* ctx, const cel_plan* cplan, const double*
   if (e == hipSuccess && elbo_total) e = launch_total(p->v_own, p->S, elbo_total, sm);
   phase_mark(p, 4, sm);
   p->marking = false;
+  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+}
+
+// cel_elbo_grad with its per-call scratch in the static buffer: the component tables, the
+// neighbour moment maps, the slot rows and the per-source sums are carved from `scratch`
+// (256-byte aligned parts) instead of the plan's own blocks; the kernels are the same.
+// Every part is written in full by the evaluation before it is read, so nothing is cleared.
+extern "C" cel_status cel_elbo_grad_static(cel_ctx* ctx, const cel_plan* cplan, const double* theta,
+                                           double* elbo_total, double* elbo_local, double* grad, void* stream) {
+  if (!ctx || !cplan || (!theta && cplan->S > 0)) return CEL_EINVAL;
+  cel_plan* p = const_cast<cel_plan*>(cplan);
+  if (p->device != ctx->device) return CEL_EINVAL;
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (p->device < (int)g_scratch_ptr.size()) base = g_scratch_ptr[p->device];
+  }
+  if (!base) return CEL_EHIP;   // cel_create resolves it; a context on this device exists
+  const bool fp64 = p->opt.pixel_fp64 != 0;
+  const size_t align = 256;
+  auto up = [&](size_t b) { return (b + align - 1) / align * align; };
+  const size_t P1 = (size_t)std::max(p->P, 1), S1 = (size_t)std::max(p->S, 1);
+  const size_t b_tables = up(P1 * (fp64 ? sizeof(Table<double>) : sizeof(Table<float>)));
+  const size_t b_maps = up((size_t)std::max<int64_t>(p->n_units, 1) * (fp64 ? sizeof(double2) : sizeof(float2)));
+  const size_t b_slots = up((size_t)std::max<int64_t>(p->n_tasks, 1) * kSlots * sizeof(double));
+  const size_t b_src = up(S1 * sizeof(double));
+  const size_t b_grad = up(S1 * kThetaN * sizeof(double));
+  const size_t need = b_tables + b_maps + b_slots + 2 * b_src + b_grad;
+  if (need > (size_t)CEL_STATIC_SCRATCH_BYTES) return CEL_ESCRATCH;
+  if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
+  unsigned char* q = static_cast<unsigned char*>(base);
+  void* tables = q;
+  void* maps = q + b_tables;
+  double* slots = reinterpret_cast<double*>(q + b_tables + b_maps);
+  double* own = reinterpret_cast<double*>(q + b_tables + b_maps + b_slots);
+  double* local = reinterpret_cast<double*>(q + b_tables + b_maps + b_slots + b_src);
+  double* gscr = reinterpret_cast<double*>(q + b_tables + b_maps + b_slots + 2 * b_src);
+  // the plan's scratch pointers point into the static buffer while the launches are enqueued
+  Table<float>* s_tf = p->tables_f;
+  Table<double>* s_td = p->tables_d;
+  float2* s_mf = p->d_maps;
+  double2* s_md = p->d_maps64;
+  double *s_slots = p->slots, *s_own = p->v_own, *s_local = p->v_local, *s_grad = p->v_grad;
+  if (fp64) {
+    p->tables_d = static_cast<Table<double>*>(tables);
+    p->d_maps64 = static_cast<double2*>(maps);
+  } else {
+    p->tables_f = static_cast<Table<float>*>(tables);
+    p->d_maps = static_cast<float2*>(maps);
+  }
+  p->slots = slots;
+  p->v_own = own;
+  p->v_local = local;
+  p->v_grad = gscr;
+  const bool marking = p->marking;
+  p->marking = false;   // no timing events: creating them may allocate
+  hipStream_t sm = (hipStream_t)stream;
+  hipError_t e = eval_any(p, theta, nullptr, 0, 1, true, -1, nullptr, sm, true, fp64, elbo_local, grad);
+  if (e == hipSuccess && elbo_total) e = launch_total(p->v_own, p->S, elbo_total, sm);
+  p->tables_f = s_tf;
+  p->tables_d = s_td;
+  p->d_maps = s_mf;
+  p->d_maps64 = s_md;
+  p->slots = s_slots;
+  p->v_own = s_own;
+  p->v_local = s_local;
+  p->v_grad = s_grad;
+  p->marking = marking;
   return e == hipSuccess ? CEL_OK : CEL_EHIP;
 }
 
