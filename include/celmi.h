@@ -67,6 +67,8 @@ typedef int32_t cel_status;
 #define CEL_DEVERR_NONFINITE_STEP 2       /* a Newton step met non-finite theta, gradient
                                              or Hessian (that source: CEL_ST_NONFINITE)  */
 #define CEL_DEVERR_NONFINITE_HESSIAN 4    /* cel_elbo_hessian produced a non-finite entry  */
+#define CEL_DEVERR_BAD_INDEX 8            /* cel_psf_fit met an image index out of range
+                                             (that fit's output rows are NaN)              */
 
 #define CEL_N_THETA 32
 #define CEL_N_PARAM 27
@@ -74,6 +76,8 @@ typedef int32_t cel_status;
 #define CEL_MAX_PSF 4
 #define CEL_MAX_PROFILE 8
 #define CEL_N_COLOUR_COMPONENTS 8
+#define CEL_MAX_EIGEN 4        /* PSF eigen-images per image (cel_psf_fit)                */
+#define CEL_PSF_MAX_SIDE 63    /* knots per side of a PSF eigen-image                     */
 
 /* One image (Section 2.2, Table 3): band, PSF as a Gaussian mixture in pixels (Section
  * 2.2.3), linear WCS, calibration and a sky knot grid (Section 2.2.1). */
@@ -129,6 +133,11 @@ typedef struct {
   int64_t n_pixels;
   const cel_prior* prior;        /* HOST                                                */
   const cel_profiles* profiles;  /* HOST                                                */
+  const double* patch_psf;       /* HOST [n_patches][CEL_MAX_PSF][6] or NULL: the PSF
+                                    mixture of each patch (a spatially varying PSF,
+                                    Section 2.2.2, e.g. from cel_psf_fit), in the layout
+                                    of cel_image.psf with the n_psf components of the
+                                    patch's image; NULL = every patch uses its image's   */
 } cel_problem;
 
 typedef struct {
@@ -264,6 +273,39 @@ typedef struct {
  * outside [0, n_colours) (n_colours > 0) or a count is negative. */
 cel_status cel_sweep(cel_ctx* ctx, const cel_plan* plan, double* theta, double* radius, int32_t* status,
                      const cel_sweep_opts* opts, cel_sweep_report* report, void* stream);
+
+/* A spatially varying PSF (Section 2.2.2, Table 1): for each image, n_eigen principal
+ * images ("eigen-images") of side x side knots centred on a light source (knot (i, j) at
+ * the offset (j - c, i - c) pixels, c = (side - 1) / 2), and loadings that vary smoothly
+ * over the image: the loading of eigen-image e at pixel position (x, y) of image n is
+ * sum_t coef[n][e][t] m_t with m = (1, u, v, u^2, u v, v^2), u = x / W_n, v = y / H_n.
+ * The PSF at (x, y) is sum_e loading_e eigen_e, negative values clipped to zero. */
+typedef struct {
+  int32_t n_images;
+  int32_t n_eigen;               /* 1..CEL_MAX_EIGEN                                     */
+  int32_t side;                  /* odd, 3..CEL_PSF_MAX_SIDE                             */
+  const double* eigen;           /* DEVICE [n_images][n_eigen][side][side]               */
+  const double* coef;            /* DEVICE [n_images][n_eigen][6]                        */
+  const double* size;            /* DEVICE [n_images][2]: W, H of each image (pixels)    */
+} cel_psf_model;
+
+/* The PSF as a Gaussian mixture (Section 2.2.3: a mixture of bivariate normals keeps a
+ * galaxy's convolution with the PSF analytic) at n_fits positions: fit f takes the PSF of
+ * image fit_img[f] (DEVICE int32 [n_fits]) at pixel position fit_xy[f] (DEVICE float64
+ * [n_fits][2], x = column, y = row) and fits an n_comp-component mixture (1..CEL_MAX_PSF)
+ * to its knot values by n_iter expectation-maximisation iterations with the knot values as
+ * weights, from a start made of the image's moments (every component at the centroid,
+ * component k's covariance the second central moment times 2^(k - (n_comp-1)/2), equal
+ * weights); a component whose weight falls to 1e-12 of the total or below keeps its
+ * parameters.  out: DEVICE float64 [n_fits][CEL_MAX_PSF][6], rows (weight, mean_x, mean_y,
+ * cov_xx, cov_xy, cov_yy) as cel_image.psf with means as offsets from (x, y) and weights
+ * summing to one; rows n_comp.. zero.  All arithmetic float64; one workgroup per fit;
+ * deterministic.  A fit whose image index is out of range gets NaN rows and sets
+ * CEL_DEVERR_BAD_INDEX.  The result feeds cel_problem.patch_psf (the fit at the centre
+ * of each patch).  Asynchronous on `stream`; allocates nothing.
+ * CEL_EINVAL: null pointers with n_fits > 0, bad sizes; CEL_EUNSUPPORTED beyond the limits. */
+cel_status cel_psf_fit(cel_ctx* ctx, const cel_psf_model* model, int32_t n_fits, const int32_t* fit_img,
+                       const double* fit_xy, int32_t n_comp, int32_t n_iter, double* out, void* stream);
 
 /* Measurement: with options.timing = 1, every ELBO / gradient evaluation records HIP events
  * on the caller's stream around its phases.  This returns the summed device milliseconds

@@ -50,10 +50,13 @@ W_COLOUR = torch.tensor([[-1.0, -1.0, 0.0, 0.0],
 
 
 class Model:
-    """The problem's fixed inputs as float64 tensors plus patch-overlap bookkeeping."""
+    """The problem's fixed inputs as float64 tensors plus patch-overlap bookkeeping.
+    patch_psf: optional [P, 4, 6] PSF mixture of each patch (a spatially varying PSF, e.g.
+    oracle.psf.patch_psfs); a source's light in an image then uses its patch's mixture."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, patch_psf=None):
         self.prob = prob
+        self.patch_psf = None if patch_psf is None else torch.as_tensor(np.asarray(patch_psf), dtype=DT)
         self.S = prob.n_sources
         t = lambda a: torch.as_tensor(np.asarray(a), dtype=DT)
         self.band = prob.img_band.astype(np.int64)
@@ -81,8 +84,10 @@ class Model:
         self.pw = prob.patch_w.astype(np.int64)
         self.ph = prob.patch_h.astype(np.int64)
         self.patches_of = [[] for _ in range(self.S)]
+        self.patch_at = {}
         for p, s in enumerate(self.psrc):
             self.patches_of[s].append(p)
+            self.patch_at[(int(s), int(self.pimg[p]))] = p
         # patches whose rectangles intersect, per patch (same image; includes itself)
         self.cover = [None] * len(self.psrc)
         for n in range(len(self.band)):
@@ -97,6 +102,13 @@ class Model:
                 self.cover[p] = ps[np.nonzero(inter[a])[0]]
         self._sky = {}
         self._x = {}
+
+    def psf_for(self, s, n):
+        """PSF mixture [K, 6] of source s in image n: its patch's where given, else the image's."""
+        K = int(self.npsf[n])
+        if self.patch_psf is not None and (int(s), int(n)) in self.patch_at:
+            return self.patch_psf[self.patch_at[(int(s), int(n))], :K]
+        return self.psf[n, :K]
 
     def pixels(self, p):
         if p not in self._x:
@@ -203,8 +215,7 @@ def source_profiles(model, nat, s, n, x0, y0, w, h):
     P = A @ Sig @ A.T                                          # galaxy covariance in pixels
     cols = torch.arange(x0, x0 + w, dtype=DT)
     rows = torch.arange(y0, y0 + h, dtype=DT)
-    K = int(model.npsf[n])
-    psf = model.psf[n, :K]                                     # [K,6]
+    psf = model.psf_for(s, n)                                  # [K,6]
     pw, pmx, pmy = psf[:, 0], psf[:, 1], psf[:, 2]
     pcxx, pcxy, pcyy = psf[:, 3], psf[:, 4], psf[:, 5]
     dx = cols[None, None, :] - (mu[0] + pmx)[:, None, None]     # [K,1,w]

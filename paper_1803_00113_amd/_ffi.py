@@ -19,7 +19,9 @@ N_Z = 16
 CEL_OK, CEL_EINVAL, CEL_ENOMEM, CEL_EHIP, CEL_EUNSUPPORTED, CEL_ESCRATCH = 0, -1, -2, -3, -4, -5
 STATIC_SCRATCH_BYTES = 256 << 20
 ST_SKIPPED, ST_ACCEPTED, ST_REJECTED, ST_CONVERGED, ST_NONFINITE = 0, 1, 2, 3, 4
-DEVERR_NONFINITE_OBJECTIVE, DEVERR_NONFINITE_STEP, DEVERR_NONFINITE_HESSIAN = 1, 2, 4
+DEVERR_NONFINITE_OBJECTIVE, DEVERR_NONFINITE_STEP, DEVERR_NONFINITE_HESSIAN, DEVERR_BAD_INDEX = 1, 2, 4, 8
+MAX_EIGEN = 4
+PSF_MAX_SIDE = 63
 
 
 class CelImage(C.Structure):
@@ -51,7 +53,13 @@ class CelProblem(C.Structure):
     _fields_ = [("n_sources", C.c_int32), ("n_images", C.c_int32), ("n_patches", C.c_int32),
                 ("images", C.POINTER(CelImage)), ("sky_knots", C.POINTER(C.c_double)),
                 ("n_sky_knots", C.c_int64), ("patches", C.POINTER(CelPatch)), ("pixels", C.c_void_p),
-                ("n_pixels", C.c_int64), ("prior", C.POINTER(CelPrior)), ("profiles", C.POINTER(CelProfiles))]
+                ("n_pixels", C.c_int64), ("prior", C.POINTER(CelPrior)), ("profiles", C.POINTER(CelProfiles)),
+                ("patch_psf", C.POINTER(C.c_double))]
+
+
+class CelPsfModel(C.Structure):
+    _fields_ = [("n_images", C.c_int32), ("n_eigen", C.c_int32), ("side", C.c_int32), ("eigen", C.c_void_p),
+                ("coef", C.c_void_p), ("size", C.c_void_p)]
 
 
 class CelOptions(C.Structure):
@@ -97,6 +105,7 @@ _sig = {
     "cel_log_prior": (C.c_int32, [_vp, _vp, C.c_int64, _vp, _vp, _vp]),
     "cel_sweep": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(CelSweepOpts), C.POINTER(CelSweepReport), _vp]),
     "cel_last_device_error": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
+    "cel_psf_fit": (C.c_int32, [_vp, C.POINTER(CelPsfModel), C.c_int32, _vp, _vp, C.c_int32, C.c_int32, _vp, _vp]),
 }
 EXPORTED = tuple(_sig)
 for _name, (_res, _args) in _sig.items():

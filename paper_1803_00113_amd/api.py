@@ -144,6 +144,12 @@ class Plan:
         cp.n_pixels = int(pixels.numel())
         cp.prior = C.pointer(prior)
         cp.profiles = C.pointer(profiles)
+        ppsf = getattr(prob, "patch_psf", None)
+        if ppsf is not None:
+            ppsf = np.ascontiguousarray(ppsf, dtype=np.float64)
+            if ppsf.shape != (cp.n_patches, F.MAX_PSF, 6):
+                raise ValueError(f"patch_psf must be [{cp.n_patches}, {F.MAX_PSF}, 6]")
+            cp.patch_psf = ppsf.ctypes.data_as(C.POINTER(C.c_double))
         h = C.c_void_p()
         with torch.cuda.device(dev):
             st = stream if stream is not None else _stream(dev)
@@ -332,6 +338,39 @@ def sweep(plan: Plan, theta, n_sweeps=3, max_newton_iters=50, use_graph=True, ra
                                          C.byref(rep), _stream(plan.ctx.device)))
     return radius, st, dict(elbo=rep.elbo_total, n_colours=rep.n_colours, n_newton_steps=rep.n_newton_steps,
                             seconds=rep.seconds, sweeps_done=rep.sweeps_done, next_colour=rep.next_colour)
+
+
+def psf_fit_at(ctx: Context, eigen, coef, size, fit_img, fit_xy, n_comp=3, n_iter=30):
+    """cel_psf_fit: Gaussian-mixture fits of spatially varying PSFs.  eigen [N,E,side,side],
+    coef [N,E,6], size [N,2] (W, H), fit_img [n] int, fit_xy [n,2] (host arrays or cuda
+    tensors).  Returns a cuda float64 tensor [n, 4, 6]."""
+    dev = ctx.device
+    as_dev = lambda a, dt: torch.as_tensor(np.asarray(a) if not isinstance(a, torch.Tensor) else a,
+                                           dtype=dt).to(dev).contiguous()
+    eig, cf, sz = as_dev(eigen, torch.float64), as_dev(coef, torch.float64), as_dev(size, torch.float64)
+    fi, fx = as_dev(fit_img, torch.int32), as_dev(fit_xy, torch.float64)
+    if eig.dim() != 4 or eig.shape[2] != eig.shape[3] or cf.shape != (eig.shape[0], eig.shape[1], 6) \
+            or sz.shape != (eig.shape[0], 2) or fx.shape != (fi.shape[0], 2):
+        raise ValueError("psf_fit_at: eigen [N,E,s,s], coef [N,E,6], size [N,2], fit_img [n], fit_xy [n,2]")
+    m = F.CelPsfModel(int(eig.shape[0]), int(eig.shape[1]), int(eig.shape[2]), eig.data_ptr(), cf.data_ptr(),
+                      sz.data_ptr())
+    n = int(fi.shape[0])
+    out = torch.zeros((n, F.MAX_PSF, 6), dtype=torch.float64, device=dev)
+    F.check("cel_psf_fit", F.lib.cel_psf_fit(ctx.h, C.byref(m), n, _ptr(fi), _ptr(fx), int(n_comp), int(n_iter),
+                                             _ptr(out), _stream(dev)))
+    return out
+
+
+def patch_psf_fits(ctx: Context, prob, n_comp=3, n_iter=30):
+    """The PSF mixture of every patch of a problem with eigen-PSFs (prob.psf_eigen,
+    prob.psf_coef): cel_psf_fit at the centre of each patch.  Returns host float64
+    [P, 4, 6], ready for prob.patch_psf."""
+    x = prob.patch_x0 + (prob.patch_w - 1) / 2.0
+    y = prob.patch_y0 + (prob.patch_h - 1) / 2.0
+    size = np.stack([prob.img_W, prob.img_H], 1).astype(np.float64)
+    out = psf_fit_at(ctx, prob.psf_eigen, prob.psf_coef, size, prob.patch_img.astype(np.int32),
+                     np.stack([x, y], 1), n_comp, n_iter)
+    return out.cpu().numpy()
 
 
 def last_device_error(ctx: Context):

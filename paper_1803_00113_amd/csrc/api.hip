@@ -141,6 +141,14 @@ static cel_status validate(const cel_problem* pr) {
   for (int p = 0; p < pr->n_patches; ++p) {
     const cel_patch& q = pr->patches[p];
     if (q.src < 0 || q.src >= pr->n_sources || q.img < 0 || q.img >= pr->n_images) return CEL_EINVAL;
+    if (pr->patch_psf) {   // the patch's own PSF mixture: as an image's
+      for (int k = 0; k < pr->images[q.img].n_psf; ++k) {
+        const double* c = pr->patch_psf + ((int64_t)p * kMaxPsf + k) * 6;
+        for (int i = 0; i < 6; ++i)
+          if (!finite(c[i])) return CEL_EINVAL;
+        if (c[0] < 0 || !(c[3] > 0) || !(c[3] * c[5] - c[4] * c[4] > 0)) return CEL_EINVAL;
+      }
+    }
     if (q.w < 1 || q.h < 1) return CEL_EINVAL;
     if ((int64_t)q.w * q.h > (int64_t(1) << 22)) return CEL_EUNSUPPORTED;
     const cel_image& im = pr->images[q.img];
@@ -824,6 +832,11 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   pk.add(&p->d_htau_d, p->htau_dh);
   pk.add(&d_user_off, user_off);
   pk.add(&d_knots, knots);
+  std::vector<double> ppsf;
+  if (pr->patch_psf && P > 0) {
+    ppsf.assign(pr->patch_psf, pr->patch_psf + (size_t)P * kMaxPsf * 6);
+    pk.add(&p->d_patch_psf, ppsf);
+  }
   // per-source active pixel counts and colours (read by the Newton steps)
   std::vector<double> npix(std::max(S, 1), 0.0);
   for (int i = 0; i < P; ++i) npix[p->patches_h[i].src] += (double)p->patches_h[i].w * p->patches_h[i].h;
@@ -919,6 +932,7 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   pa.trial_variant = p->trial_variant;
   pa.fd = point ? 0 : p->fd_mode;
   pa.sky_min = p->d_skymin;
+  pa.patch_psf = p->d_patch_psf;
   pa.theta_vstride = theta_vstride;
   phase_mark(p, 0, sm);
   if (prep_base) {   // variant 0 of every source and its moment maps (neighbours read these)
@@ -1020,6 +1034,7 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
   pa.trial_variant = p->trial_variant;
   pa.fd = p->fd_mode;
   pa.sky_min = p->d_skymin;
+  pa.patch_psf = p->d_patch_psf;
   hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
   if (e == hipSuccess) e = launch_maps_t<T>(p, tables, sm);
   FusedArgs<T> fa;
@@ -1088,6 +1103,7 @@ static hipError_t prep_base_t(cel_plan* p, const double* theta, hipStream_t sm) 
   pa.trial_variant = p->trial_variant;
   pa.fd = p->fd_mode;
   pa.sky_min = p->d_skymin;
+  pa.patch_psf = p->d_patch_psf;
   hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
   if (e == hipSuccess) e = launch_maps_t<T>(p, tables, sm);
   return e;
@@ -1115,6 +1131,7 @@ static hipError_t prep_class_t(cel_plan* p, const double* theta, int cls, const 
   pa.trial_variant = p->trial_variant;
   pa.fd = p->fd_mode;
   pa.sky_min = p->d_skymin;
+  pa.patch_psf = p->d_patch_psf;
   return launch_prep_tables<T>(pa, np, 1, sm);
 }
 

@@ -21,6 +21,7 @@ struct PrepArgs {
   int32_t fd;                  // variants 1..54 are central-difference points
   const double* sky_min;       // per patch: smallest sky value (component cut)
   int64_t theta_vstride;       // > 0: variant v reads theta + v * theta_vstride (per-variant points)
+  const double* patch_psf;     // [P][kMaxPsf][6] per-patch PSF mixtures (null: the image's)
 };
 
 struct FinalizeArgs {

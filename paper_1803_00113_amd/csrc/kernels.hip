@@ -86,6 +86,9 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
   const double t10 = a10 * sig[0] + a11 * sig[1], t11 = a10 * sig[1] + a11 * sig[2];
   const double Sxx = t00 * a00 + t01 * a01, Sxy = t00 * a10 + t01 * a11, Syy = t10 * a10 + t11 * a11;
   const int K = im.n_psf;
+  // the PSF mixture of this patch: its own where the PSF varies over the image
+  const double(*psf)[6] = a.patch_psf ? reinterpret_cast<const double(*)[6]>(a.patch_psf + (int64_t)pi_ * kMaxPsf * 6)
+                                      : im.psf;
   // flux moments given the type (equation conditional): log l ~ N(m, v)
   const double aa = ex[11];
   const double w[2] = {1.0 - aa, aa};
@@ -147,9 +150,9 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
       const int pj = isdev ? a.prof->n_exp + jj : jj;
       tau = star ? 0.0 : a.prof->tau[pj];
       const double alpha = star ? 1.0 : a.prof->alpha[pj];
-      const double cxx = im.psf[k][3] + tau * Sxx, cxy = im.psf[k][4] + tau * Sxy, cyy = im.psf[k][5] + tau * Syy;
+      const double cxx = psf[k][3] + tau * Sxx, cxy = psf[k][4] + tau * Sxy, cyy = psf[k][5] + tau * Syy;
       const double det = cxx * cyy - cxy * cxy, rdet = 1.0 / det;
-      const double wt = im.psf[k][0] * alpha;
+      const double wt = psf[k][0] * alpha;
       Pxx = cyy * rdet;
       Pxy = -cxy * rdet;
       Pyy = cxx * rdet;
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
     const T pv[3] = {(T)Pxx, (T)Pxy, (T)Pyy};
     if (star) {
       T* r = tb->star[k];
-      const double ox = used ? im.psf[k][1] : 0.0, oy = used ? im.psf[k][2] : 0.0;
+      const double ox = used ? psf[k][1] : 0.0, oy = used ? psf[k][2] : 0.0;
       r[0] = (T)(used ? mux + ox : 0.0);
       r[1] = (T)(used ? muy + oy : 0.0);
       r[2] = pv[0];

@@ -78,6 +78,7 @@ struct cel_plan {
   double2* d_maps64 = nullptr;
   double* d_pixconst = nullptr;
   double* d_skymin = nullptr;     // per patch: smallest sky value
+  double* d_patch_psf = nullptr;  // per patch PSF mixtures [P][kMaxPsf][6] (null: the image's)
   int32_t* d_err = nullptr;       // the context's condition word
   double* d_total = nullptr;
   std::vector<int32_t*> d_class_patches, d_class_tasks, d_class_src;

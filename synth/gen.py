@@ -94,6 +94,10 @@ class Problem:
     theta0: np.ndarray
     truth: dict = field(default_factory=dict)
     name: str = ""
+    # spatially varying PSF (None: each image's PSF is img_psf everywhere): eigen-images
+    # [N, E, 51, 51] and quadratic loading coefficients [N, E, 6] per image
+    psf_eigen: np.ndarray = None
+    psf_coef: np.ndarray = None
 
     @property
     def n_images(self):
@@ -198,6 +202,68 @@ def _psf_offsets(rng, n, psf, npsf):
     return out
 
 
+def psf_true_at(img, x, y):
+    """The image's true PSF mixture at pixel position (x, y) when it varies over the frame
+    (Section 2.2.2: the PSF has smooth spatial variation): each component's covariance is
+    scaled by (1 + a u + b v + c u v)^2 and sheared, its mean shifted, u = x/W - 1/2,
+    v = y/H - 1/2, with per-component drift coefficients drawn by the generator."""
+    K = img["npsf"]
+    out = np.array(img["psf"], dtype=np.float64).copy()
+    u, v = x / img["W"] - 0.5, y / img["H"] - 0.5
+    for k in range(K):
+        d = img["psf_drift"][k]
+        sc = (1.0 + d[0] * u + d[1] * v + d[2] * u * v) ** 2
+        cxx, cxy, cyy = out[k, 3] * sc, out[k, 4] * sc, out[k, 5] * sc
+        cxy += d[3] * u * math.sqrt(cxx * cyy)
+        out[k, 3], out[k, 4], out[k, 5] = cxx, cxy, cyy
+        out[k, 1] += d[4] * v
+        out[k, 2] += d[5] * u
+    return out
+
+
+PSF_SIDE = 51         # knots per side of a PSF eigen-image (Table 1: F = 51 x 51)
+N_EIGEN = 4           # eigen-images per image (Table 1: E = 4)
+PSF_LOADING_TERMS = 6  # loadings are quadratic in position: 1, u, v, u^2, u v, v^2
+
+
+def loading_monomials(img, x, y):
+    """Monomials of the loading polynomial at pixel position (x, y), u = x/W, v = y/H."""
+    u, v = x / img["W"], y / img["H"]
+    return np.array([1.0, u, v, u * u, u * v, v * v])
+
+
+def eigen_psf(rng, img, grid=5, photons=400_000, side=PSF_SIDE, n_eigen=N_EIGEN):
+    """Stand-in for the survey's PSF preprocessing (Section 2.2.2: the PSF is fitted by
+    pre-existing software and represented by the top principal components of the PSF
+    rendered on a grid centred on a source, with loadings that vary smoothly over the
+    image).  The PSF is rendered at a grid x grid set of positions by histogramming photon
+    offsets drawn from the true PSF there (binned to the nearest pixel, the centre at the
+    middle knot), the images' top principal components (uncentred, by SVD) are the
+    eigen-images, and each loading is fitted by least squares as a quadratic in position.
+    Returns (eigen [E, side, side], coefficients [E, 6])."""
+    H, W = img["H"], img["W"]
+    xs = np.linspace(0.05 * W, 0.95 * W, grid)
+    ys = np.linspace(0.05 * H, 0.95 * H, grid)
+    half = side // 2
+    rows, mons = [], []
+    for y in ys:
+        for x in xs:
+            off = _psf_offsets(rng, photons, psf_true_at(img, x, y), img["npsf"])
+            c = np.rint(off[:, 0]).astype(np.int64) + half
+            r = np.rint(off[:, 1]).astype(np.int64) + half
+            ok = (c >= 0) & (c < side) & (r >= 0) & (r < side)
+            im = np.zeros((side, side))
+            np.add.at(im, (r[ok], c[ok]), 1.0)
+            rows.append(im.ravel() / photons)
+            mons.append(loading_monomials(img, x, y))
+    X, Mo = np.array(rows), np.array(mons)
+    U, S, Vt = np.linalg.svd(X, full_matrices=False)
+    eig = Vt[:n_eigen]
+    load = U[:, :n_eigen] * S[:n_eigen]
+    coef = np.linalg.lstsq(Mo, load, rcond=None)[0].T        # [E, 6]
+    return eig.reshape(n_eigen, side, side), coef
+
+
 def render(rng, img, canvas, sources, profiles):
     """Counts on a canvas (y0, x0, h, w) of image `img` from skyglow and the given sources."""
     y0, x0, h, w = canvas
@@ -216,7 +282,9 @@ def render(rng, img, canvas, sources, profiles):
         else:
             off = _galaxy_offsets(rng, n, src, profiles)
         pos = src["u"][None, :] + off
-        pix = pos @ A.T + b[None, :] + _psf_offsets(rng, n, img["psf"], img["npsf"])
+        pix = pos @ A.T + b[None, :]
+        psf = psf_true_at(img, *(A @ src["u"] + b)) if "psf_drift" in img else img["psf"]
+        pix = pix + _psf_offsets(rng, n, psf, img["npsf"])
         c = np.rint(pix[:, 0]).astype(np.int64) - x0
         r = np.rint(pix[:, 1]).astype(np.int64) - y0
         ok = (c >= 0) & (c < w) & (r >= 0) & (r < h)
@@ -323,6 +391,10 @@ def _assemble(name, images, sources, patch_rects, pixel_lists, prior, profiles, 
                  angle=np.array([s["angle"] for s in sources]))
     if extra:
         truth.update(extra)
+    eig = coef = None
+    if images and "eigen" in images[0]:
+        eig = np.array([im["eigen"] for im in images], np.float64)
+        coef = np.array([im["eigen_coef"] for im in images], np.float64)
     return Problem(
         n_sources=len(sources),
         img_band=np.array([im["band"] for im in images], np.int32),
@@ -347,7 +419,7 @@ def _assemble(name, images, sources, patch_rects, pixel_lists, prior, profiles, 
         prior_axis=prior["prior_axis"],
         exp_alpha=exp_a, exp_tau=exp_t, dev_alpha=dev_a, dev_tau=dev_t,
         theta0=np.array(theta0, np.float64).reshape(len(sources), N_THETA),
-        truth=truth, name=name)
+        truth=truth, name=name, psf_eigen=eig, psf_coef=coef)
 
 
 def _image(rng, band, H, W, sky0, A=None, b=None, sky_grad=0.0, qh=2, qw=2, npsf=3, iota=1.0, psf=None,
@@ -545,7 +617,21 @@ def _extent_halfwidth(src, psf_sigma_max):
     return int(np.clip(math.ceil(size * grow), 8, 48))
 
 
-def config4(seed=SEED_BASE + 4, n_sources=600, H=2048, W=1489, n_epochs=3):
+def _drifting_psf(rng, img):
+    """Give an image a PSF that drifts over the frame and its eigen-PSF representation."""
+    K = img["npsf"]
+    img["psf_drift"] = np.column_stack([rng.uniform(-0.25, 0.25, K), rng.uniform(-0.25, 0.25, K),
+                                        rng.uniform(-0.2, 0.2, K), rng.uniform(-0.3, 0.3, K),
+                                        rng.uniform(-0.4, 0.4, K), rng.uniform(-0.4, 0.4, K)])
+    img["eigen"], img["eigen_coef"] = eigen_psf(rng, img)
+
+
+def config4(seed=SEED_BASE + 4, n_sources=600, H=2048, W=1489, n_epochs=3, bands=None, eigen=False, sky_q=None,
+            name=None):
+    """The field workload.  eigen: each image's PSF drifts over the frame and is given as
+    E = 4 eigen-images with quadratic loadings (Section 2.2.2); sky_q = (qh, qw): a knot
+    grid of that size sampling a sky field with curvature (Section 2.2.1; Table 1 gives
+    Q = 192 x 256)."""
     rng = np.random.default_rng(seed)
     profiles = load_profiles()
     prior = make_prior(rng, star_prob=0.3)
@@ -557,9 +643,12 @@ def config4(seed=SEED_BASE + 4, n_sources=600, H=2048, W=1489, n_epochs=3):
             ang = math.radians(rng.uniform(-0.3, 0.3))
             A = np.array([[math.cos(ang), -math.sin(ang)], [math.sin(ang), math.cos(ang)]])
             b = rng.uniform(-20, 20, 2)
-        for band in range(N_BANDS):
-            images.append(_image(rng, band, H, W, rng.uniform(50, 200), A=A, b=b, sky_grad=0.005))
-    margin = 70
+        for band in (range(N_BANDS) if bands is None else bands):
+            kw = {} if sky_q is None else dict(qh=sky_q[0], qw=sky_q[1], sky_wave=0.2)
+            images.append(_image(rng, band, H, W, rng.uniform(50, 200), A=A, b=b, sky_grad=0.005, **kw))
+            if eigen:
+                _drifting_psf(rng, images[-1])
+    margin = min(70, H // 4, W // 4)
     sources = []
     for _ in range(n_sources):
         u = np.array([rng.uniform(margin, W - margin), rng.uniform(margin, H - margin)])
@@ -578,8 +667,22 @@ def config4(seed=SEED_BASE + 4, n_sources=600, H=2048, W=1489, n_epochs=3):
                 rects.append((s, n, x0, y0, x1 - x0, y1 - y0))
     frames = [render(rng, images[n], (0, 0, H, W), sources, profiles) for n in range(len(images))]
     pix = [frames[n][y0:y0 + h, x0:x0 + w] for (s, n, x0, y0, w, h) in rects]
-    return _assemble(f"field_{n_sources}src_{H}x{W}_5bx{n_epochs}e", images, sources, rects, pix,
-                     prior, profiles, theta0)
+    name = name or f"field_{n_sources}src_{H}x{W}_{len(images) // n_epochs}bx{n_epochs}e"
+    return _assemble(name, images, sources, rects, pix, prior, profiles, theta0)
+
+
+def config_eigen(seed=SEED_BASE + 7, n_sources=600, H=2048, W=1489):
+    """The field workload with a spatially varying PSF given by eigen-images (E = 4 on
+    51 x 51 knots, quadratic loadings) and a 192 x 256 sky knot grid (Table 1)."""
+    return config4(seed=seed, n_sources=n_sources, H=H, W=W, eigen=True, sky_q=(192, 256),
+                   name=f"field_eigenpsf_{n_sources}src_{H}x{W}_5bx3e_sky192x256")
+
+
+def config_eigen_small(seed=SEED_BASE + 8):
+    """A small field with a drifting PSF: 14 sources on 300 x 260 pixels, bands g and r over
+    two epochs, a 24 x 32 sky knot grid."""
+    return config4(seed=seed, n_sources=14, H=300, W=260, n_epochs=2, bands=(1, 2), eigen=True, sky_q=(24, 32),
+                   name="field_eigenpsf_14src_300x260_2bx2e_sky24x32")
 
 
 def truth_point(prob):
@@ -663,7 +766,9 @@ def subset(prob, sources=None, images=None, name=None):
         prior_ccov=prob.prior_ccov, prior_radius=prob.prior_radius, prior_profile=prob.prior_profile,
         prior_axis=prob.prior_axis, exp_alpha=prob.exp_alpha, exp_tau=prob.exp_tau,
         dev_alpha=prob.dev_alpha, dev_tau=prob.dev_tau, theta0=prob.theta0[src].copy(), truth=truth,
-        name=name or (prob.name + "_subset"))
+        name=name or (prob.name + "_subset"),
+        psf_eigen=None if prob.psf_eigen is None else prob.psf_eigen[img],
+        psf_coef=None if prob.psf_coef is None else prob.psf_coef[img])
 
 
 def crop_patches(prob, max_side, name=None):

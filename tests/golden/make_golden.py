@@ -18,6 +18,9 @@ the generator still produces the same inputs.
                 initial point, its global ELBO, and one oracle Newton step (with its local
                 model g, H, p, predicted gain) for the first 48 sources of colour class 0
   config4_sweep config4_sweep.npz: three oracle sweeps of the field (float64)
+  eigen         eigen_oracle.npz: the field with a spatially varying PSF (E = 4 eigen-
+                images of 51 x 51 knots) and a 192 x 256 sky knot grid: the oracle's PSF
+                fit of every patch, every L_s and gradient and the global ELBO
 
 Run from the repository root:  python -m tests.golden.make_golden NAME [NAME ...]
 (per-source work runs in a process pool; CEL_GOLDEN_PROCS sets its size, default 8).
@@ -33,6 +36,7 @@ import torch
 
 from oracle import elbo as E
 from oracle import newton as NW
+from oracle import psf as OP
 from synth import gen
 from tests.golden.inputs_hash import inputs_hash
 
@@ -214,8 +218,39 @@ def make_config4_sweep(n_sweeps=3, max_iter=50):
           n_steps=np.array(n_steps), n_sweeps=np.array(n_sweeps), max_iter=np.array(max_iter))
 
 
+def _fit_patch(p):
+    prob = _M.prob
+    n = int(prob.patch_img[p])
+    x = prob.patch_x0[p] + (prob.patch_w[p] - 1) / 2.0
+    y = prob.patch_y0[p] + (prob.patch_h[p] - 1) / 2.0
+    img = OP.psf_image(prob.psf_eigen[n], prob.psf_coef[n], float(prob.img_W[n]), float(prob.img_H[n]), x, y)
+    return OP.fit_mixture(img, EIGEN_K, EIGEN_ITER)
+
+
+EIGEN_K, EIGEN_ITER = 3, 30
+
+
+def make_eigen():
+    """The field workload with a spatially varying PSF (eigen-images) and a 192 x 256 sky
+    grid: the oracle's PSF fit of every patch (3 components, 30 iterations), then every L_s
+    and gradient and the global ELBO with those PSFs."""
+    global _M
+    prob = gen.config_eigen()
+    _M = E.Model(prob)
+    with _pool() as pool:
+        fits = pool.map(_fit_patch, range(prob.n_patches), chunksize=16)
+    psf = np.zeros((prob.n_patches, OP.MAX_PSF, 6))
+    psf[:, :EIGEN_K] = np.array(fits)
+    _M = E.Model(prob, patch_psf=psf)
+    with _pool() as pool:
+        loc, g = _all_value_grad(pool, prob.n_sources)
+        total = _global_elbo(pool, prob.n_sources)
+    _save("eigen_oracle.npz", prob, patch_psf=psf, psf_k=np.array(EIGEN_K), psf_iter=np.array(EIGEN_ITER),
+          elbo_total=np.array(total), elbo_local=loc, grad=g)
+
+
 MAKERS = dict(config1=make_config1, skew_sweep=make_skew_sweep, config2=make_config2, config3=make_config3,
-              config4=make_config4, config4_sweep=make_config4_sweep)
+              config4=make_config4, config4_sweep=make_config4_sweep, eigen=make_eigen)
 
 if __name__ == "__main__":
     for name in sys.argv[1:] or ["config1"]:
