@@ -346,6 +346,58 @@ cel_status cel_phase_times(cel_plan* plan, double* ms, int64_t* n_calls, int32_t
 cel_status cel_loglik(cel_ctx* ctx, const cel_plan* plan, const double* z_fixed, int32_t n_cand,
                       const double* z_cand, const uint8_t* mask, double* ll, void* stream);
 
+/* Options of cel_mcmc_step (Section 3).  Defaults of the paper's runs: n_temps = T = 200,
+ * n_runs = N' = 25, n_post = B' = 25. */
+typedef struct {
+  int32_t n_temps;               /* T: annealing temperatures (>= 1)                     */
+  int32_t n_runs;                /* N': runs per source type (1..28)                     */
+  int32_t n_post;                /* B': slice-sampling sweeps at the target per run (>= 1) */
+  int32_t max_step_out;          /* m: the stepping-out interval grows at most m-1 times  */
+  int32_t max_shrink;            /* shrinkage draws before an update keeps its point      */
+  const double* gamma;           /* HOST [n_temps + 1]: gamma_0 = 0 < ... < gamma_T = 1   */
+  double width[CEL_Z_N];         /* slice width per point coordinate (layout of cel_loglik) */
+  double box;                    /* half-width (pixels) of the position's uniform prior
+                                    around z_fixed's position                            */
+  uint64_t seed;                 /* first word of the random generator's key              */
+} cel_mcmc_opts;
+
+typedef struct {
+  int64_t rounds;                /* lockstep rounds of candidate evaluations              */
+  int64_t n_chains;              /* 2 n_runs per selected source                          */
+  int64_t evaluations;           /* candidate log targets evaluated by the chains         */
+  int64_t candidate_pixels;      /* sum over evaluations of the source's active pixels    */
+} cel_mcmc_report;
+
+/* One MCMC update of every selected source (Section 3, equation eqzs: each source sampled
+ * from p(z_s | x, z_-s) with every other source at z_fixed; selected sources that do not
+ * overlap are conditionally independent, so a colour class updated at once equals updating
+ * its members in turn).  Per source and type a (0 galaxy, 1 star): n_runs annealed
+ * importance sampling runs (Section 3.1) from the start points z_init (draws from the prior
+ * pi_0 = p(w | a), made by the caller) through pi_t = p(w | a) p(x | w, a, z_-s)^gamma_t,
+ * each transition one slice-sampling-within-Gibbs sweep over the type's coordinates (u,
+ * log r, colours; a galaxy also angle, log radius, profile weight, axis ratio; univariate
+ * slice sampling with stepping out and shrinkage), the run's log weight
+ * sum_t (gamma_t - gamma_{t-1}) log p(x | w^(t-1)); then n_post further sweeps at the target
+ * (Section 3.2), each leaving one sample.  p(a = 1 | x, z_-s) by Bayes' rule from the prior
+ * probability of a star and the mean weights; a type is drawn from it, then one of its
+ * n_runs x n_post samples uniformly.  Likelihood as cel_loglik (exact Poisson, pixels of
+ * the source's patches), prior as cel_log_prior plus the position's uniform prior on the
+ * box (a constant, left out); the angle is periodic (an accepted angle is mapped to
+ * [0, pi)).  Random numbers: Philox4x64-10 with key (seed, key) at counters fixed by
+ * (chain, sweep, coordinate, draw), so results do not depend on launch configuration.
+ * z_fixed: DEVICE [S][16]; mask: HOST uint8 [S] (NULL = all); z_init: DEVICE
+ * [2][n_runs][S][16] (type 0 rows first); z_out: DEVICE [S][16] (the new point of each
+ * selected source); p_star: DEVICE [S]; log_evidence: DEVICE [S][2] (log of the mean
+ * weight per type); samples: DEVICE [S][2][n_runs][n_post][16] or NULL; rows of
+ * unselected sources untouched.  report: HOST or NULL.  Pixel precision as the context's
+ * pixel_fp64 option.  Synchronous (the host polls the chains every 16 rounds).  Allocates
+ * its scratch on the plan at first use.
+ * CEL_EINVAL: null pointers, bad options (gamma NULL, n_runs > 28, negative widths). */
+cel_status cel_mcmc_step(cel_ctx* ctx, const cel_plan* plan, const double* z_fixed, const uint8_t* mask,
+                         const double* z_init, const cel_mcmc_opts* opts, uint64_t key, double* z_out,
+                         double* p_star, double* log_evidence, double* samples, cel_mcmc_report* report,
+                         void* stream);
+
 /* Log prior density log p(w | a) of n point values (the start distribution pi_0 of the
  * annealed importance sampler, Section 3.1; the priors of Section 2.1), over the point
  * layout's coordinates (see cel_loglik): log r ~ normal(prior mean, variance of the type),

@@ -69,6 +69,17 @@ class CelOptions(C.Structure):
                 ("radius_min", C.c_double), ("timing", C.c_int32)]
 
 
+class CelMcmcOpts(C.Structure):
+    _fields_ = [("n_temps", C.c_int32), ("n_runs", C.c_int32), ("n_post", C.c_int32), ("max_step_out", C.c_int32),
+                ("max_shrink", C.c_int32), ("gamma", C.POINTER(C.c_double)), ("width", C.c_double * N_Z),
+                ("box", C.c_double), ("seed", C.c_uint64)]
+
+
+class CelMcmcReport(C.Structure):
+    _fields_ = [("rounds", C.c_int64), ("n_chains", C.c_int64), ("evaluations", C.c_int64),
+                ("candidate_pixels", C.c_int64)]
+
+
 class CelSweepOpts(C.Structure):
     _fields_ = [("n_sweeps", C.c_int32), ("max_newton_iters", C.c_int32), ("use_graph", C.c_int32),
                 ("start_colour", C.c_int32), ("max_classes", C.c_int32)]
@@ -105,6 +116,8 @@ _sig = {
     "cel_log_prior": (C.c_int32, [_vp, _vp, C.c_int64, _vp, _vp, _vp]),
     "cel_sweep": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(CelSweepOpts), C.POINTER(CelSweepReport), _vp]),
     "cel_last_device_error": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
+    "cel_mcmc_step": (C.c_int32, [_vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, C.POINTER(CelMcmcOpts), C.c_uint64, _vp,
+                                  _vp, _vp, _vp, C.POINTER(CelMcmcReport), _vp]),
     "cel_psf_fit": (C.c_int32, [_vp, C.POINTER(CelPsfModel), C.c_int32, _vp, _vp, C.c_int32, C.c_int32, _vp, _vp]),
 }
 EXPORTED = tuple(_sig)

@@ -302,6 +302,45 @@ def loglik(plan: Plan, z_fixed, z_cand, mask=None):
     return ll
 
 
+def mcmc_step(plan: Plan, z_fixed, z_init, opts, key, mask=None, want_samples=False):
+    """cel_mcmc_step: one MCMC update of the selected sources (annealed importance sampling
+    with slice-sampling-within-Gibbs transitions, then further chains and the type draw).
+    z_fixed [S,16] and z_init [2,N',S,16] cuda float64 tensors; opts: dict with n_temps,
+    n_runs, n_post, max_step_out, max_shrink, gamma (host sequence of n_temps + 1), width
+    (16 per-coordinate slice widths), box, seed; key: the generator key's second word.
+    Returns dict(z [S,16], p_star [S], log_evidence [S,2], samples [S,2,N',B',16] or None,
+    report)."""
+    for t in (z_fixed, z_init):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("z_fixed / z_init must be contiguous cuda float64 tensors")
+    Np, Bp, T = int(opts["n_runs"]), int(opts["n_post"]), int(opts["n_temps"])
+    if tuple(z_fixed.shape) != (plan.S, F.N_Z) or tuple(z_init.shape) != (2, Np, plan.S, F.N_Z):
+        raise ValueError("z_fixed must be [S,16] and z_init [2,n_runs,S,16]")
+    gam = np.ascontiguousarray(np.asarray(opts["gamma"], dtype=np.float64))
+    if gam.shape != (T + 1,):
+        raise ValueError("gamma must hold n_temps + 1 temperatures")
+    o = F.CelMcmcOpts()
+    o.n_temps, o.n_runs, o.n_post = T, Np, Bp
+    o.max_step_out, o.max_shrink = int(opts["max_step_out"]), int(opts["max_shrink"])
+    o.gamma = gam.ctypes.data_as(C.POINTER(C.c_double))
+    for k in range(F.N_Z):
+        o.width[k] = float(opts["width"][k]) if k < len(opts["width"]) else 0.0
+    o.box, o.seed = float(opts["box"]), int(opts["seed"])
+    dev = plan.ctx.device
+    z_out = z_fixed.clone()
+    p_star = torch.full((plan.S,), float("nan"), dtype=torch.float64, device=dev)
+    log_ev = torch.full((plan.S, 2), float("nan"), dtype=torch.float64, device=dev)
+    smp = torch.zeros((plan.S, 2, Np, Bp, F.N_Z), dtype=torch.float64, device=dev) if want_samples else None
+    rep = F.CelMcmcReport()
+    keep, m = _mask(plan, mask)
+    F.check("cel_mcmc_step", F.lib.cel_mcmc_step(plan.ctx.h, plan.h, _ptr(z_fixed), m, _ptr(z_init), C.byref(o),
+                                                 int(key), _ptr(z_out), _ptr(p_star), _ptr(log_ev), _ptr(smp),
+                                                 C.byref(rep), _stream(dev)))
+    return dict(z=z_out, p_star=p_star, log_evidence=log_ev, samples=smp,
+                report=dict(rounds=rep.rounds, n_chains=rep.n_chains, evaluations=rep.evaluations,
+                            candidate_pixels=rep.candidate_pixels))
+
+
 def log_prior(plan: Plan, z):
     """cel_log_prior: log p(w | a) of point values z [..., 16] (contiguous cuda float64);
     returns a tensor of z's leading shape."""

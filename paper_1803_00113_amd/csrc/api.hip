@@ -1270,17 +1270,11 @@ extern "C" cel_status cel_elbo_grad_plain(cel_ctx* ctx, const cel_plan* cplan, c
 // Exact Poisson log-likelihood at point values (Section 3.1's target p(x | w_s, a_s, z_{-s})):
 // the other sources at z_fixed give the neighbour maps once; each chunk of candidates is a
 // set of variants of the objective's pixel pass over the selected sources' work items.
-extern "C" cel_status cel_loglik(cel_ctx* ctx, const cel_plan* cplan, const double* z_fixed, int32_t n_cand,
-                                 const double* z_cand, const uint8_t* mask, double* ll, void* stream) {
-  if (!ctx || !cplan || n_cand < 0) return CEL_EINVAL;
-  cel_plan* p = const_cast<cel_plan*>(cplan);
-  if (p->S > 0 && n_cand > 0 && (!z_fixed || !z_cand || !ll)) return CEL_EINVAL;
-  if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
-  if (p->S == 0 || n_cand == 0) return CEL_OK;
-  hipStream_t sm = (hipStream_t)stream;
+namespace celmi {
+
+cel_status point_setup(cel_plan* p, const double* z_fixed, const std::vector<uint8_t>& m, int chunk, hipStream_t sm) {
   const bool fp64 = p->opt.pixel_fp64 != 0;
   const int S = p->S;
-  const int chunk = std::min<int>(n_cand, kVariants);
   cel_status st = ensure_variants(p, chunk, fp64);
   if (st == CEL_OK) st = ensure_newton(p);
   if (st == CEL_OK && p->pt_cap < chunk) {
@@ -1290,19 +1284,20 @@ extern "C" cel_status cel_loglik(cel_ctx* ctx, const cel_plan* cplan, const doub
     p->pt_cap = chunk;
   }
   if (st) return st;
-  std::vector<uint8_t> m(S, 1);
-  if (mask)
-    for (int s = 0; s < S; ++s) m[s] = mask[s] ? 1 : 0;
-  bool any = false;
-  for (int s = 0; s < S; ++s) any = any || m[s];
-  if (!any) return CEL_OK;
-  const int cls = p->n_colours;   // the selection, staged as the step class
-  hipError_t e = stage_selection(p, m, true, sm);
-  double* th_base = p->d_pt_theta;
+  hipError_t e = stage_selection(p, m, true, sm);   // the selection, staged as the step class
+  if (e == hipSuccess) e = launch_point_theta(z_fixed, S, p->d_pt_theta, nullptr, sm);
+  if (e == hipSuccess) e = prep_base(p, p->d_pt_theta, sm, fp64);
+  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+}
+
+hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* ll, hipStream_t sm) {
+  const bool fp64 = p->opt.pixel_fp64 != 0;
+  const int S = p->S;
+  const int chunk = p->pt_cap;
+  const int cls = p->n_colours;
   double* th_cand = p->d_pt_theta + (int64_t)S * kThetaN;
   const int64_t row = (int64_t)S * kThetaN;
-  if (e == hipSuccess) e = launch_point_theta(z_fixed, S, th_base, nullptr, sm);
-  if (e == hipSuccess) e = prep_base(p, th_base, sm, fp64);
+  hipError_t e = hipSuccess;
   for (int c0 = 0; c0 < n_cand && e == hipSuccess; c0 += chunk) {
     const int nc = std::min(chunk, n_cand - c0);
     e = launch_point_theta(z_cand + (int64_t)c0 * S * CEL_Z_N, (int64_t)nc * S, th_cand, p->d_pt_ok, sm);
@@ -1312,7 +1307,29 @@ extern "C" cel_status cel_loglik(cel_ctx* ctx, const cel_plan* cplan, const doub
              : enqueue_eval<float>(p, th_cand, nullptr, 0, nc, false, cls, nullptr, sm, false, out, nullptr, row);
     if (e == hipSuccess) e = launch_support_masked(p->d_pt_ok, p->d_mask, S, (int64_t)nc * S, out, sm);
   }
-  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+  return e;
+}
+
+}  // namespace celmi
+
+extern "C" cel_status cel_loglik(cel_ctx* ctx, const cel_plan* cplan, const double* z_fixed, int32_t n_cand,
+                                 const double* z_cand, const uint8_t* mask, double* ll, void* stream) {
+  if (!ctx || !cplan || n_cand < 0) return CEL_EINVAL;
+  cel_plan* p = const_cast<cel_plan*>(cplan);
+  if (p->S > 0 && n_cand > 0 && (!z_fixed || !z_cand || !ll)) return CEL_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
+  if (p->S == 0 || n_cand == 0) return CEL_OK;
+  hipStream_t sm = (hipStream_t)stream;
+  const int S = p->S;
+  std::vector<uint8_t> m(S, 1);
+  if (mask)
+    for (int s = 0; s < S; ++s) m[s] = mask[s] ? 1 : 0;
+  bool any = false;
+  for (int s = 0; s < S; ++s) any = any || m[s];
+  if (!any) return CEL_OK;
+  cel_status st = point_setup(p, z_fixed, m, std::min<int>(n_cand, kVariants), sm);
+  if (st) return st;
+  return point_loglik(p, n_cand, z_cand, ll, sm) == hipSuccess ? CEL_OK : CEL_EHIP;
 }
 
 extern "C" cel_status cel_log_prior(cel_ctx* ctx, const cel_plan* plan, int64_t n, const double* z, double* out,

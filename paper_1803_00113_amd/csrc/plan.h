@@ -130,6 +130,15 @@ struct cel_plan {
   double* d_pt_theta = nullptr;
   uint8_t* d_pt_ok = nullptr;
   int pt_cap = 0;
+  // MCMC source step scratch (grow-only): chain records (bytes), candidate rows, their log
+  // likelihoods and log priors, selection + mask + counter words, samples, temperatures
+  char* mc_chains = nullptr;
+  double* mc_cand = nullptr;
+  double* mc_vals = nullptr;
+  int32_t* mc_sel = nullptr;
+  double* mc_samples = nullptr;
+  double* mc_gamma = nullptr;
+  size_t mc_chains_cap = 0, mc_cand_cap = 0, mc_vals_cap = 0, mc_sel_cap = 0, mc_samples_cap = 0, mc_gamma_cap = 0;
   struct Block {
     void* ptr;
     size_t bytes;
@@ -174,4 +183,9 @@ cel_status ensure_newton(cel_plan* p);
 hipError_t stage_selection(cel_plan* p, const std::vector<uint8_t>& m, bool as_class, hipStream_t sm);
 // global ELBO at theta into p->d_total (tables, ELBO-only pixel pass, finalisation, total)
 hipError_t launch_total_after_eval(cel_plan* p, const double* theta, hipStream_t sm);
+// Point likelihood passes: point_setup stages the selection (m[s] != 0) and the neighbour
+// maps at z_fixed, with scratch for `chunk` candidates per launch (<= kVariants); then each
+// point_loglik writes ll[c][s] for the selected sources of n_cand candidate rows z_cand.
+cel_status point_setup(cel_plan* p, const double* z_fixed, const std::vector<uint8_t>& m, int chunk, hipStream_t sm);
+hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* ll, hipStream_t sm);
 }  // namespace celmi

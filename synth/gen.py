@@ -721,6 +721,31 @@ def perturbed_points(z, n, seed):
     return out
 
 
+def prior_draws(prob, z_fixed, n_runs, seed, box):
+    """Start points of annealed importance sampling runs drawn from the prior of each source
+    type (the generative model of Section 2.1, the runs' pi_0): [2, n_runs, S, 16] point
+    values, index 0 galaxy, 1 star.  Position uniform on the square of half-width `box`
+    around z_fixed's position, log flux normal, colours from the type's mixture, angle
+    uniform on [0, pi), log radius normal, profile weight and axis ratio beta (drawn for
+    stars too, where they are unused)."""
+    rng = np.random.default_rng(seed)
+    S = prob.n_sources
+    out = np.zeros((2, n_runs, S, 16))
+    for a in (0, 1):
+        for r in range(n_runs):
+            for s in range(S):
+                z = out[a, r, s]
+                z[0:2] = np.asarray(z_fixed[s, 0:2]) + rng.uniform(-box, box, 2)
+                z[2] = float(a)
+                z[3] = rng.normal(prob.prior_r[a, 0], math.sqrt(prob.prior_r[a, 1]))
+                z[4:8] = draw_gmm(rng, prob.prior_cw[a], prob.prior_cmean[a], prob.prior_ccov[a])
+                z[8] = rng.uniform(0, math.pi)
+                z[9] = rng.normal(prob.prior_radius[0], math.sqrt(prob.prior_radius[1]))
+                z[10] = rng.beta(*prob.prior_profile)
+                z[11] = rng.beta(*prob.prior_axis)
+    return out
+
+
 def make_config(k, **kw):
     return {1: config1, 2: config2, 3: config3, 4: config4}[k](**kw)
 

@@ -18,6 +18,8 @@ the generator still produces the same inputs.
                 initial point, its global ELBO, and one oracle Newton step (with its local
                 model g, H, p, predicted gain) for the first 48 sources of colour class 0
   config4_sweep config4_sweep.npz: three oracle sweeps of the field (float64)
+  mcmc          mcmc_oracle.npz: the oracle's MCMC source step (annealed importance
+                sampling, slice sampling, type draw) of both sources of a small problem
   eigen         eigen_oracle.npz: the field with a spatially varying PSF (E = 4 eigen-
                 images of 51 x 51 knots) and a 192 x 256 sky knot grid: the oracle's PSF
                 fit of every patch, every L_s and gradient and the global ELBO
@@ -36,6 +38,7 @@ import torch
 
 from oracle import elbo as E
 from oracle import newton as NW
+from oracle import mcmc as MC
 from oracle import psf as OP
 from synth import gen
 from tests.golden.inputs_hash import inputs_hash
@@ -249,8 +252,44 @@ def make_eigen():
           elbo_total=np.array(total), elbo_local=loc, grad=g)
 
 
+MCMC_T = 4
+MCMC_OPTS = dict(n_temps=MCMC_T, n_runs=3, n_post=2, seed=7, gamma=[(t / MCMC_T) ** 4 for t in range(MCMC_T + 1)])
+MCMC_KEY = 3
+MCMC_INIT_SEED = 5
+
+
+def mcmc_problem():
+    """The small problem of the stored MCMC step: 1 star + 1 galaxy, bands g and r, patches
+    cropped to 12 x 12, the sources at their true points."""
+    prob = gen.crop_patches(gen.subset(gen.config1(), images=[1, 2]), 12)
+    return prob, gen.truth_point(prob)
+
+
+def _mcmc_source(s):
+    prob, z = mcmc_problem()
+    opts = dict(MC.DEFAULTS, **MCMC_OPTS)
+    init = gen.prior_draws(prob, z, opts["n_runs"], seed=MCMC_INIT_SEED, box=opts["box"])
+    return MC.source_step(E.Model(prob), z, s, init[:, :, s], opts, key=(opts["seed"], MCMC_KEY))
+
+
+def make_mcmc():
+    """The oracle's MCMC step of both sources of the small problem (T = 4, N' = 3, B' = 2)."""
+    prob, _ = mcmc_problem()
+    with _pool() as pool:
+        res = pool.map(_mcmc_source, range(prob.n_sources))
+    opts = dict(MC.DEFAULTS, **MCMC_OPTS)
+    _save("mcmc_oracle.npz", prob, samples=np.array([r["samples"] for r in res]),
+          log_evidence=np.array([r["log_evidence"] for r in res]), p_star=np.array([r["p_star"] for r in res]),
+          z=np.array([r["z"] for r in res]), a=np.array([r["a"] for r in res]),
+          logw=np.array([r["logw"] for r in res]), n_temps=np.array(opts["n_temps"]), n_runs=np.array(opts["n_runs"]),
+          n_post=np.array(opts["n_post"]), gamma=np.array(opts["gamma"]), width=np.array(opts["width"]),
+          box=np.array(opts["box"]), max_step_out=np.array(opts["max_step_out"]),
+          max_shrink=np.array(opts["max_shrink"]), seed=np.array(opts["seed"]), key=np.array(MCMC_KEY),
+          init_seed=np.array(MCMC_INIT_SEED))
+
+
 MAKERS = dict(config1=make_config1, skew_sweep=make_skew_sweep, config2=make_config2, config3=make_config3,
-              config4=make_config4, config4_sweep=make_config4_sweep, eigen=make_eigen)
+              config4=make_config4, config4_sweep=make_config4_sweep, eigen=make_eigen, mcmc=make_mcmc)
 
 if __name__ == "__main__":
     for name in sys.argv[1:] or ["config1"]:
