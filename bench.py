@@ -196,28 +196,70 @@ def loglik_leg(log, prob, units, n_cand=56, reps=3):
     return res
 
 
-def serve_leg(log, rates=(20.0, 50.0, 100.0, 200.0), n_requests=200, pool=8):
+def mcmc_leg(log, T=200, n_runs=25, n_post=25):
+    """The MCMC source step at the paper's settings (Section 3.2: T = 200 temperatures,
+    N' = 25 runs per type, B' = 25 further sweeps) on colour class 0 of a 120-source blended
+    field (5 bands): every chain's candidates evaluated in batched likelihood passes.
+    Reports seconds, lockstep rounds and candidate-pixel evaluations per second (summed over
+    chains: each evaluation covers the source's active pixels)."""
+    import torch
+    from paper_1803_00113_amd import api
+    from synth import gen
+    prob = gen.subset(gen.config2(n_sources=120), images=list(range(5)))
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    z = gen.truth_point(prob)
+    cls = plan.colours == 0
+    opts = dict(n_temps=T, n_runs=n_runs, n_post=n_post, max_step_out=8, max_shrink=200, box=2.0, seed=11,
+                gamma=[(t / T) ** 4 for t in range(T + 1)],
+                width=[0.5, 0.5, 0, 0.3, 0.2, 0.2, 0.2, 0.2, 0.5, 0.3, 0.2, 0.2, 0, 0, 0, 0])
+    zf = torch.as_tensor(z, device="cuda").contiguous()
+    init = torch.as_tensor(gen.prior_draws(prob, z, n_runs, gen.SEED_BASE + 9, 2.0), device="cuda").contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = api.mcmc_step(plan, zf, init, opts, 1, mask=cls)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rep = r["report"]
+    sel = torch.as_tensor(cls, device="cuda")
+    res = dict(workload=prob.name, sources=int(cls.sum()), n_temps=T, n_runs=n_runs, n_post=n_post,
+               chains=rep["n_chains"], rounds=rep["rounds"], seconds=dt, evaluations=rep["evaluations"],
+               candidate_pixel_evals_per_s=rep["candidate_pixels"] / dt, ms_per_round=1e3 * dt / rep["rounds"],
+               seconds_per_source=dt / int(cls.sum()),
+               p_star_mean=float(r["p_star"][sel].mean().item()))
+    log(f"mcmc: {res}")
+    return res
+
+
+def serve_leg(log, rates=(20.0, 50.0, 100.0, 200.0), n_requests=2000):
     """Region requests of 1-200 sources (patch side 16-96, 5 bands) arriving as a Poisson
-    process; each request takes 10 Newton rounds.  Arrivals cycle through `pool` generated
-    regions."""
+    process at each rate; each request takes 10 Newton rounds.  Every request is a distinct
+    region cut from a 1500-source field (runs of whole overlapping groups), so each
+    admission prepares a region not seen before; the same 2000 regions are offered at each
+    rate, in a different random order.  Reports p50 / p99 latency (arrival to result on the
+    host), throughput and the admission times with their slope on the resident set."""
     from paper_1803_00113_amd import serve
     from synth import gen
-    regions = [gen.config5_request(gen.SEED_BASE + 5 + 100 * i) for i in range(pool)]
-    # untimed warm-up: each region once through a server (first plan builds and launches)
-    warm = [serve.Request(i, regions[i], 0.001 * i, rounds=10) for i in range(pool)]
+    field = gen.serving_field()
+    regions = gen.region_requests(field, n_requests, gen.SEED_BASE + 77)
+    # untimed warm-up: a few regions through a server (first launches of every kernel)
+    warm = [serve.Request(i, regions[i], 0.001 * i, rounds=10) for i in range(8)]
     serve.Server(0, rounds=10).run(warm)
     out = []
     for rate in rates:
         rng = np.random.default_rng(int(rate))
         t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
-        reqs = [serve.Request(i, regions[i % pool], float(t[i]), rounds=10) for i in range(n_requests)]
+        order = rng.permutation(n_requests)
+        reqs = [serve.Request(i, regions[order[i]], float(t[i]), rounds=10) for i in range(n_requests)]
         srv = serve.Server(0, rounds=10)
         st = srv.run(reqs)
         st["rate_req_per_s"] = rate
         st["requests"] = n_requests
+        st["distinct_regions"] = len({r.prob.name for r in reqs})
         st["mean_sources_per_request"] = float(np.mean([r.prob.n_sources for r in reqs]))
+        st["sustained"] = bool(st["req_per_s"] >= 0.95 * rate)
         log(f"serving at {rate} req/s: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
-            f"{st['req_per_s']:.1f} req/s served")
+            f"{st['req_per_s']:.1f} req/s served; admission {st.get('admission_ms')}")
         out.append(st)
     return out
 
@@ -272,6 +314,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-hessian", action="store_true")
     ap.add_argument("--no-loglik", action="store_true")
+    ap.add_argument("--no-mcmc", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -354,8 +397,15 @@ def main():
 
     hess = None if args.no_hessian else hessian_leg(log, prob)
     llk = None if args.no_loglik else loglik_leg(log, prob, units)
+    mcmc = None if args.no_mcmc else mcmc_leg(log)
     sweep = None if args.no_sweep else sweep_leg(log)
     serving = None if args.no_serve else serve_leg(log)
+
+    # the headline latency: p99 at the highest offered rate that was sustained
+    head = None
+    if serving:
+        ok = [x for x in serving if x["sustained"]]
+        head = max(ok, key=lambda x: x["rate_req_per_s"]) if ok else serving[0]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -371,8 +421,11 @@ def main():
                    "active_pixels": units, "seed": gen.SEED_BASE + 2},
         "roofline": roofline, "cpu_baseline": cpu,
         "plain": plain, "batched_vs_plain": (value / plain["value"]) if plain else None,
-        "p99_region_latency_ms": serving[0]["p99_ms"] if serving else None,
-        "serving": serving, "sweep": sweep, "hessian": hess, "loglik": llk,
+        "p99_region_latency_ms": head["p99_ms"] if head else None,
+        "p99_region_latency_at_req_per_s": head["rate_req_per_s"] if head else None,
+        "p99_region_latency_ms_by_rate": ({str(int(x["rate_req_per_s"])): round(x["p99_ms"], 3) for x in serving}
+                                          if serving else None),
+        "serving": serving, "sweep": sweep, "hessian": hess, "loglik": llk, "mcmc": mcmc,
     }
     print(json.dumps(line), flush=True)
 

@@ -179,9 +179,23 @@ cel_status cel_last_device_error(cel_ctx* ctx, int32_t* code);
 cel_status cel_prepare(cel_ctx* ctx, const cel_problem* prob, cel_plan** out, void* stream);
 void cel_plan_free(cel_plan* plan);
 
-/* Plan facts.  colours: HOST [n_sources] or NULL; returns counts via out-pointers. */
+/* Add a problem's sources, images and patches to a plan (a serving loop admitting a region
+ * request into its resident set).  The part's ids follow the plan's: source s of the part
+ * becomes n_sources + s, and so on for images and patches; its patches refer to its own
+ * images, so no source of the part overlaps one already in the plan.  part->pixels is
+ * DEVICE memory read during the call.  The cost depends on the part only (amortised: the
+ * plan's device arrays grow by doubling): the part is validated and prepared on its own
+ * (as cel_prepare) and spliced in; results for sources already in the plan are unchanged
+ * bit for bit.  The part must share the plan's prior and profile tables (CEL_EINVAL
+ * otherwise); per-patch PSFs are not supported here (CEL_EUNSUPPORTED).  Captured sweep
+ * graphs of the plan are dropped.  Synchronous; the plan must not be in use meanwhile. */
+cel_status cel_plan_append(cel_ctx* ctx, cel_plan* plan, const cel_problem* part, void* stream);
+
+/* Plan facts.  colours: HOST [n_sources] or NULL; returns counts via out-pointers (any may
+ * be NULL): active pixels, colour classes, work items, and the device bytes the plan holds
+ * now (its tables, pixels and the scratch of the calls made so far). */
 cel_status cel_plan_info(const cel_plan* plan, int64_t* n_units, int32_t* n_colours, int32_t* colours,
-                         int64_t* n_work_items);
+                         int64_t* n_work_items, int64_t* device_bytes);
 
 /* ELBO (Section 4.2, equation elbo).  theta: DEVICE float64 [S*32].
  * elbo_total: DEVICE float64 [1] -- every pixel of the union of patches once, minus

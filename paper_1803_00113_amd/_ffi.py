@@ -102,8 +102,9 @@ _sig = {
     "cel_destroy": (None, [_vp]),
     "cel_prepare": (C.c_int32, [_vp, C.POINTER(CelProblem), C.POINTER(_vp), _vp]),
     "cel_plan_free": (None, [_vp]),
+    "cel_plan_append": (C.c_int32, [_vp, _vp, C.POINTER(CelProblem), _vp]),
     "cel_plan_info": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                  C.POINTER(C.c_int64)]),
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "cel_elbo_eval": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cel_elbo_grad": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cel_elbo_grad_plain": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),

@@ -117,6 +117,38 @@ def host_tables(prob):
     return images, knots, patches, pr, pf
 
 
+def _problem_struct(ctx, prob, pixels_device):
+    """The cel_problem of a problem (host tables by value, pixels on the device); returns it
+    with the objects that keep its memory alive."""
+    dev = ctx.device
+    images, knots, patches, prior, profiles = host_tables(prob)
+    if pixels_device is not None:
+        if not (pixels_device.is_cuda and pixels_device.dtype == torch.float32 and pixels_device.is_contiguous()):
+            raise ValueError("pixels_device must be a contiguous cuda float32 tensor")
+        pixels = pixels_device
+    else:
+        pixels = torch.as_tensor(np.ascontiguousarray(prob.pixels, dtype=np.float32)).to(dev)
+    cp = F.CelProblem()
+    cp.n_sources = int(prob.n_sources)
+    cp.n_images = int(len(prob.img_band))
+    cp.n_patches = int(len(prob.patch_src))
+    cp.images = images.ctypes.data_as(C.POINTER(F.CelImage))
+    cp.sky_knots = knots.ctypes.data_as(C.POINTER(C.c_double))
+    cp.n_sky_knots = int(knots.size)
+    cp.patches = patches.ctypes.data_as(C.POINTER(F.CelPatch))
+    cp.pixels = C.c_void_p(pixels.data_ptr())
+    cp.n_pixels = int(pixels.numel())
+    cp.prior = C.pointer(prior)
+    cp.profiles = C.pointer(profiles)
+    ppsf = getattr(prob, "patch_psf", None)
+    if ppsf is not None:
+        ppsf = np.ascontiguousarray(ppsf, dtype=np.float64)
+        if ppsf.shape != (cp.n_patches, F.MAX_PSF, 6):
+            raise ValueError(f"patch_psf must be [{cp.n_patches}, {F.MAX_PSF}, 6]")
+        cp.patch_psf = ppsf.ctypes.data_as(C.POINTER(C.c_double))
+    return cp, (images, knots, patches, prior, profiles, pixels, ppsf)
+
+
 class Plan:
     """A prepared problem (cel_prepare).  Pixels are read once, during construction."""
 
@@ -125,31 +157,7 @@ class Plan:
         prob.pixels is copied to the device)."""
         self.ctx = ctx
         dev = ctx.device
-        images, knots, patches, prior, profiles = host_tables(prob)
-        if pixels_device is not None:
-            if not (pixels_device.is_cuda and pixels_device.dtype == torch.float32 and pixels_device.is_contiguous()):
-                raise ValueError("pixels_device must be a contiguous cuda float32 tensor")
-            pixels = pixels_device
-        else:
-            pixels = torch.as_tensor(np.ascontiguousarray(prob.pixels, dtype=np.float32)).to(dev)
-        cp = F.CelProblem()
-        cp.n_sources = int(prob.n_sources)
-        cp.n_images = int(len(prob.img_band))
-        cp.n_patches = int(len(prob.patch_src))
-        cp.images = images.ctypes.data_as(C.POINTER(F.CelImage))
-        cp.sky_knots = knots.ctypes.data_as(C.POINTER(C.c_double))
-        cp.n_sky_knots = int(knots.size)
-        cp.patches = patches.ctypes.data_as(C.POINTER(F.CelPatch))
-        cp.pixels = C.c_void_p(pixels.data_ptr())
-        cp.n_pixels = int(pixels.numel())
-        cp.prior = C.pointer(prior)
-        cp.profiles = C.pointer(profiles)
-        ppsf = getattr(prob, "patch_psf", None)
-        if ppsf is not None:
-            ppsf = np.ascontiguousarray(ppsf, dtype=np.float64)
-            if ppsf.shape != (cp.n_patches, F.MAX_PSF, 6):
-                raise ValueError(f"patch_psf must be [{cp.n_patches}, {F.MAX_PSF}, 6]")
-            cp.patch_psf = ppsf.ctypes.data_as(C.POINTER(C.c_double))
+        cp, keep = _problem_struct(ctx, prob, pixels_device)
         h = C.c_void_p()
         with torch.cuda.device(dev):
             st = stream if stream is not None else _stream(dev)
@@ -157,13 +165,34 @@ class Plan:
         self.h = h
         self._lib = F.lib
         self.S = int(prob.n_sources)
+        self._refresh()
+
+    def append(self, prob, pixels_device=None):
+        """cel_plan_append: add a problem's sources, images and patches after the plan's
+        own (ids offset).  Returns the id of the part's first source."""
+        first = self.S
+        cp, keep = _problem_struct(self.ctx, prob, pixels_device)
+        with torch.cuda.device(self.ctx.device):
+            F.check("cel_plan_append", F.lib.cel_plan_append(self.ctx.h, self.h, C.byref(cp), _stream(self.ctx.device)))
+        self.S += int(prob.n_sources)
+        self._refresh()
+        return first
+
+    def _refresh(self):
         nu, nc, nw = C.c_int64(), C.c_int32(), C.c_int64()
-        col = (C.c_int32 * max(self.S, 1))()
-        F.check("cel_plan_info", F.lib.cel_plan_info(h, C.byref(nu), C.byref(nc), col, C.byref(nw)))
+        col = np.zeros(max(self.S, 1), dtype=np.int32)
+        F.check("cel_plan_info", F.lib.cel_plan_info(self.h, C.byref(nu), C.byref(nc),
+                                                     col.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nw), None))
         self.n_units = int(nu.value)
         self.n_colours = int(nc.value)
         self.n_work_items = int(nw.value)
-        self.colours = np.array(col[:self.S], dtype=np.int32)
+        self.colours = col[:self.S].copy()
+
+    def device_bytes(self):
+        """Device bytes the plan holds now (cel_plan_info)."""
+        b = C.c_int64()
+        F.check("cel_plan_info", F.lib.cel_plan_info(self.h, None, None, None, None, C.byref(b)))
+        return int(b.value)
 
     def close(self):
         lib = getattr(self, "_lib", None)

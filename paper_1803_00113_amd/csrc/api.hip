@@ -312,6 +312,31 @@ static cel_status track(cel_plan* p, X** ptr, size_t n) {
   return st;
 }
 
+cel_status plan_alloc(cel_plan* p, size_t bytes, void** ptr) {
+  size_t got = 0;
+  cel_status st = ctx_alloc(p->ctx, bytes, ptr, &got);
+  if (!st) p->allocs.push_back({*ptr, got});
+  return st;
+}
+
+void plan_untrack(cel_plan* p, void* ptr) {
+  // (the packed block holds many arrays: it lives as long as the plan)
+  if (!ptr || ptr == p->pack_base) return;
+  for (size_t i = 0; i < p->allocs.size(); ++i) {
+    if (p->allocs[i].ptr != ptr) continue;
+    const cel_plan::Block b = p->allocs[i];
+    p->allocs.erase(p->allocs.begin() + i);
+    cel_ctx* c = p->ctx;
+    if (c && c->cache_bytes + b.bytes <= kCacheCap) {
+      c->cache.emplace(b.bytes, b.ptr);
+      c->cache_bytes += b.bytes;
+    } else {
+      (void)hipFree(b.ptr);
+    }
+    return;
+  }
+}
+
 template <typename X>
 static cel_status track_upload(cel_plan* p, X** ptr, const std::vector<X>& v) {
   cel_status st = track(p, ptr, v.size());
@@ -343,6 +368,7 @@ static cel_status upload_pack(cel_plan* p, UploadPack& pk, hipStream_t sm) {
   char* base = nullptr;
   cel_status st = track(p, &base, pk.total);
   if (st) return st;
+  p->pack_base = base;
   // staged through the context's pinned buffer (grown when a larger plan needs it)
   cel_ctx* c = p->ctx;
   if (c->stage_cap < pk.total) {
@@ -373,18 +399,18 @@ cel_status ensure_variants(cel_plan* p, int nv, bool fp64) {
   }
   cel_status st;
   if (fp64 && p->nv_d < nv) {
-    if ((st = track(p, &p->tables_d, (size_t)nv * std::max(p->P, 1)))) return st;
+    if ((st = track(p, &p->tables_d, (size_t)nv * std::max<int64_t>(p->cap_P, 1)))) return st;
     p->nv_d = nv;
   }
   if (!fp64 && p->nv_f < nv) {
-    if ((st = track(p, &p->tables_f, (size_t)nv * std::max(p->P, 1)))) return st;
+    if ((st = track(p, &p->tables_f, (size_t)nv * std::max<int64_t>(p->cap_P, 1)))) return st;
     p->nv_f = nv;
   }
   if (p->nv_slots < nv) {
-    if ((st = track(p, &p->slots, (size_t)nv * std::max<int64_t>(p->n_tasks, 1) * kSlots))) return st;
-    if ((st = track(p, &p->v_local, (size_t)nv * std::max(p->S, 1)))) return st;
-    if ((st = track(p, &p->v_own, (size_t)nv * std::max(p->S, 1)))) return st;
-    if ((st = track(p, &p->v_grad, (size_t)nv * std::max(p->S, 1) * kThetaN))) return st;
+    if ((st = track(p, &p->slots, (size_t)nv * std::max<int64_t>(p->cap_T, 1) * kSlots))) return st;
+    if ((st = track(p, &p->v_local, (size_t)nv * std::max<int64_t>(p->cap_S, 1)))) return st;
+    if ((st = track(p, &p->v_own, (size_t)nv * std::max<int64_t>(p->cap_S, 1)))) return st;
+    if ((st = track(p, &p->v_grad, (size_t)nv * std::max<int64_t>(p->cap_S, 1) * kThetaN))) return st;
     p->nv_slots = nv;
   }
   return CEL_OK;
@@ -429,22 +455,33 @@ hipError_t stage_selection(cel_plan* p, const std::vector<uint8_t>& m, bool as_c
 cel_status ensure_newton(cel_plan* p) {
   if (p->newton_ready) return CEL_OK;
   cel_status st;
-  const size_t S1 = std::max(p->S, 1);
+  const size_t S1 = (size_t)std::max<int64_t>(p->cap_S, 1);
+  const size_t P1 = (size_t)std::max<int64_t>(p->cap_P, 1), T1 = (size_t)std::max<int64_t>(p->cap_T, 1);
   // (the per-source pixel counts and colours were uploaded with the plan)
   if ((st = track(p, &p->d_theta_trial, S1 * kThetaN)) || (st = track(p, &p->d_pred, S1)) ||
       (st = track(p, &p->d_step_norm, S1)) || (st = track(p, &p->d_trial_active, S1)) ||
       (st = track(p, &p->d_mask, S1)) || (st = track(p, &p->d_counter, 1)) ||
-      (st = track(p, &p->d_hslots, (size_t)std::max<int64_t>(p->n_tasks, 1) * 80)) ||
-      (st = track(p, &p->d_step_src, S1)) || (st = track(p, &p->d_step_patches, (size_t)std::max(p->P, 1))) ||
-      (st = track(p, &p->d_step_tasks, (size_t)std::max<int64_t>(p->n_tasks, 1))) ||
+      (st = track(p, &p->d_hslots, T1 * 80)) ||
+      (st = track(p, &p->d_step_src, S1)) || (st = track(p, &p->d_step_patches, P1)) ||
+      (st = track(p, &p->d_step_tasks, T1)) ||
       (st = track(p, &p->d_hess, S1 * kParamN * kParamN)) ||
       (st = track(p, &p->d_hpart, S1 * kHessParts * kHessPartN)))
     return st;
   if (hipMemset(p->d_trial_active, 0, S1) != hipSuccess) return CEL_EHIP;
-  // pinned words, event and stream: a kit from a freed plan when one is there
+  // pinned words, event and stream: the plan's own (after an append), else a kit from a
+  // freed plan when one is there
   HostKit k;
   cel_ctx* c = p->ctx;
-  if (c && !c->kits.empty()) {
+  if (p->mask_copied) {
+    k.h_mask = p->h_mask;
+    k.mask_cap = p->mask_cap;
+    k.h_lists = p->h_lists;
+    k.lists_cap = p->lists_cap;
+    k.h_counter = p->h_counter;
+    k.h_total = p->h_total;
+    k.mask_copied = p->mask_copied;
+    k.own_stream = p->own_stream;
+  } else if (c && !c->kits.empty()) {
     k = c->kits.back();
     c->kits.pop_back();
   }
@@ -455,7 +492,7 @@ cel_status ensure_newton(cel_plan* p) {
     if (hipHostMalloc((void**)&k.h_mask, S1, 0) != hipSuccess) return CEL_ENOMEM;
     k.mask_cap = S1;
   }
-  const size_t lists = S1 + (size_t)std::max(p->P, 1) + (size_t)std::max<int64_t>(p->n_tasks, 1);
+  const size_t lists = S1 + P1 + T1;
   if (k.lists_cap < lists) {
     if (k.h_lists) (void)hipHostFree(k.h_lists);
     k.h_lists = nullptr;
@@ -713,6 +750,10 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
     d.task_end = (int)p->tasks_h.size();
   }
   p->n_tasks = (int64_t)p->tasks_h.size();
+  p->cap_S = S;
+  p->cap_P = P;
+  p->cap_T = p->n_tasks;
+  p->cap_U = p->n_units;
   // stable LSD radix sort on the inverted cost (the ids are generated in ascending order)
   {
     std::vector<uint64_t> tmp(keys.size());
@@ -878,8 +919,13 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
 }
 
 extern "C" cel_status cel_plan_info(const cel_plan* plan, int64_t* n_units, int32_t* n_colours, int32_t* colours,
-                                    int64_t* n_work_items) {
+                                    int64_t* n_work_items, int64_t* device_bytes) {
   if (!plan) return CEL_EINVAL;
+  if (device_bytes) {
+    int64_t b = 0;
+    for (const auto& blk : plan->allocs) b += (int64_t)blk.bytes;
+    *device_bytes = b;
+  }
   if (n_units) *n_units = plan->n_units;
   if (n_colours) *n_colours = plan->n_colours;
   if (n_work_items) *n_work_items = plan->n_tasks;

@@ -43,6 +43,13 @@ struct cel_plan {
   cel_options opt;
   int S = 0, N = 0, P = 0;
   int64_t n_units = 0, n_tasks = 0;
+  // sizes the per-call scratch is allocated for (>= S, P, n_tasks, n_units; grown by
+  // cel_plan_append), and the element capacity of each persistent device array that an
+  // append may grow, by the address of its pointer field (absent: exactly its count)
+  int64_t cap_S = 0, cap_P = 0, cap_T = 0, cap_U = 0;
+  std::map<const void*, size_t> dev_cap;
+  void* pack_base = nullptr;        // the one block holding the plan's small tables and lists
+  std::vector<size_t> cls_cap[3];   // capacities of the per-colour source, patch, item lists
   int nexp = 0, ndev = 0;
   // host copies
   std::vector<cel_image> images_h;
@@ -162,6 +169,10 @@ void ctx_release(cel_ctx* c);
 // a device block of at least `bytes` from the context's cache, else newly allocated
 cel_status ctx_alloc(cel_ctx* c, size_t bytes, void** ptr, size_t* got);
 cel_status ensure_variants(cel_plan* p, int nv, bool fp64);
+// a device block of `bytes` owned by the plan (freed with it)
+cel_status plan_alloc(cel_plan* p, size_t bytes, void** ptr);
+// give a block the plan owns back to the context (no work may still use it)
+void plan_untrack(cel_plan* p, void* ptr);
 // (local_out / grad_out: where variant 0's local objectives and gradients go when nv == 1;
 // null = the plan's per-variant arrays)
 hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv, bool grad, int cls,

@@ -3,25 +3,20 @@
 Each request is a region: its own sources, patches, pixels and initial parameters.  The
 loop keeps a set of resident requests whose variational state (theta, trust radii) stays
 in device memory.  At every device step:
-  1. requests that have arrived are admitted, oldest first, while the estimated device
-     footprint of the resident set stays within the HBM budget (a request that does not
-     fit waits; it is never failed for lack of memory);
-     Under a burst of arrivals (the last two rebuilds less than two intervals apart),
-     admissions are held while the last rebuild of the merged plan is younger than
-     `min_rebuild_interval_s`: a rebuild costs a few milliseconds of host work, and arrivals
-     a few milliseconds apart then share one; outside bursts an arrival is admitted at once;
-  2. if a request was admitted, the resident requests are merged into one plan (their
-     pixel arrays are concatenated on the device; sources of different requests never
-     overlap, so the merged colouring restricted to a request equals its own), and their
-     parameters and trust radii into one device array each;
-  3. one trust-radius Newton round runs, in one batched cel_newton_step, on every resident
+  1. requests that have arrived are admitted, oldest first, while twice the estimated
+     device footprint of the requests laid out in the plan stays within the HBM budget (the
+     plan's arrays grow by doubling); a request that does not fit waits, it is never failed
+     for lack of memory.  Admission appends the request to the resident plan
+     (cel_plan_append): only the request is prepared, so it costs the same whatever is
+     resident;
+  2. one trust-region Newton round runs, in one batched cel_newton_step, on every resident
      request's current colour class (a request cycles through its classes);
-  4. requests that have completed their rounds leave: their parameters and objective are
+  3. requests that have completed their rounds leave: their parameters and objective are
      copied to the host and the latency (arrival to result on the host) is recorded;
      cancelled requests leave without a result (a request may be cancelled while pending
-     or after a given number of rounds).  A request that leaves stays in the merged plan,
-     masked out, until the next admission rebuilds it (or until such requests hold more
-     than half of the plan's sources), so that leaving costs no rebuild.
+     or after a given number of rounds).  A request that leaves stays laid out, masked
+     out, until such requests hold more than half of the plan's sources; the resident
+     requests are then laid out again in a new plan.
 Work of different requests shares launches; a request's results do not depend on which
 others are resident (every per-source reduction has a fixed order).
 """
@@ -35,20 +30,65 @@ import torch
 
 from . import api
 
-TABLE_BYTES = 1536           # per patch and variant, float32 component table (upper bound)
 VARIANTS_EXACT = 2           # Newton with the exact Hessian: iterate, trial
 VARIANTS_FD = 56             # Newton with a difference Hessian: iterate, 54 differences, trial
+# bytes of one component table (device.h: Table<float>; Table<double> is twice as large):
+# header 16, star 4 x 8, galaxy 4 x 16 x 4, star cut radii 4, galaxy cut radii 4 x 16,
+# second-derivative terms 4 x 16 x 8, exponent rows 4 x 4 + 4 x 16 x 4, PSF offsets 4 x 2
+TABLE_F = 4 * (16 + 4 * 8 + 4 * 16 * 4 + 4 + 4 * 16 + 4 * 16 * 8 + 4 * 4 + 4 * 16 * 4 + 4 * 2)
+TABLE_D = 2 * TABLE_F
+CHUNK = 512                  # pixels per work item (the library's default)
+IMAGE_RECORD = 280           # sizeof(cel_image)
+PRIOR_RECORDS = 8192         # prior and profile tables, rounded up
 
 
-def footprint_bytes(prob, variants=VARIANTS_EXACT):
-    """Estimated device bytes a request needs inside a merged plan (pixels, per-pixel
-    arrays, Newton tables and slots, Hessian slots and matrices, per-source scratch)."""
-    units = int(np.sum(prob.patch_w.astype(np.int64) * prob.patch_h))
-    P = int(len(prob.patch_src))
-    S = int(prob.n_sources)
-    items = int(np.sum((prob.patch_w.astype(np.int64) * prob.patch_h + 511) // 512))
-    return (units * (4 + 8 + 8) + P * variants * TABLE_BYTES + items * (variants * 16 + 80) * 8
-            + S * variants * (8 + 8 + 32 * 8) + S * (32 * 8 * 3 + 27 * 27 * 8) + P * 64)
+def _al(b):
+    return (int(b) + 255) // 256 * 256
+
+
+def neighbour_entries(prob):
+    """Entries of the patch overlap lists: ordered pairs of patches of different sources
+    whose rectangles intersect in the same image."""
+    e = 0
+    for n in np.unique(prob.patch_img):
+        ps = np.nonzero(prob.patch_img == n)[0]
+        x0, y0 = prob.patch_x0[ps].astype(np.int64), prob.patch_y0[ps].astype(np.int64)
+        x1, y1 = x0 + prob.patch_w[ps], y0 + prob.patch_h[ps]
+        src = prob.patch_src[ps]
+        inter = ((x0[:, None] < x1[None, :]) & (x0[None, :] < x1[:, None]) & (y0[:, None] < y1[None, :])
+                 & (y0[None, :] < y1[:, None]) & (src[:, None] != src[None, :]))
+        e += int(inter.sum())
+    return e
+
+
+def footprint_bytes(prob, variants=VARIANTS_EXACT, fp64=False, chunk=CHUNK):
+    """Device bytes a request's own plan holds once Newton steps have run (an upper bound of
+    cel_plan_info's device_bytes): the plan's tables and lists, pixels, data constants and
+    moment maps, `variants` component tables (float64 ones when fp64: the Hessian on float64
+    pixels) with their slot rows and per-source outputs, and the Newton scratch (Hessian
+    slots and matrices).  Every block counted rounded up to 256 bytes."""
+    S, N, P = int(prob.n_sources), int(len(prob.img_band)), int(len(prob.patch_src))
+    sizes = prob.patch_w.astype(np.int64) * prob.patch_h
+    U = int(sizes.sum())
+    T = int(((sizes + chunk - 1) // chunk).sum())
+    E = neighbour_entries(prob)
+    C = 16                                   # colour classes (each adds three aligned lists)
+    pack = (_al(P * 48) + _al(N * IMAGE_RECORD) + _al(E * 4) + _al(T * 16) + 2 * _al(T * 4) + _al((S + 1) * 4)
+            + _al(N * 4) + PRIOR_RECORDS + _al(P * 8) + _al(len(prob.sky_knots) * 8) + _al(S * 8) + _al(S * 4)
+            + (S + P + T) * 4 + 3 * C * 256)
+    pixels = _al(U * 8) + _al(2 * P * 8) + _al(P * 8) + 256 + _al(U * 8)          # (count, sky), constants, maps
+    if fp64:
+        pixels += 2 * _al(U * 16)
+    # the plan keeps the one-variant tables and sums made at preparation beside those of the
+    # Newton steps
+    tables = _al(P * TABLE_F) + (_al(variants * P * TABLE_D) if fp64 else _al(variants * P * TABLE_F))
+    sums = sum(_al(nv * T * 128) + 2 * _al(nv * S * 8) + _al(nv * S * 256) for nv in (1, variants))
+    newton = (_al(S * 256) + 2 * _al(S * 8) + 2 * _al(S) + 256 + _al(T * 640) + _al(S * 4) + _al(P * 4)
+              + _al(T * 4) + _al(S * 5832) + _al(S * 24320))
+    return pack + pixels + tables + sums + newton + SLACK
+
+
+SLACK = 1 << 16              # blocks beyond those counted above (alignment of small lists)
 
 
 SHARED = ("prior_a", "prior_r", "prior_cw", "prior_cmean", "prior_ccov", "prior_radius", "prior_profile",
@@ -129,98 +169,144 @@ class Stats:
     latencies: list = field(default_factory=list)
     steps: int = 0
     deferred_admissions: int = 0
-    held_admissions: int = 0      # steps whose arrivals waited for the rebuild interval
-    rebuilds: int = 0
+    admissions: int = 0
+    rebuilds: int = 0             # re-layouts of the resident set (after most of a plan left)
     cancelled: int = 0
     units_evaluated: int = 0
     wall: float = 0.0
+    admit_s: list = field(default_factory=list)          # seconds per admission
+    admit_resident: list = field(default_factory=list)   # sources in the plan before it
+    admit_sources: list = field(default_factory=list)    # sources of the admitted request
 
     def summary(self):
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
-        return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                    mean_ms=float(lat.mean() * 1e3), completed=len(self.latencies),
-                    req_per_s=len(self.latencies) / max(self.wall, 1e-9), steps=self.steps,
-                    deferred_admissions=self.deferred_admissions, held_admissions=self.held_admissions,
-                    rebuilds=self.rebuilds,
-                    cancelled=self.cancelled,
-                    units_per_s=self.units_evaluated / max(self.wall, 1e-9), wall_s=self.wall)
+        out = dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                   mean_ms=float(lat.mean() * 1e3), completed=len(self.latencies),
+                   req_per_s=len(self.latencies) / max(self.wall, 1e-9), steps=self.steps,
+                   admissions=self.admissions, deferred_admissions=self.deferred_admissions,
+                   rebuilds=self.rebuilds, cancelled=self.cancelled,
+                   units_per_s=self.units_evaluated / max(self.wall, 1e-9), wall_s=self.wall)
+        if self.admit_s:
+            a = np.array(self.admit_s) * 1e3
+            res = np.array(self.admit_resident, dtype=np.float64)
+            own = np.array(self.admit_sources, dtype=np.float64)
+            out["admission_ms"] = dict(p50=float(np.percentile(a, 50)), p99=float(np.percentile(a, 99)),
+                                       mean=float(a.mean()))
+            # admission time against the resident set and against the request's own size:
+            # least-squares slopes of ms on sources (a cost independent of the resident set
+            # has a resident slope near zero)
+            if len(a) > 2 and np.ptp(res) > 0 and np.ptp(own) > 0:
+                X = np.column_stack([np.ones_like(a), res, own])
+                coef = np.linalg.lstsq(X, a, rcond=None)[0]
+                out["admission_ms"].update(ms_per_resident_source=float(coef[1]),
+                                           ms_per_request_source=float(coef[2]),
+                                           resident_sources_max=int(res.max()))
+        return out
 
 
 class Server:
-    """Continuous-batching loop on one device."""
+    """Continuous-batching loop on one device.
 
-    def __init__(self, device=0, hbm_budget_bytes=16 << 30, rounds=10, min_rebuild_interval_s=0.01, **ctx_opts):
+    Admission appends the request to the resident plan (cel_plan_append: the request alone is
+    prepared and spliced in, so an admission costs what the request costs, whatever is
+    resident).  The parameters and trust radii of everything laid out in the plan live in
+    one device array each, grown by doubling.  A request that finishes or is cancelled stays
+    laid out, masked out of the Newton rounds, until such requests hold more than half of
+    the plan's sources; the resident requests are then laid out again in a new plan (its cost
+    amortised over the requests that left)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=16 << 30, rounds=10, **ctx_opts):
         self.ctx = api.Context(device, **ctx_opts)
         self.dev = self.ctx.device
         self.variants = VARIANTS_FD if ctx_opts.get("hessian_fd") else VARIANTS_EXACT
+        self.fp64 = bool(ctx_opts.get("hessian_fp64") or ctx_opts.get("pixel_fp64"))
         self.budget = int(hbm_budget_bytes)
         self.rounds = int(rounds)
         self.resident: list[Request] = []
         self.plan = None
-        self.theta = self.radius = None   # merged state of the requests laid out in the plan
-        self.in_plan: list[Request] = []
-        self.dirty = False
-        self.min_rebuild_interval = float(min_rebuild_interval_s)
-        self.last_rebuild = self.prev_rebuild = -float("inf")
+        self.laid: list[Request] = []       # requests laid out in the plan, in order
+        self.theta_buf = self.radius_buf = None
         self.stats = Stats()
 
-    # -- admission and merging ---------------------------------------------------------------
-    def _attach(self, r: Request, now):
+    # -- admission and layout --------------------------------------------------------------
+    def _rows(self):
+        return self.plan.S if self.plan is not None else 0
+
+    def _ensure_rows(self, n, used):
+        """Room for n rows of parameters and radii, the first `used` kept."""
+        cap = 0 if self.theta_buf is None else self.theta_buf.shape[0]
+        if n <= cap:
+            return
+        new_cap = max(n, 2 * cap, 64)
+        th = torch.empty((new_cap, 32), dtype=torch.float64, device=self.dev)
+        ra = torch.empty(new_cap, dtype=torch.float64, device=self.dev)
+        if used:
+            th[:used] = self.theta_buf[:used]
+            ra[:used] = self.radius_buf[:used]
+        self.theta_buf, self.radius_buf = th, ra
+
+    def _lay_out(self, r, theta=None, radius=None):
+        """Append request r to the plan (or start one); its state from theta/radius or its
+        initial parameters."""
         p = r.prob
-        r.theta = torch.as_tensor(p.theta0, dtype=torch.float64, device=self.dev).contiguous()
-        r.radius = torch.full((p.n_sources,), 1.0, dtype=torch.float64, device=self.dev)
-        r.pixels = torch.as_tensor(np.ascontiguousarray(p.pixels, np.float32)).to(self.dev)
+        if r.pixels is None:
+            r.pixels = torch.as_tensor(np.ascontiguousarray(p.pixels, np.float32)).to(self.dev)
+        if self.plan is None:
+            self.plan = api.Plan(self.ctx, p, pixels_device=r.pixels)
+            first = 0
+        else:
+            first = self.plan.append(p, pixels_device=r.pixels)
+        n = p.n_sources
+        self._ensure_rows(first + n, first)
+        self.theta_buf[first:first + n] = (torch.as_tensor(p.theta0, dtype=torch.float64, device=self.dev)
+                                           if theta is None else theta)
+        self.radius_buf[first:first + n] = 1.0 if radius is None else radius
+        r.offset = first
+        r.colours = self.plan.colours[first:first + n]
+        r.n_colours = int(r.colours.max()) + 1 if n else 1
+        r.in_plan = True
+        self.laid.append(r)
+
+    def _admit(self, r, now):
+        t0 = time.perf_counter()
+        before = self._rows()
         r.admitted = now
         r.rounds = self.rounds
-        r.units = int(np.sum(p.patch_w.astype(np.int64) * p.patch_h))
+        r.units = int(np.sum(r.prob.patch_w.astype(np.int64) * r.prob.patch_h))
+        self._lay_out(r)
+        self.resident.append(r)
+        self.stats.admissions += 1
+        self.stats.admit_s.append(time.perf_counter() - t0)
+        self.stats.admit_resident.append(before)
+        self.stats.admit_sources.append(r.prob.n_sources)
+
+    def _relayout(self):
+        """A new plan holding the resident requests only (their state carried over)."""
+        keep = [(r, self.theta_buf[r.offset:r.offset + r.prob.n_sources].clone(),
+                 self.radius_buf[r.offset:r.offset + r.prob.n_sources].clone()) for r in self.resident]
+        for r in self.laid:
+            r.in_plan = False
+        self.plan = None
+        self.laid = []
+        self.theta_buf = self.radius_buf = None
+        for r, th, ra in keep:
+            self._lay_out(r, th, ra)
+        self.stats.rebuilds += 1
 
     def _cancel(self, r):
         r.cancelled = True
-        r.theta = r.radius = r.pixels = None
+        r.pixels = None
         self.stats.cancelled += 1
 
-    def _rebuild(self):
-        # the state of requests already in the plan comes from the merged arrays
-        for r in self.resident:
-            if r.in_plan:
-                sl = slice(r.offset, r.offset + r.prob.n_sources)
-                r.theta, r.radius = self.theta[sl], self.radius[sl]
-        self.plan = None
-        self.theta = self.radius = None
-        self.in_plan = []
-        if not self.resident:
-            return
-        merged = merge([r.prob for r in self.resident])
-        pixels = torch.cat([r.pixels for r in self.resident])
-        self.plan = api.Plan(self.ctx, merged, pixels_device=pixels)
-        off = 0
-        for r in self.resident:
-            r.colours = self.plan.colours[off:off + r.prob.n_sources]
-            r.n_colours = int(r.colours.max()) + 1 if r.prob.n_sources else 1
-            r.offset = off
-            r.in_plan = True
-            off += r.prob.n_sources
-        self.theta = torch.cat([r.theta for r in self.resident]).contiguous()
-        self.radius = torch.cat([r.radius for r in self.resident]).contiguous()
-        for r in self.resident:
-            r.theta = r.radius = None
-        self.in_plan = list(self.resident)
-        self.stats.rebuilds += 1
-
     def _leave(self, gone):
-        """Requests leaving the resident set stay in the plan, masked out; a rebuild is
-        asked for once they hold more than half of its sources."""
         self.resident = [r for r in self.resident if r not in gone]
-        idle = sum(r.prob.n_sources for r in self.in_plan if r not in self.resident)
-        if self.plan is not None and 2 * idle > self.plan.S:
-            self.dirty = True
+        for r in gone:
+            r.pixels = None
 
     def step(self, now, pending):
         """Admit what fits from `pending` (arrived requests, oldest first), run one Newton
         round for every resident request, retire finished and cancelled ones.  Returns the
         retired requests."""
-        changed = False
-        # cancellations: pending requests are dropped, resident ones leave the plan
         cancelled = [r for r in pending if r.cancel_after_rounds is not None and r.cancel_after_rounds <= 0]
         for r in cancelled:
             pending.remove(r)
@@ -231,28 +317,21 @@ class Server:
         cancelled += gone
         for r in cancelled:
             self._cancel(r)
-        # (requests that left but stay in the plan do not count: an admission rebuilds the
-        # plan without them, after the old one is released)
-        used = sum(r.footprint for r in self.resident)
-        burst = self.last_rebuild - self.prev_rebuild < 2 * self.min_rebuild_interval
-        hold = bool(pending) and bool(self.resident) and burst and now - self.last_rebuild < self.min_rebuild_interval
-        if hold:
-            self.stats.held_admissions += 1
-        while pending and not hold:
+        # requests that left but are still laid out count until the next re-layout; the
+        # plan's arrays grow by doubling, so twice the laid-out footprint is held to the budget
+        idle = sum(r.prob.n_sources for r in self.laid if r not in self.resident)
+        if self.plan is not None and 2 * idle > self.plan.S:
+            self._relayout()
+        used = sum(r.footprint for r in self.laid)
+        while pending:
             r = pending[0]
-            r.footprint = r.footprint or footprint_bytes(r.prob, self.variants)
-            if used + r.footprint > self.budget and self.resident:
+            r.footprint = r.footprint or footprint_bytes(r.prob, self.variants, self.fp64)
+            if 2 * (used + r.footprint) > self.budget and self.resident:
                 self.stats.deferred_admissions += 1
                 break
             pending.pop(0)
-            self._attach(r, now)
-            self.resident.append(r)
+            self._admit(r, now)
             used += r.footprint
-            changed = True
-        if changed or self.dirty:
-            self._rebuild()
-            self.dirty = False
-            self.prev_rebuild, self.last_rebuild = self.last_rebuild, now
         if not self.resident:
             return cancelled
         S = self.plan.S
@@ -260,7 +339,8 @@ class Server:
         for r in self.resident:
             c = r.done_rounds % r.n_colours
             mask[r.offset:r.offset + r.prob.n_sources] = r.colours == c
-        status, local = api.newton_step(self.plan, self.theta, self.radius, mask)
+        theta, radius = self.theta_buf[:S], self.radius_buf[:S]
+        status, local = api.newton_step(self.plan, theta, radius, mask)
         self.stats.steps += 1
         self.stats.units_evaluated += sum(r.units for r in self.resident)
         finished = []
@@ -269,7 +349,7 @@ class Server:
             if r.done_rounds >= r.rounds:
                 finished.append(r)
         if finished:
-            theta_h = self.theta.cpu().numpy()
+            theta_h = theta.cpu().numpy()
             tot_local = local.cpu().numpy()
             st = status.cpu().numpy()
             t_done = time.perf_counter()
@@ -279,7 +359,6 @@ class Server:
                 r.result_local = tot_local[sl]
                 r.result_status = st[sl]
                 r.finished = t_done
-                r.pixels = None
             self._leave(finished)
         return finished + cancelled
 

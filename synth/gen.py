@@ -609,6 +609,35 @@ def config_skew(seed=SEED_BASE + 6, n_groups=2, H=83, W=97, qh=4, qw=5):
                      prior, profiles, theta0)
 
 
+def serving_field(seed=SEED_BASE + 5, n_sources=1500):
+    """A survey field from which region requests are cut: sources in overlapping groups of
+    1-5, patch sides 16-96, 5 bands, the survey's shared prior (the serving workload's
+    shapes)."""
+    return _grouped(f"serving_field_{n_sources}src_5b_side16-96", seed, n_sources, 16, 96, 1, "prior",
+                    prior_seed=SURVEY_PRIOR_SEED)
+
+
+def region_requests(field_prob, n, seed, max_sources=200):
+    """n region requests cut from a field: each a run of whole groups starting at a random
+    group, of U{1..max_sources} sources (shorter at the field's end); distinct requests are
+    distinct regions, and each holds its sources' patches and pixels only."""
+    rng = np.random.default_rng(seed)
+    gid = field_prob.truth["group"]
+    starts = np.concatenate([[0], np.nonzero(np.diff(gid))[0] + 1])
+    out = []
+    for _ in range(n):
+        g0 = int(rng.integers(0, len(starts)))
+        s0 = int(starts[g0])
+        want = int(rng.integers(1, max_sources + 1))
+        s1 = min(s0 + want, field_prob.n_sources)
+        # end on a group boundary (at least one whole group)
+        ends = starts[starts > s0]
+        cut = ends[ends <= s1]
+        s1 = int(cut[-1]) if len(cut) else (int(ends[0]) if len(ends) else field_prob.n_sources)
+        out.append(subset(field_prob, sources=range(s0, s1), name=f"region_{s0}-{s1}"))
+    return out
+
+
 def _extent_halfwidth(src, psf_sigma_max):
     """A conservative source extent in pixels (stand-in for a detector's extent estimate):
     a few times the PSF width plus the galaxy half-light radius, growing slowly with flux."""
