@@ -310,6 +310,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--pixels-per-lane", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default launch settings instead of tuning the plan")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-hessian", action="store_true")
@@ -338,6 +340,10 @@ def main():
     plan = api.Plan(ctx, prob)
     theta = torch.as_tensor(prob.theta0, device=dev)
     units = plan.n_units
+    tuning = None
+    if not (args.no_tune or args.pixels_per_lane or args.chunk):
+        tuning = plan.tune(theta)
+        log(f"tuned launch settings: {tuning}")
     log(f"{prob.name}: {units} active pixels, {plan.n_work_items} work items")
 
     for _ in range(args.warmup):
@@ -356,6 +362,8 @@ def main():
         f"{[round(x / max(ncalls, 1), 4) for x in ms_phase]}")
     assert np.isfinite(out[0].item())
 
+    ppl = tuning["pixels_per_lane"] if tuning else (args.pixels_per_lane or 2)
+    mppl = tuning["map_pixels_per_lane"] if tuning else 8
     pairs = covering_pairs(prob)
     flops = units * FLOP_OWN + pairs * FLOP_PAIR
     nb = max(ncalls, 1)
@@ -365,11 +373,12 @@ def main():
     bytes_fused = units * BYTES_UNIT + pairs * BYTES_PAIR
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=counted_traffic(),
-                    kernel="k_fused<float, 2 px/lane, grad>", kernel_ms=round(kernel_ms, 4),
+                    kernel=f"k_fused<float, {ppl} px/lane, grad>", kernel_ms=round(kernel_ms, 4),
                     algorithmic_flop_per_launch=flops, covering_pairs=pairs,
                     algorithmic_bytes_per_launch=bytes_fused,
                     achieved_hbm_GBps=round(bytes_fused / (kernel_ms * 1e-3) / 1e9, 1),
-                    map_kernel=dict(kernel="k_maps<float, 8 px/lane>", kernel_ms=round(maps_ms, 4),
+                    map_kernel=dict(kernel=(f"k_maps<float, {mppl} px/lane>" if mppl > 0 else "k_maps_runs<float>"),
+                                    kernel_ms=round(maps_ms, 4),
                                     achieved=round(units * FLOP_MAP / (maps_ms * 1e-3) / 1e12, 3),
                                     algorithmic_flop_per_launch=units * FLOP_MAP),
                     phases_ms=[round(x / nb, 4) for x in ms_phase])
@@ -418,7 +427,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": prob.name, "n_sources": prob.n_sources, "n_images": prob.n_images,
-                   "active_pixels": units, "seed": gen.SEED_BASE + 2},
+                   "active_pixels": units, "seed": gen.SEED_BASE + 2,
+                   "work_items": plan.n_work_items, "launch_tuning": tuning},
         "roofline": roofline, "cpu_baseline": cpu,
         "plain": plain, "batched_vs_plain": (value / plain["value"]) if plain else None,
         "p99_region_latency_ms": head["p99_ms"] if head else None,

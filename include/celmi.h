@@ -151,6 +151,10 @@ typedef struct {
                                     float32 gradients, 1e-3 with float64 ones             */
   double radius0, radius_max, eta, gtol, ftol, radius_min;   /* trust region (0 = default) */
   int32_t timing;                /* 1: record HIP events around each phase (see below)  */
+  int32_t map_pixels_per_lane;   /* neighbour moment maps: 1, 2, 4 or 8 (default; 0 in
+                                    the struct = default) pixels per lane 64 apart, values
+                                    directly; -1: runs of 8 pixels along a row, values by
+                                    recurrence                                           */
 } cel_options;
 
 typedef struct cel_ctx cel_ctx;
@@ -218,9 +222,9 @@ cel_status cel_elbo_grad(cel_ctx* ctx, const cel_plan* plan, const double* theta
  * library's first cel_create on that device until the process ends, instead of the plan's
  * own blocks.  It calls no allocating routine.  Same kernels and launch order as
  * cel_elbo_grad, so the outputs are bitwise identical.  Arguments as cel_elbo_grad.
- * Need in bytes (each part rounded up to 256): n_patches x 4656 (float64 pixels: 9312)
+ * Need in bytes (each part rounded up to 256): n_patches x 4928 (float64 pixels: 9856)
  * + active pixels x 8 (16) + work items x 128 + sources x 272; CEL_ESCRATCH beyond the
- * buffer (the 1000-source batched workload of 1.7e7 pixels needs 190 MB).  All calls on
+ * buffer (the 1000-source batched workload of 1.7e7 pixels needs 193 MB).  All calls on
  * one device share the buffer: calls that overlap in time on one device (several streams,
  * several host threads, several contexts) race and must be serialised by the caller; a
  * call's outputs are complete once its stream is synchronised. */
@@ -424,16 +428,47 @@ cel_status cel_mcmc_step(cel_ctx* ctx, const cel_plan* plan, const double* z_fix
  * CEL_EINVAL: null pointers with n > 0, n < 0. */
 cel_status cel_log_prior(cel_ctx* ctx, const cel_plan* plan, int64_t n, const double* z, double* out, void* stream);
 
-/* Launch tuning of the pixel pass (the paper's thread-level execution study and its remark
- * that sources of varying size make SIMD across sources hard): times the ELBO-and-gradient
- * evaluation at theta with 1, 2 and 4 pixels per lane (one warm-up and three timed calls
- * each, on `stream`, synchronised) and keeps the fastest in the plan; later evaluations,
- * Newton steps and sweeps of the plan use it (captured sweep graphs are dropped).  Outputs
- * of a plan are deterministic once its setting is fixed; different settings sum partial
- * results in different groupings (last-bit differences).  theta: DEVICE [S][32].
- * pixels_per_lane: HOST int32 out (may be NULL).  Writes no caller buffer but
- * pixels_per_lane; the plan's internal scratch holds the last timed evaluation. */
-cel_status cel_tune(cel_ctx* ctx, cel_plan* plan, const double* theta, int32_t* pixels_per_lane, void* stream);
+/* Candidate launch settings for cel_tune.  A count of 0 keeps the plan's current value of
+ * that setting; a NULL space means the defaults: work items of 256, 512, 1024 and 2048
+ * pixels; 1, 2 and 4 pixels per lane in the pixel pass; 1, 2, 4, 8 pixels per lane and the
+ * row-run variant (-1) in the moment-map pass.  Values as in cel_options. */
+typedef struct cel_tune_space {
+  int32_t n_chunk;
+  int32_t chunk_pixels[8];
+  int32_t n_pixels_per_lane;
+  int32_t pixels_per_lane[4];
+  int32_t n_map;
+  int32_t map_pixels_per_lane[6];
+} cel_tune_space;
+
+/* The settings cel_tune kept, and the time of one ELBO-and-gradient evaluation with them
+ * (the least of the timed calls). */
+typedef struct cel_tuning {
+  int32_t chunk_pixels;
+  int32_t pixels_per_lane;
+  int32_t map_pixels_per_lane;
+  int32_t n_timed;            /* settings timed */
+  double ms_per_eval;
+} cel_tuning;
+
+/* Launch tuning of the evaluation (the paper's thread-level execution study and its remark
+ * that sources of varying size make SIMD across sources hard), kept per plan.  Times the
+ * ELBO-and-gradient evaluation at theta (one warm-up and five timed calls per setting, the
+ * least time counts, on `stream`, synchronised) over the work-item size and the pixel
+ * pass's pixels per lane together, then over the moment-map variants at the chosen pair,
+ * and keeps the fastest in the plan: a new work-item size re-cuts the plan's work items
+ * (item tables, launch orders, per-colour lists and the scratch sized by the item count,
+ * as cel_prepare would have cut them with that chunk_pixels).  Later evaluations, Newton
+ * steps, sweeps, samplers and appends of the plan use the settings; captured sweep graphs
+ * are dropped.  A tuned plan gives, bit for bit, the outputs of a plan prepared on a
+ * context created with the kept settings; different settings sum partial results in
+ * different groupings (last-bit differences).  theta: DEVICE [S][32].  space: HOST, may be
+ * NULL.  out: HOST, may be NULL.  Writes no caller buffer but out; the plan's internal
+ * scratch holds the last timed evaluation.  CEL_EINVAL: a candidate outside cel_options'
+ * ranges or a count beyond its array.  On an error other than CEL_EINVAL the plan may only
+ * be freed. */
+cel_status cel_tune(cel_ctx* ctx, cel_plan* plan, const double* theta, const cel_tune_space* space,
+                    cel_tuning* out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -66,7 +66,7 @@ class CelOptions(C.Structure):
     _fields_ = [("pixels_per_lane", C.c_int32), ("chunk_pixels", C.c_int32), ("pixel_fp64", C.c_int32),
                 ("hessian_fp64", C.c_int32), ("hessian_fd", C.c_int32), ("fd_step", C.c_double), ("radius0", C.c_double),
                 ("radius_max", C.c_double), ("eta", C.c_double), ("gtol", C.c_double), ("ftol", C.c_double),
-                ("radius_min", C.c_double), ("timing", C.c_int32)]
+                ("radius_min", C.c_double), ("timing", C.c_int32), ("map_pixels_per_lane", C.c_int32)]
 
 
 class CelMcmcOpts(C.Structure):
@@ -78,6 +78,16 @@ class CelMcmcOpts(C.Structure):
 class CelMcmcReport(C.Structure):
     _fields_ = [("rounds", C.c_int64), ("n_chains", C.c_int64), ("evaluations", C.c_int64),
                 ("candidate_pixels", C.c_int64)]
+
+
+class CelTuneSpace(C.Structure):
+    _fields_ = [("n_chunk", C.c_int32), ("chunk_pixels", C.c_int32 * 8), ("n_pixels_per_lane", C.c_int32),
+                ("pixels_per_lane", C.c_int32 * 4), ("n_map", C.c_int32), ("map_pixels_per_lane", C.c_int32 * 6)]
+
+
+class CelTuning(C.Structure):
+    _fields_ = [("chunk_pixels", C.c_int32), ("pixels_per_lane", C.c_int32), ("map_pixels_per_lane", C.c_int32),
+                ("n_timed", C.c_int32), ("ms_per_eval", C.c_double)]
 
 
 class CelSweepOpts(C.Structure):
@@ -112,7 +122,7 @@ _sig = {
     "cel_elbo_hessian": (C.c_int32, [_vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, _vp, _vp, _vp]),
     "cel_newton_step": (C.c_int32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, _vp, _vp]),
     "cel_phase_times": (C.c_int32, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
-    "cel_tune": (C.c_int32, [_vp, _vp, _vp, C.POINTER(C.c_int32), _vp]),
+    "cel_tune": (C.c_int32, [_vp, _vp, _vp, C.POINTER(CelTuneSpace), C.POINTER(CelTuning), _vp]),
     "cel_loglik": (C.c_int32, [_vp, _vp, _vp, C.c_int32, _vp, C.POINTER(C.c_uint8), _vp, _vp]),
     "cel_log_prior": (C.c_int32, [_vp, _vp, C.c_int64, _vp, _vp, _vp]),
     "cel_sweep": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(CelSweepOpts), C.POINTER(CelSweepReport), _vp]),

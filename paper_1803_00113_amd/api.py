@@ -32,7 +32,7 @@ class Context:
     """A library context on one HIP device (cel_create)."""
 
     def __init__(self, device=0, pixels_per_lane=0, chunk_pixels=0, pixel_fp64=False, hessian_fp64=False,
-                 hessian_fd=False, fd_step=0.0, timing=False, **tr):
+                 hessian_fd=False, fd_step=0.0, timing=False, map_pixels_per_lane=0, **tr):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the celmi library needs an MI355X (gfx950)")
         o = F.CelOptions()
@@ -43,6 +43,7 @@ class Context:
         o.hessian_fd = int(bool(hessian_fd))
         o.fd_step = float(fd_step)
         o.timing = int(bool(timing))
+        o.map_pixels_per_lane = int(map_pixels_per_lane)
         for k in ("radius0", "radius_max", "eta", "gtol", "ftol", "radius_min"):
             setattr(o, k, float(tr.get(k, 0.0)))
         h = C.c_void_p()
@@ -217,13 +218,32 @@ class Plan:
         F.check("cel_phase_times", F.lib.cel_phase_times(self.h, ms, C.byref(n), int(bool(reset))))
         return list(ms), int(n.value)
 
-    def tune(self, theta):
-        """cel_tune: times the evaluation at theta with 1, 2 and 4 pixels per lane, keeps the
-        fastest for this plan and returns it."""
+    def tune(self, theta, chunk_pixels=None, pixels_per_lane=None, map_pixels_per_lane=None):
+        """cel_tune: times the gradient evaluation at theta over work-item sizes, pixel-pass
+        pixels per lane and moment-map variants (each argument a list of candidates; None:
+        the library's defaults; []: keep the plan's value), keeps the fastest settings for
+        this plan and returns them as a dict."""
         th = self._theta(theta)
-        ppl = C.c_int32()
-        F.check("cel_tune", F.lib.cel_tune(self.ctx.h, self.h, _ptr(th), C.byref(ppl), _stream(self.ctx.device)))
-        return int(ppl.value)
+        space = None
+        if not (chunk_pixels is None and pixels_per_lane is None and map_pixels_per_lane is None):
+            space = F.CelTuneSpace()
+            for name, vals, dflt in (("chunk", chunk_pixels, [256, 512, 1024, 2048]),
+                                     ("pixels_per_lane", pixels_per_lane, [1, 2, 4]),
+                                     ("map", map_pixels_per_lane, [1, 2, 4, 8, -1])):
+                vals = dflt if vals is None else list(vals)
+                arr = getattr(space, "chunk_pixels" if name == "chunk" else
+                              "map_pixels_per_lane" if name == "map" else "pixels_per_lane")
+                if len(vals) > len(arr):
+                    raise ValueError(f"at most {len(arr)} candidates for {name}")
+                for i, v in enumerate(vals):
+                    arr[i] = int(v)
+                setattr(space, "n_" + name, len(vals))
+        out = F.CelTuning()
+        F.check("cel_tune", F.lib.cel_tune(self.ctx.h, self.h, _ptr(th), C.byref(space) if space is not None else None,
+                                           C.byref(out), _stream(self.ctx.device)))
+        self._refresh()
+        return dict(chunk_pixels=out.chunk_pixels, pixels_per_lane=out.pixels_per_lane,
+                    map_pixels_per_lane=out.map_pixels_per_lane, n_timed=out.n_timed, ms_per_eval=out.ms_per_eval)
 
     def _out(self, *shape):
         return torch.empty(shape, dtype=torch.float64, device=self.ctx.device)

@@ -35,6 +35,7 @@ cel_options default_options() {
   std::memset(&o, 0, sizeof(o));
   o.pixels_per_lane = 2;
   o.chunk_pixels = 512;
+  o.map_pixels_per_lane = 8;
   o.fd_step = 0.0;   // resolved in merge_options: 1e-2 (float32 pixels), 1e-3 (float64)
   o.radius0 = 1.0;
   o.radius_max = 100.0;
@@ -50,6 +51,7 @@ static cel_options merge_options(const cel_options* in) {
   if (!in) return o;
   if (in->pixels_per_lane) o.pixels_per_lane = in->pixels_per_lane;
   if (in->chunk_pixels) o.chunk_pixels = in->chunk_pixels;
+  if (in->map_pixels_per_lane != 0) o.map_pixels_per_lane = in->map_pixels_per_lane;
   o.pixel_fp64 = in->pixel_fp64;
   o.hessian_fp64 = in->hessian_fp64;
   o.hessian_fd = in->hessian_fd;
@@ -567,6 +569,9 @@ extern "C" cel_status cel_create(cel_ctx** out, int32_t hip_device, const cel_op
   resolve_fd_step(o);
   if (!(o.pixels_per_lane == 1 || o.pixels_per_lane == 2 || o.pixels_per_lane == 4)) return CEL_EINVAL;
   if (o.chunk_pixels < 64 || o.chunk_pixels % 64 != 0 || o.chunk_pixels > (1 << 20)) return CEL_EINVAL;
+  if (!(o.map_pixels_per_lane == -1 || o.map_pixels_per_lane == 1 || o.map_pixels_per_lane == 2 ||
+        o.map_pixels_per_lane == 4 || o.map_pixels_per_lane == 8))
+    return CEL_EINVAL;
   if (hipSetDevice(hip_device) != hipSuccess) return CEL_EHIP;
   if (resolve_static_scratch(hip_device, nd) != CEL_OK) return CEL_EHIP;
   int32_t* err = nullptr;
@@ -611,6 +616,82 @@ extern "C" void cel_plan_free(cel_plan* plan) {
   (void)hipSetDevice(plan->device);
   plan_release(plan);
 }
+
+// The plan's work items at its chunk size (opt.chunk_pixels): the items of every patch, the
+// patches' item ranges, the launch order, the items the moment maps need and the per-colour
+// item lists.  Host tables only.
+namespace celmi {
+cel_status build_tiling(cel_plan* p) {
+  // work items: runs of chunk pixels per patch (patch-major), launch order by cost
+  // Cost of a work item: pixels x (1 + neighbour patches / 2), kept as the integer
+  // pixels x (2 + neighbour patches); the order is by decreasing cost, ties by item id
+  // (keys: inverted cost above the id).
+  const int CH = p->opt.chunk_pixels;
+  int64_t n_items = 0;
+  for (int i = 0; i < p->P; ++i) n_items += ((int64_t)p->patches_h[i].w * p->patches_h[i].h + CH - 1) / CH;
+  if (n_items > (int64_t)1 << 30) return CEL_EUNSUPPORTED;
+  p->tasks_h.clear();
+  p->tasks_h.reserve(n_items);
+  std::vector<uint64_t> keys;
+  keys.reserve(n_items);
+  for (int i = 0; i < p->P; ++i) {
+    DPatch& d = p->patches_h[i];
+    const int n = d.w * d.h;
+    d.task_begin = (int)p->tasks_h.size();
+    for (int b = 0; b < n; b += CH) {
+      DTask t;
+      t.patch = i;
+      t.pix_begin = b;
+      t.pix_end = std::min(n, b + CH);
+      t.pad = 0;
+      const uint64_t c = (uint64_t)(t.pix_end - t.pix_begin) * (uint64_t)(2 + (d.nbr_end - d.nbr_begin));
+      const uint64_t inv = 0xffffffffull - std::min<uint64_t>(c, 0xffffffffull);
+      keys.push_back((inv << 32) | (uint64_t)p->tasks_h.size());
+      p->tasks_h.push_back(t);
+    }
+    d.task_end = (int)p->tasks_h.size();
+  }
+  p->n_tasks = (int64_t)p->tasks_h.size();
+  // stable LSD radix sort on the inverted cost (the ids are generated in ascending order)
+  {
+    std::vector<uint64_t> tmp(keys.size());
+    for (int pass = 0; pass < 4; ++pass) {
+      const int shift = 32 + 8 * pass;
+      size_t count[257] = {0};
+      for (uint64_t k : keys) ++count[((k >> shift) & 0xff) + 1];
+      for (int b = 0; b < 256; ++b) count[b + 1] += count[b];
+      for (uint64_t k : keys) tmp[count[(k >> shift) & 0xff]++] = k;
+      keys.swap(tmp);
+    }
+  }
+  p->order_h.resize(p->n_tasks);
+  for (int64_t i = 0; i < p->n_tasks; ++i) p->order_h[i] = (int32_t)(keys[i] & 0xffffffffull);
+  // the moment maps are read only where another source's patch overlaps: keep the work
+  // items whose pixel rows meet a neighbour's rectangle
+  p->map_order_h.clear();
+  for (int t : p->order_h) {
+    const DTask& tk = p->tasks_h[t];
+    const DPatch& d = p->patches_h[tk.patch];
+    const int r0 = d.y0 + tk.pix_begin / d.w, r1 = d.y0 + (tk.pix_end - 1) / d.w;
+    const int c0 = r0 == r1 ? d.x0 + tk.pix_begin % d.w : d.x0;
+    const int c1 = r0 == r1 ? d.x0 + (tk.pix_end - 1) % d.w : d.x0 + d.w - 1;
+    bool need = false;
+    for (int nb = d.nbr_begin; nb < d.nbr_end && !need; ++nb) {
+      const DPatch& q = p->patches_h[p->nbr_idx_h[nb]];
+      need = q.x0 <= c1 && c0 < q.x0 + q.w && q.y0 <= r1 && r0 < q.y0 + q.h;
+    }
+    if (need) p->map_order_h.push_back(t);
+  }
+  // per-colour work-item lists (for masked launches), in launch order
+  p->class_tasks.resize(std::max<size_t>(p->class_tasks.size(), (size_t)p->n_colours));
+  for (int c = 0; c < p->n_colours; ++c) p->class_tasks[c].clear();
+  for (int i : p->order_h) {
+    const int c = p->colour[p->patches_h[p->tasks_h[i].patch].src];
+    p->class_tasks[c].push_back(i);
+  }
+  return CEL_OK;
+}
+}  // namespace celmi
 
 extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan** out, void* stream) {
   if (!ctx || !out) return CEL_EINVAL;
@@ -717,86 +798,21 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
       p->n_colours = std::max(p->n_colours, c + 1);
     }
   }
-  // work items: runs of chunk pixels per patch (patch-major), launch order by cost
-  // Cost of a work item: pixels x (1 + neighbour patches / 2), kept as the integer
-  // pixels x (2 + neighbour patches); the order is by decreasing cost, ties by item id
-  // (keys: inverted cost above the id).
-  const int CH = p->opt.chunk_pixels;
-  int64_t n_items = 0;
-  for (int i = 0; i < P; ++i) n_items += ((int64_t)p->patches_h[i].w * p->patches_h[i].h + CH - 1) / CH;
-  if (n_items > (int64_t)1 << 30) {
-    plan_release(p);
-    return CEL_EUNSUPPORTED;
-  }
-  p->tasks_h.clear();
-  p->tasks_h.reserve(n_items);
-  std::vector<uint64_t> keys;
-  keys.reserve(n_items);
-  for (int i = 0; i < P; ++i) {
-    DPatch& d = p->patches_h[i];
-    const int n = d.w * d.h;
-    d.task_begin = (int)p->tasks_h.size();
-    for (int b = 0; b < n; b += CH) {
-      DTask t;
-      t.patch = i;
-      t.pix_begin = b;
-      t.pix_end = std::min(n, b + CH);
-      t.pad = 0;
-      const uint64_t c = (uint64_t)(t.pix_end - t.pix_begin) * (uint64_t)(2 + (d.nbr_end - d.nbr_begin));
-      const uint64_t inv = 0xffffffffull - std::min<uint64_t>(c, 0xffffffffull);
-      keys.push_back((inv << 32) | (uint64_t)p->tasks_h.size());
-      p->tasks_h.push_back(t);
-    }
-    d.task_end = (int)p->tasks_h.size();
-  }
-  p->n_tasks = (int64_t)p->tasks_h.size();
-  p->cap_S = S;
-  p->cap_P = P;
-  p->cap_T = p->n_tasks;
-  p->cap_U = p->n_units;
-  // stable LSD radix sort on the inverted cost (the ids are generated in ascending order)
-  {
-    std::vector<uint64_t> tmp(keys.size());
-    for (int pass = 0; pass < 4; ++pass) {
-      const int shift = 32 + 8 * pass;
-      size_t count[257] = {0};
-      for (uint64_t k : keys) ++count[((k >> shift) & 0xff) + 1];
-      for (int b = 0; b < 256; ++b) count[b + 1] += count[b];
-      for (uint64_t k : keys) tmp[count[(k >> shift) & 0xff]++] = k;
-      keys.swap(tmp);
-    }
-  }
-  p->order_h.resize(p->n_tasks);
-  for (int64_t i = 0; i < p->n_tasks; ++i) p->order_h[i] = (int32_t)(keys[i] & 0xffffffffull);
-  // the moment maps are read only where another source's patch overlaps: keep the work
-  // items whose pixel rows meet a neighbour's rectangle
-  p->map_order_h.clear();
-  for (int t : p->order_h) {
-    const DTask& tk = p->tasks_h[t];
-    const DPatch& d = p->patches_h[tk.patch];
-    const int r0 = d.y0 + tk.pix_begin / d.w, r1 = d.y0 + (tk.pix_end - 1) / d.w;
-    const int c0 = r0 == r1 ? d.x0 + tk.pix_begin % d.w : d.x0;
-    const int c1 = r0 == r1 ? d.x0 + (tk.pix_end - 1) % d.w : d.x0 + d.w - 1;
-    bool need = false;
-    for (int nb = d.nbr_begin; nb < d.nbr_end && !need; ++nb) {
-      const DPatch& q = p->patches_h[p->nbr_idx_h[nb]];
-      need = q.x0 <= c1 && c0 < q.x0 + q.w && q.y0 <= r1 && r0 < q.y0 + q.h;
-    }
-    if (need) p->map_order_h.push_back(t);
-  }
-  // per-colour lists of patches and work items (for masked launches)
   p->class_patches.assign(p->n_colours, {});
-  p->class_tasks.assign(p->n_colours, {});
   p->class_src.assign(p->n_colours, {});
   for (int s = 0; s < S; ++s) {
     const int c = p->colour[s];
     p->class_src[c].push_back(s);
     for (int i = p->patch_ptr_h[s]; i < p->patch_ptr_h[s + 1]; ++i) p->class_patches[c].push_back(i);
   }
-  for (int i : p->order_h) {
-    const int c = p->colour[p->patches_h[p->tasks_h[i].patch].src];
-    p->class_tasks[c].push_back(i);
+  if ((st = build_tiling(p))) {
+    plan_release(p);
+    return st;
   }
+  p->cap_S = S;
+  p->cap_P = P;
+  p->cap_T = p->n_tasks;
+  p->cap_U = p->n_units;
   // prior tables
   {
     const cel_prior& pp = *pr->prior;
@@ -946,8 +962,7 @@ static hipError_t launch_maps_t(cel_plan* p, const Table<T>* tables, hipStream_t
   ma.base = tables;
   ma.maps = sizeof(T) == 8 ? (void*)p->d_maps64 : (void*)p->d_maps;
   ma.img_npsf = p->d_npsf;
-  // the value-only pass keeps 8 pixels per lane: more independent exponentials per wavefront
-  return launch_maps<T>(ma, p->nexp, p->ndev, 8, (int)p->map_order_h.size(), sm);
+  return launch_maps<T>(ma, p->nexp, p->ndev, p->opt.map_pixels_per_lane, (int)p->map_order_h.size(), sm);
 }
 
 // Enqueue prep + fused + finalize for `nv` variants starting at variant v0 over either all
@@ -1386,54 +1401,116 @@ extern "C" cel_status cel_log_prior(cel_ctx* ctx, const cel_plan* plan, int64_t 
   return launch_log_prior(plan->d_prior, z, n, out, (hipStream_t)stream) == hipSuccess ? CEL_OK : CEL_EHIP;
 }
 
-extern "C" cel_status cel_tune(cel_ctx* ctx, cel_plan* p, const double* theta, int32_t* pixels_per_lane,
-                                void* stream) {
+static bool valid_chunk(int c) { return c >= 64 && c % 64 == 0 && c <= (1 << 20); }
+static bool valid_ppl(int c) { return c == 1 || c == 2 || c == 4; }
+static bool valid_map(int c) { return c == -1 || c == 1 || c == 2 || c == 4 || c == 8; }
+
+extern "C" cel_status cel_tune(cel_ctx* ctx, cel_plan* p, const double* theta, const cel_tune_space* space,
+                               cel_tuning* out, void* stream) {
   if (!ctx || !p || (!theta && p->S > 0)) return CEL_EINVAL;
+  std::vector<int> chunks{256, 512, 1024, 2048}, ppls{1, 2, 4}, maps{1, 2, 4, 8, -1};
+  if (space) {
+    if (space->n_chunk < 0 || space->n_chunk > 8 || space->n_pixels_per_lane < 0 || space->n_pixels_per_lane > 4 ||
+        space->n_map < 0 || space->n_map > 6)
+      return CEL_EINVAL;
+    chunks.assign(space->chunk_pixels, space->chunk_pixels + space->n_chunk);
+    ppls.assign(space->pixels_per_lane, space->pixels_per_lane + space->n_pixels_per_lane);
+    maps.assign(space->map_pixels_per_lane, space->map_pixels_per_lane + space->n_map);
+  }
+  for (int c : chunks)
+    if (!valid_chunk(c)) return CEL_EINVAL;
+  for (int c : ppls)
+    if (!valid_ppl(c)) return CEL_EINVAL;
+  for (int c : maps)
+    if (!valid_map(c)) return CEL_EINVAL;
+  if (chunks.empty()) chunks.push_back(p->opt.chunk_pixels);
+  if (ppls.empty()) ppls.push_back(p->opt.pixels_per_lane);
+  if (maps.empty()) maps.push_back(p->opt.map_pixels_per_lane);
   if (hipSetDevice(p->device) != hipSuccess) return CEL_EHIP;
-  const int keep = p->opt.pixels_per_lane;
+  cel_tuning res{p->opt.chunk_pixels, p->opt.pixels_per_lane, p->opt.map_pixels_per_lane, 0, 0.0};
   if (p->S == 0) {
-    if (pixels_per_lane) *pixels_per_lane = keep;
+    if (out) *out = res;
     return CEL_OK;
   }
   hipStream_t sm = (hipStream_t)stream;
   const bool fp64 = p->opt.pixel_fp64 != 0;
-  cel_status st = ensure_variants(p, 1, fp64);
-  if (st) return st;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
-    if (ev[0]) (void)hipEventDestroy(ev[0]);
-    return CEL_EHIP;
-  }
+  constexpr int kReps = 5;
+  hipEvent_t ev[kReps + 1] = {};
+  for (auto& x : ev)
+    if (hipEventCreate(&x) != hipSuccess) {
+      for (auto& y : ev)
+        if (y) (void)hipEventDestroy(y);
+      return CEL_EHIP;
+    }
   const bool marking = p->marking;
   p->marking = false;
-  int best = keep;
-  float best_ms = INFINITY;
-  hipError_t e = hipSuccess;
-  for (int c : {1, 2, 4}) {
-    p->opt.pixels_per_lane = c;
-    e = eval_any(p, theta, nullptr, 0, 1, true, -1, nullptr, sm, true, fp64);   // warm-up
-    if (e == hipSuccess) e = hipEventRecord(ev[0], sm);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = eval_any(p, theta, nullptr, 0, 1, true, -1, nullptr, sm, true, fp64);
-    if (e == hipSuccess) e = hipEventRecord(ev[1], sm);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-    if (e != hipSuccess) break;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = c;
+  // the least time of kReps evaluations after a warm-up, in ms (negative on a HIP error)
+  auto time_it = [&]() -> double {
+    hipError_t e = eval_any(p, theta, nullptr, 0, 1, true, -1, nullptr, sm, true, fp64);
+    for (int r = 0; r <= kReps && e == hipSuccess; ++r) {
+      e = hipEventRecord(ev[r], sm);
+      if (e == hipSuccess && r < kReps) e = eval_any(p, theta, nullptr, 0, 1, true, -1, nullptr, sm, true, fp64);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[kReps]);
+    double best = INFINITY;
+    for (int r = 0; r < kReps && e == hipSuccess; ++r) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[r], ev[r + 1]);
+      best = std::min(best, (double)ms);
+    }
+    ++res.n_timed;
+    return e == hipSuccess ? best : -1.0;
+  };
+  cel_status st = CEL_OK;
+  double best_ms = INFINITY;
+  // work-item size and pixel-pass lanes together (the pass's cost depends on both) ...
+  for (int c : chunks) {
+    if ((st = plan_retile(p, c, sm))) break;
+    if ((st = ensure_variants(p, 1, fp64))) break;
+    for (int l : ppls) {
+      p->opt.pixels_per_lane = l;
+      const double ms = time_it();
+      if (ms < 0) {
+        st = CEL_EHIP;
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        res.chunk_pixels = c;
+        res.pixels_per_lane = l;
+      }
+    }
+    if (st) break;
+  }
+  // ... then the moment-map variant at the chosen pair
+  if (!st) st = plan_retile(p, res.chunk_pixels, sm);
+  if (!st) {
+    p->opt.pixels_per_lane = res.pixels_per_lane;
+    best_ms = INFINITY;
+    for (int m : maps) {
+      p->opt.map_pixels_per_lane = m;
+      const double ms = time_it();
+      if (ms < 0) {
+        st = CEL_EHIP;
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        res.map_pixels_per_lane = m;
+      }
     }
   }
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
+  for (auto& x : ev) (void)hipEventDestroy(x);
   p->marking = marking;
-  p->opt.pixels_per_lane = e == hipSuccess ? best : keep;
-  // sweep graphs captured with the previous setting are rebuilt on their next use
+  p->opt.pixels_per_lane = res.pixels_per_lane;
+  p->opt.map_pixels_per_lane = res.map_pixels_per_lane;
+  res.ms_per_eval = best_ms;
+  // sweep graphs captured with another setting are rebuilt on their next use
   for (auto& g : p->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   p->graphs.clear();
-  if (pixels_per_lane) *pixels_per_lane = p->opt.pixels_per_lane;
-  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+  if (out) *out = res;
+  return st;
 }
 
 extern "C" cel_status cel_phase_times(cel_plan* p, double* ms, int64_t* n_calls, int32_t reset) {

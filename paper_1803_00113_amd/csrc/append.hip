@@ -64,6 +64,70 @@ struct Growth {
   }
 };
 
+// Give up the per-call scratch sized by the plan's capacities (component tables, slot rows,
+// per-source outputs, moment maps, point and Newton buffers); the caller allocates it again
+// at the new capacities.  The blocks go back once the queued copies are done.
+cel_status drop_scratch(Growth& g) {
+  cel_plan* p = g.p;
+  for (void* b : {(void*)p->tables_f, (void*)p->tables_d, (void*)p->slots, (void*)p->v_local, (void*)p->v_own,
+                  (void*)p->v_grad, (void*)p->d_maps, (void*)p->d_maps64, (void*)p->d_pt_theta, (void*)p->d_pt_ok})
+    g.old_blocks.push_back(b);
+  p->tables_f = nullptr;
+  p->tables_d = nullptr;
+  p->slots = p->v_local = p->v_own = p->v_grad = nullptr;
+  p->nv_f = p->nv_d = p->nv_slots = 0;
+  p->d_pt_theta = nullptr;
+  p->d_pt_ok = nullptr;
+  p->pt_cap = 0;
+  if (p->newton_ready) {
+    for (void* b : {(void*)p->d_theta_trial, (void*)p->d_pred, (void*)p->d_step_norm, (void*)p->d_trial_active,
+                    (void*)p->d_mask, (void*)p->d_counter, (void*)p->d_hslots, (void*)p->d_step_src,
+                    (void*)p->d_step_patches, (void*)p->d_step_tasks, (void*)p->d_hess, (void*)p->d_hpart})
+      g.old_blocks.push_back(b);
+    p->newton_ready = false;
+  }
+  const bool m64 = p->d_maps64 != nullptr;
+  p->d_maps = nullptr;
+  p->d_maps64 = nullptr;
+  void* b = nullptr;
+  cel_status st = plan_alloc(p, (size_t)std::max<int64_t>(p->cap_U, 1) * sizeof(float2), &b);
+  if (st) return st;
+  p->d_maps = static_cast<float2*>(b);
+  if (m64) {
+    if ((st = plan_alloc(p, (size_t)std::max<int64_t>(p->cap_U, 1) * sizeof(double2), &b))) return st;
+    p->d_maps64 = static_cast<double2*>(b);
+  }
+  return CEL_OK;
+}
+
+// After a change of the class lists or of the capacities: the evaluation scratch exists
+// again, the Newton scratch too when the plan had it, and the step class (entry n_colours of
+// the class lists) points at the Newton step's lists.  Captured sweep graphs, which hold the
+// old arrays and class sizes, are dropped.
+cel_status restore_scratch(cel_plan* p, bool had_step) {
+  cel_status st = ensure_variants(p, 1, p->opt.pixel_fp64 != 0);
+  if (st) return st;
+  if (had_step) {
+    if (p->newton_ready) {
+      p->class_src.resize(p->n_colours + 1);
+      p->class_patches.resize(p->n_colours + 1);
+      p->class_tasks.resize(p->n_colours + 1);
+      p->d_class_src.resize(p->n_colours + 1);
+      p->d_class_patches.resize(p->n_colours + 1);
+      p->d_class_tasks.resize(p->n_colours + 1);
+      p->d_class_src[p->n_colours] = p->d_step_src;
+      p->d_class_patches[p->n_colours] = p->d_step_patches;
+      p->d_class_tasks[p->n_colours] = p->d_step_tasks;
+    } else if ((st = ensure_newton(p))) {
+      return st;
+    }
+  }
+  for (auto& gr : p->graphs)
+    if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+  p->graphs.clear();
+  return CEL_OK;
+}
+
 }  // namespace
 
 extern "C" void cel_plan_free(cel_plan* plan);
@@ -87,6 +151,11 @@ extern "C" cel_status cel_plan_append(cel_ctx* ctx, cel_plan* p, const cel_probl
   if (hipSetDevice(p->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     cel_plan_free(q);
     return CEL_EHIP;
+  }
+  // the part's work items are cut at the plan's size (cel_tune may have changed it)
+  if ((st = plan_retile(q, p->opt.chunk_pixels, sm))) {
+    cel_plan_free(q);
+    return st;
   }
   const int S0 = p->S, N0 = p->N, P0 = p->P;
   const int64_t U0 = p->n_units, T0 = p->n_tasks;
@@ -203,73 +272,63 @@ extern "C" cel_status cel_plan_append(cel_ctx* ctx, cel_plan* p, const cel_probl
     return st;
   }
   // --- per-call scratch: regrown when the plan outgrows its capacities -------------------
-  const bool regrow = S > p->cap_S || P > p->cap_P || T > p->cap_T || U > p->cap_U;
-  if (regrow) {
+  if (S > p->cap_S || P > p->cap_P || T > p->cap_T || U > p->cap_U) {
     p->cap_S = std::max<int64_t>(S, 2 * p->cap_S);
     p->cap_P = std::max<int64_t>(P, 2 * p->cap_P);
     p->cap_T = std::max<int64_t>(T, 2 * p->cap_T);
     p->cap_U = std::max<int64_t>(U, 2 * p->cap_U);
-    for (void* b : {(void*)p->tables_f, (void*)p->tables_d, (void*)p->slots, (void*)p->v_local, (void*)p->v_own,
-                    (void*)p->v_grad, (void*)p->d_maps, (void*)p->d_maps64, (void*)p->d_pt_theta, (void*)p->d_pt_ok})
-      g.old_blocks.push_back(b);
-    p->tables_f = nullptr;
-    p->tables_d = nullptr;
-    p->slots = p->v_local = p->v_own = p->v_grad = nullptr;
-    p->nv_f = p->nv_d = p->nv_slots = 0;
-    p->d_pt_theta = nullptr;
-    p->d_pt_ok = nullptr;
-    p->pt_cap = 0;
-    if (p->newton_ready) {
-      for (void* b : {(void*)p->d_theta_trial, (void*)p->d_pred, (void*)p->d_step_norm, (void*)p->d_trial_active,
-                      (void*)p->d_mask, (void*)p->d_counter, (void*)p->d_hslots, (void*)p->d_step_src,
-                      (void*)p->d_step_patches, (void*)p->d_step_tasks, (void*)p->d_hess, (void*)p->d_hpart})
-        g.old_blocks.push_back(b);
-      p->newton_ready = false;
-    }
-    const bool m64 = p->d_maps64 != nullptr;
-    p->d_maps = nullptr;
-    p->d_maps64 = nullptr;
-    void* b = nullptr;
-    if ((st = plan_alloc(p, (size_t)p->cap_U * sizeof(float2), &b))) {
+    if ((st = drop_scratch(g))) {
       cel_plan_free(q);
       return st;
-    }
-    p->d_maps = static_cast<float2*>(b);
-    if (m64) {
-      if ((st = plan_alloc(p, (size_t)p->cap_U * sizeof(double2), &b))) {
-        cel_plan_free(q);
-        return st;
-      }
-      p->d_maps64 = static_cast<double2*>(b);
     }
   }
   // the evaluation calls allocate nothing: their scratch exists before they are made
-  if ((st = ensure_variants(p, 1, p->opt.pixel_fp64 != 0))) {
+  if ((st = restore_scratch(p, had_step))) {
     cel_plan_free(q);
     return st;
   }
-  if (had_step) {
-    if (p->newton_ready) {   // the step class entry follows the (possibly new) colour count
-      p->class_src.resize(p->n_colours + 1);
-      p->class_patches.resize(p->n_colours + 1);
-      p->class_tasks.resize(p->n_colours + 1);
-      p->d_class_src.resize(p->n_colours + 1);
-      p->d_class_patches.resize(p->n_colours + 1);
-      p->d_class_tasks.resize(p->n_colours + 1);
-      p->d_class_src[p->n_colours] = p->d_step_src;
-      p->d_class_patches[p->n_colours] = p->d_step_patches;
-      p->d_class_tasks[p->n_colours] = p->d_step_tasks;
-    } else if ((st = ensure_newton(p))) {
-      cel_plan_free(q);
-      return st;
-    }
-  }
-  // captured sweep graphs hold the old arrays and class sizes
-  for (auto& gr : p->graphs)
-    if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
-  p->graphs.clear();
   hipError_t e = hipStreamSynchronize(sm);
   for (void* b : g.old_blocks) plan_untrack(p, b);
   cel_plan_free(q);
+  return e == hipSuccess ? CEL_OK : CEL_EHIP;
+}
+
+cel_status celmi::plan_retile(cel_plan* p, int chunk, hipStream_t sm) {
+  if (chunk == p->opt.chunk_pixels) return CEL_OK;
+  if (hipSetDevice(p->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return CEL_EHIP;
+  const int keep = p->opt.chunk_pixels;
+  const bool had_step = p->newton_ready;
+  p->opt.chunk_pixels = chunk;
+  cel_status st = build_tiling(p);
+  if (st) {   // too many items: the old cut stays
+    p->opt.chunk_pixels = keep;
+    (void)build_tiling(p);
+    return st;
+  }
+  const int64_t T = p->n_tasks;
+  const int C = p->n_colours;
+  Growth g{p, sm, {}};
+  const auto H2D = hipMemcpyHostToDevice;
+  // the patches' item ranges changed in place; the item lists are written whole
+  if ((st = g.put(p->d_patches, p->patches_h.data(), p->patches_h.size(), H2D)) ||
+      (st = g.grow(&p->d_tasks, 0, T)) || (st = g.put(p->d_tasks, p->tasks_h.data(), T, H2D)) ||
+      (st = g.grow(&p->d_order, 0, T)) || (st = g.put(p->d_order, p->order_h.data(), T, H2D)) ||
+      (st = g.grow(&p->d_map_order, 0, p->map_order_h.size())) ||
+      (st = g.put(p->d_map_order, p->map_order_h.data(), p->map_order_h.size(), H2D)))
+    return st;
+  for (int k = 0; k < 3; ++k) p->cls_cap[k].resize(std::max<size_t>(p->cls_cap[k].size(), C), 0);
+  for (int c = 0; c < C; ++c) {
+    const size_t nt = p->class_tasks[c].size();
+    if ((st = g.grow(&p->d_class_tasks[c], 0, nt, &p->cls_cap[2][c])) ||
+        (st = g.put(p->d_class_tasks[c], p->class_tasks[c].data(), nt, H2D)))
+      return st;
+  }
+  if (T > p->cap_T) {
+    p->cap_T = T;
+    if ((st = drop_scratch(g))) return st;
+  }
+  if ((st = restore_scratch(p, had_step))) return st;
+  hipError_t e = hipStreamSynchronize(sm);
+  for (void* b : g.old_blocks) plan_untrack(p, b);
   return e == hipSuccess ? CEL_OK : CEL_EHIP;
 }

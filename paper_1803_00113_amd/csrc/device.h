@@ -47,6 +47,9 @@ enum Slot {
 //   component at offset d from its centre is q0 dx^2 + q1 (2 dx dy) + q2 dy^2 + q3
 //   (values-only evaluation: neighbour maps, Hessian)
 // off[k]: centre of PSF component k minus mu (the PSF mean offset)
+// rq[k][0], rq[k][1 + j]: exp(-P_xx) of the star and of galaxy component j = 2^(2 q0), the
+//   factor by which the ratio of a component's values at consecutive columns changes
+//   (values along a row by recurrence: neighbour maps)
 template <typename T>
 struct alignas(16) Table {
   T hdr[16];
@@ -58,6 +61,7 @@ struct alignas(16) Table {
   T sq[kMaxPsf][4];
   T gq[kMaxPsf][2 * kMaxProf][4];
   T off[kMaxPsf][2];
+  T rq[kMaxPsf][1 + 2 * kMaxProf];
 };
 
 struct DPatch {

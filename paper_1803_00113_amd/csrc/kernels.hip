@@ -178,6 +178,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
       for (int e = 0; e < 4; ++e) tb->sq[k][e] = qv[e];
       tb->off[k][0] = (T)ox;
       tb->off[k][1] = (T)oy;
+      tb->rq[k][0] = (T)exp(-Pxx);
     } else {
       T* r = tb->gal[k][j];
       r[0] = pv[0];
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
       r[2] = pv[2];
       r[3] = (T)lw;
       tb->rc2[k][j] = (T)rc2 + (T)0;
+      tb->rq[k][1 + j] = (T)exp(-Pxx);
 #pragma unroll
       for (int e = 0; e < 4; ++e) tb->gq[k][j][e] = qv[e];
       const double h = 0.5 * tau * tau;
@@ -392,6 +394,111 @@ __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
       }
       px[i] = c;
       py[i] = r;
+    }
+  }
+}
+
+// Values of one mixture component over a run of kRun consecutive pixels of one row,
+// accumulated into acc[0..kRun): x0 the first pixel's column offset from the component's
+// centre, dy the row offset, q = (q0, q1, q2, log2 weight) its exponent record, c = 2^(2 q0).
+// The exponent is quadratic along the row, so the value is advanced by the ratio
+// r(x) = 2^(q(x+1) - q(x)), and r by the constant factor c: two products per pixel instead of
+// an exponent and an exponential.  The first value is the direct one; a first value below
+// 2^-100 is formed 2^64 larger and scaled back as it is accumulated, so that a run rising
+// towards the centre never starts from an underflowed value.
+constexpr int kRun = 8;
+template <typename T>
+__device__ __forceinline__ void comp_run(const T* __restrict__ q, T c, T x0, T dy, T* acc) {
+  const T e0 = fma(q[0], x0 * x0, fma(q[1], (T)2 * x0 * dy, fma(q[2], dy * dy, q[3])));
+  const bool low = e0 < (T)-100;
+  T v = fexp2<T>(low ? e0 + (T)64 : e0);
+  const T scale = low ? (T)5.42101086242752217e-20 : (T)1;   // 2^-64
+  T r = fexp2<T>(fma(q[0], fma((T)2, x0, (T)1), (T)2 * q[1] * dy));
+  acc[0] = fma(v, scale, acc[0]);
+#pragma unroll
+  for (int k = 1; k < kRun; ++k) {
+    v *= r;
+    r *= c;
+    acc[k] = fma(v, scale, acc[k]);
+  }
+}
+
+// k_maps_runs: the same moments as k_maps, each lane taking a run of up to kRun consecutive
+// pixels of one row of the work item (runs are cut at row ends), values by recurrence along
+// the run.  Runs of one row: ceil(row length / kRun); the work item's rows: a partial first
+// row, full rows, a partial last row.
+template <typename T, int NEXP, int NDEV>
+__global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
+  const int pos = xcd_position((int)blockIdx.x, (int)gridDim.x);
+  const int t = a.order ? a.order[pos] : pos;
+  const DTask task = a.tasks[t];
+  const DPatch P = a.patches[task.patch];
+  const Table<T>* __restrict__ tb = reinterpret_cast<const Table<T>*>(a.base) + task.patch;
+  const int K = a.img_npsf[P.img];
+  const int lane = threadIdx.x;
+  const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
+  const T k0 = tb->hdr[4], k1 = tb->hdr[5], w01 = tb->hdr[6], pi = tb->hdr[7];
+  const bool use_gal = tb->hdr[2] != (T)0, use_star = tb->hdr[3] != (T)0;
+  const int w = P.w, pb = task.pix_begin, pe = task.pix_end;
+  if (pe <= pb) return;
+  const int r0 = pb / w, r1 = (pe - 1) / w;
+  const int c_first = pb - r0 * w;
+  const int len_first = r0 == r1 ? pe - pb : w - c_first;
+  const int n_first = (len_first + kRun - 1) / kRun;
+  const int per_row = (w + kRun - 1) / kRun;
+  const int n_mid = r1 > r0 + 1 ? (r1 - r0 - 1) * per_row : 0;
+  const int len_last = r0 == r1 ? 0 : pe - r1 * w;
+  const int n_runs = n_first + n_mid + (len_last + kRun - 1) / kRun;
+  T box[4];
+  run_box<T>(pb, pe, w, box);   // the whole work item (one pass or several)
+  for (int g0 = 0; g0 < n_runs; g0 += 64) {
+    const int g = g0 + lane;
+    int row, col0, len;
+    if (g < n_first) {
+      row = r0;
+      col0 = c_first + kRun * g;
+      len = min(kRun, len_first - kRun * g);
+    } else if (g < n_first + n_mid) {
+      const int h = g - n_first, rr = h / per_row, sgm = h - rr * per_row;
+      row = r0 + 1 + rr;
+      col0 = kRun * sgm;
+      len = min(kRun, w - kRun * sgm);
+    } else {
+      const int sgm = g - n_first - n_mid;
+      row = r1;
+      col0 = kRun * sgm;
+      len = min(kRun, len_last - kRun * sgm);
+    }
+    if (g >= n_runs) len = 0;
+    T fe[kRun], fd[kRun], f1[kRun];
+#pragma unroll
+    for (int i = 0; i < kRun; ++i) fe[i] = fd[i] = f1[i] = (T)0;
+    for (int k = 0; k < K; ++k) {
+      const T mx = tb->star[k][0], my = tb->star[k][1];
+      const T x0 = (T)col0 - mx, dy = (T)row - my;
+      const T d2 = box_dist2<T>(mx, my, box);
+      const auto d2s = uniform_cut_key(use_star ? d2 : (T)INFINITY), d2g = uniform_cut_key(use_gal ? d2 : (T)INFINITY);
+      if (!(d2s > cut_key(tb->rc2s[k]))) comp_run<T>(tb->sq[k], tb->rq[k][0], x0, dy, f1);
+#pragma unroll
+      for (int j = 0; j < NEXP; ++j)
+        if (!(d2g > cut_key(tb->rc2[k][j]))) comp_run<T>(tb->gq[k][j], tb->rq[k][1 + j], x0, dy, fe);
+#pragma unroll
+      for (int j = 0; j < NDEV; ++j)
+        if (!(d2g > cut_key(tb->rc2[k][kMaxProf + j])))
+          comp_run<T>(tb->gq[k][kMaxProf + j], tb->rq[k][1 + kMaxProf + j], x0, dy, fd);
+    }
+    const int64_t at = P.off + (int64_t)row * w + col0;
+#pragma unroll
+    for (int i = 0; i < kRun; ++i) {
+      if (i >= len) break;
+      const T f0 = pi * fd[i] + ((T)1 - pi) * fe[i];
+      const T a0 = L0 * f0, a1 = L1 * f1[i], d = a0 - a1;
+      const T Es = w0 * a0 + w1 * a1;
+      const T Vs = fma(k0 * f0, f0, fma(k1 * f1[i], f1[i], w01 * d * d));
+      if constexpr (sizeof(T) == 8)
+        reinterpret_cast<double2*>(a.maps)[at + i] = make_double2(Es, Vs);
+      else
+        reinterpret_cast<float2*>(a.maps)[at + i] = make_float2(Es, Vs);
     }
   }
 }
@@ -873,6 +980,9 @@ hipError_t launch_maps(const MapArgs& a, int nexp, int ndev, int ppl, int n_item
   } else if (ppl == 8) {
     if (std_prof) hipLaunchKernelGGL((k_maps<T, 8, 6, 8>), dim3(n_items), dim3(64), 0, st, a);
     else hipLaunchKernelGGL((k_maps<T, 8, 8, 8>), dim3(n_items), dim3(64), 0, st, a);
+  } else if (ppl == -1) {   // runs along rows, values by recurrence
+    if (std_prof) hipLaunchKernelGGL((k_maps_runs<T, 6, 8>), dim3(n_items), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_maps_runs<T, 8, 8>), dim3(n_items), dim3(64), 0, st, a);
   } else {
     return hipErrorInvalidValue;
   }

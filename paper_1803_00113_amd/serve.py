@@ -34,8 +34,9 @@ VARIANTS_EXACT = 2           # Newton with the exact Hessian: iterate, trial
 VARIANTS_FD = 56             # Newton with a difference Hessian: iterate, 54 differences, trial
 # bytes of one component table (device.h: Table<float>; Table<double> is twice as large):
 # header 16, star 4 x 8, galaxy 4 x 16 x 4, star cut radii 4, galaxy cut radii 4 x 16,
-# second-derivative terms 4 x 16 x 8, exponent rows 4 x 4 + 4 x 16 x 4, PSF offsets 4 x 2
-TABLE_F = 4 * (16 + 4 * 8 + 4 * 16 * 4 + 4 + 4 * 16 + 4 * 16 * 8 + 4 * 4 + 4 * 16 * 4 + 4 * 2)
+# second-derivative terms 4 x 16 x 8, exponent rows 4 x 4 + 4 x 16 x 4, PSF offsets 4 x 2,
+# row recurrence factors 4 x 17
+TABLE_F = 4 * (16 + 4 * 8 + 4 * 16 * 4 + 4 + 4 * 16 + 4 * 16 * 8 + 4 * 4 + 4 * 16 * 4 + 4 * 2 + 4 * 17)
 TABLE_D = 2 * TABLE_F
 CHUNK = 512                  # pixels per work item (the library's default)
 IMAGE_RECORD = 280           # sizeof(cel_image)

@@ -101,21 +101,82 @@ def test_small_batched_fp32(small2, chunk):
     say(f"  max grad rel err {err:.2e}")
 
 
-def test_tuned_plan_matches_a_plan_built_with_its_setting(small2):
-    """cel_tune keeps one of 1, 2, 4 pixels per lane; the tuned plan's outputs equal, bit for
-    bit, those of a plan created with that setting, and stay within the oracle's tolerance."""
+def test_tuned_plan_matches_a_plan_built_with_its_settings(small2):
+    """cel_tune picks a work-item size, pixels per lane and a moment-map variant for the plan;
+    the tuned plan's outputs equal, bit for bit, those of a plan prepared with those settings,
+    and stay within the oracle's tolerance."""
     say("case: small config2 launch tuning")
     prob, (o_tot, o_loc, o_g) = small2
     ctx = api.Context(0)
     plan = api.Plan(ctx, prob)
-    ppl = plan.tune(prob.theta0)
-    say(f"  tuned pixels per lane: {ppl}")
-    assert ppl in (1, 2, 4)
+    t = plan.tune(prob.theta0)
+    say(f"  tuned: {t}")
+    assert t["chunk_pixels"] in (256, 512, 1024, 2048) and t["pixels_per_lane"] in (1, 2, 4)
+    assert t["map_pixels_per_lane"] in (1, 2, 4, 8, -1) and t["n_timed"] == 4 * 3 + 5 and t["ms_per_eval"] > 0
     t1, l1, g1 = api.elbo_grad(plan, prob.theta0)
-    _, t2, l2, g2 = run(prob, pixels_per_lane=ppl)
+    fresh, t2, l2, g2 = run(prob, chunk_pixels=t["chunk_pixels"], pixels_per_lane=t["pixels_per_lane"],
+                            map_pixels_per_lane=t["map_pixels_per_lane"])
     torch.cuda.synchronize()
+    assert plan.n_work_items == fresh.n_work_items
     assert t1.item() == t2 and np.array_equal(l1.cpu().numpy(), l2) and np.array_equal(g1.cpu().numpy(), g2)
     check(prob, t2, l2, g2, o_tot, o_loc, o_g)
+
+
+def _step(plan, theta, mask):
+    th = torch.as_tensor(theta, device="cuda").contiguous()
+    r = torch.ones(plan.S, dtype=torch.float64, device="cuda")
+    st, loc = api.newton_step(plan, th, r, mask)
+    torch.cuda.synchronize()
+    return th.cpu().numpy(), r.cpu().numpy(), st.cpu().numpy(), np.nan_to_num(loc.cpu().numpy())
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_retiled_plan_equals_fresh_plans_through_newton_and_append():
+    """Re-cutting a plan's work items (cel_tune over one candidate) after Newton steps, to
+    more items than its capacity and then to fewer, and appending a request after: each
+    time its gradient and Newton step equal those of a plan prepared with the settings."""
+    say("case: re-cut work items, Newton steps and an append")
+    from paper_1803_00113_amd import serve
+    prob = gen.crop_patches(gen.config5_request(3000, n_sources=30), 40)
+    ctx = api.Context(0)
+    plan = api.Plan(ctx, prob)
+    mask = plan.colours == 0
+    _step(plan, prob.theta0, mask)                       # Newton scratch exists
+    n512 = plan.n_work_items
+    for chunk, ppl, mp in ((128, 2, 4), (4096, 4, -1)):
+        t = plan.tune(prob.theta0, chunk_pixels=[chunk], pixels_per_lane=[ppl], map_pixels_per_lane=[mp])
+        assert (t["chunk_pixels"], t["pixels_per_lane"], t["map_pixels_per_lane"]) == (chunk, ppl, mp)
+        ref = api.Plan(api.Context(0, chunk_pixels=chunk, pixels_per_lane=ppl, map_pixels_per_lane=mp), prob)
+        assert plan.n_work_items == ref.n_work_items and (plan.n_work_items > n512) == (chunk == 128)
+        for x, y in zip(api.elbo_grad(plan, prob.theta0), api.elbo_grad(ref, prob.theta0)):
+            assert torch.equal(x, y)
+        assert _same(_step(plan, prob.theta0, mask), _step(ref, prob.theta0, mask))
+        say(f"  chunk {chunk}: {plan.n_work_items} items, identical")
+    extra = gen.crop_patches(gen.config5_request(3100, n_sources=9), 40)
+    plan.append(extra)
+    merged = serve.merge([prob, extra])
+    merged.pixels = np.concatenate([prob.pixels, extra.pixels])
+    ref = api.Plan(api.Context(0, chunk_pixels=4096, pixels_per_lane=4, map_pixels_per_lane=-1), merged)
+    theta = np.vstack([prob.theta0, extra.theta0])
+    assert plan.n_work_items == ref.n_work_items
+    for x, y in zip(api.elbo_grad(plan, theta), api.elbo_grad(ref, theta)):
+        assert torch.equal(x, y)
+    m2 = plan.colours == 1
+    assert _same(_step(plan, theta, m2), _step(ref, theta, m2))
+
+
+@pytest.mark.parametrize("mp", [1, 2, 4, -1])
+def test_map_variants_against_oracle(small2, mp):
+    """Every moment-map variant (1, 2, 4 pixels per lane, the row-run recurrence; 8 is the
+    default every other test runs) stays within the oracle's tolerance."""
+    say(f"case: small config2 map variant {mp}")
+    prob, (o_tot, o_loc, o_g) = small2
+    _, tot, loc, g = run(prob, map_pixels_per_lane=mp)
+    err = check(prob, tot, loc, g, o_tot, o_loc, o_g)
+    say(f"  max grad rel err {err:.2e}")
 
 
 def test_small_batched_fp64(small2):
