@@ -151,8 +151,8 @@ typedef struct {
                                     float32 gradients, 1e-3 with float64 ones             */
   double radius0, radius_max, eta, gtol, ftol, radius_min;   /* trust region (0 = default) */
   int32_t timing;                /* 1: record HIP events around each phase (see below)  */
-  int32_t map_pixels_per_lane;   /* neighbour moment maps: 1, 2, 4 or 8 (default; 0 in
-                                    the struct = default) pixels per lane 64 apart, values
+  int32_t map_pixels_per_lane;   /* neighbour moment maps: 1, 2, 4 (default; 0 in the
+                                    struct = default) or 8 pixels per lane 64 apart, values
                                     directly; -1: runs of 8 pixels along a row, values by
                                     recurrence                                           */
 } cel_options;
@@ -222,9 +222,9 @@ cel_status cel_elbo_grad(cel_ctx* ctx, const cel_plan* plan, const double* theta
  * library's first cel_create on that device until the process ends, instead of the plan's
  * own blocks.  It calls no allocating routine.  Same kernels and launch order as
  * cel_elbo_grad, so the outputs are bitwise identical.  Arguments as cel_elbo_grad.
- * Need in bytes (each part rounded up to 256): n_patches x 4928 (float64 pixels: 9856)
+ * Need in bytes (each part rounded up to 256): n_patches x 6016 (float64 pixels: 12032)
  * + active pixels x 8 (16) + work items x 128 + sources x 272; CEL_ESCRATCH beyond the
- * buffer (the 1000-source batched workload of 1.7e7 pixels needs 193 MB).  All calls on
+ * buffer (the 1000-source batched workload of 1.7e7 pixels needs 204 MB).  All calls on
  * one device share the buffer: calls that overlap in time on one device (several streams,
  * several host threads, several contexts) race and must be serialised by the caller; a
  * call's outputs are complete once its stream is synchronised. */

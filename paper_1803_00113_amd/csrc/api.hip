@@ -35,7 +35,7 @@ cel_options default_options() {
   std::memset(&o, 0, sizeof(o));
   o.pixels_per_lane = 2;
   o.chunk_pixels = 512;
-  o.map_pixels_per_lane = 8;
+  o.map_pixels_per_lane = 4;
   o.fd_step = 0.0;   // resolved in merge_options: 1e-2 (float32 pixels), 1e-3 (float64)
   o.radius0 = 1.0;
   o.radius_max = 100.0;
@@ -994,6 +994,7 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   pa.fd = point ? 0 : p->fd_mode;
   pa.sky_min = p->d_skymin;
   pa.patch_psf = p->d_patch_psf;
+  pa.records = p->opt.map_pixels_per_lane == -1 ? kRecRuns : 0;
   pa.theta_vstride = theta_vstride;
   phase_mark(p, 0, sm);
   if (prep_base) {   // variant 0 of every source and its moment maps (neighbours read these)
@@ -1096,6 +1097,7 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
   pa.fd = p->fd_mode;
   pa.sky_min = p->d_skymin;
   pa.patch_psf = p->d_patch_psf;
+  pa.records = p->opt.map_pixels_per_lane == -1 ? kRecRuns : 0;
   hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
   if (e == hipSuccess) e = launch_maps_t<T>(p, tables, sm);
   FusedArgs<T> fa;
@@ -1150,7 +1152,7 @@ hipError_t plain_eval(cel_plan* p, const double* theta, hipStream_t sm, bool fp6
 }
 
 template <typename T>
-static hipError_t prep_base_t(cel_plan* p, const double* theta, hipStream_t sm) {
+static hipError_t prep_base_t(cel_plan* p, const double* theta, hipStream_t sm, bool hess) {
   Table<T>* tables = reinterpret_cast<Table<T>*>(sizeof(T) == 8 ? (void*)p->tables_d : (void*)p->tables_f);
   PrepArgs pa;
   std::memset(&pa, 0, sizeof(pa));
@@ -1165,17 +1167,19 @@ static hipError_t prep_base_t(cel_plan* p, const double* theta, hipStream_t sm) 
   pa.fd = p->fd_mode;
   pa.sky_min = p->d_skymin;
   pa.patch_psf = p->d_patch_psf;
+  pa.records = (p->opt.map_pixels_per_lane == -1 ? kRecRuns : 0) | (hess ? kRecHessian : 0);
   hipError_t e = launch_prep_tables<T>(pa, p->P, 1, sm);
   if (e == hipSuccess) e = launch_maps_t<T>(p, tables, sm);
   return e;
 }
 
-hipError_t prep_base(cel_plan* p, const double* theta, hipStream_t sm, bool fp64) {
-  return fp64 ? prep_base_t<double>(p, theta, sm) : prep_base_t<float>(p, theta, sm);
+hipError_t prep_base(cel_plan* p, const double* theta, hipStream_t sm, bool fp64, bool hess) {
+  return fp64 ? prep_base_t<double>(p, theta, sm, hess) : prep_base_t<float>(p, theta, sm, hess);
 }
 
 template <typename T>
-static hipError_t prep_class_t(cel_plan* p, const double* theta, int cls, const uint8_t* active, hipStream_t sm) {
+static hipError_t prep_class_t(cel_plan* p, const double* theta, int cls, const uint8_t* active, hipStream_t sm,
+                               bool hess) {
   const int np = (int)p->class_patches[cls].size();
   if (np == 0) return hipSuccess;
   PrepArgs pa;
@@ -1193,11 +1197,14 @@ static hipError_t prep_class_t(cel_plan* p, const double* theta, int cls, const 
   pa.fd = p->fd_mode;
   pa.sky_min = p->d_skymin;
   pa.patch_psf = p->d_patch_psf;
+  pa.records = (p->opt.map_pixels_per_lane == -1 ? kRecRuns : 0) | (hess ? kRecHessian : 0);
   return launch_prep_tables<T>(pa, np, 1, sm);
 }
 
-hipError_t prep_class(cel_plan* p, const double* theta, int cls, const uint8_t* active, hipStream_t sm, bool fp64) {
-  return fp64 ? prep_class_t<double>(p, theta, cls, active, sm) : prep_class_t<float>(p, theta, cls, active, sm);
+hipError_t prep_class(cel_plan* p, const double* theta, int cls, const uint8_t* active, hipStream_t sm, bool fp64,
+                      bool hess) {
+  return fp64 ? prep_class_t<double>(p, theta, cls, active, sm, hess)
+              : prep_class_t<float>(p, theta, cls, active, sm, hess);
 }
 
 hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv, bool grad, int cls,

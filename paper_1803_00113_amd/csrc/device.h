@@ -49,20 +49,36 @@ enum Slot {
 // off[k]: centre of PSF component k minus mu (the PSF mean offset)
 // rq[k][0], rq[k][1 + j]: exp(-P_xx) of the star and of galaxy component j = 2^(2 q0), the
 //   factor by which the ratio of a component's values at consecutive columns changes
-//   (values along a row by recurrence: neighbour maps)
+//   (values along a row by recurrence: neighbour maps; written when that map variant is on)
+// gq[k][j][4..7]: (c^2 P_xx, c^2 P_xy, c^2 P_yy, tau/2), c = -log2(e)/2 -- with u' = c P d
+//   (from gq[k][j][0..2]) the own-source kernel forms the exponent as d . u' + q3 and the
+//   covariance derivative from u' u'^T - c^2 P = c^2 (u u^T - P); its mean and covariance
+//   sums are c and c^2 times the plain ones and are divided back once per slot row.  One
+//   component's eight values are one 32-byte scalar load.
+// gt is written only for the exact Hessian's preparations
 template <typename T>
-struct alignas(16) Table {
+// The records the pixel kernels read for every component (header, star records, cut radii,
+// exponent records) come first and together, so that a wavefront's scalar loads of one
+// patch's table touch as few cache lines as possible; the Hessian's and the other kernels'
+// records follow.  gq starts on a 32-byte boundary (one 32-byte load per component) and
+// the table's size is a multiple of 64 bytes.
+struct alignas(64) Table {
   T hdr[16];
   T star[kMaxPsf][8];
-  T gal[kMaxPsf][2 * kMaxProf][4];
   T rc2s[kMaxPsf];
   T rc2[kMaxPsf][2 * kMaxProf];
-  T gt[kMaxPsf][2 * kMaxProf][8];
   T sq[kMaxPsf][4];
-  T gq[kMaxPsf][2 * kMaxProf][4];
+  T pad0[4];
+  T gq[kMaxPsf][2 * kMaxProf][8];
+  T gal[kMaxPsf][2 * kMaxProf][4];
+  T gt[kMaxPsf][2 * kMaxProf][8];
   T off[kMaxPsf][2];
   T rq[kMaxPsf][1 + 2 * kMaxProf];
+  T pad1[12];
 };
+
+// the exponent's scale in the own-source records: c = -log2(e) / 2
+constexpr double kExpScale = -0.72134752044448170368;
 
 struct DPatch {
   int32_t src, img, x0, y0, w, h;

@@ -22,7 +22,10 @@ struct PrepArgs {
   const double* sky_min;       // per patch: smallest sky value (component cut)
   int64_t theta_vstride;       // > 0: variant v reads theta + v * theta_vstride (per-variant points)
   const double* patch_psf;     // [P][kMaxPsf][6] per-patch PSF mixtures (null: the image's)
+  int32_t records;             // extra table records: kRecHessian (gt), kRecRuns (rq)
 };
+constexpr int kRecHessian = 1;
+constexpr int kRecRuns = 2;
 
 struct FinalizeArgs {
   int32_t n_jobs;              // sources handled by this launch

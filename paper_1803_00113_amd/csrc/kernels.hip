@@ -178,7 +178,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
       for (int e = 0; e < 4; ++e) tb->sq[k][e] = qv[e];
       tb->off[k][0] = (T)ox;
       tb->off[k][1] = (T)oy;
-      tb->rq[k][0] = (T)exp(-Pxx);
+      if (a.records & kRecRuns) tb->rq[k][0] = (T)exp(-Pxx);
     } else {
       T* r = tb->gal[k][j];
       r[0] = pv[0];
@@ -186,9 +186,16 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
       r[2] = pv[2];
       r[3] = (T)lw;
       tb->rc2[k][j] = (T)rc2 + (T)0;
-      tb->rq[k][1 + j] = (T)exp(-Pxx);
+      if (a.records & kRecRuns) tb->rq[k][1 + j] = (T)exp(-Pxx);
 #pragma unroll
       for (int e = 0; e < 4; ++e) tb->gq[k][j][e] = qv[e];
+      const double c2 = kExpScale * kExpScale;
+      T* gs = tb->gq[k][j] + 4;
+      gs[0] = (T)(c2 * Pxx);
+      gs[1] = (T)(c2 * Pxy);
+      gs[2] = (T)(c2 * Pyy);
+      gs[3] = (T)(0.5 * tau);
+      if (!(a.records & kRecHessian)) continue;
       const double h = 0.5 * tau * tau;
       T* q = tb->gt[k][j];
       q[0] = (T)tau;
@@ -206,13 +213,28 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
 // ----------------------------------------------------------------------------------------
 // k_fused: the per-pixel hot loop
 
+// Copy the galaxy components' exponent records of the K PSF components of one table into
+// LDS (one wavefront; 16-byte vectors).  Each component's record is then one broadcast LDS
+// read rather than a scalar-cache load: the tables of the wavefronts resident on a compute
+// unit exceed its scalar cache.
+template <typename T>
+__device__ __forceinline__ void stage_records(const Table<T>* __restrict__ tb, int K, int lane,
+                                              T (*rec)[2 * kMaxProf][8]) {
+  constexpr int kVec = 16 / sizeof(T);   // values per 16-byte vector
+  const int n = K * 2 * kMaxProf * 8 / kVec;
+  const uint4* src = reinterpret_cast<const uint4*>(&tb->gq[0][0][0]);
+  uint4* dst = reinterpret_cast<uint4*>(&rec[0][0][0]);
+  for (int i = lane; i < n; i += 64) dst[i] = src[i];
+  __syncthreads();
+}
+
 // Values of a source's star (f1) and galaxy (f0) light at PPL pixels (local coords of the
 // source's own patch).  Neighbour evaluation: no derivatives.  A type of weight exactly 0
 // (a point value of the type) is not evaluated: its light enters the moments only through
 // that weight.
 template <typename T, int PPL, int NEXP, int NDEV>
-__device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int K, const T* px, const T* py,
-                                            const T* box, T* f0, T* f1) {
+__device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, const T (*__restrict__ rec)[2 * kMaxProf][8],
+                                            int K, const T* px, const T* py, const T* box, T* f0, T* f1) {
   T fe[PPL], fd[PPL];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) fe[i] = fd[i] = f1[i] = (T)0;
@@ -229,16 +251,11 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
       yy[i] = dy[i] * dy[i];
     }
     const T d2 = box_dist2<T>(mx, my, box);
-    // this PSF component's records and cut radii, read before any is used (one wait for
-    // all of them instead of one per component)
-    T rc[NEXP + NDEV], qv[NEXP + NDEV][4];
+    // this PSF component's cut radii, read before any is used (one wait for all of them
+    // instead of one per component); the exponent records come from the LDS copy
+    T rc[NEXP + NDEV];
 #pragma unroll
-    for (int j = 0; j < NEXP + NDEV; ++j) {
-      const int c = j < NEXP ? j : kMaxProf + (j - NEXP);
-      rc[j] = tb->rc2[k][c];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) qv[j][e] = tb->gq[k][c][e];
-    }
+    for (int j = 0; j < NEXP + NDEV; ++j) rc[j] = tb->rc2[k][j < NEXP ? j : kMaxProf + (j - NEXP)];
     // a type of weight 0 sees its components at infinite distance: all skipped
     const auto d2s = uniform_cut_key(use_star ? d2 : (T)INFINITY), d2g = uniform_cut_key(use_gal ? d2 : (T)INFINITY);
     if (!(d2s > cut_key(tb->rc2s[k]))) {
@@ -249,13 +266,13 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
     for (int j = 0; j < NEXP; ++j) {
       if (d2g > cut_key(rc[j])) continue;
 #pragma unroll
-      for (int i = 0; i < PPL; ++i) fe[i] += comp_value<T>(qv[j], xx[i], xy[i], yy[i]);
+      for (int i = 0; i < PPL; ++i) fe[i] += comp_value<T>(rec[k][j], xx[i], xy[i], yy[i]);
     }
 #pragma unroll
     for (int j = 0; j < NDEV; ++j) {
       if (d2g > cut_key(rc[NEXP + j])) continue;
 #pragma unroll
-      for (int i = 0; i < PPL; ++i) fd[i] += comp_value<T>(qv[NEXP + j], xx[i], xy[i], yy[i]);
+      for (int i = 0; i < PPL; ++i) fd[i] += comp_value<T>(rec[k][kMaxProf + j], xx[i], xy[i], yy[i]);
     }
   }
   const T pi = tb->hdr[7];
@@ -266,6 +283,9 @@ __device__ __forceinline__ void eval_values(const Table<T>* __restrict__ tb, int
 // Own source: values and partial derivatives w.r.t. the pixel-frame centre mu, the
 // pixel-frame galaxy covariance S and the profile weight.  For N = weight * normal(p; m, C)
 // with P = C^{-1}, u = P (p - m):  dN/dmu = N u,  dN/dC = N (u u^T - P) / 2,  dC/dS = tau.
+// The records hold c P with c = -log2(e)/2 (gq, sq), so the lanes form u' = c u and the
+// exponent d . u' + log2 weight directly; the sums g = sum N u' and s = sum tau/2 N (u' u'^T
+// - c^2 P) are c and c^2 times the plain derivatives (divided back per slot row).
 template <typename T, int PPL>
 struct OwnPix {
   T f1[PPL], g1x[PPL], g1y[PPL];
@@ -273,27 +293,27 @@ struct OwnPix {
   T fd[PPL], gdx[PPL], gdy[PPL], sdxx[PPL], sdxy[PPL], sdyy[PPL];
 };
 
-// MODE 0: value only; 1: value and d/dmu; 2: value, d/dmu and d/dS
+// MODE 0: value only; 1: value and d/dmu; 2: value, d/dmu and d/dS.  q: (c P_xx, c P_xy,
+// c P_yy, log2 weight); r (MODE 2): (c^2 P_xx, c^2 P_xy, c^2 P_yy, tau/2)
 template <typename T, int PPL, int MODE>
-__device__ __forceinline__ void comp_own(T pxx, T pxy, T pyy, T lw, T htau, const T* dx, const T* dy, T* f, T* gx,
-                                         T* gy, T* sxx, T* sxy, T* syy) {
-  const T hl = (T)(-0.5 * kLog2e);
+__device__ __forceinline__ void comp_own(const T* __restrict__ q, const T* __restrict__ r, const T* dx, const T* dy,
+                                         T* f, T* gx, T* gy, T* sxx, T* sxy, T* syy) {
+  const T q0 = q[0], q1 = q[1], q2 = q[2], lw = q[3];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) {
-    const T ux = fma(pxx, dx[i], pxy * dy[i]);
-    const T uy = fma(pxy, dx[i], pyy * dy[i]);
-    const T q = fma(dx[i], ux, dy[i] * uy);
-    const T N = fexp2<T>(fma(q, hl, lw));
+    const T ux = fma(q0, dx[i], q1 * dy[i]);
+    const T uy = fma(q1, dx[i], q2 * dy[i]);
+    const T N = fexp2<T>(fma(dx[i], ux, fma(dy[i], uy, lw)));
     f[i] += N;
     if (MODE >= 1) {
       gx[i] = fma(N, ux, gx[i]);
       gy[i] = fma(N, uy, gy[i]);
     }
     if (MODE >= 2) {
-      const T tN = htau * N;
-      sxx[i] = fma(tN, fma(ux, ux, -pxx), sxx[i]);
-      sxy[i] = fma(tN, fma(ux, uy, -pxy), sxy[i]);
-      syy[i] = fma(tN, fma(uy, uy, -pyy), syy[i]);
+      const T tN = r[3] * N;
+      sxx[i] = fma(tN, fma(ux, ux, -r[0]), sxx[i]);
+      sxy[i] = fma(tN, fma(ux, uy, -r[1]), sxy[i]);
+      syy[i] = fma(tN, fma(uy, uy, -r[2]), syy[i]);
     }
   }
 }
@@ -304,8 +324,8 @@ __device__ __forceinline__ void comp_own(T pxx, T pxy, T pyy, T lw, T htau, cons
 // value of the type) is not evaluated: its light enters the moments only through that
 // weight, so the objective is unchanged.
 template <typename T, int PPL, int NEXP, int NDEV, bool DERIV>
-__device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const T* __restrict__ htau, int K,
-                                         const T* px, const T* py, const T* box, OwnPix<T, PPL>& o) {
+__device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const T (*__restrict__ rec)[2 * kMaxProf][8],
+                                         int K, const T* px, const T* py, const T* box, OwnPix<T, PPL>& o) {
 #pragma unroll
   for (int i = 0; i < PPL; ++i) {
     o.f1[i] = o.g1x[i] = o.g1y[i] = (T)0;
@@ -328,19 +348,17 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
     // a type of weight 0 sees its components at infinite distance: all skipped
     const auto d2s = uniform_cut_key(use_star ? d2 : (T)INFINITY), d2g = uniform_cut_key(use_gal ? d2 : (T)INFINITY);
     if (!(d2s > cut_key(tb->rc2s[k])))
-      comp_own<T, PPL, DERIV ? 1 : 0>(tb->star[k][2], tb->star[k][3], tb->star[k][4], tb->star[k][5], (T)0, dx, dy,
-                                      o.f1, o.g1x, o.g1y, z, z, z);
+      comp_own<T, PPL, DERIV ? 1 : 0>(tb->sq[k], nullptr, dx, dy, o.f1, o.g1x, o.g1y, z, z, z);
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
       if (!(d2g > cut_key(tb->rc2[k][j])))
-        comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3], htau[j], dx,
-                              dy, o.fe, o.gex, o.gey, o.sexx, o.sexy, o.seyy);
+        comp_own<T, PPL, DERIV ? 2 : 0>(rec[k][j], rec[k][j] + 4, dx, dy, o.fe, o.gex, o.gey, o.sexx, o.sexy,
+                                        o.seyy);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
       if (!(d2g > cut_key(tb->rc2[k][kMaxProf + j])))
-        comp_own<T, PPL, DERIV ? 2 : 0>(tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1], tb->gal[k][kMaxProf + j][2],
-                              tb->gal[k][kMaxProf + j][3], htau[kMaxProf + j], dx, dy, o.fd, o.gdx, o.gdy, o.sdxx,
-                              o.sdxy, o.sdyy);
+        comp_own<T, PPL, DERIV ? 2 : 0>(rec[k][kMaxProf + j], rec[k][kMaxProf + j] + 4, dx, dy, o.fd, o.gdx,
+                                        o.gdy, o.sdxx, o.sdxy, o.sdyy);
   }
 }
 
@@ -357,6 +375,8 @@ __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
   const int lane = threadIdx.x;
   const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
   const T k0 = tb->hdr[4], k1 = tb->hdr[5], w01 = tb->hdr[6];
+  __shared__ T rec[kMaxPsf][2 * kMaxProf][8];
+  stage_records<T>(tb, K, lane, rec);
   // patch-local coordinates of this lane's pixels, advanced by a carry per group
   const int step = 64 * PPL;
   const int step_rows = step / P.w, step_cols = step - step_rows * P.w;
@@ -372,7 +392,7 @@ __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
   for (int base = task.pix_begin; base < task.pix_end; base += step) {
     T f0[PPL], f1[PPL], box[4];
     run_box<T>(base, min(base + step, task.pix_end), P.w, box);
-    eval_values<T, PPL, NEXP, NDEV>(tb, K, px, py, box, f0, f1);
+    eval_values<T, PPL, NEXP, NDEV>(tb, rec, K, px, py, box, f0, f1);
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
       const int idx = base + i * 64 + lane;
@@ -504,7 +524,8 @@ __global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
 }
 
 template <typename T, int PPL, bool GRAD, int NEXP, int NDEV>
-__global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restrict__ htau) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && PPL < 4 ? 6 : 1))) void k_fused(FusedArgs<T> a,
+                                                                                   const T* __restrict__ htau) {
   const int v = a.variant0 + blockIdx.y;
   const int wi = a.order_offset + xcd_position((int)blockIdx.x, (int)gridDim.x);
   const int t = a.order ? a.order[wi] : wi;
@@ -514,6 +535,9 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
   const Table<T>* __restrict__ tb = a.own + (int64_t)v * a.variant_stride + task.patch;
   const int K = a.img_npsf[P.img];
   const int lane = threadIdx.x;
+  // the galaxy components' records of this patch, staged in LDS once per work item
+  __shared__ T rec[kMaxPsf][2 * kMaxProf][8];
+  stage_records<T>(tb, K, lane, rec);
   const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
   const T k0 = tb->hdr[4], k1 = tb->hdr[5], w01 = tb->hdr[6], pi = tb->hdr[7];
   // objective sums in FP64 per lane.  The 11 gradient sums are kept per lane in the pixel
@@ -565,7 +589,7 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
     int ibox[4];
     run_box<int>(base, min(base + step, task.pix_end), P.w, ibox);
     const T box[4] = {(T)ibox[0], (T)ibox[1], (T)ibox[2], (T)ibox[3]};
-    eval_own<T, PPL, NEXP, NDEV, GRAD>(tb, htau, K, px, py, box, o);
+    eval_own<T, PPL, NEXP, NDEV, GRAD>(tb, rec, K, px, py, box, o);
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
       f1[i] = o.f1[i];
@@ -655,7 +679,10 @@ __global__ __launch_bounds__(64) void k_fused(FusedArgs<T> a, const T* __restric
       const bool first = group < kFlush;
 #pragma unroll
       for (int q = 0; q < S_T; ++q) {
-        const double s = wave_sum<T>((double)part[q]);
+        // the centre sums carry the records' scale c, the covariance sums c^2
+        const double unscale = (q == S_MU_X || q == S_MU_Y) ? 1.0 / kExpScale
+                               : (q == S_S_XX || q == S_S_XY || q == S_S_YY) ? 1.0 / (kExpScale * kExpScale) : 1.0;
+        const double s = wave_sum<T>((double)part[q]) * unscale;
         if (lane == 0) out[q] = first ? s : out[q] + s;
         part[q] = (T)0;
       }

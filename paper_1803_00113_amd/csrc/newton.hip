@@ -1299,7 +1299,7 @@ static hipError_t enqueue_newton_class(cel_plan* p, double* theta, double* radiu
   const bool analytic = !p->opt.hessian_fd;
   if (analytic) {
     // tables (and maps) at the iterate, then the exact Hessians with the gradients
-    e = maps_current ? prep_class(p, theta, cls, active, sm, fp64) : prep_base(p, theta, sm, fp64);
+    e = maps_current ? prep_class(p, theta, cls, active, sm, fp64, true) : prep_base(p, theta, sm, fp64, true);
     if (e == hipSuccess)
       e = enqueue_hessian(p, theta, p->d_class_tasks[cls], (int)p->class_tasks[cls].size(), p->d_class_src[cls], nsrc,
                           active, true, p->v_local, p->v_grad, p->d_hess, sm);
@@ -1568,7 +1568,7 @@ extern "C" cel_status cel_elbo_hessian(cel_ctx* ctx, const cel_plan* cplan, cons
   for (int s = 0; s < p->S; ++s) p->h_mask[s] = mask ? (mask[s] ? 1 : 0) : 1;
   hipError_t e = hipMemcpyAsync(p->d_mask, p->h_mask, p->S, hipMemcpyHostToDevice, sm);
   if (e == hipSuccess) e = hipEventRecord(p->mask_copied, sm);
-  if (e == hipSuccess) e = prep_base(p, theta, sm, fp64);
+  if (e == hipSuccess) e = prep_base(p, theta, sm, fp64, true);
   if (e == hipSuccess)
     e = enqueue_hessian(p, theta, p->d_order, (int)p->n_tasks, nullptr, p->S, p->d_mask, true,
                         elbo_local ? elbo_local : p->v_local, grad ? grad : p->v_grad, hess, sm);

@@ -179,11 +179,13 @@ hipError_t eval_any(cel_plan* p, const double* theta, const double* theta_trial,
                     const uint8_t* active, hipStream_t sm, bool prep_base, bool fp64, double* local_out = nullptr,
                     double* grad_out = nullptr);
 hipError_t plain_eval(cel_plan* p, const double* theta, hipStream_t sm, bool fp64);
-// component tables at the iterate for every patch and the neighbour moment maps
-hipError_t prep_base(cel_plan* p, const double* theta, hipStream_t sm, bool fp64);
+// component tables at the iterate for every patch and the neighbour moment maps (hess: with
+// the exact Hessian's records)
+hipError_t prep_base(cel_plan* p, const double* theta, hipStream_t sm, bool fp64, bool hess = false);
 // component tables at the iterate for the patches of colour class cls only (sources flagged
 // in active); the maps are left as they are
-hipError_t prep_class(cel_plan* p, const double* theta, int cls, const uint8_t* active, hipStream_t sm, bool fp64);
+hipError_t prep_class(cel_plan* p, const double* theta, int cls, const uint8_t* active, hipStream_t sm, bool fp64,
+                      bool hess = false);
 // record a phase boundary event (k = 0..4) of the current evaluation when timing is on
 void phase_mark(cel_plan* p, int k, hipStream_t sm);
 cel_status ensure_newton(cel_plan* p);

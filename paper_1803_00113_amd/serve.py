@@ -33,10 +33,11 @@ from . import api
 VARIANTS_EXACT = 2           # Newton with the exact Hessian: iterate, trial
 VARIANTS_FD = 56             # Newton with a difference Hessian: iterate, 54 differences, trial
 # bytes of one component table (device.h: Table<float>; Table<double> is twice as large):
-# header 16, star 4 x 8, galaxy 4 x 16 x 4, star cut radii 4, galaxy cut radii 4 x 16,
-# second-derivative terms 4 x 16 x 8, exponent rows 4 x 4 + 4 x 16 x 4, PSF offsets 4 x 2,
-# row recurrence factors 4 x 17
-TABLE_F = 4 * (16 + 4 * 8 + 4 * 16 * 4 + 4 + 4 * 16 + 4 * 16 * 8 + 4 * 4 + 4 * 16 * 4 + 4 * 2 + 4 * 17)
+# header 16, star 4 x 8, star cut radii 4, galaxy cut radii 4 x 16, star exponent rows
+# 4 x 4, padding 4, galaxy exponent records 4 x 16 x 8, galaxy 4 x 16 x 4,
+# second-derivative terms 4 x 16 x 8, PSF offsets 4 x 2, row recurrence factors 4 x 17,
+# padding 12
+TABLE_F = 4 * (16 + 4 * 8 + 4 + 4 * 16 + 4 * 4 + 4 + 4 * 16 * 8 + 4 * 16 * 4 + 4 * 16 * 8 + 4 * 2 + 4 * 17 + 12)
 TABLE_D = 2 * TABLE_F
 CHUNK = 512                  # pixels per work item (the library's default)
 IMAGE_RECORD = 280           # sizeof(cel_image)

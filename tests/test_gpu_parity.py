@@ -168,9 +168,9 @@ def test_retiled_plan_equals_fresh_plans_through_newton_and_append():
     assert _same(_step(plan, theta, m2), _step(ref, theta, m2))
 
 
-@pytest.mark.parametrize("mp", [1, 2, 4, -1])
+@pytest.mark.parametrize("mp", [1, 2, 8, -1])
 def test_map_variants_against_oracle(small2, mp):
-    """Every moment-map variant (1, 2, 4 pixels per lane, the row-run recurrence; 8 is the
+    """Every moment-map variant (1, 2, 8 pixels per lane, the row-run recurrence; 4 is the
     default every other test runs) stays within the oracle's tolerance."""
     say(f"case: small config2 map variant {mp}")
     prob, (o_tot, o_loc, o_g) = small2
