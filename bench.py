@@ -27,6 +27,11 @@ sys.path.insert(0, ROOT)
 # adjoint accumulation; per (pixel, covering neighbour) pair: adding its moments.
 # map kernel, per active pixel: the source's 45-component mixture value and its moments.
 FLOP_OWN = 1368 + 47          # FP arithmetic + transcendentals (45 exp, 1 log, 1 reciprocal)
+# of which: per pixel 102 + log + reciprocal; per galaxy component 29 + exp, per star
+# component 16 + exp (42 galaxy and 3 star components)
+FLOP_OWN_FIXED = 104
+FLOP_PER_COMPONENT = (42 * 30 + 3 * 17) / 45
+VALU_LANE_RATE = 1024 * 16 * 2.4e9   # SIMDs x lanes per cycle x clock: one VALU op per lane
 FLOP_PAIR = 2
 FLOP_MAP = 348 + 45
 BYTES_UNIT = 8                # (count, sky) pair per active pixel read by the pixel kernel
@@ -73,6 +78,46 @@ def counted_traffic():
     if not m or m.group(2) != h:
         return None
     return int(m.group(1))
+
+
+def executed_work(units, pairs, kernel_ms, achieved):
+    """The pixel kernel's executed arithmetic next to the algorithmic figure: the component
+    cut leaves (transcendentals per pixel - 2) of the 45 components evaluated per pixel
+    (counter profile); `achieved` / `frac` of the roofline count all 45 (the method's work),
+    these count the evaluated ones.  valu_issue_frac: measured VALU lane-instructions per
+    second over one VALU operation per lane per cycle on every SIMD."""
+    c = counted_valu()
+    if c is None:
+        return None
+    valu, trans = c
+    comps = trans - 2.0
+    flops = units * (FLOP_OWN_FIXED + comps * FLOP_PER_COMPONENT) + pairs * FLOP_PAIR
+    rate = flops / (kernel_ms * 1e-3) / 1e12
+    return dict(component_evals_per_pixel=round(comps, 2), component_fraction=round(comps / 45, 3),
+                achieved=round(rate, 3), frac=round(rate / PEAK_FP32_TFLOPS, 4),
+                frac_of_fp32_without_packed=round(rate / (PEAK_FP32_TFLOPS / 2), 4),
+                algorithmic_achieved=achieved, valu_lane_instr_per_pixel=valu,
+                valu_issue_frac=round(units * valu / (kernel_ms * 1e-3) / VALU_LANE_RATE, 3))
+
+
+def counted_valu():
+    """(VALU lane-instructions, transcendental instructions) per active pixel of k_fused from
+    the committed rocprofv3 VALU counter profile, or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    import re
+    prof = os.path.join(ROOT, "profiles", "k_fused_batched_1000src_valu_counters.md")
+    src = os.path.join(ROOT, "paper_1803_00113_amd", "csrc", "kernels.hip")
+    try:
+        text = open(prof).read()
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"valu_lane_instr_per_pixel=([0-9.]+) trans_per_pixel=([0-9.]+) kernels_hip_sha256_prefix=([0-9a-f]+)",
+                  text)
+    if not m or m.group(3) != h:
+        return None
+    return float(m.group(1)), float(m.group(2))
 
 
 def sweep_leg(log, plain_sweeps=1):
@@ -400,6 +445,7 @@ def main():
                                     kernel_ms=round(maps_ms, 4),
                                     achieved=round(units * FLOP_MAP / (maps_ms * 1e-3) / 1e12, 3),
                                     algorithmic_flop_per_launch=units * FLOP_MAP),
+                    executed=executed_work(units, pairs, kernel_ms, achieved),
                     phases_ms=[round(x / nb, 4) for x in ms_phase],
                     ms_per_step_with_phase_events=round(ms_step_events, 4))
 

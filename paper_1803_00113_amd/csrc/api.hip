@@ -1468,40 +1468,54 @@ extern "C" cel_status cel_tune(cel_ctx* ctx, cel_plan* p, const double* theta, c
     ++res.n_timed;
     return e == hipSuccess ? best : -1.0;
   };
+  // a candidate replaces the kept setting only when it is faster by more than the margin
+  // (timing noise of a few tenths of a percent must not flip the choice between runs)
+  constexpr double kMargin = 0.02;
+  const int cur_chunk = p->opt.chunk_pixels, cur_ppl = p->opt.pixels_per_lane, cur_map = p->opt.map_pixels_per_lane;
   cel_status st = CEL_OK;
-  double best_ms = INFINITY;
-  // work-item size and pixel-pass lanes together (the pass's cost depends on both) ...
+  auto has = [](const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); };
+  // work-item size and pixel-pass lanes together (the pass's cost depends on both), the
+  // plan's current pair first when it is a candidate ...
+  const bool cur_pair = has(chunks, cur_chunk) && has(ppls, cur_ppl);
+  double best_ms = cur_pair ? time_it() : INFINITY;
+  if (best_ms < 0) st = CEL_EHIP;
   for (int c : chunks) {
-    if ((st = plan_retile(p, c, sm))) break;
-    if ((st = ensure_variants(p, 1, fp64))) break;
+    if (st) break;
     for (int l : ppls) {
+      if (cur_pair && c == cur_chunk && l == cur_ppl) continue;
+      if ((st = plan_retile(p, c, sm)) || (st = ensure_variants(p, 1, fp64))) break;
       p->opt.pixels_per_lane = l;
       const double ms = time_it();
       if (ms < 0) {
         st = CEL_EHIP;
         break;
       }
-      if (ms < best_ms) {
+      if (ms < best_ms * (1.0 - kMargin) || best_ms == INFINITY) {
         best_ms = ms;
         res.chunk_pixels = c;
         res.pixels_per_lane = l;
       }
     }
-    if (st) break;
   }
-  // ... then the moment-map variant at the chosen pair
+  // ... then the moment-map variants at the chosen pair, the current one first
   if (!st) st = plan_retile(p, res.chunk_pixels, sm);
+  if (!st) st = ensure_variants(p, 1, fp64);
   if (!st) {
     p->opt.pixels_per_lane = res.pixels_per_lane;
-    best_ms = INFINITY;
+    const bool cur_in = has(maps, cur_map);
+    p->opt.map_pixels_per_lane = cur_map;
+    best_ms = cur_in ? time_it() : INFINITY;
+    if (best_ms < 0) st = CEL_EHIP;
     for (int m : maps) {
+      if (st) break;
+      if (cur_in && m == cur_map) continue;
       p->opt.map_pixels_per_lane = m;
       const double ms = time_it();
       if (ms < 0) {
         st = CEL_EHIP;
         break;
       }
-      if (ms < best_ms) {
+      if (ms < best_ms * (1.0 - kMargin) || best_ms == INFINITY) {
         best_ms = ms;
         res.map_pixels_per_lane = m;
       }
