@@ -272,6 +272,12 @@ def mcmc_leg(log, T=200, n_runs=25, n_post=25):
                candidate_pixel_evals_per_s=rep["candidate_pixels"] / dt, ms_per_round=1e3 * dt / rep["rounds"],
                seconds_per_source=dt / int(cls.sum()),
                p_star_mean=float(r["p_star"][sel].mean().item()))
+    # the chains' potential scale reduction over the coordinates each type samples
+    rh = r["rhat"][sel].cpu().numpy()
+    moved = np.concatenate([rh[:, 0, [0, 1, 3, 4, 5, 6, 7, 8, 9, 10, 11]].ravel(), rh[:, 1, [0, 1, 3, 4, 5, 6, 7]].ravel()])
+    moved = moved[np.isfinite(moved)]
+    res["rhat_median"] = float(np.median(moved)) if moved.size else None
+    res["rhat_frac_below_1_1"] = float((moved < 1.1).mean()) if moved.size else None
     log(f"mcmc: {res}")
     return res
 

@@ -406,15 +406,21 @@ typedef struct {
  * z_fixed: DEVICE [S][16]; mask: HOST uint8 [S] (NULL = all); z_init: DEVICE
  * [2][n_runs][S][16] (type 0 rows first); z_out: DEVICE [S][16] (the new point of each
  * selected source); p_star: DEVICE [S]; log_evidence: DEVICE [S][2] (log of the mean
- * weight per type); samples: DEVICE [S][2][n_runs][n_post][16] or NULL; rows of
- * unselected sources untouched.  report: HOST or NULL.  Pixel precision as the context's
+ * weight per type); samples: DEVICE [S][2][n_runs][n_post][16] or NULL; rhat: DEVICE
+ * [S][2][16] or NULL: the potential scale reduction factor of the n_runs chains of n_post
+ * samples per type and coordinate (Gelman and Rubin 1992, the criterion Section 3.2
+ * monitors the chains by: with chain means m_j, their mean g and chain variances v_j of
+ * divisor n_post - 1, B = n_post / (n_runs - 1) sum_j (m_j - g)^2, W = mean_j v_j,
+ * R = sqrt(((n_post - 1) / n_post W + B / n_post) / W); NaN for a coordinate no chain
+ * moves or when n_runs or n_post is 1, +infinity when only the chains' values differ);
+ * rows of unselected sources untouched.  report: HOST or NULL.  Pixel precision as the context's
  * pixel_fp64 option.  Synchronous (the host polls the chains every 16 rounds).  Allocates
  * its scratch on the plan at first use.
  * CEL_EINVAL: null pointers, bad options (gamma NULL, n_runs > 28, negative widths). */
 cel_status cel_mcmc_step(cel_ctx* ctx, const cel_plan* plan, const double* z_fixed, const uint8_t* mask,
                          const double* z_init, const cel_mcmc_opts* opts, uint64_t key, double* z_out,
-                         double* p_star, double* log_evidence, double* samples, cel_mcmc_report* report,
-                         void* stream);
+                         double* p_star, double* log_evidence, double* samples, double* rhat,
+                         cel_mcmc_report* report, void* stream);
 
 /* Log prior density log p(w | a) of n point values (the start distribution pi_0 of the
  * annealed importance sampler, Section 3.1; the priors of Section 2.1), over the point

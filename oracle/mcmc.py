@@ -189,7 +189,8 @@ def source_step(model, z_fixed, s, z_init, opts, key, stats=None):
     """The MCMC update of source s (equation eqzs) with every other source at z_fixed.
     z_init [2, N', 16]: the start points of the runs per type (draws from the prior).
     Returns dict(z (the new point), p_star = p(a = 1 | x, z_-s), log_evidence [2],
-    logw [2, N'], samples [2, N', B', 16])."""
+    logw [2, N'], samples [2, N', B', 16], rhat [2, 16]: the N' chains' potential scale
+    reduction per type and coordinate)."""
     Np, Bp = opts["n_runs"], opts["n_post"]
     target = SourceTarget(model, z_fixed, s, opts["box"])
     logw = np.zeros((2, Np))
@@ -212,7 +213,31 @@ def source_step(model, z_fixed, s, z_init, opts, key, stats=None):
     a_star = 1 if uniform(out[0]) < p_star else 0
     j = min(int(math.floor(uniform(out[1]) * Np * Bp)), Np * Bp - 1)
     z = samples[a_star, j // Bp, j % Bp].copy()
-    return dict(z=z, p_star=p_star, log_evidence=log_ev, logw=logw, samples=samples, a=a_star, index=j)
+    return dict(z=z, p_star=p_star, log_evidence=log_ev, logw=logw, samples=samples, a=a_star, index=j,
+                rhat=np.array([rhat(samples[a]) for a in (0, 1)]))
+
+
+def rhat(samples):
+    """Potential scale reduction factor of m chains of n draws, per coordinate (Gelman and
+    Rubin, "Inference from iterative simulation using multiple sequences", Statistical
+    Science 1992), the convergence and mixing criterion with which Section 3.2 monitors the
+    N' chains of B' steps.  samples [m, n, d] -> [d].  With chain means mean_j, their mean
+    g, chain variances s_j^2 (divisor n - 1): B = n / (m - 1) sum_j (mean_j - g)^2,
+    W = mean_j s_j^2, V = (n - 1) / n W + B / n, R = sqrt(V / W).  Reading: the basic form,
+    without the degrees-of-freedom correction; each coordinate on its own scale (the angle
+    as stored, in [0, pi)); a coordinate that does not move in any chain (W = 0) gives
+    0 / 0 = NaN, one with W = 0 < B gives +infinity; fewer than 2 chains or 2 draws: NaN."""
+    x = np.asarray(samples, dtype=np.float64)
+    m, n = x.shape[0], x.shape[1]
+    if m < 2 or n < 2:
+        return np.full(x.shape[2:], np.nan)
+    means = x.mean(axis=1)
+    g = means.mean(axis=0)
+    B = n / (m - 1) * ((means - g) ** 2).sum(axis=0)
+    W = x.var(axis=1, ddof=1).mean(axis=0)
+    V = (n - 1) / n * W + B / n
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.sqrt(V / W)
 
 
 DEFAULTS = dict(n_temps=200, n_runs=25, n_post=25, max_step_out=8, max_shrink=200, gamma_power=4.0, box=2.0,

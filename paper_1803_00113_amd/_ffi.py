@@ -128,7 +128,7 @@ _sig = {
     "cel_sweep": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(CelSweepOpts), C.POINTER(CelSweepReport), _vp]),
     "cel_last_device_error": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
     "cel_mcmc_step": (C.c_int32, [_vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, C.POINTER(CelMcmcOpts), C.c_uint64, _vp,
-                                  _vp, _vp, _vp, C.POINTER(CelMcmcReport), _vp]),
+                                  _vp, _vp, _vp, _vp, C.POINTER(CelMcmcReport), _vp]),
     "cel_psf_fit": (C.c_int32, [_vp, C.POINTER(CelPsfModel), C.c_int32, _vp, _vp, C.c_int32, C.c_int32, _vp, _vp]),
 }
 EXPORTED = tuple(_sig)

@@ -358,6 +358,7 @@ def mcmc_step(plan: Plan, z_fixed, z_init, opts, key, mask=None, want_samples=Fa
     n_runs, n_post, max_step_out, max_shrink, gamma (host sequence of n_temps + 1), width
     (16 per-coordinate slice widths), box, seed; key: the generator key's second word.
     Returns dict(z [S,16], p_star [S], log_evidence [S,2], samples [S,2,N',B',16] or None,
+    rhat [S,2,16] (the chains' potential scale reduction; NaN rows for unselected sources),
     report)."""
     for t in (z_fixed, z_init):
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
@@ -380,12 +381,13 @@ def mcmc_step(plan: Plan, z_fixed, z_init, opts, key, mask=None, want_samples=Fa
     p_star = torch.full((plan.S,), float("nan"), dtype=torch.float64, device=dev)
     log_ev = torch.full((plan.S, 2), float("nan"), dtype=torch.float64, device=dev)
     smp = torch.zeros((plan.S, 2, Np, Bp, F.N_Z), dtype=torch.float64, device=dev) if want_samples else None
+    rhat = torch.full((plan.S, 2, F.N_Z), float("nan"), dtype=torch.float64, device=dev)
     rep = F.CelMcmcReport()
     keep, m = _mask(plan, mask)
     F.check("cel_mcmc_step", F.lib.cel_mcmc_step(plan.ctx.h, plan.h, _ptr(z_fixed), m, _ptr(z_init), C.byref(o),
                                                  int(key), _ptr(z_out), _ptr(p_star), _ptr(log_ev), _ptr(smp),
-                                                 C.byref(rep), _stream(dev)))
-    return dict(z=z_out, p_star=p_star, log_evidence=log_ev, samples=smp,
+                                                 _ptr(rhat), C.byref(rep), _stream(dev)))
+    return dict(z=z_out, p_star=p_star, log_evidence=log_ev, samples=smp, rhat=rhat,
                 report=dict(rounds=rep.rounds, n_chains=rep.n_chains, evaluations=rep.evaluations,
                             candidate_pixels=rep.candidate_pixels))
 

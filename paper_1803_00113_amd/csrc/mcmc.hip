@@ -29,6 +29,10 @@
 
 namespace celmi {
 
+// runs per source type: both types' chains of a source are candidates of one likelihood
+// launch, at most kVariants of them
+constexpr int kMcmcMaxRuns = kVariants / 2;
+
 enum McmcPhase : int32_t { PH_INIT = 0, PH_STEP_L = 1, PH_STEP_R = 2, PH_SHRINK = 3, PH_DONE = 4 };
 
 struct McmcChain {
@@ -323,6 +327,49 @@ __global__ __launch_bounds__(64) void k_mcmc_finish(McmcArgs a, double log_odds_
   if (n_eval) n_eval[s] = ne;
 }
 
+// Potential scale reduction factor (Gelman and Rubin 1992) of each selected source's n_runs
+// chains of n_post draws, per type and coordinate: the criterion with which the chains of
+// Section 3.2 are monitored.  B = n / (m - 1) sum_j (mean_j - g)^2, W = mean_j s_j^2 (chain
+// variances with divisor n - 1), V = (n - 1) / n W + B / n, R = sqrt(V / W) (0 / 0 = NaN for
+// a coordinate no chain moves).  One thread per (selected source, type, coordinate), FP64,
+// sums in chain and draw order.
+__global__ __launch_bounds__(256) void k_mcmc_rhat(McmcArgs a, double* rhat) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)a.n_sel * 2 * CEL_Z_N) return;
+  const int k = (int)(id % CEL_Z_N), type = (int)((id / CEL_Z_N) % 2), js = (int)(id / (2 * CEL_Z_N));
+  const int s = a.sel[js];
+  const int m = a.n_runs, n = a.n_post;
+  double* out = rhat + ((int64_t)s * 2 + type) * CEL_Z_N + k;
+  if (m < 2 || n < 2) {
+    *out = NAN;
+    return;
+  }
+  const double* x = a.samples + ((int64_t)s * 2 + type) * m * (int64_t)n * CEL_Z_N + k;
+  double mean[kMcmcMaxRuns];
+  double g = 0.0;
+  for (int j = 0; j < m; ++j) {
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += x[((int64_t)j * n + i) * CEL_Z_N];
+    mean[j] = t / n;
+    g += mean[j];
+  }
+  g /= m;
+  double b = 0.0, w = 0.0;
+  for (int j = 0; j < m; ++j) {
+    const double d = mean[j] - g;
+    b += d * d;
+    double v = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double e = x[((int64_t)j * n + i) * CEL_Z_N] - mean[j];
+      v += e * e;
+    }
+    w += v / (n - 1);
+  }
+  const double B = (double)n / (m - 1) * b, W = w / m;
+  const double V = (double)(n - 1) / n * W + B / n;
+  *out = sqrt(V / W);
+}
+
 }  // namespace celmi
 
 using namespace celmi;
@@ -345,13 +392,13 @@ cel_status grow(cel_plan* p, X** ptr, size_t* cap, size_t n) {
 
 extern "C" cel_status cel_mcmc_step(cel_ctx* ctx, const cel_plan* cplan, const double* z_fixed, const uint8_t* mask,
                                     const double* z_init, const cel_mcmc_opts* opts, uint64_t key, double* z_out,
-                                    double* p_star, double* log_evidence, double* samples, cel_mcmc_report* report,
-                                    void* stream) {
+                                    double* p_star, double* log_evidence, double* samples, double* rhat,
+                                    cel_mcmc_report* report, void* stream) {
   if (!ctx || !cplan || !opts) return CEL_EINVAL;
   cel_plan* p = const_cast<cel_plan*>(cplan);
   const cel_mcmc_opts& o = *opts;
   if (o.n_temps < 1 || o.n_runs < 1 || o.n_post < 1 || o.max_step_out < 1 || o.max_shrink < 1 || !o.gamma ||
-      !(o.box > 0) || 2 * o.n_runs > kVariants)
+      !(o.box > 0) || o.n_runs > kMcmcMaxRuns)
     return CEL_EINVAL;
   if (o.n_temps > (1 << 24) || o.n_post > (1 << 20)) return CEL_EUNSUPPORTED;
   for (int k = 0; k < CEL_Z_N; ++k)
@@ -447,6 +494,11 @@ extern "C" cel_status cel_mcmc_step(cel_ctx* ctx, const cel_plan* cplan, const d
     hipLaunchKernelGGL(k_mcmc_finish, dim3((n_sel + 63) / 64), dim3(64), 0, sm, a, p->prior_h.log_a - p->prior_h.log_1ma, z_out,
                        p_star, log_evidence, report ? d_ne : (int64_t*)nullptr);
     e = hipGetLastError();
+    if (e == hipSuccess && rhat) {
+      const int64_t n_r = (int64_t)n_sel * 2 * CEL_Z_N;
+      hipLaunchKernelGGL(k_mcmc_rhat, dim3((unsigned)((n_r + 255) / 256)), dim3(256), 0, sm, a, rhat);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess && report) {
       std::vector<int64_t> ne(S, 0);
       e = hipMemcpyAsync(ne.data(), d_ne, sizeof(int64_t) * S, hipMemcpyDeviceToHost, sm);

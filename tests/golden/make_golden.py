@@ -19,7 +19,8 @@ the generator still produces the same inputs.
                 model g, H, p, predicted gain) for the first 48 sources of colour class 0
   config4_sweep config4_sweep.npz: three oracle sweeps of the field (float64)
   mcmc          mcmc_oracle.npz: the oracle's MCMC source step (annealed importance
-                sampling, slice sampling, type draw) of both sources of a small problem
+                sampling, slice sampling, type draw, the chains' potential scale
+                reduction) of both sources of a small problem
   eigen         eigen_oracle.npz: the field with a spatially varying PSF (E = 4 eigen-
                 images of 51 x 51 knots) and a 192 x 256 sky knot grid: the oracle's PSF
                 fit of every patch, every L_s and gradient and the global ELBO
@@ -281,7 +282,8 @@ def make_mcmc():
     _save("mcmc_oracle.npz", prob, samples=np.array([r["samples"] for r in res]),
           log_evidence=np.array([r["log_evidence"] for r in res]), p_star=np.array([r["p_star"] for r in res]),
           z=np.array([r["z"] for r in res]), a=np.array([r["a"] for r in res]),
-          logw=np.array([r["logw"] for r in res]), n_temps=np.array(opts["n_temps"]), n_runs=np.array(opts["n_runs"]),
+          logw=np.array([r["logw"] for r in res]), rhat=np.array([r["rhat"] for r in res]),
+          n_temps=np.array(opts["n_temps"]), n_runs=np.array(opts["n_runs"]),
           n_post=np.array(opts["n_post"]), gamma=np.array(opts["gamma"]), width=np.array(opts["width"]),
           box=np.array(opts["box"]), max_step_out=np.array(opts["max_step_out"]),
           max_shrink=np.array(opts["max_shrink"]), seed=np.array(opts["seed"]), key=np.array(MCMC_KEY),

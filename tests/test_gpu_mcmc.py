@@ -3,8 +3,8 @@ within-Gibbs transitions, further slice-sampling chains, Bayes' rule over the ty
 the C ABI, against the oracle's sampler.
 
 On the float64 pixel path the likelihood agrees with the oracle's to ~1e-13 relative, so
-every slice-sampling decision is taken alike: the samples, the log evidences, p(star) and
-the drawn point equal the oracle's (1e-9 relative).  With float32 pixels decisions near a
+every slice-sampling decision is taken alike: the samples, the log evidences, p(star), the
+drawn point and the chains' potential scale reduction equal the oracle's (1e-9 relative).  With float32 pixels decisions near a
 slice threshold may go the other way and trajectories then part; the test reports how many
 chains kept the float64 trajectory and bounds the log evidence and p(star)."""
 import sys
@@ -63,6 +63,12 @@ def test_mcmc_step_fp64_matches_oracle(tiny):
         assert np.allclose(r["log_evidence"][s], ref["log_evidence"][s], rtol=1e-9)
         assert abs(r["p_star"][s] - ref["p_star"][s]) <= 1e-9
         assert np.allclose(r["z"][s], ref["z"][s], rtol=1e-9, atol=1e-12) and r["z"][s, 2] == ref["a"][s]
+        # the chains' potential scale reduction: the same finite values, NaN and +inf where
+        # the oracle has them (coordinates no chain moves; a star's unused galaxy coordinates)
+        rh, orh = r["rhat"][s], ref["rhat"][s]
+        assert np.array_equal(np.isnan(rh), np.isnan(orh)) and np.array_equal(np.isinf(rh), np.isinf(orh))
+        fin = np.isfinite(orh)
+        assert np.allclose(rh[fin], orh[fin], rtol=1e-9), np.abs(rh[fin] - orh[fin]).max()
         say(f"  s={s}: log evidence {r['log_evidence'][s]} oracle {ref['log_evidence'][s]}, "
             f"p(star) {r['p_star'][s]:.6f}")
     assert r["report"]["n_chains"] == 2 * 2 * opts["n_runs"] and r["report"]["rounds"] > 0
@@ -78,8 +84,9 @@ def test_mcmc_step_mask_and_determinism(tiny):
     one = _run(tiny, True, mask=np.array([False, True]))
     assert np.array_equal(one["samples"][1], both["samples"][1]) and np.array_equal(one["z"][1], both["z"][1])
     assert np.array_equal(one["z"][0], z[0]) and np.isnan(one["p_star"][0]) and np.all(one["samples"][0] == 0)
+    assert np.isnan(one["rhat"][0]).all() and np.array_equal(one["rhat"][1], both["rhat"][1], equal_nan=True)
     again = _run(tiny, True)
-    for k in ("samples", "z", "p_star", "log_evidence"):
+    for k in ("samples", "z", "p_star", "log_evidence", "rhat"):
         assert np.array_equal(again[k], both[k], equal_nan=True)
 
 

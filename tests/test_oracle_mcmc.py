@@ -153,3 +153,41 @@ def test_source_step_is_bayes_rule_on_its_estimates_and_deterministic(tiny):
     assert np.all(np.abs(smp[:, 0:2] - z[s, 0:2]) <= OPTS["box"])
     assert np.all((smp[:, 10] >= 0) & (smp[:, 10] <= 1) & (smp[:, 11] > 0) & (smp[:, 11] <= 1))
     assert np.all((smp[:, 8] >= 0) & (smp[:, 8] < math.pi))
+
+
+def test_rhat_worked_example():
+    """Two chains (1, 2, 3) and (2, 3, 4): chain means 2 and 3, grand mean 5/2, between-chain
+    B = 3 / 1 x (1/4 + 1/4) = 3/2, within-chain W = (1 + 1) / 2 = 1, V = 2/3 + 1/2 = 7/6,
+    R = sqrt(7/6) (worked by hand from the definition in Gelman and Rubin 1992)."""
+    x = np.array([[1.0, 2.0, 3.0], [2.0, 3.0, 4.0]])[:, :, None]
+    assert M.rhat(x)[0] == pytest.approx(math.sqrt(7.0 / 6.0), rel=1e-15)
+
+
+def test_rhat_of_chains_with_known_between_and_within_spread():
+    """Chain j = c_j + e, one zero-mean pattern e of sample variance s2 shared by every chain:
+    W = s2 exactly and B = n var(c) (divisor m - 1), so R^2 = ((n - 1) / n s2 + var(c)) / s2."""
+    rng = np.random.default_rng(1)
+    n, m = 40, 5
+    e = rng.normal(size=n)
+    e -= e.mean()
+    s2 = e.var(ddof=1)
+    c = np.array([0.0, 0.3, -0.2, 1.1, 0.4])
+    x = (c[:, None] + e[None, :])[:, :, None]
+    want = math.sqrt(((n - 1) / n * s2 + c.var(ddof=1)) / s2)
+    assert M.rhat(x)[0] == pytest.approx(want, rel=1e-12)
+
+
+def test_rhat_invariances_and_limits():
+    """Invariant under x -> a x + b (a != 0) coordinatewise; near 1 for independent draws
+    from one distribution; large when the chains sit apart; NaN for a coordinate no chain
+    moves and for a single draw per chain."""
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=(4, 50, 3)) + np.array([0.0, 0.5, 2.0])[None, None, :] * np.arange(4)[:, None, None]
+    r = M.rhat(x)
+    assert np.allclose(M.rhat(-3.0 * x + 7.0), r, rtol=1e-12)
+    assert r[0] < r[1] < r[2] and r[2] > 2.0
+    iid = M.rhat(rng.normal(size=(4, 100_000, 1)))[0]
+    assert abs(iid - 1.0) < 2e-3
+    const = np.zeros((3, 5, 1))
+    assert np.isnan(M.rhat(const)[0])
+    assert np.isnan(M.rhat(rng.normal(size=(3, 1, 2)))).all()
