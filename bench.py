@@ -466,7 +466,9 @@ def main():
         dtp = time.perf_counter() - t0
         same = bool(torch.equal(outp[2], out[2]) and torch.equal(outp[0], out[0]))
         plain = dict(value=units * args.plain_steps / dtp, ms_per_step=1e3 * dtp / args.plain_steps,
-                     identical_to_batched=same)
+                     identical_to_batched=same,
+                     form="component tables and moment maps batched; the pixel and finalisation "
+                          "kernels launched once per source (the paper's one-source-at-a-time pixel loop)")
         log(f"plain: {plain['ms_per_step']:.2f} ms/step (identical outputs: {same})")
 
     if args.copy_calibration:
