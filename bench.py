@@ -44,7 +44,7 @@ PAPER_CONTEXT = [
     dict(figure="VI time per light source (trust-region Newton to convergence)", value=9.0, unit="s",
          hardware="1 core of an Intel Xeon E5-2698 v3 at 2.3 GHz", precision="FP64", where="Section 5.3"),
     dict(figure="MCMC wall-clock relative to VI", value=1000.0, unit="x", hardware="1 core of an Intel Xeon E5-2698 v3",
-         precision="FP64", where="Sections 1 and 5.3"),
+         precision="FP64", where="abstract; Section 5.3"),
     dict(figure="peak sustained rate of the VI code", value=1.54, unit="PFLOP/s",
          hardware="9,568 Cori nodes of Intel Xeon Phi 7250 (KNL)", precision="FP64", where="Section 6.4"),
 ]
