@@ -973,7 +973,8 @@ constexpr int kPointPixelsPerLane = 4;
 template <typename T>
 static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* theta_trial, int v0, int nv,
                                bool grad, int cls, const uint8_t* active, hipStream_t sm, bool prep_base,
-                               double* local_out, double* grad_out, int64_t theta_vstride = 0) {
+                               double* local_out, double* grad_out, int64_t theta_vstride = 0,
+                               const uint8_t* active_v = nullptr) {
   // theta_vstride > 0: likelihood mode -- variant v's parameters at theta + v * theta_vstride,
   // no differences, no KL, the pixel sums of variant v to local_out + v * S
   const bool point = theta_vstride > 0;
@@ -996,6 +997,8 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   pa.patch_psf = p->d_patch_psf;
   pa.records = p->opt.map_pixels_per_lane == -1 ? kRecRuns : 0;
   pa.theta_vstride = theta_vstride;
+  pa.active_v = active_v;   // (launch variant, source) pairs to evaluate: the likelihood pass
+  pa.active_v_stride = p->S;
   phase_mark(p, 0, sm);
   if (prep_base) {   // variant 0 of every source and its moment maps (neighbours read these)
     pa.variant0 = 0;
@@ -1038,6 +1041,8 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   fa.active = active;
   fa.variant0 = v0;
   fa.img_npsf = p->d_npsf;
+  fa.active_v = active_v;
+  fa.active_v_stride = p->S;
   // the likelihood pass (values only, often one type per candidate) takes 4 pixels per lane
   // whatever the plan's setting: more independent work per wavefront for thin candidates
   // (10.2 ms per 56 x 1000 candidates against 12.1 at 2 and 10.8 at 8)
@@ -1071,6 +1076,8 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   fz.fd = point ? 0 : p->fd_mode;
   fz.theta_vstride = theta_vstride;
   fz.no_kl = point ? 1 : 0;
+  fz.active_v = active_v;
+  fz.active_v_stride = p->S;
   if (point) fz.err = nullptr;   // a candidate's non-finite likelihood is a result, not a fault
   if (cls >= 0) {
     // jobs = members of the class
@@ -1358,7 +1365,8 @@ cel_status point_setup(cel_plan* p, const double* z_fixed, const std::vector<uin
   return e == hipSuccess ? CEL_OK : CEL_EHIP;
 }
 
-hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* ll, hipStream_t sm) {
+hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* ll, hipStream_t sm,
+                        const uint8_t* act) {
   const bool fp64 = p->opt.pixel_fp64 != 0;
   const int S = p->S;
   const int chunk = p->pt_cap;
@@ -1371,8 +1379,9 @@ hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* l
     e = launch_point_theta(z_cand + (int64_t)c0 * S * CEL_Z_N, (int64_t)nc * S, th_cand, p->d_pt_ok, sm);
     if (e != hipSuccess) break;
     double* out = ll + (int64_t)c0 * S;
-    e = fp64 ? enqueue_eval<double>(p, th_cand, nullptr, 0, nc, false, cls, nullptr, sm, false, out, nullptr, row)
-             : enqueue_eval<float>(p, th_cand, nullptr, 0, nc, false, cls, nullptr, sm, false, out, nullptr, row);
+    const uint8_t* act_c = act ? act + (int64_t)c0 * S : nullptr;
+    e = fp64 ? enqueue_eval<double>(p, th_cand, nullptr, 0, nc, false, cls, nullptr, sm, false, out, nullptr, row, act_c)
+             : enqueue_eval<float>(p, th_cand, nullptr, 0, nc, false, cls, nullptr, sm, false, out, nullptr, row, act_c);
     if (e == hipSuccess) e = launch_support_masked(p->d_pt_ok, p->d_mask, S, (int64_t)nc * S, out, sm);
   }
   return e;

@@ -126,6 +126,8 @@ struct FusedArgs {
   const uint8_t* active;       // per source (nullptr = all)
   int32_t variant0;            // variant index of blockIdx.y == 0
   const int32_t* img_npsf;     // PSF components per image
+  const uint8_t* active_v;     // per (launch variant, source), row stride active_v_stride (nullptr = all)
+  int64_t active_v_stride;
 };
 
 struct MapArgs {

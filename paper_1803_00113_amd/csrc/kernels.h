@@ -23,6 +23,8 @@ struct PrepArgs {
   int64_t theta_vstride;       // > 0: variant v reads theta + v * theta_vstride (per-variant points)
   const double* patch_psf;     // [P][kMaxPsf][6] per-patch PSF mixtures (null: the image's)
   int32_t records;             // extra table records: kRecHessian (gt), kRecRuns (rq)
+  const uint8_t* active_v;     // per (launch variant, source), row stride active_v_stride (null = all)
+  int64_t active_v_stride;
 };
 constexpr int kRecHessian = 1;
 constexpr int kRecRuns = 2;
@@ -53,6 +55,8 @@ struct FinalizeArgs {
   int32_t* err;                // device condition word (CEL_DEVERR_*), may be null
   int64_t theta_vstride;       // as in PrepArgs
   int32_t no_kl;               // 1: the pixel sum alone (point likelihood), no KL
+  const uint8_t* active_v;     // per (launch variant, source), row stride active_v_stride (null = all)
+  int64_t active_v_stride;
 };
 
 template <typename T>

@@ -54,6 +54,7 @@ __global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
   const int v = a.variant0 + blockIdx.y;
   const DPatch P = a.patches[pi_];
   if (a.active && !a.active[P.src]) return;
+  if (a.active_v && !a.active_v[(int64_t)blockIdx.y * a.active_v_stride + P.src]) return;
   const cel_image& im = a.images[P.img];
   double th[kThetaN];
   load_theta(a.theta, a.theta_trial, a.theta_vstride, P.src, v, a.fd_step, th, a.trial_variant, a.fd);
@@ -532,6 +533,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const DTask task = a.tasks[t];
   const DPatch P = a.patches[task.patch];
   if (a.active && !a.active[P.src]) return;
+  if (a.active_v && !a.active_v[(int64_t)blockIdx.y * a.active_v_stride + P.src]) return;
   const Table<T>* __restrict__ tb = a.own + (int64_t)v * a.variant_stride + task.patch;
   const int K = a.img_npsf[P.img];
   const int lane = threadIdx.x;
@@ -720,6 +722,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   const int vv = blockIdx.y;
   const int v = a.variant0 + vv;
   if (a.active && !a.active[s]) return;
+  if (a.active_v && !a.active_v[(int64_t)vv * a.active_v_stride + s]) return;
   double th[kThetaN];
   load_theta(a.theta, a.theta_trial, a.theta_vstride, s, v, a.fd_step, th, a.trial_variant, a.fd);
   double g[kThetaN];

@@ -61,6 +61,7 @@ struct McmcArgs {
   double width[CEL_Z_N];
   double box;
   uint64_t key0, key1;
+  uint8_t* act;               // [2 n_runs][S]: the chain of (candidate, source) still runs
 };
 
 // ---------------------------------------------------------------------------------------
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(256) void k_mcmc_advance(McmcArgs a) {
   McmcChain c = a.chains[i];
   double* smp = a.samples + (((int64_t)s * 2 + type) * a.n_runs + run) * (int64_t)a.n_post * CEL_Z_N;
   double* cand = a.z_cand + ((int64_t)cc * a.S + s) * CEL_Z_N;
-  if (c.phase == PH_DONE) return;   // its candidate row still holds its point
+  if (c.phase == PH_DONE) return;   // its candidate row still holds its point, not evaluated
   // the evaluated candidate: log prior, log likelihood, the position's box
   const int64_t at = (int64_t)cc * a.S + s;
   double lpc = a.lp_cand[at], llc = a.ll_cand[at];
@@ -243,6 +244,8 @@ __global__ __launch_bounds__(256) void k_mcmc_advance(McmcArgs a) {
   for (int k = 0; k < CEL_Z_N; ++k) cand[k] = c.z[k];
   if (c.phase != PH_DONE) cand[c_coords[type][c.ci]] = next;
   a.chains[i] = c;
+  // a finished chain's candidate is not evaluated again
+  if (c.phase == PH_DONE) a.act[at] = 0;
 }
 
 // Chains from their start points; every candidate row of a selected source its start point.
@@ -267,6 +270,7 @@ __global__ __launch_bounds__(256) void k_mcmc_init(McmcArgs a) {
   c.t = c.ci = c.J = c.K = c.shrink = c.n_eval = c.pad = 0;
   c.phase = PH_INIT;
   a.chains[i] = c;
+  a.act[(int64_t)cc * a.S + s] = 1;
 }
 
 // Rows of unselected sources: their fixed point (the likelihood pass reads every row).
@@ -424,6 +428,7 @@ extern "C" cel_status cel_mcmc_step(cel_ctx* ctx, const cel_plan* cplan, const d
   if ((st = grow(p, &p->mc_chains, &p->mc_chains_cap, (size_t)n_chains * sizeof(McmcChain))) ||
       (st = grow(p, &p->mc_cand, &p->mc_cand_cap, (size_t)nch * S * CEL_Z_N)) ||
       (st = grow(p, &p->mc_vals, &p->mc_vals_cap, (size_t)2 * nch * S)) ||
+      (st = grow(p, &p->mc_act, &p->mc_act_cap, (size_t)nch * S)) ||
       (st = grow(p, &p->mc_sel, &p->mc_sel_cap, (size_t)n_sel + S + 2)) ||
       (!samples && (st = grow(p, &p->mc_samples, &p->mc_samples_cap, n_smp))))
     return st;
@@ -455,6 +460,7 @@ extern "C" cel_status cel_mcmc_step(cel_ctx* ctx, const cel_plan* cplan, const d
   a.z_fixed = z_fixed;
   a.z_init = z_init;
   a.z_cand = p->mc_cand;
+  a.act = p->mc_act;
   a.ll_cand = p->mc_vals;
   a.lp_cand = p->mc_vals + (size_t)nch * S;
   a.samples = samples ? samples : p->mc_samples;
@@ -476,7 +482,7 @@ extern "C" cel_status cel_mcmc_step(cel_ctx* ctx, const cel_plan* cplan, const d
   int32_t* h_active = p->h_counter;   // pinned word of the plan's Newton kit
   while (e == hipSuccess) {
     for (int r = 0; r < kCheck && e == hipSuccess; ++r, ++rounds) {
-      e = point_loglik(p, nch, p->mc_cand, ll_c, sm);
+      e = point_loglik(p, nch, p->mc_cand, ll_c, sm, p->mc_act);
       if (e == hipSuccess) e = launch_log_prior(p->d_prior, p->mc_cand, rows, lp_c, sm);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_mcmc_advance, dim3(blocks), dim3(256), 0, sm, a);

@@ -142,10 +142,11 @@ struct cel_plan {
   char* mc_chains = nullptr;
   double* mc_cand = nullptr;
   double* mc_vals = nullptr;
+  uint8_t* mc_act = nullptr;       // per (candidate, source): the chain still runs
   int32_t* mc_sel = nullptr;
   double* mc_samples = nullptr;
   double* mc_gamma = nullptr;
-  size_t mc_chains_cap = 0, mc_cand_cap = 0, mc_vals_cap = 0, mc_sel_cap = 0, mc_samples_cap = 0, mc_gamma_cap = 0;
+  size_t mc_chains_cap = 0, mc_cand_cap = 0, mc_vals_cap = 0, mc_sel_cap = 0, mc_samples_cap = 0, mc_gamma_cap = 0, mc_act_cap = 0;
   struct Block {
     void* ptr;
     size_t bytes;
@@ -204,7 +205,10 @@ hipError_t stage_selection(cel_plan* p, const std::vector<uint8_t>& m, bool as_c
 hipError_t launch_total_after_eval(cel_plan* p, const double* theta, hipStream_t sm);
 // Point likelihood passes: point_setup stages the selection (m[s] != 0) and the neighbour
 // maps at z_fixed, with scratch for `chunk` candidates per launch (<= kVariants); then each
-// point_loglik writes ll[c][s] for the selected sources of n_cand candidate rows z_cand.
+// point_loglik writes ll[c][s] for the selected sources of n_cand candidate rows z_cand
+// (act: optional [n_cand][S] flags; a (candidate, source) flagged 0 is not evaluated and its
+// ll entry is left as it was).
 cel_status point_setup(cel_plan* p, const double* z_fixed, const std::vector<uint8_t>& m, int chunk, hipStream_t sm);
-hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* ll, hipStream_t sm);
+hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* ll, hipStream_t sm,
+                        const uint8_t* act = nullptr);
 }  // namespace celmi
