@@ -79,6 +79,28 @@ def test_batched_workload_full_size(fp64):
         assert np.all(g[:, 27:] == 0)
 
 
+def test_batched_workload_full_size_tuned():
+    """The launch configuration the benchmark times is the tuned plan's (cel_tune may choose
+    another work-item size, pixels per lane or map variant on a given box): its global ELBO,
+    L_s and gradients against the oracle's stored values, and every candidate work-item size
+    re-cut on the same plan at the same bar."""
+    say("case: batched workload, 1000 sources, full size, tuned plan and every work-item size")
+    prob = gen.config2()
+    ref = load_golden("config2_oracle.npz", prob)
+    plan = api.Plan(api.Context(0), prob)
+    th = torch.as_tensor(prob.theta0, device="cuda").contiguous()
+    o_tot = float(ref["elbo_total"])
+    settings = [plan.tune(th)] + [plan.tune(th, chunk_pixels=[c], pixels_per_lane=[], map_pixels_per_lane=[])
+                                  for c in (256, 1024, 2048, 512)]
+    for t in settings:
+        tot, loc, g = api.elbo_grad(plan, th)
+        tot, loc, g = tot.item(), loc.cpu().numpy(), g.cpu().numpy()
+        say(f"  {t['chunk_pixels']} px items, {t['pixels_per_lane']} px/lane, maps {t['map_pixels_per_lane']}: "
+            f"total rel {abs(tot - o_tot) / abs(o_tot):.1e}")
+        check(prob, tot, loc, None, o_tot, ref["elbo_local"], None)
+        check_grad_full(g[:, :27], ref["grad"][:, :27])
+
+
 def test_adjoint_workload_full_size():
     """The gradient through torch.autograd (forward = ELBO kernel, backward = adjoint kernel
     with the pixel terms recomputed) for all 4096 sources, float32 pixels."""

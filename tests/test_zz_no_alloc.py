@@ -49,7 +49,7 @@ def test_static_scratch_equals_plan_scratch(fp64):
 
 
 def test_static_scratch_full_batched_workload_and_limit():
-    """The 1000-source batched workload (float32 pixels, 190 MB of scratch) fits the static
+    """The 1000-source batched workload (float32 pixels, 204 MB of scratch) fits the static
     buffer and matches; with float64 pixels (tables and maps twice as large) it does not and
     the call returns CEL_ESCRATCH without writing the outputs."""
     say("case: static-scratch gradient, batched workload, limit")
@@ -68,4 +68,8 @@ def test_static_scratch_full_batched_workload_and_limit():
     torch.cuda.synchronize()
     assert all(bool((t == 7.0).all()) for t in out)
     # the float32 plan still works after the rejected call
+    _same(plan, prob.theta0)
+    # and after its work items are re-cut (more items: larger slot rows in the buffer)
+    plan.tune(torch.as_tensor(prob.theta0, device="cuda").contiguous(), chunk_pixels=[256],
+              pixels_per_lane=[], map_pixels_per_lane=[])
     _same(plan, prob.theta0)
