@@ -1366,7 +1366,7 @@ cel_status point_setup(cel_plan* p, const double* z_fixed, const std::vector<uin
 }
 
 hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* ll, hipStream_t sm,
-                        const uint8_t* act) {
+                        const uint8_t* act, bool mark_support) {
   const bool fp64 = p->opt.pixel_fp64 != 0;
   const int S = p->S;
   const int chunk = p->pt_cap;
@@ -1382,7 +1382,7 @@ hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* l
     const uint8_t* act_c = act ? act + (int64_t)c0 * S : nullptr;
     e = fp64 ? enqueue_eval<double>(p, th_cand, nullptr, 0, nc, false, cls, nullptr, sm, false, out, nullptr, row, act_c)
              : enqueue_eval<float>(p, th_cand, nullptr, 0, nc, false, cls, nullptr, sm, false, out, nullptr, row, act_c);
-    if (e == hipSuccess) e = launch_support_masked(p->d_pt_ok, p->d_mask, S, (int64_t)nc * S, out, sm);
+    if (e == hipSuccess && mark_support) e = launch_support_masked(p->d_pt_ok, p->d_mask, S, (int64_t)nc * S, out, sm);
   }
   return e;
 }

@@ -482,7 +482,9 @@ extern "C" cel_status cel_mcmc_step(cel_ctx* ctx, const cel_plan* cplan, const d
   int32_t* h_active = p->h_counter;   // pinned word of the plan's Newton kit
   while (e == hipSuccess) {
     for (int r = 0; r < kCheck && e == hipSuccess; ++r, ++rounds) {
-      e = point_loglik(p, nch, p->mc_cand, ll_c, sm, p->mc_act);
+      // (a candidate outside the support has log prior -infinity, which the advance reads
+      // as a rejected point: the likelihood pass need not mark it)
+      e = point_loglik(p, nch, p->mc_cand, ll_c, sm, p->mc_act, false);
       if (e == hipSuccess) e = launch_log_prior(p->d_prior, p->mc_cand, rows, lp_c, sm);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_mcmc_advance, dim3(blocks), dim3(256), 0, sm, a);

@@ -207,8 +207,9 @@ hipError_t launch_total_after_eval(cel_plan* p, const double* theta, hipStream_t
 // maps at z_fixed, with scratch for `chunk` candidates per launch (<= kVariants); then each
 // point_loglik writes ll[c][s] for the selected sources of n_cand candidate rows z_cand
 // (act: optional [n_cand][S] flags; a (candidate, source) flagged 0 is not evaluated and its
-// ll entry is left as it was).
+// ll entry is left as it was; mark_support: set -infinity for candidates outside the
+// support, which a caller that also takes the prior density, -infinity there, may skip).
 cel_status point_setup(cel_plan* p, const double* z_fixed, const std::vector<uint8_t>& m, int chunk, hipStream_t sm);
 hipError_t point_loglik(cel_plan* p, int n_cand, const double* z_cand, double* ll, hipStream_t sm,
-                        const uint8_t* act = nullptr);
+                        const uint8_t* act = nullptr, bool mark_support = true);
 }  // namespace celmi
