@@ -49,7 +49,8 @@ __device__ __forceinline__ void galaxy_cov(double angle, double radius, double a
 // k_prep_tables: one wavefront per (variant, patch)
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_prep_tables(PrepArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_prep_tables(
+    PrepArgs a) {
   const int pi_ = a.patch_list ? a.patch_list[blockIdx.x] : a.patch_offset + (int)blockIdx.x;
   const int v = a.variant0 + blockIdx.y;
   const DPatch P = a.patches[pi_];
