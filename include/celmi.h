@@ -463,7 +463,7 @@ typedef struct cel_tuning {
  * least time counts, on `stream`, synchronised) over the work-item size and the pixel
  * pass's pixels per lane together, then over the moment-map variants at the chosen pair,
  * and keeps the fastest in the plan -- the plan's current setting, timed first when it is
- * a candidate, gives way only to one faster by more than 2 % (timing noise does not flip
+ * a candidate, gives way only to one faster by more than 5 % (timing noise does not flip
  * the choice): a new work-item size re-cuts the plan's work items
  * (item tables, launch orders, per-colour lists and the scratch sized by the item count,
  * as cel_prepare would have cut them with that chunk_pixels).  Later evaluations, Newton

@@ -1477,9 +1477,10 @@ extern "C" cel_status cel_tune(cel_ctx* ctx, cel_plan* p, const double* theta, c
     ++res.n_timed;
     return e == hipSuccess ? best : -1.0;
   };
-  // a candidate replaces the kept setting only when it is faster by more than the margin
-  // (timing noise of a few tenths of a percent must not flip the choice between runs)
-  constexpr double kMargin = 0.02;
+  // a candidate replaces the kept setting only when it is faster by more than the margin:
+  // settings within a few percent of each other trade places from box to box and run to
+  // run, and a choice that flips would change the plan's results in their last bits
+  constexpr double kMargin = 0.05;
   const int cur_chunk = p->opt.chunk_pixels, cur_ppl = p->opt.pixels_per_lane, cur_map = p->opt.map_pixels_per_lane;
   cel_status st = CEL_OK;
   auto has = [](const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); };
