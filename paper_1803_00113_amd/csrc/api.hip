@@ -853,15 +853,6 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
     p->prof_h = d;
     p->nexp = pf.n_exp;
     p->ndev = pf.n_dev;
-    std::vector<float> hf(2 * kMaxProf, 0.f);
-    std::vector<double> hd(2 * kMaxProf, 0.0);
-    for (int j = 0; j < pf.n_exp; ++j) { hf[j] = (float)(0.5 * pf.exp_tau[j]); hd[j] = 0.5 * pf.exp_tau[j]; }
-    for (int j = 0; j < pf.n_dev; ++j) {
-      hf[kMaxProf + j] = (float)(0.5 * pf.dev_tau[j]);
-      hd[kMaxProf + j] = 0.5 * pf.dev_tau[j];
-    }
-    p->htau_fh = hf;
-    p->htau_dh = hd;
   }
   std::vector<int32_t> npsf(std::max(N, 1), 1);
   for (int n = 0; n < N; ++n) npsf[n] = pr->images[n].n_psf;
@@ -885,8 +876,6 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   pk.add(&p->d_npsf, npsf);
   pk.add(&p->d_prior, prior1);
   pk.add(&p->d_prof, prof1);
-  pk.add(&p->d_htau_f, p->htau_fh);
-  pk.add(&p->d_htau_d, p->htau_dh);
   pk.add(&d_user_off, user_off);
   pk.add(&d_knots, knots);
   std::vector<double> ppsf;
@@ -979,7 +968,6 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   // no differences, no KL, the pixel sums of variant v to local_out + v * S
   const bool point = theta_vstride > 0;
   Table<T>* tables = reinterpret_cast<Table<T>*>(sizeof(T) == 8 ? (void*)p->tables_d : (void*)p->tables_f);
-  const T* htau = sizeof(T) == 8 ? (const T*)p->d_htau_d : (const T*)p->d_htau_f;
   hipError_t e = hipSuccess;
   PrepArgs pa;
   std::memset(&pa, 0, sizeof(pa));
@@ -1047,7 +1035,7 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
   // whatever the plan's setting: more independent work per wavefront for thin candidates
   // (10.2 ms per 56 x 1000 candidates against 12.1 at 2 and 10.8 at 8)
   const int ppl = point ? kPointPixelsPerLane : p->opt.pixels_per_lane;
-  e = launch_fused<T>(fa, htau, p->nexp, p->ndev, ppl, grad, n_items, nv, sm);
+  e = launch_fused<T>(fa, p->nexp, p->ndev, ppl, grad, n_items, nv, sm);
   if (e != hipSuccess) return e;
   phase_mark(p, 3, sm);
   FinalizeArgs fz;
@@ -1090,7 +1078,6 @@ static hipError_t enqueue_eval(cel_plan* p, const double* theta, const double* t
 template <typename T>
 static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm) {
   Table<T>* tables = reinterpret_cast<Table<T>*>(sizeof(T) == 8 ? (void*)p->tables_d : (void*)p->tables_f);
-  const T* htau = sizeof(T) == 8 ? (const T*)p->d_htau_d : (const T*)p->d_htau_f;
   PrepArgs pa;
   std::memset(&pa, 0, sizeof(pa));
   pa.theta = theta;
@@ -1146,7 +1133,7 @@ static hipError_t plain_eval_t(cel_plan* p, const double* theta, hipStream_t sm)
     if (pe > pb) {
       const int tb = p->patches_h[pb].task_begin, te = p->patches_h[pe - 1].task_end;
       fa.order_offset = tb;
-      e = launch_fused<T>(fa, htau, p->nexp, p->ndev, p->opt.pixels_per_lane, true, te - tb, 1, sm);
+      e = launch_fused<T>(fa, p->nexp, p->ndev, p->opt.pixels_per_lane, true, te - tb, 1, sm);
     }
     fz.src_offset = s;
     if (e == hipSuccess) e = launch_finalize(fz, 1, sm);

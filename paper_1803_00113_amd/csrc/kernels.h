@@ -62,7 +62,7 @@ struct FinalizeArgs {
 template <typename T>
 hipError_t launch_prep_tables(const PrepArgs& a, int n_patches_launch, int n_variants, hipStream_t st);
 template <typename T>
-hipError_t launch_fused(const FusedArgs<T>& a, const T* htau, int nexp, int ndev, int ppl, bool grad, int n_items,
+hipError_t launch_fused(const FusedArgs<T>& a, int nexp, int ndev, int ppl, bool grad, int n_items,
                         int n_variants, hipStream_t st);
 template <typename T>
 hipError_t launch_maps(const MapArgs& a, int nexp, int ndev, int ppl, int n_items, hipStream_t st);

@@ -526,8 +526,8 @@ __global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
 }
 
 template <typename T, int PPL, bool GRAD, int NEXP, int NDEV>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && PPL < 4 ? 6 : 1))) void k_fused(FusedArgs<T> a,
-                                                                                   const T* __restrict__ htau) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && PPL < 4 ? 6 : 1))) void k_fused(
+    FusedArgs<T> a) {
   const int v = a.variant0 + blockIdx.y;
   const int wi = a.order_offset + xcd_position((int)blockIdx.x, (int)gridDim.x);
   const int t = a.order ? a.order[wi] : wi;
@@ -970,27 +970,27 @@ hipError_t launch_prep_tables(const PrepArgs& a, int n_patches_launch, int n_var
 }
 
 template <typename T, int PPL, bool GRAD>
-static hipError_t fused_dispatch(const FusedArgs<T>& a, const T* htau, int nexp, int ndev, int n_items, int n_var,
+static hipError_t fused_dispatch(const FusedArgs<T>& a, int nexp, int ndev, int n_items, int n_var,
                                  hipStream_t st) {
   dim3 grid(n_items, n_var);
   if (nexp == 6 && ndev == 8)
-    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 6, 8>), grid, dim3(64), 0, st, a, htau);
+    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 6, 8>), grid, dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 8, 8>), grid, dim3(64), 0, st, a, htau);
+    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 8, 8>), grid, dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fused(const FusedArgs<T>& a, const T* htau, int nexp, int ndev, int ppl, bool grad, int n_items,
+hipError_t launch_fused(const FusedArgs<T>& a, int nexp, int ndev, int ppl, bool grad, int n_items,
                         int n_variants, hipStream_t st) {
   if (n_items <= 0 || n_variants <= 0) return hipSuccess;
   switch (ppl * 2 + (grad ? 1 : 0)) {
-    case 2: return fused_dispatch<T, 1, false>(a, htau, nexp, ndev, n_items, n_variants, st);
-    case 3: return fused_dispatch<T, 1, true>(a, htau, nexp, ndev, n_items, n_variants, st);
-    case 4: return fused_dispatch<T, 2, false>(a, htau, nexp, ndev, n_items, n_variants, st);
-    case 5: return fused_dispatch<T, 2, true>(a, htau, nexp, ndev, n_items, n_variants, st);
-    case 8: return fused_dispatch<T, 4, false>(a, htau, nexp, ndev, n_items, n_variants, st);
-    case 9: return fused_dispatch<T, 4, true>(a, htau, nexp, ndev, n_items, n_variants, st);
+    case 2: return fused_dispatch<T, 1, false>(a, nexp, ndev, n_items, n_variants, st);
+    case 3: return fused_dispatch<T, 1, true>(a, nexp, ndev, n_items, n_variants, st);
+    case 4: return fused_dispatch<T, 2, false>(a, nexp, ndev, n_items, n_variants, st);
+    case 5: return fused_dispatch<T, 2, true>(a, nexp, ndev, n_items, n_variants, st);
+    case 8: return fused_dispatch<T, 4, false>(a, nexp, ndev, n_items, n_variants, st);
+    case 9: return fused_dispatch<T, 4, true>(a, nexp, ndev, n_items, n_variants, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1167,9 +1167,9 @@ template hipError_t launch_prep_tables<float>(const PrepArgs&, int, int, hipStre
 template hipError_t launch_prep_tables<double>(const PrepArgs&, int, int, hipStream_t);
 template hipError_t launch_maps<float>(const MapArgs&, int, int, int, int, hipStream_t);
 template hipError_t launch_maps<double>(const MapArgs&, int, int, int, int, hipStream_t);
-template hipError_t launch_fused<float>(const FusedArgs<float>&, const float*, int, int, int, bool, int, int,
+template hipError_t launch_fused<float>(const FusedArgs<float>&, int, int, int, bool, int, int,
                                         hipStream_t);
-template hipError_t launch_fused<double>(const FusedArgs<double>&, const double*, int, int, int, bool, int, int,
+template hipError_t launch_fused<double>(const FusedArgs<double>&, int, int, int, bool, int, int,
                                          hipStream_t);
 
 }  // namespace celmi

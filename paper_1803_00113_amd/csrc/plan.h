@@ -64,8 +64,6 @@ struct cel_plan {
   std::vector<std::vector<int32_t>> class_patches, class_tasks, class_src;
   celmi::DPrior prior_h;
   celmi::DProfiles prof_h;
-  std::vector<float> htau_fh;
-  std::vector<double> htau_dh;
   // device tables
   celmi::DPatch* d_patches = nullptr;
   cel_image* d_images = nullptr;
@@ -77,8 +75,6 @@ struct cel_plan {
   int32_t* d_npsf = nullptr;
   celmi::DPrior* d_prior = nullptr;
   celmi::DProfiles* d_prof = nullptr;
-  float* d_htau_f = nullptr;
-  double* d_htau_d = nullptr;
   float2* d_xs = nullptr;
   double2* d_xs64 = nullptr;    // only with float64 pixel / Hessian options
   float2* d_maps = nullptr;     // (E_s, V_s) of each patch's source at the base parameters
