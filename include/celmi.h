@@ -458,13 +458,14 @@ typedef struct cel_tuning {
 } cel_tuning;
 
 /* Launch tuning of the evaluation (the paper's thread-level execution study and its remark
- * that sources of varying size make SIMD across sources hard), kept per plan.  Times the
- * ELBO-and-gradient evaluation at theta (one warm-up and five timed calls per setting, the
- * least time counts, on `stream`, synchronised) over the work-item size and the pixel
- * pass's pixels per lane together, then over the moment-map variants at the chosen pair,
- * and keeps the fastest in the plan -- the plan's current setting, timed first when it is
- * a candidate, gives way only to one faster by more than 5 % (timing noise does not flip
- * the choice): a new work-item size re-cuts the plan's work items
+ * that sources of varying size make SIMD across sources hard), kept per plan.  After 40
+ * untimed evaluations (the device's clocks settle), times the ELBO-and-gradient evaluation
+ * at theta over the work-item size and the pixel pass's pixels per lane together, then over
+ * the moment-map variants at the chosen pair: every setting in two passes through all
+ * candidates, each time one warm-up and five timed calls, the least time counting, on
+ * `stream`, synchronised.  The fastest setting replaces the plan's current one when that is
+ * no candidate or is slower by more than 5 % (settings closer than that trade places from
+ * run to run): a new work-item size re-cuts the plan's work items
  * (item tables, launch orders, per-colour lists and the scratch sized by the item count,
  * as cel_prepare would have cut them with that chunk_pixels).  Later evaluations, Newton
  * steps, sweeps, samplers and appends of the plan use the settings; captured sweep graphs

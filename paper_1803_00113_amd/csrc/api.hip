@@ -1465,57 +1465,78 @@ extern "C" cel_status cel_tune(cel_ctx* ctx, cel_plan* p, const double* theta, c
     return e == hipSuccess ? best : -1.0;
   };
   // a candidate replaces the kept setting only when it is faster by more than the margin:
-  // settings within a few percent of each other trade places from box to box and run to
-  // run, and a choice that flips would change the plan's results in their last bits
+  // settings within a few percent of each other trade places from run to run, and a choice
+  // that flips would change the plan's results in their last bits
   constexpr double kMargin = 0.05;
+  constexpr int kPasses = 2, kWarm = 40;
   const int cur_chunk = p->opt.chunk_pixels, cur_ppl = p->opt.pixels_per_lane, cur_map = p->opt.map_pixels_per_lane;
   cel_status st = CEL_OK;
-  auto has = [](const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); };
-  // work-item size and pixel-pass lanes together (the pass's cost depends on both), the
-  // plan's current pair first when it is a candidate ...
-  const bool cur_pair = has(chunks, cur_chunk) && has(ppls, cur_ppl);
-  double best_ms = cur_pair ? time_it() : INFINITY;
-  if (best_ms < 0) st = CEL_EHIP;
-  for (int c : chunks) {
-    if (st) break;
-    for (int l : ppls) {
-      if (cur_pair && c == cur_chunk && l == cur_ppl) continue;
-      if ((st = plan_retile(p, c, sm)) || (st = ensure_variants(p, 1, fp64))) break;
-      p->opt.pixels_per_lane = l;
-      const double ms = time_it();
-      if (ms < 0) {
-        st = CEL_EHIP;
-        break;
-      }
-      if (ms < best_ms * (1.0 - kMargin) || best_ms == INFINITY) {
-        best_ms = ms;
-        res.chunk_pixels = c;
-        res.pixels_per_lane = l;
+  // the device's clocks settle before anything is timed: evaluations right after an idle
+  // spell run slower while the clocks ramp, which would count against whatever came first
+  {
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < kWarm && e == hipSuccess; ++r) e = eval_any(p, theta, nullptr, 0, 1, true, -1, nullptr, sm, true, fp64);
+    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    if (e != hipSuccess) st = CEL_EHIP;
+  }
+  // each candidate's time: the least over kPasses passes through all candidates (a drift of
+  // the clocks during the search then favours none of them); the fastest replaces the
+  // plan's setting when it beats it by the margin (or the setting is not a candidate)
+  auto pick = [&](const std::vector<double>& t, int cur) {
+    int f = 0;
+    for (int i = 1; i < (int)t.size(); ++i)
+      if (t[i] < t[f]) f = i;
+    return (cur >= 0 && !(t[f] < t[cur] * (1.0 - kMargin))) ? cur : f;
+  };
+  // work-item size and pixel-pass lanes together (the pass's cost depends on both) ...
+  const int np = (int)ppls.size();
+  std::vector<double> t_pair(chunks.size() * np, INFINITY);
+  for (int pass = 0; pass < kPasses && !st; ++pass)
+    for (int ci = 0; ci < (int)chunks.size() && !st; ++ci) {
+      if ((st = plan_retile(p, chunks[ci], sm)) || (st = ensure_variants(p, 1, fp64))) break;
+      for (int li = 0; li < np; ++li) {
+        p->opt.pixels_per_lane = ppls[li];
+        const double ms = time_it();
+        if (ms < 0) {
+          st = CEL_EHIP;
+          break;
+        }
+        t_pair[ci * np + li] = std::min(t_pair[ci * np + li], ms);
       }
     }
+  double best_ms = INFINITY;
+  if (!st) {
+    int cur = -1;
+    for (int i = 0; i < (int)t_pair.size(); ++i)
+      if (chunks[i / np] == cur_chunk && ppls[i % np] == cur_ppl) cur = i;
+    const int k = pick(t_pair, cur);
+    res.chunk_pixels = chunks[k / np];
+    res.pixels_per_lane = ppls[k % np];
+    best_ms = t_pair[k];
+    st = plan_retile(p, res.chunk_pixels, sm);
   }
-  // ... then the moment-map variants at the chosen pair, the current one first
-  if (!st) st = plan_retile(p, res.chunk_pixels, sm);
   if (!st) st = ensure_variants(p, 1, fp64);
+  // ... then the moment-map variants at the chosen pair
   if (!st) {
     p->opt.pixels_per_lane = res.pixels_per_lane;
-    const bool cur_in = has(maps, cur_map);
-    p->opt.map_pixels_per_lane = cur_map;
-    best_ms = cur_in ? time_it() : INFINITY;
-    if (best_ms < 0) st = CEL_EHIP;
-    for (int m : maps) {
-      if (st) break;
-      if (cur_in && m == cur_map) continue;
-      p->opt.map_pixels_per_lane = m;
-      const double ms = time_it();
-      if (ms < 0) {
-        st = CEL_EHIP;
-        break;
+    std::vector<double> t_map(maps.size(), INFINITY);
+    for (int pass = 0; pass < kPasses && !st; ++pass)
+      for (int mi = 0; mi < (int)maps.size(); ++mi) {
+        p->opt.map_pixels_per_lane = maps[mi];
+        const double ms = time_it();
+        if (ms < 0) {
+          st = CEL_EHIP;
+          break;
+        }
+        t_map[mi] = std::min(t_map[mi], ms);
       }
-      if (ms < best_ms * (1.0 - kMargin) || best_ms == INFINITY) {
-        best_ms = ms;
-        res.map_pixels_per_lane = m;
-      }
+    if (!st) {
+      int cur = -1;
+      for (int i = 0; i < (int)maps.size(); ++i)
+        if (maps[i] == cur_map) cur = i;
+      const int k = pick(t_map, cur);
+      res.map_pixels_per_lane = maps[k];
+      best_ms = t_map[k];
     }
   }
   for (auto& x : ev) (void)hipEventDestroy(x);
