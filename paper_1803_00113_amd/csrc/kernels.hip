@@ -347,18 +347,24 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
       dy[i] = py[i] - my;
     }
     const T d2 = box_dist2<T>(mx, my, box);
+    // this PSF component's cut radii, read before any is used: one wait for all of them
+    // instead of a scalar load and its wait ahead of each component
+    T rc[NEXP + NDEV];
+#pragma unroll
+    for (int j = 0; j < NEXP + NDEV; ++j) rc[j] = tb->rc2[k][j < NEXP ? j : kMaxProf + (j - NEXP)];
+    const T rcs = tb->rc2s[k];
     // a type of weight 0 sees its components at infinite distance: all skipped
     const auto d2s = uniform_cut_key(use_star ? d2 : (T)INFINITY), d2g = uniform_cut_key(use_gal ? d2 : (T)INFINITY);
-    if (!(d2s > cut_key(tb->rc2s[k])))
+    if (!(d2s > cut_key(rcs)))
       comp_own<T, PPL, DERIV ? 1 : 0>(tb->sq[k], nullptr, dx, dy, o.f1, o.g1x, o.g1y, z, z, z);
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
-      if (!(d2g > cut_key(tb->rc2[k][j])))
+      if (!(d2g > cut_key(rc[j])))
         comp_own<T, PPL, DERIV ? 2 : 0>(rec[k][j], rec[k][j] + 4, dx, dy, o.fe, o.gex, o.gey, o.sexx, o.sexy,
                                         o.seyy);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
-      if (!(d2g > cut_key(tb->rc2[k][kMaxProf + j])))
+      if (!(d2g > cut_key(rc[NEXP + j])))
         comp_own<T, PPL, DERIV ? 2 : 0>(rec[k][kMaxProf + j], rec[k][kMaxProf + j] + 4, dx, dy, o.fd, o.gdx,
                                         o.gdy, o.sdxx, o.sdxy, o.sdyy);
   }

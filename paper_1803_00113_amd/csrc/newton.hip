@@ -262,6 +262,10 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
     const T dx = px - mx, dy = py - my;
     const T xx = dx * dx, xy = (T)2 * dx * dy, yy = dy * dy;
     const auto d2k = uniform_cut_key(box_dist2<T>(mx, my, box));
+    // the cut radii of this PSF component, read before any is used (one wait for all)
+    T rc[NEXP + NDEV];
+#pragma unroll
+    for (int j = 0; j < NEXP + NDEV; ++j) rc[j] = tb->rc2[k][j < NEXP ? j : kMaxProf + (j - NEXP)];
     if (!(d2k > cut_key(tb->rc2s[k]))) {
       const T Pxx = tb->star[k][2], Pxy = tb->star[k][3], Pyy = tb->star[k][4];
       const T ux = fma(Pxx, dx, Pxy * dy), uy = fma(Pxy, dx, Pyy * dy);
@@ -275,12 +279,12 @@ __device__ __forceinline__ void eval_own_hess(const Table<T>* __restrict__ tb, i
     }
 #pragma unroll
     for (int j = 0; j < NEXP; ++j)
-      if (!(d2k > cut_key(tb->rc2[k][j])))
+      if (!(d2k > cut_key(rc[j])))
         gal_hess<T>(tb->gq[k][j], tb->gal[k][j][0], tb->gal[k][j][1], tb->gal[k][j][2], tb->gal[k][j][3],
                     tb->gt[k][j], omp, dx, dy, xx, xy, yy, fe, gme, gse, hmm, hms, hss);
 #pragma unroll
     for (int j = 0; j < NDEV; ++j)
-      if (!(d2k > cut_key(tb->rc2[k][kMaxProf + j])))
+      if (!(d2k > cut_key(rc[NEXP + j])))
         gal_hess<T>(tb->gq[k][kMaxProf + j], tb->gal[k][kMaxProf + j][0], tb->gal[k][kMaxProf + j][1],
                     tb->gal[k][kMaxProf + j][2], tb->gal[k][kMaxProf + j][3], tb->gt[k][kMaxProf + j], pi, dx, dy, xx,
                     xy, yy, fd, gmd, gsd, hmm, hms, hss);
