@@ -421,16 +421,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       g1z[j] = j < 2 ? o.g1[j] : (T)0;
       dz[j] = L0 * o.g0[j] - L1 * g1z[j];
     }
+    // the (z, z) block: with E_zz = w0 L0 h0 + w1 L1 h1 and
+    //   V_zz = 2 (k0 (g0 g0^T + f0 h0) + k1 (g1 g1^T + f1 h1) + w01 (dz dz^T + d (L0 h0 - L1 h1))),
+    // c_E E_zz + c_V V_zz = rho0 h0 + rho1 h1 + 2 c_V (k0 g0 g0^T + k1 g1 g1^T + w01 dz dz^T),
+    // rho0 = c_E w0 L0 + 2 c_V (k0 f0 + w01 L0 d), rho1 = c_E w1 L1 + 2 c_V (k1 f1 - w01 L1 d)
+    // (g1 and h1 vanish outside the centre coordinates z < 2)
+    const T cV2 = (T)2 * cV;
+    const T rho0 = fma(cE, w0 * L0, cV2 * fma(k0, f0, w01 * L0 * d));
+    const T rho1 = fma(cE, w1 * L1, cV2 * fma(k1, f1, -w01 * L1 * d));
+    T ag[6], cd[6], bg[2];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      ag[j] = cV2 * k0 * o.g0[j];
+      cd[j] = cV2 * w01 * dz[j];
+    }
+    bg[0] = cV2 * k1 * g1z[0];
+    bg[1] = cV2 * k1 * g1z[1];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
 #pragma unroll
       for (int j = i; j < 6; ++j) {
-        const T h0ij = o.h0[zidx(i, j)];
-        const T h1ij = (i < 2 && j < 2) ? o.h1[i + j] : (T)0;
-        const T Euv = w0 * L0 * h0ij + w1 * L1 * h1ij;
-        const T Vuv = (T)2 * (k0 * (o.g0[i] * o.g0[j] + f0 * h0ij) + k1 * (g1z[i] * g1z[j] + f1 * h1ij) +
-                              w01 * (dz[i] * dz[j] + d * (L0 * h0ij - L1 * h1ij)));
-        Q[qidx(5 + i, 5 + j)] += fma(cE, Euv, cV * Vuv);
+        T q = Q[qidx(5 + i, 5 + j)];
+        q = fma(rho0, o.h0[zidx(i, j)], q);
+        if (i < 2 && j < 2) {
+          q = fma(rho1, o.h1[i + j], q);
+          q = fma(bg[i], g1z[j], q);
+        }
+        q = fma(ag[i], o.g0[j], q);
+        q = fma(cd[i], dz[j], q);
+        Q[qidx(5 + i, 5 + j)] = q;
       }
     }
     T Eu[kPrim], Vu[kPrim];
@@ -480,15 +499,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     Q[qidx(1, 3)] += cV * ((T)2 * w0 * L0 * f0 * f0);
     Q[qidx(2, 2)] += cV * ((T)2 * w1 * e1 * f1 * f1 + (T)2 * w01 * f1 * f1);
     Q[qidx(2, 4)] += cV * ((T)2 * w1 * L1 * f1 * f1);
+    // the (amplitude, z) pairs are linear in g0, g1 and dz with weights fixed per pixel:
+    //   Q[0][z] += c_E (-dz) + c_V (-2 L0^2 e0 f0 g0 + 2 L1^2 e1 f1 g1 + 2 (1 - 2a) d dz)
+    //   Q[1][z] += c_E w0 g0 + c_V (4 w0 L0 e0 f0 g0 + 2 w01 (f0 dz + d g0))
+    //   Q[2][z] += c_E w1 g1 + c_V (4 w1 L1 e1 f1 g1 - 2 w01 (f1 dz + d g1))
+    //   Q[3][z] += c_V 2 w0 L0^2 f0 g0,  Q[4][z] += c_V 2 w1 L1^2 f1 g1
+    const T a0 = -cV2 * L0 * L0 * e0 * f0, b0 = cV2 * L1 * L1 * e1 * f1, c0 = fma(cV2 * oma2, d, -cE);
+    const T a1 = fma(cE, w0, cV2 * fma((T)2 * w0 * L0 * e0, f0, w01 * d)), c1 = cV2 * w01 * f0;
+    const T b2 = fma(cE, w1, cV2 * fma((T)2 * w1 * L1 * e1, f1, -w01 * d)), c2 = -cV2 * w01 * f1;
+    const T a3 = cV2 * w0 * L0 * L0 * f0, b4 = cV2 * w1 * L1 * L1 * f1;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      const T g0j = o.g0[j], g1j = g1z[j], dzj = dz[j];
-      Q[qidx(0, 5 + j)] += fma(cE, -dzj, cV * ((T)-2 * L0 * L0 * e0 * f0 * g0j + (T)2 * L1 * L1 * e1 * f1 * g1j +
-                                               (T)2 * oma2 * d * dzj));
-      Q[qidx(1, 5 + j)] += fma(cE, w0 * g0j, cV * ((T)4 * w0 * L0 * e0 * f0 * g0j + (T)2 * w01 * (dzj * f0 + d * g0j)));
-      Q[qidx(2, 5 + j)] += fma(cE, w1 * g1j, cV * ((T)4 * w1 * L1 * e1 * f1 * g1j - (T)2 * w01 * (dzj * f1 + d * g1j)));
-      Q[qidx(3, 5 + j)] += cV * ((T)2 * w0 * L0 * L0 * f0 * g0j);
-      Q[qidx(4, 5 + j)] += cV * ((T)2 * w1 * L1 * L1 * f1 * g1j);
+      const T g0j = o.g0[j], dzj = dz[j];
+      T q0 = fma(a0, g0j, fma(c0, dzj, Q[qidx(0, 5 + j)]));
+      T q1 = fma(a1, g0j, fma(c1, dzj, Q[qidx(1, 5 + j)]));
+      T q2 = fma(c2, dzj, Q[qidx(2, 5 + j)]);
+      if (j < 2) {
+        q0 = fma(b0, g1z[j], q0);
+        q2 = fma(b2, g1z[j], q2);
+        Q[qidx(4, 5 + j)] = fma(b4, g1z[j], Q[qidx(4, 5 + j)]);
+      }
+      Q[qidx(0, 5 + j)] = q0;
+      Q[qidx(1, 5 + j)] = q1;
+      Q[qidx(2, 5 + j)] = q2;
+      Q[qidx(3, 5 + j)] = fma(a3, g0j, Q[qidx(3, 5 + j)]);
     }
     col += step_cols;
     row += step_rows;
