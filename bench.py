@@ -72,6 +72,34 @@ def covering_pairs(prob):
     return int(total)
 
 
+def overlapped_units(prob):
+    """Number of active pixels of each patch that another source's patch also covers (the
+    pixels where a source's moments are read by its neighbours), summed over patches."""
+    total = 0
+    for n in range(prob.n_images):
+        ps = np.nonzero(prob.patch_img == n)[0]
+        x0, y0 = prob.patch_x0[ps].astype(np.int64), prob.patch_y0[ps].astype(np.int64)
+        x1, y1 = x0 + prob.patch_w[ps], y0 + prob.patch_h[ps]
+        src = prob.patch_src[ps]
+        order = np.argsort(x0, kind="stable")
+        masks = {}
+        for a_i, a in enumerate(order):
+            for b in order[a_i + 1:]:
+                if x0[b] >= x1[a]:
+                    break
+                if src[a] == src[b]:
+                    continue
+                xa, xb = max(x0[a], x0[b]), min(x1[a], x1[b])
+                ya, yb = max(y0[a], y0[b]), min(y1[a], y1[b])
+                if xb <= xa or yb <= ya:
+                    continue
+                for c in (a, b):
+                    m = masks.setdefault(c, np.zeros((prob.patch_h[ps[c]], prob.patch_w[ps[c]]), bool))
+                    m[ya - y0[c]:yb - y0[c], xa - x0[c]:xb - x0[c]] = True
+        total += sum(int(m.sum()) for m in masks.values())
+    return int(total)
+
+
 def counted_traffic():
     """HBM bytes per k_fused launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     profile, or None when the kernel source has changed since the counters were taken."""
@@ -465,6 +493,7 @@ def main():
     ppl = tuning["pixels_per_lane"] if tuning else (args.pixels_per_lane or 2)
     mppl = tuning["map_pixels_per_lane"] if tuning else 4
     pairs = covering_pairs(prob)
+    map_units = overlapped_units(prob)
     flops = units * FLOP_OWN + pairs * FLOP_PAIR
     nb = max(ncalls, 1)
     kernel_ms = ms_phase[2] / nb
@@ -478,9 +507,9 @@ def main():
                     algorithmic_bytes_per_launch=bytes_fused,
                     achieved_hbm_GBps=round(bytes_fused / (kernel_ms * 1e-3) / 1e9, 1),
                     map_kernel=dict(kernel=(f"k_maps<float, {mppl} px/lane>" if mppl > 0 else "k_maps_runs<float>"),
-                                    kernel_ms=round(maps_ms, 4),
-                                    achieved=round(units * FLOP_MAP / (maps_ms * 1e-3) / 1e12, 3),
-                                    algorithmic_flop_per_launch=units * FLOP_MAP),
+                                    kernel_ms=round(maps_ms, 4), overlapped_units=map_units,
+                                    achieved=round(map_units * FLOP_MAP / (maps_ms * 1e-3) / 1e12, 3),
+                                    algorithmic_flop_per_launch=map_units * FLOP_MAP),
                     executed=executed_work(units, pairs, kernel_ms, achieved),
                     phases_ms=[round(x / nb, 4) for x in ms_phase],
                     ms_per_step_with_phase_events=round(ms_step_events, 4))

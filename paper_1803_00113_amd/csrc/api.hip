@@ -666,22 +666,41 @@ cel_status build_tiling(cel_plan* p) {
   }
   p->order_h.resize(p->n_tasks);
   for (int64_t i = 0; i < p->n_tasks; ++i) p->order_h[i] = (int32_t)(keys[i] & 0xffffffffull);
-  // the moment maps are read only where another source's patch overlaps: keep the work
-  // items whose pixel rows meet a neighbour's rectangle
-  p->map_order_h.clear();
-  for (int t : p->order_h) {
-    const DTask& tk = p->tasks_h[t];
-    const DPatch& d = p->patches_h[tk.patch];
-    const int r0 = d.y0 + tk.pix_begin / d.w, r1 = d.y0 + (tk.pix_end - 1) / d.w;
-    const int c0 = r0 == r1 ? d.x0 + tk.pix_begin % d.w : d.x0;
-    const int c1 = r0 == r1 ? d.x0 + (tk.pix_end - 1) % d.w : d.x0 + d.w - 1;
-    bool need = false;
-    for (int nb = d.nbr_begin; nb < d.nbr_end && !need; ++nb) {
+  // the moment maps are read only where another source's patch overlaps: the map work
+  // items cover each patch's overlap box (the bounding box of its intersections with its
+  // neighbours' rectangles) in runs of at most CH pixels, row-major within the box, larger
+  // runs first (a patch's full runs stay together)
+  p->map_tasks_h.clear();
+  for (int i = 0; i < p->P; ++i) {
+    const DPatch& d = p->patches_h[i];
+    int bx0 = d.w, bx1 = 0, by0 = d.h, by1 = 0;
+    for (int nb = d.nbr_begin; nb < d.nbr_end; ++nb) {
       const DPatch& q = p->patches_h[p->nbr_idx_h[nb]];
-      need = q.x0 <= c1 && c0 < q.x0 + q.w && q.y0 <= r1 && r0 < q.y0 + q.h;
+      const int xa = std::max(q.x0 - d.x0, 0), xb = std::min(q.x0 + q.w - d.x0, d.w);
+      const int ya = std::max(q.y0 - d.y0, 0), yb = std::min(q.y0 + q.h - d.y0, d.h);
+      if (xb <= xa || yb <= ya) continue;
+      bx0 = std::min(bx0, xa);
+      bx1 = std::max(bx1, xb);
+      by0 = std::min(by0, ya);
+      by1 = std::max(by1, yb);
     }
-    if (need) p->map_order_h.push_back(t);
+    if (bx1 <= bx0 || by1 <= by0) continue;
+    const int bw = bx1 - bx0, n = bw * (by1 - by0);
+    for (int b = 0; b < n; b += CH) {
+      DMapTask m;
+      std::memset(&m, 0, sizeof(m));
+      m.patch = i;
+      m.pix_begin = b;
+      m.pix_end = std::min(n, b + CH);
+      m.x0 = bx0;
+      m.y0 = by0;
+      m.w = bw;
+      p->map_tasks_h.push_back(m);
+    }
   }
+  std::stable_sort(p->map_tasks_h.begin(), p->map_tasks_h.end(), [](const DMapTask& u, const DMapTask& v) {
+    return u.pix_end - u.pix_begin > v.pix_end - v.pix_begin;
+  });
   // per-colour work-item lists (for masked launches), in launch order
   p->class_tasks.resize(std::max<size_t>(p->class_tasks.size(), (size_t)p->n_colours));
   for (int c = 0; c < p->n_colours; ++c) p->class_tasks[c].clear();
@@ -871,7 +890,7 @@ extern "C" cel_status cel_prepare(cel_ctx* ctx, const cel_problem* pr, cel_plan*
   pk.add(&p->d_nbr, p->nbr_idx_h);
   pk.add(&p->d_tasks, p->tasks_h);
   pk.add(&p->d_order, p->order_h);
-  pk.add(&p->d_map_order, p->map_order_h);
+  pk.add(&p->d_map_tasks, p->map_tasks_h);
   pk.add(&p->d_patch_ptr, p->patch_ptr_h);
   pk.add(&p->d_npsf, npsf);
   pk.add(&p->d_prior, prior1);
@@ -945,13 +964,12 @@ template <typename T>
 static hipError_t launch_maps_t(cel_plan* p, const Table<T>* tables, hipStream_t sm) {
   MapArgs ma;
   std::memset(&ma, 0, sizeof(ma));
-  ma.tasks = p->d_tasks;
-  ma.order = p->d_map_order;
+  ma.tasks = p->d_map_tasks;
   ma.patches = p->d_patches;
   ma.base = tables;
   ma.maps = sizeof(T) == 8 ? (void*)p->d_maps64 : (void*)p->d_maps;
   ma.img_npsf = p->d_npsf;
-  return launch_maps<T>(ma, p->nexp, p->ndev, p->opt.map_pixels_per_lane, (int)p->map_order_h.size(), sm);
+  return launch_maps<T>(ma, p->nexp, p->ndev, p->opt.map_pixels_per_lane, (int)p->map_tasks_h.size(), sm);
 }
 
 // Enqueue prep + fused + finalize for `nv` variants starting at variant v0 over either all

@@ -159,7 +159,7 @@ extern "C" cel_status cel_plan_append(cel_ctx* ctx, cel_plan* p, const cel_probl
   }
   const int S0 = p->S, N0 = p->N, P0 = p->P;
   const int64_t U0 = p->n_units, T0 = p->n_tasks;
-  const int E0 = (int)p->nbr_idx_h.size(), M0 = (int)p->map_order_h.size();
+  const int E0 = (int)p->nbr_idx_h.size(), M0 = (int)p->map_tasks_h.size();
   // --- host tables --------------------------------------------------------------------
   p->images_h.insert(p->images_h.end(), q->images_h.begin(), q->images_h.end());
   for (DPatch d : q->patches_h) {
@@ -178,7 +178,10 @@ extern "C" cel_status cel_plan_append(cel_ctx* ctx, cel_plan* p, const cel_probl
     p->tasks_h.push_back(t);
   }
   for (int v : q->order_h) p->order_h.push_back(v + (int)T0);
-  for (int v : q->map_order_h) p->map_order_h.push_back(v + (int)T0);
+  for (DMapTask m : q->map_tasks_h) {
+    m.patch += P0;
+    p->map_tasks_h.push_back(m);
+  }
   for (int s = 1; s <= q->S; ++s) p->patch_ptr_h.push_back(q->patch_ptr_h[s] + P0);
   for (const auto& a : q->adj) {
     std::vector<int> b(a);
@@ -240,8 +243,8 @@ extern "C" cel_status cel_plan_append(cel_ctx* ctx, cel_plan* p, const cel_probl
       (st = g.put(p->d_nbr + E0, p->nbr_idx_h.data() + E0, p->nbr_idx_h.size() - E0, H2D)) ||
       (st = g.grow(&p->d_tasks, T0, T)) || (st = g.put(p->d_tasks + T0, p->tasks_h.data() + T0, T - T0, H2D)) ||
       (st = g.grow(&p->d_order, T0, T)) || (st = g.put(p->d_order + T0, p->order_h.data() + T0, T - T0, H2D)) ||
-      (st = g.grow(&p->d_map_order, M0, p->map_order_h.size())) ||
-      (st = g.put(p->d_map_order + M0, p->map_order_h.data() + M0, p->map_order_h.size() - M0, H2D)) ||
+      (st = g.grow(&p->d_map_tasks, M0, p->map_tasks_h.size())) ||
+      (st = g.put(p->d_map_tasks + M0, p->map_tasks_h.data() + M0, p->map_tasks_h.size() - M0, H2D)) ||
       (st = g.grow(&p->d_patch_ptr, S0 + 1, S + 1)) ||
       (st = g.put(p->d_patch_ptr + S0 + 1, p->patch_ptr_h.data() + S0 + 1, S - S0, H2D)) ||
       (st = g.grow(&p->d_npsf, N0, N)) || (st = g.put(p->d_npsf + N0, npsf.data(), npsf.size(), H2D)) ||
@@ -313,8 +316,8 @@ cel_status celmi::plan_retile(cel_plan* p, int chunk, hipStream_t sm) {
   if ((st = g.put(p->d_patches, p->patches_h.data(), p->patches_h.size(), H2D)) ||
       (st = g.grow(&p->d_tasks, 0, T)) || (st = g.put(p->d_tasks, p->tasks_h.data(), T, H2D)) ||
       (st = g.grow(&p->d_order, 0, T)) || (st = g.put(p->d_order, p->order_h.data(), T, H2D)) ||
-      (st = g.grow(&p->d_map_order, 0, p->map_order_h.size())) ||
-      (st = g.put(p->d_map_order, p->map_order_h.data(), p->map_order_h.size(), H2D)))
+      (st = g.grow(&p->d_map_tasks, 0, p->map_tasks_h.size())) ||
+      (st = g.put(p->d_map_tasks, p->map_tasks_h.data(), p->map_tasks_h.size(), H2D)))
     return st;
   for (int k = 0; k < 3; ++k) p->cls_cap[k].resize(std::max<size_t>(p->cls_cap[k].size(), C), 0);
   for (int c = 0; c < C; ++c) {

@@ -130,9 +130,16 @@ struct FusedArgs {
   int64_t active_v_stride;
 };
 
+// A work item of the moment-map pass: pixels [pix_begin, pix_end) of a patch's overlap box
+// (the bounding box of its intersections with the other sources' patches, w pixels wide,
+// at patch-local (x0, y0)), row-major within the box.  Neighbours read a patch's moments
+// only inside that box.
+struct DMapTask {
+  int32_t patch, pix_begin, pix_end, x0, y0, w, pad0, pad1;
+};
+
 struct MapArgs {
-  const DTask* tasks;
-  const int32_t* order;        // work items to run (null = identity)
+  const DMapTask* tasks;       // in launch order
   const DPatch* patches;
   const void* base;            // variant-0 tables
   void* maps;                  // out: (E_s, V_s) per packed pixel

@@ -370,13 +370,12 @@ __device__ __forceinline__ void eval_own(const Table<T>* __restrict__ tb, const 
   }
 }
 
-// k_maps: every source's own moments E_s, V_s (values only) on every pixel of its
-// patches at the base parameters, read by the pixel kernel for overlapping neighbours.
+// k_maps: every source's own moments E_s, V_s (values only) on its patches' overlap boxes at
+// the base parameters, read by the pixel kernel for overlapping neighbours.
 template <typename T, int PPL, int NEXP, int NDEV>
 __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
   const int pos = xcd_position((int)blockIdx.x, (int)gridDim.x);
-  const int t = a.order ? a.order[pos] : pos;
-  const DTask task = a.tasks[t];
+  const DMapTask task = a.tasks[pos];
   const DPatch P = a.patches[task.patch];
   const Table<T>* __restrict__ tb = reinterpret_cast<const Table<T>*>(a.base) + task.patch;
   const int K = a.img_npsf[P.img];
@@ -385,21 +384,29 @@ __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
   const T k0 = tb->hdr[4], k1 = tb->hdr[5], w01 = tb->hdr[6];
   __shared__ T rec[kMaxPsf][2 * kMaxProf][8];
   stage_records<T>(tb, K, lane, rec);
-  // patch-local coordinates of this lane's pixels, advanced by a carry per group
+  // box-local coordinates of this lane's pixels, advanced by a carry per group (patch-local:
+  // plus the box corner)
+  const int bw = task.w;
   const int step = 64 * PPL;
-  const int step_rows = step / P.w, step_cols = step - step_rows * P.w;
-  const T wT = (T)P.w, srT = (T)step_rows, scT = (T)step_cols;
-  T px[PPL], py[PPL];
+  const int step_rows = step / bw, step_cols = step - step_rows * bw;
+  int col[PPL], row[PPL];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) {
     const int idx = task.pix_begin + i * 64 + lane;
-    const int row = idx / P.w;
-    px[i] = (T)(idx - row * P.w);
-    py[i] = (T)row;
+    row[i] = idx / bw;
+    col[i] = idx - row[i] * bw;
   }
   for (int base = task.pix_begin; base < task.pix_end; base += step) {
-    T f0[PPL], f1[PPL], box[4];
-    run_box<T>(base, min(base + step, task.pix_end), P.w, box);
+    T px[PPL], py[PPL], f0[PPL], f1[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      px[i] = (T)(col[i] + task.x0);
+      py[i] = (T)(row[i] + task.y0);
+    }
+    int ibox[4];
+    run_box<int>(base, min(base + step, task.pix_end), bw, ibox);
+    const T box[4] = {(T)(ibox[0] + task.x0), (T)(ibox[1] + task.x0), (T)(ibox[2] + task.y0),
+                      (T)(ibox[3] + task.y0)};
     eval_values<T, PPL, NEXP, NDEV>(tb, rec, K, px, py, box, f0, f1);
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
@@ -408,20 +415,20 @@ __global__ __launch_bounds__(64) void k_maps(MapArgs a) {
       const T a0 = L0 * f0[i], a1 = L1 * f1[i], d = a0 - a1;
       const T Es = w0 * a0 + w1 * a1;
       const T Vs = fma(k0 * f0[i], f0[i], fma(k1 * f1[i], f1[i], w01 * d * d));
+      const int64_t at = P.off + (int64_t)(row[i] + task.y0) * P.w + col[i] + task.x0;
       if constexpr (sizeof(T) == 8)
-        reinterpret_cast<double2*>(a.maps)[P.off + idx] = make_double2(Es, Vs);
+        reinterpret_cast<double2*>(a.maps)[at] = make_double2(Es, Vs);
       else
-        reinterpret_cast<float2*>(a.maps)[P.off + idx] = make_float2(Es, Vs);
+        reinterpret_cast<float2*>(a.maps)[at] = make_float2(Es, Vs);
     }
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
-      T c = px[i] + scT, r = py[i] + srT;
-      if (c >= wT) {
-        c -= wT;
-        r += (T)1;
+      col[i] += step_cols;
+      row[i] += step_rows;
+      if (col[i] >= bw) {
+        col[i] -= bw;
+        row[i] += 1;
       }
-      px[i] = c;
-      py[i] = r;
     }
   }
 }
@@ -458,8 +465,7 @@ __device__ __forceinline__ void comp_run(const T* __restrict__ q, T c, T x0, T d
 template <typename T, int NEXP, int NDEV>
 __global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
   const int pos = xcd_position((int)blockIdx.x, (int)gridDim.x);
-  const int t = a.order ? a.order[pos] : pos;
-  const DTask task = a.tasks[t];
+  const DMapTask task = a.tasks[pos];
   const DPatch P = a.patches[task.patch];
   const Table<T>* __restrict__ tb = reinterpret_cast<const Table<T>*>(a.base) + task.patch;
   const int K = a.img_npsf[P.img];
@@ -467,7 +473,8 @@ __global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
   const T L0 = tb->hdr[0], L1 = tb->hdr[1], w0 = tb->hdr[2], w1 = tb->hdr[3];
   const T k0 = tb->hdr[4], k1 = tb->hdr[5], w01 = tb->hdr[6], pi = tb->hdr[7];
   const bool use_gal = tb->hdr[2] != (T)0, use_star = tb->hdr[3] != (T)0;
-  const int w = P.w, pb = task.pix_begin, pe = task.pix_end;
+  // rows and columns below are local to the overlap box (w wide at (bx, by) in the patch)
+  const int w = task.w, pb = task.pix_begin, pe = task.pix_end, bx = task.x0, by = task.y0;
   if (pe <= pb) return;
   const int r0 = pb / w, r1 = (pe - 1) / w;
   const int c_first = pb - r0 * w;
@@ -479,6 +486,10 @@ __global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
   const int n_runs = n_first + n_mid + (len_last + kRun - 1) / kRun;
   T box[4];
   run_box<T>(pb, pe, w, box);   // the whole work item (one pass or several)
+  box[0] += (T)bx;
+  box[1] += (T)bx;
+  box[2] += (T)by;
+  box[3] += (T)by;
   for (int g0 = 0; g0 < n_runs; g0 += 64) {
     const int g = g0 + lane;
     int row, col0, len;
@@ -503,7 +514,7 @@ __global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
     for (int i = 0; i < kRun; ++i) fe[i] = fd[i] = f1[i] = (T)0;
     for (int k = 0; k < K; ++k) {
       const T mx = tb->star[k][0], my = tb->star[k][1];
-      const T x0 = (T)col0 - mx, dy = (T)row - my;
+      const T x0 = (T)(col0 + bx) - mx, dy = (T)(row + by) - my;
       const T d2 = box_dist2<T>(mx, my, box);
       const auto d2s = uniform_cut_key(use_star ? d2 : (T)INFINITY), d2g = uniform_cut_key(use_gal ? d2 : (T)INFINITY);
       if (!(d2s > cut_key(tb->rc2s[k]))) comp_run<T>(tb->sq[k], tb->rq[k][0], x0, dy, f1);
@@ -515,7 +526,7 @@ __global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
         if (!(d2g > cut_key(tb->rc2[k][kMaxProf + j])))
           comp_run<T>(tb->gq[k][kMaxProf + j], tb->rq[k][1 + kMaxProf + j], x0, dy, fd);
     }
-    const int64_t at = P.off + (int64_t)row * w + col0;
+    const int64_t at = P.off + (int64_t)(row + by) * P.w + col0 + bx;
 #pragma unroll
     for (int i = 0; i < kRun; ++i) {
       if (i >= len) break;

@@ -54,7 +54,8 @@ struct cel_plan {
   // host copies
   std::vector<cel_image> images_h;
   std::vector<celmi::DPatch> patches_h;
-  std::vector<int32_t> patch_ptr_h, nbr_idx_h, order_h, map_order_h;
+  std::vector<int32_t> patch_ptr_h, nbr_idx_h, order_h;
+  std::vector<celmi::DMapTask> map_tasks_h;   // moment-map work items, in launch order
   std::vector<celmi::DTask> tasks_h;
   std::vector<std::vector<int>> adj;
   std::vector<int> colour;
@@ -70,7 +71,7 @@ struct cel_plan {
   int32_t* d_nbr = nullptr;
   celmi::DTask* d_tasks = nullptr;
   int32_t* d_order = nullptr;
-  int32_t* d_map_order = nullptr;
+  celmi::DMapTask* d_map_tasks = nullptr;
   int32_t* d_patch_ptr = nullptr;
   int32_t* d_npsf = nullptr;
   celmi::DPrior* d_prior = nullptr;
