@@ -75,7 +75,9 @@ def footprint_bytes(prob, variants=VARIANTS_EXACT, fp64=False, chunk=CHUNK):
     T = int(((sizes + chunk - 1) // chunk).sum())
     E = neighbour_entries(prob)
     C = 16                                   # colour classes (each adds three aligned lists)
-    pack = (_al(P * 48) + _al(N * IMAGE_RECORD) + _al(E * 4) + _al(T * 16) + 2 * _al(T * 4) + _al((S + 1) * 4)
+    # (work items 16 bytes, their launch order 4, moment-map work items 32: at most one per
+    # work item, a patch's overlap box being no larger than the patch)
+    pack = (_al(P * 48) + _al(N * IMAGE_RECORD) + _al(E * 4) + _al(T * 16) + _al(T * 4) + _al(T * 32) + _al((S + 1) * 4)
             + _al(N * 4) + PRIOR_RECORDS + _al(P * 8) + _al(len(prob.sky_knots) * 8) + _al(S * 8) + _al(S * 4)
             + (S + P + T) * 4 + 3 * C * 256)
     pixels = _al(U * 8) + _al(2 * P * 8) + _al(P * 8) + 256 + _al(U * 8)          # (count, sky), constants, maps
