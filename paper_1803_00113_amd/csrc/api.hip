@@ -618,8 +618,8 @@ extern "C" void cel_plan_free(cel_plan* plan) {
 }
 
 // The plan's work items at its chunk size (opt.chunk_pixels): the items of every patch, the
-// patches' item ranges, the launch order, the items the moment maps need and the per-colour
-// item lists.  Host tables only.
+// patches' item ranges, the launch order, the moment-map items over the patches' overlap
+// boxes and the per-colour item lists.  Host tables only.
 namespace celmi {
 cel_status build_tiling(cel_plan* p) {
   // work items: runs of chunk pixels per patch (patch-major), launch order by cost

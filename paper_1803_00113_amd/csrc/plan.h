@@ -187,8 +187,8 @@ hipError_t prep_class(cel_plan* p, const double* theta, int cls, const uint8_t* 
 // record a phase boundary event (k = 0..4) of the current evaluation when timing is on
 void phase_mark(cel_plan* p, int k, hipStream_t sm);
 cel_status ensure_newton(cel_plan* p);
-// the work items at p->opt.chunk_pixels (host tables: items, patch ranges, launch orders,
-// per-colour item lists)
+// the work items at p->opt.chunk_pixels (host tables: items, patch ranges, launch order,
+// moment-map items, per-colour item lists)
 cel_status build_tiling(cel_plan* p);
 // re-cut a prepared plan's work items at `chunk` pixels: host tables, their device copies and
 // the per-call scratch sized by the item count (waits for the device first)
