@@ -1045,10 +1045,17 @@ __global__ __launch_bounds__(64) void k_trsolve(TrArgs a) {
       const bool lowside = col < pc;
       const double alo = lowside ? al : be, ahi = lowside ? be : al;
       double c = 1.0, sn = 0.0;
-      if (fabs(ga) > 1e-15 * sqrt(alo * ahi)) {
-        const double zeta = (ahi - alo) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        c = 1.0 / sqrt(1.0 + t * t);
+      // the pair is rotated unless orthogonal to 1e-15 of its norms' product
+      // (|ga| > 1e-15 sqrt(alo ahi), compared squared)
+      if (ga * ga > 1e-30 * (alo * ahi)) {
+        // t = tan of the rotation angle, the root of smaller magnitude of t^2 + 2 zeta t - 1 = 0
+        // with zeta = (ahi - alo) / (2 ga), written without zeta: with d = ahi - alo,
+        // t = sign(d) 2 ga / (|d| + sqrt(d^2 + 4 ga^2)) (d = 0: t = sign(ga), both roots of
+        // size 1 annihilate the pair); c = 1 / sqrt(1 + t^2), |t| <= 1
+        const double d = ahi - alo;
+        const double r = sqrt(fma(d, d, 4.0 * ga * ga));
+        const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + r);
+        c = rsqrt(fma(t, t, 1.0));
         sn = c * t;
         rotated = 1.0;
       }
