@@ -697,14 +697,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     if (GRAD && (group % kFlush == kFlush - 1 || base + step >= task.pix_end)) {
       const bool first = group < kFlush;
+      // the wavefront sums first (independent: their shuffle chains overlap), then lane 0
+      // stores them
+      double sq[S_T];
 #pragma unroll
       for (int q = 0; q < S_T; ++q) {
         // the centre sums carry the records' scale c, the covariance sums c^2
         const double unscale = (q == S_MU_X || q == S_MU_Y) ? 1.0 / kExpScale
                                : (q == S_S_XX || q == S_S_XY || q == S_S_YY) ? 1.0 / (kExpScale * kExpScale) : 1.0;
-        const double s = wave_sum<T>((double)part[q]) * unscale;
-        if (lane == 0) out[q] = first ? s : out[q] + s;
+        sq[q] = wave_sum<T>((double)part[q]) * unscale;
         part[q] = (T)0;
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < S_T; ++q) out[q] = first ? sq[q] : out[q] + sq[q];
       }
     }
     // next group: advance each lane's coordinates by step pixels

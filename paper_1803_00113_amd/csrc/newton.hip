@@ -531,21 +531,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       row += 1;
     }
   }
+  // the slot row's 79 wavefront sums, eight at a time: the sums of a batch are independent,
+  // so their shuffle chains overlap, and lane 0 stores the batch after them (a store after
+  // every sum would hold each chain's latency on its own)
   double* out = a.hslots + (int64_t)t * kHSlots;
-  const double ts = wave_sum<double>(tsum), to = wave_sum<double>(town);
-  if (lane == 0) {
-    out[0] = ts;
-    out[1] = to;
-  }
+  constexpr int kNS = 2 + kPrim + kHQ;
+  constexpr int kBatch = 2;
 #pragma unroll
-  for (int u = 0; u < kPrim; ++u) {
-    const double v = wave_sum<double>((double)G[u]);
-    if (lane == 0) out[2 + u] = v;
-  }
+  for (int b = 0; b < kNS; b += kBatch) {
+    double sb[kBatch];
 #pragma unroll
-  for (int u = 0; u < kHQ; ++u) {
-    const double v = wave_sum<double>((double)Q[u]);
-    if (lane == 0) out[2 + kPrim + u] = v;
+    for (int i = 0; i < kBatch; ++i) {
+      const int u = b + i;
+      if (u < kNS)
+        sb[i] = wave_sum<double>(u == 0 ? tsum : u == 1 ? town : u < 2 + kPrim ? (double)G[u - 2] : (double)Q[u - 2 - kPrim]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i)
+        if (b + i < kNS) out[b + i] = sb[i];
+    }
   }
 }
 
