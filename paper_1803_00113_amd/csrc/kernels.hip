@@ -542,6 +542,14 @@ __global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
   }
 }
 
+// the factor that takes each gradient sum of a work item back to the plain derivative: the
+// centre sums carry the records' scale c, the covariance sums c^2
+static __device__ __constant__ double c_slot_unscale[S_T] = {
+    1.0, 1.0, 1.0, 1.0, 1.0, 1.0 / kExpScale, 1.0 / kExpScale, 1.0 / (kExpScale * kExpScale),
+    1.0 / (kExpScale * kExpScale), 1.0 / (kExpScale * kExpScale), 1.0};
+static_assert(S_MU_X == 5 && S_MU_Y == 6 && S_S_XX == 7 && S_S_YY == 9 && S_PI == 10 && S_T == 11,
+              "slot order of the scale table");
+
 template <typename T, int PPL, bool GRAD, int NEXP, int NDEV>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && PPL < 4 ? 6 : 1))) void k_fused(
     FusedArgs<T> a) {
@@ -697,20 +705,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     if (GRAD && (group % kFlush == kFlush - 1 || base + step >= task.pix_end)) {
       const bool first = group < kFlush;
-      // the wavefront sums first (independent: their shuffle chains overlap), then lane 0
-      // stores them
-      double sq[S_T];
+      // the 11 wavefront sums together; the lane holding sum q stores it, scaled back
+      const int slot = wave_sums_slot<S_T>(lane);
+      const double sq = wave_sums<S_T, 32, T>(part, lane);
 #pragma unroll
-      for (int q = 0; q < S_T; ++q) {
-        // the centre sums carry the records' scale c, the covariance sums c^2
-        const double unscale = (q == S_MU_X || q == S_MU_Y) ? 1.0 / kExpScale
-                               : (q == S_S_XX || q == S_S_XY || q == S_S_YY) ? 1.0 / (kExpScale * kExpScale) : 1.0;
-        sq[q] = wave_sum<T>((double)part[q]) * unscale;
-        part[q] = (T)0;
-      }
-      if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < S_T; ++q) out[q] = first ? sq[q] : out[q] + sq[q];
+      for (int q = 0; q < S_T; ++q) part[q] = (T)0;
+      if (slot >= 0) {
+        const double v = sq * c_slot_unscale[slot];
+        out[slot] = first ? v : out[slot] + v;
       }
     }
     // next group: advance each lane's coordinates by step pixels
@@ -725,20 +727,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       py[i] = r;
     }
   }
-  const double s_t = wave_sum<T>(acc_t), s_own = wave_sum<T>(acc_own);
-  if (lane == 0) {
-    out[S_T] = s_t;
-    out[S_T_OWN] = s_own;
-    if (GRAD && task.pix_begin >= task.pix_end)
-      for (int q = 0; q < S_T; ++q) out[q] = 0.0;
-  }
+  const double acc[2] = {acc_t, acc_own};
+  const double s_t = wave_sums<2>(acc, lane);   // lane 0: the pixel term, lane 32: the owned part
+  const int tslot = wave_sums_slot<2>(lane);
+  if (tslot >= 0) out[S_T + tslot] = s_t;
+  if (GRAD && task.pix_begin >= task.pix_end && lane == 0)
+    for (int q = 0; q < S_T; ++q) out[q] = 0.0;
 }
 
 // ----------------------------------------------------------------------------------------
-// k_finalize: one thread per (variant, source)
-
-// one wavefront per (variant, source): lanes take the source's patches, partial sums are
-// combined by a fixed butterfly, lane 0 applies the shape chain rule and the KL
+// k_finalize: one wavefront per (variant, source): lanes take the source's patches, partial
+// sums are combined in a fixed pairing, lane 0 applies the shape chain rule and the KL
+constexpr int kRed = 2 + kParamN + 3 + 1;   // pixel term, owned part, gradient, S gradient, profile
 __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   const int jj = blockIdx.x;
   const int lane = threadIdx.x;
@@ -822,15 +822,36 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
     gS[2] += h11;
     gpi += sm[S_PI];
   }
-  // combine the lanes' partial sums (fixed order: deterministic)
-  local = wave_sum<double>(local);
-  own = wave_sum<double>(own);
+  // combine the lanes' partial sums (fixed order: deterministic), all of them together; the
+  // lane holding a sum puts it in LDS, from where every lane reads them all
+  __shared__ double red[kRed];
+  if (a.want_grad) {
+    double v[kRed];
+    v[0] = local;
+    v[1] = own;
+    #pragma unroll
+    for (int k = 0; k < kParamN; ++k) v[2 + k] = g[k];
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) v[2 + kParamN + k] = gS[k];
+    v[kRed - 1] = gpi;
+    const double sv = wave_sums<kRed>(v, lane);
+    const int sl = wave_sums_slot<kRed>(lane);
+    if (sl >= 0) red[sl] = sv;
+  } else {
+    const double v[2] = {local, own};
+    const double sv = wave_sums<2>(v, lane);
+    const int sl = wave_sums_slot<2>(lane);
+    if (sl >= 0) red[sl] = sv;
+  }
+  __syncthreads();
+  local = red[0];
+  own = red[1];
   if (a.want_grad) {
     #pragma unroll
-    for (int k = 0; k < kParamN; ++k) g[k] = wave_sum<double>(g[k]);
+    for (int k = 0; k < kParamN; ++k) g[k] = red[2 + k];
     #pragma unroll
-    for (int k = 0; k < 3; ++k) gS[k] = wave_sum<double>(gS[k]);
-    gpi = wave_sum<double>(gpi);
+    for (int k = 0; k < 3; ++k) gS[k] = red[2 + kParamN + k];
+    gpi = red[kRed - 1];
   }
   // the central-difference variants (1..54) carry the pixel part of the gradient only: the
   // KL part of the Hessian is taken analytically by the trust-region kernel

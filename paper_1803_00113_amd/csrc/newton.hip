@@ -531,26 +531,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       row += 1;
     }
   }
-  // the slot row's 79 wavefront sums, eight at a time: the sums of a batch are independent,
-  // so their shuffle chains overlap, and lane 0 stores the batch after them (a store after
-  // every sum would hold each chain's latency on its own)
+  // the slot row's 79 wavefront sums, formed together in two groups (the first 64 of the 77
+  // first- and second-order sums, exchanged in the pixel precision at the first step; then
+  // the two objective sums with the last 13); the lane holding a sum stores it
   double* out = a.hslots + (int64_t)t * kHSlots;
-  constexpr int kNS = 2 + kPrim + kHQ;
-  constexpr int kBatch = 2;
+  constexpr int kGQ = kPrim + kHQ, kA = 64, kB = 2 + kGQ - kA;
+  {
+    T v[kA];
 #pragma unroll
-  for (int b = 0; b < kNS; b += kBatch) {
-    double sb[kBatch];
+    for (int i = 0; i < kA; ++i) v[i] = i < kPrim ? G[i] : Q[i - kPrim];
+    const double sv = wave_sums<kA, 32, T>(v, lane);
+    const int sl = wave_sums_slot<kA>(lane);
+    if (sl >= 0) out[2 + sl] = sv;
+  }
+  {
+    double v[kB];
+    v[0] = tsum;
+    v[1] = town;
 #pragma unroll
-    for (int i = 0; i < kBatch; ++i) {
-      const int u = b + i;
-      if (u < kNS)
-        sb[i] = wave_sum<double>(u == 0 ? tsum : u == 1 ? town : u < 2 + kPrim ? (double)G[u - 2] : (double)Q[u - 2 - kPrim]);
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i)
-        if (b + i < kNS) out[b + i] = sb[i];
-    }
+    for (int i = 2; i < kB; ++i) v[i] = (double)Q[kA + i - 2 - kPrim];
+    const double sv = wave_sums<kB>(v, lane);
+    const int sl = wave_sums_slot<kB>(lane);
+    if (sl >= 0) out[sl < 2 ? sl : kA + sl] = sv;
   }
 }
 

@@ -140,6 +140,50 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wavefront sums of M values per lane together.  At each lane offset O = 32, 16, ... a lane
+// keeps half of its values (the first half when bit O of its index is clear, else the second)
+// and adds the partner lane's copies of those, so the values per lane halve at every step
+// (M/2 + M/4 + ... exchanges instead of 6 M); once one value is left a plain butterfly
+// finishes.  Every sum takes the same additions, in the same pairing and operand order, as
+// wave_sum's butterfly, so the results are bitwise those of M wave_sum calls.  U is the
+// type the lanes hold (float values are exchanged as floats and widened before the first
+// addition, which is exact).  Lane l returns the sum of value wave_sums_slot<M>(l) (-1: none;
+// each value has exactly one such lane).
+template <int M, int O = 32, typename U>
+__device__ __forceinline__ double wave_sums(const U* v, int lane) {
+  if constexpr (M == 1) {
+    double x = (double)v[0];
+#pragma unroll
+    for (int off = O; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+  } else {
+    static_assert(O >= 1, "more values than lanes");
+    constexpr int A = (M + 1) / 2, B = M - A;
+    const bool hi = (lane & O) != 0;
+    double w[A];
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+      const U f = v[i], s = i < B ? v[A + i] : (U)0;
+      const U send = hi ? f : s;
+      w[i] = (double)(hi ? s : f) + (double)__shfl_xor(send, O, 64);
+    }
+    return wave_sums<A, O / 2, double>(w, lane);
+  }
+}
+
+template <int M, int O = 32>
+__device__ __forceinline__ int wave_sums_slot(int lane) {
+  if constexpr (M == 1) {
+    return (O == 0 || (lane & (2 * O - 1)) == 0) ? 0 : -1;
+  } else {
+    constexpr int A = (M + 1) / 2, B = M - A;
+    const int r = wave_sums_slot<A, O / 2>(lane);
+    if (r < 0) return -1;
+    if (lane & O) return r < B ? A + r : -1;
+    return r;
+  }
+}
+
 // Colour bounds of both types (Section 4.2.3 at their optimal weights): the values
 // -log sum_j w_j exp(-D_j) and their gradients with respect to the colour means (gm) and
 // log colour variances (gv), summed over the prior components j with weights xi_j,
