@@ -128,6 +128,7 @@ struct FusedArgs {
   const int32_t* img_npsf;     // PSF components per image
   const uint8_t* active_v;     // per (launch variant, source), row stride active_v_stride (nullptr = all)
   int64_t active_v_stride;
+  double unscale[2];           // set by the launcher: 1/c and 1/c^2 for the centre and covariance sums
 };
 
 // A work item of the moment-map pass: pixels [pix_begin, pix_end) of a patch's overlap box

@@ -542,14 +542,6 @@ __global__ __launch_bounds__(64) void k_maps_runs(MapArgs a) {
   }
 }
 
-// the factor that takes each gradient sum of a work item back to the plain derivative: the
-// centre sums carry the records' scale c, the covariance sums c^2
-static __device__ __constant__ double c_slot_unscale[S_T] = {
-    1.0, 1.0, 1.0, 1.0, 1.0, 1.0 / kExpScale, 1.0 / kExpScale, 1.0 / (kExpScale * kExpScale),
-    1.0 / (kExpScale * kExpScale), 1.0 / (kExpScale * kExpScale), 1.0};
-static_assert(S_MU_X == 5 && S_MU_Y == 6 && S_S_XX == 7 && S_S_YY == 9 && S_PI == 10 && S_T == 11,
-              "slot order of the scale table");
-
 template <typename T, int PPL, bool GRAD, int NEXP, int NDEV>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && PPL < 4 ? 6 : 1))) void k_fused(
     FusedArgs<T> a) {
@@ -705,14 +697,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     if (GRAD && (group % kFlush == kFlush - 1 || base + step >= task.pix_end)) {
       const bool first = group < kFlush;
-      // the 11 wavefront sums together; the lane holding sum q stores it, scaled back
-      const int slot = wave_sums_slot<S_T>(lane);
+      // the 11 wavefront sums together, then lane 0 reads each from the lane holding it and
+      // stores it scaled back (the centre sums carry the records' scale c, the covariance
+      // sums c^2); no per-lane slot index or address lives across the pixel loop
       const double sq = wave_sums<S_T, 32, T>(part, lane);
+      // (the factors come with the kernel arguments, in scalar registers: no vector registers
+      // hold them across the pixel loop)
+      const double* unscale = a.unscale;
 #pragma unroll
-      for (int q = 0; q < S_T; ++q) part[q] = (T)0;
-      if (slot >= 0) {
-        const double v = sq * c_slot_unscale[slot];
-        out[slot] = first ? v : out[slot] + v;
+      for (int q = 0; q < S_T; ++q) {
+        part[q] = (T)0;
+        const double s = read_lane(sq, wave_sums_lane<S_T>(q));
+        const double v = (q == S_MU_X || q == S_MU_Y) ? s * unscale[0]
+                         : (q == S_S_XX || q == S_S_XY || q == S_S_YY) ? s * unscale[1] : s;
+        if (lane == 0) out[q] = first ? v : out[q] + v;
       }
     }
     // next group: advance each lane's coordinates by step pixels
@@ -1017,10 +1015,13 @@ template <typename T, int PPL, bool GRAD>
 static hipError_t fused_dispatch(const FusedArgs<T>& a, int nexp, int ndev, int n_items, int n_var,
                                  hipStream_t st) {
   dim3 grid(n_items, n_var);
+  FusedArgs<T> k = a;
+  k.unscale[0] = 1.0 / kExpScale;
+  k.unscale[1] = 1.0 / (kExpScale * kExpScale);
   if (nexp == 6 && ndev == 8)
-    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 6, 8>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 6, 8>), grid, dim3(64), 0, st, k);
   else
-    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 8, 8>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_fused<T, PPL, GRAD, 8, 8>), grid, dim3(64), 0, st, k);
   return hipGetLastError();
 }
 

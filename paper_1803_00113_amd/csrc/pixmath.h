@@ -171,6 +171,24 @@ __device__ __forceinline__ double wave_sums(const U* v, int lane) {
   }
 }
 
+// the lane that wave_sums leaves holding the sum of value q (the lowest such lane)
+template <int M, int O = 32>
+__host__ __device__ constexpr int wave_sums_lane(int q) {
+  if constexpr (M == 1) {
+    return 0;
+  } else {
+    constexpr int A = (M + 1) / 2;
+    return q < A ? wave_sums_lane<A, O / 2>(q) : O + wave_sums_lane<A, O / 2>(q - A);
+  }
+}
+
+// a double held by lane l, read by every lane (l wavefront-uniform)
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 template <int M, int O = 32>
 __device__ __forceinline__ int wave_sums_slot(int lane) {
   if constexpr (M == 1) {
