@@ -13,7 +13,7 @@
 //                  reduced across the wavefront into one slot row per work item
 //   k_finalize     per source: fixed-order reduction of its slot rows, FP64 chain rule to
 //                  the unconstrained parameters, KL_s and its gradient (equations eq:kl,
-//                  kleq, the GMM colour bound and Supplement A)
+//                  kleq, the GMM colour bound and Supplement A) on a second wavefront
 //   k_total        one workgroup: fixed-order sum of the per-source owned objectives
 #include <math.h>
 
@@ -734,12 +734,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 }
 
 // ----------------------------------------------------------------------------------------
-// k_finalize: one wavefront per (variant, source): lanes take the source's patches, partial
-// sums are combined in a fixed pairing, lane 0 applies the shape chain rule and the KL
+// k_finalize: two wavefronts per (variant, source).  The first: lanes take the source's
+// patches, partial sums are combined in a fixed pairing, lane 0 applies the shape chain
+// rule.  The second meanwhile evaluates the KL term and its gradient, which do not depend on
+// the pixels, and hands them over in LDS.
 constexpr int kRed = 2 + kParamN + 3 + 1;   // pixel term, owned part, gradient, S gradient, profile
-__global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
+__global__ __launch_bounds__(128) void k_finalize(FinalizeArgs a) {
   const int jj = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool kl_wave = threadIdx.x >= 64;
   const int s = a.job_src ? a.job_src[jj] : jj + a.src_offset;
   const int vv = blockIdx.y;
   const int v = a.variant0 + vv;
@@ -747,101 +750,118 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
   if (a.active_v && !a.active_v[(int64_t)vv * a.active_v_stride + s]) return;
   double th[kThetaN];
   load_theta(a.theta, a.theta_trial, a.theta_vstride, s, v, a.fd_step, th, a.trial_variant, a.fd);
+  // the central-difference variants (1..54) carry the pixel part of the gradient only: the
+  // KL part of the Hessian is taken analytically by the trust-region kernel
+  const bool fd_variant = a.fd && v >= 1 && v <= 2 * kParamN;
+  // the lanes' partial sums (first wavefront) and the KL value and its gradient, negated
+  // (second wavefront)
+  __shared__ double red[kRed], klg[1 + kParamN];
   double g[kThetaN];
   #pragma unroll
   for (int k = 0; k < kThetaN; ++k) g[k] = 0.0;
-  const double aa = sigmoid(th[2]);
-  const double w0 = 1.0 - aa, w1 = aa;
+  double local = 0, own = 0, gS[3] = {0, 0, 0}, gpi = 0;
   const double ang = th[23], rad = exp(th[24]), prof = sigmoid(th[25]), axis = sigmoid(th[26]);
   double sig[3];
-  galaxy_cov(ang, rad, axis, sig);
-  double local = 0, own = 0, gS[3] = {0, 0, 0}, gpi = 0;
-  const double* slots = a.slots + (int64_t)vv * a.slot_variant_stride;
-  for (int p = a.patch_ptr[s] + lane; p < a.patch_ptr[s + 1]; p += 64) {
-    const DPatch P = a.patches[p];
-    double sm[13];
-    #pragma unroll
-    for (int q = 0; q < 13; ++q) sm[q] = 0.0;
-    for (int t = P.task_begin; t < P.task_end; ++t)
+  if (kl_wave) {
+    // KL by the whole wavefront; its gradient is subtracted from zeros here and added to the
+    // pixel gradient below (a - b and a + (0 - b) are the same number)
+    const double kl = a.no_kl ? 0.0 : kl_source_wave(*a.prior, th, g, fd_variant ? 0.0 : 1.0, lane);
+    if (lane == 0) {
+      klg[0] = kl;
       #pragma unroll
-      for (int q = 0; q < 13; ++q) sm[q] += slots[(int64_t)t * kSlots + q];
-    local += sm[S_T] + a.pix_const[2 * p];
-    own += sm[S_T_OWN] + a.pix_const[2 * p + 1];
-    if (!a.want_grad) continue;
-    const cel_image& im = a.images[P.img];
-    double L[2], M[2], var[2];
-    #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      double m = th[3 + i];
-      var[i] = exp(th[5 + i]);
-      #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double W = c_W[im.band][c];
-        m += W * th[7 + 4 * i + c];
-        var[i] += W * W * exp(th[15 + 4 * i + c]);
-      }
-      L[i] = im.iota * exp(m + 0.5 * var[i]);
-      M[i] = im.iota * im.iota * exp(2.0 * m + 2.0 * var[i]);
+      for (int k = 0; k < kParamN; ++k) klg[1 + k] = g[k];
     }
-    // E_s = w0 L0 f0 + w1 L1 f1,  V_s = w0 M0 f0^2 + w1 M1 f1^2 - E_s^2
-    const double A0 = sm[S_CE_F0], A1 = sm[S_CE_F1], B00 = sm[S_CV_F00], B11 = sm[S_CV_F11], B01 = sm[S_CV_F01];
-    const double gL0 = w0 * A0 - 2.0 * w0 * (w0 * L[0] * B00 + w1 * L[1] * B01);
-    const double gL1 = w1 * A1 - 2.0 * w1 * (w0 * L[0] * B01 + w1 * L[1] * B11);
-    const double gM0 = w0 * B00, gM1 = w1 * B11;
-    const double ga = L[1] * A1 - L[0] * A0 + M[1] * B11 - M[0] * B00 -
-                      2.0 * (w0 * L[0] * L[1] * B01 - w0 * L[0] * L[0] * B00 + w1 * L[1] * L[1] * B11 -
-                             w1 * L[0] * L[1] * B01);
-    g[2] += ga * aa * (1.0 - aa);
-    const double gL[2] = {gL0, gL1}, gM[2] = {gM0, gM1};
-    #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const double gm = gL[i] * L[i] + 2.0 * gM[i] * M[i];
-      const double gv = 0.5 * gL[i] * L[i] + 2.0 * gM[i] * M[i];
-      g[3 + i] += gm;
-      g[5 + i] += gv * exp(th[5 + i]);
-      #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double W = c_W[im.band][c];
-        g[7 + 4 * i + c] += gm * W;
-        g[15 + 4 * i + c] += gv * W * W * exp(th[15 + 4 * i + c]);
-      }
-    }
-    // centre: mu = A u + b
-    g[0] += im.A[0][0] * sm[S_MU_X] + im.A[1][0] * sm[S_MU_Y];
-    g[1] += im.A[0][1] * sm[S_MU_X] + im.A[1][1] * sm[S_MU_Y];
-    // covariance: S = A Sigma A^T;  d/dSigma (matrix) = A^T G A
-    const double Gxx = sm[S_S_XX], Gxy = 0.5 * sm[S_S_XY], Gyy = sm[S_S_YY];
-    const double a00 = im.A[0][0], a01 = im.A[0][1], a10 = im.A[1][0], a11 = im.A[1][1];
-    const double h00 = a00 * (Gxx * a00 + Gxy * a10) + a10 * (Gxy * a00 + Gyy * a10);
-    const double h01 = a00 * (Gxx * a01 + Gxy * a11) + a10 * (Gxy * a01 + Gyy * a11);
-    const double h11 = a01 * (Gxx * a01 + Gxy * a11) + a11 * (Gxy * a01 + Gyy * a11);
-    gS[0] += h00;
-    gS[1] += 2.0 * h01;
-    gS[2] += h11;
-    gpi += sm[S_PI];
-  }
-  // combine the lanes' partial sums (fixed order: deterministic), all of them together; the
-  // lane holding a sum puts it in LDS, from where every lane reads them all
-  __shared__ double red[kRed];
-  if (a.want_grad) {
-    double v[kRed];
-    v[0] = local;
-    v[1] = own;
-    #pragma unroll
-    for (int k = 0; k < kParamN; ++k) v[2 + k] = g[k];
-    #pragma unroll
-    for (int k = 0; k < 3; ++k) v[2 + kParamN + k] = gS[k];
-    v[kRed - 1] = gpi;
-    const double sv = wave_sums<kRed>(v, lane);
-    const int sl = wave_sums_slot<kRed>(lane);
-    if (sl >= 0) red[sl] = sv;
   } else {
-    const double v[2] = {local, own};
-    const double sv = wave_sums<2>(v, lane);
-    const int sl = wave_sums_slot<2>(lane);
-    if (sl >= 0) red[sl] = sv;
+    const double aa = sigmoid(th[2]);
+    const double w0 = 1.0 - aa, w1 = aa;
+    galaxy_cov(ang, rad, axis, sig);
+    const double* slots = a.slots + (int64_t)vv * a.slot_variant_stride;
+    for (int p = a.patch_ptr[s] + lane; p < a.patch_ptr[s + 1]; p += 64) {
+      const DPatch P = a.patches[p];
+      double sm[13];
+      #pragma unroll
+      for (int q = 0; q < 13; ++q) sm[q] = 0.0;
+      for (int t = P.task_begin; t < P.task_end; ++t)
+        #pragma unroll
+        for (int q = 0; q < 13; ++q) sm[q] += slots[(int64_t)t * kSlots + q];
+      local += sm[S_T] + a.pix_const[2 * p];
+      own += sm[S_T_OWN] + a.pix_const[2 * p + 1];
+      if (!a.want_grad) continue;
+      const cel_image& im = a.images[P.img];
+      double L[2], M[2], var[2];
+      #pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        double m = th[3 + i];
+        var[i] = exp(th[5 + i]);
+        #pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double W = c_W[im.band][c];
+          m += W * th[7 + 4 * i + c];
+          var[i] += W * W * exp(th[15 + 4 * i + c]);
+        }
+        L[i] = im.iota * exp(m + 0.5 * var[i]);
+        M[i] = im.iota * im.iota * exp(2.0 * m + 2.0 * var[i]);
+      }
+      // E_s = w0 L0 f0 + w1 L1 f1,  V_s = w0 M0 f0^2 + w1 M1 f1^2 - E_s^2
+      const double A0 = sm[S_CE_F0], A1 = sm[S_CE_F1], B00 = sm[S_CV_F00], B11 = sm[S_CV_F11], B01 = sm[S_CV_F01];
+      const double gL0 = w0 * A0 - 2.0 * w0 * (w0 * L[0] * B00 + w1 * L[1] * B01);
+      const double gL1 = w1 * A1 - 2.0 * w1 * (w0 * L[0] * B01 + w1 * L[1] * B11);
+      const double gM0 = w0 * B00, gM1 = w1 * B11;
+      const double ga = L[1] * A1 - L[0] * A0 + M[1] * B11 - M[0] * B00 -
+                        2.0 * (w0 * L[0] * L[1] * B01 - w0 * L[0] * L[0] * B00 + w1 * L[1] * L[1] * B11 -
+                               w1 * L[0] * L[1] * B01);
+      g[2] += ga * aa * (1.0 - aa);
+      const double gL[2] = {gL0, gL1}, gM[2] = {gM0, gM1};
+      #pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const double gm = gL[i] * L[i] + 2.0 * gM[i] * M[i];
+        const double gv = 0.5 * gL[i] * L[i] + 2.0 * gM[i] * M[i];
+        g[3 + i] += gm;
+        g[5 + i] += gv * exp(th[5 + i]);
+        #pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double W = c_W[im.band][c];
+          g[7 + 4 * i + c] += gm * W;
+          g[15 + 4 * i + c] += gv * W * W * exp(th[15 + 4 * i + c]);
+        }
+      }
+      // centre: mu = A u + b
+      g[0] += im.A[0][0] * sm[S_MU_X] + im.A[1][0] * sm[S_MU_Y];
+      g[1] += im.A[0][1] * sm[S_MU_X] + im.A[1][1] * sm[S_MU_Y];
+      // covariance: S = A Sigma A^T;  d/dSigma (matrix) = A^T G A
+      const double Gxx = sm[S_S_XX], Gxy = 0.5 * sm[S_S_XY], Gyy = sm[S_S_YY];
+      const double a00 = im.A[0][0], a01 = im.A[0][1], a10 = im.A[1][0], a11 = im.A[1][1];
+      const double h00 = a00 * (Gxx * a00 + Gxy * a10) + a10 * (Gxy * a00 + Gyy * a10);
+      const double h01 = a00 * (Gxx * a01 + Gxy * a11) + a10 * (Gxy * a01 + Gyy * a11);
+      const double h11 = a01 * (Gxx * a01 + Gxy * a11) + a11 * (Gxy * a01 + Gyy * a11);
+      gS[0] += h00;
+      gS[1] += 2.0 * h01;
+      gS[2] += h11;
+      gpi += sm[S_PI];
+    }
+    // combine the lanes' partial sums (fixed order: deterministic), all of them together; the
+    // lane holding a sum puts it in LDS, from where every lane reads them all
+    if (a.want_grad) {
+      double v[kRed];
+      v[0] = local;
+      v[1] = own;
+      #pragma unroll
+      for (int k = 0; k < kParamN; ++k) v[2 + k] = g[k];
+      #pragma unroll
+      for (int k = 0; k < 3; ++k) v[2 + kParamN + k] = gS[k];
+      v[kRed - 1] = gpi;
+      const double sv = wave_sums<kRed>(v, lane);
+      const int sl = wave_sums_slot<kRed>(lane);
+      if (sl >= 0) red[sl] = sv;
+    } else {
+      const double v[2] = {local, own};
+      const double sv = wave_sums<2>(v, lane);
+      const int sl = wave_sums_slot<2>(lane);
+      if (sl >= 0) red[sl] = sv;
+    }
   }
   __syncthreads();
+  if (kl_wave) return;
   local = red[0];
   own = red[1];
   if (a.want_grad) {
@@ -851,15 +871,13 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs a) {
     for (int k = 0; k < 3; ++k) gS[k] = red[2 + kParamN + k];
     gpi = red[kRed - 1];
   }
-  // the central-difference variants (1..54) carry the pixel part of the gradient only: the
-  // KL part of the Hessian is taken analytically by the trust-region kernel
-  const bool fd_variant = a.fd && v >= 1 && v <= 2 * kParamN;
-  // KL by the whole wavefront; subtracts the KL gradient
-  const double kl = a.no_kl ? 0.0 : kl_source_wave(*a.prior, th, g, fd_variant ? 0.0 : 1.0, lane);
   if (lane != 0) return;
+  const double kl = klg[0];
   local -= kl;
   own -= kl;
   if (a.want_grad) {
+    #pragma unroll
+    for (int k = 0; k < kParamN; ++k) g[k] += klg[1 + k];
     // Sigma(angle, radius, axis) chain rule
     const double c = cos(ang), sn = sin(ang), r2 = rad * rad, a2 = axis * axis;
     const double dxx_dt = 2.0 * r2 * c * sn * (a2 - 1.0), dyy_dt = -dxx_dt;
@@ -1067,7 +1085,7 @@ hipError_t launch_maps(const MapArgs& a, int nexp, int ndev, int ppl, int n_item
 
 hipError_t launch_finalize(const FinalizeArgs& a, int n_variants, hipStream_t st) {
   if (a.n_jobs <= 0 || n_variants <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(a.n_jobs, n_variants), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(k_finalize, dim3(a.n_jobs, n_variants), dim3(128), 0, st, a);
   return hipGetLastError();
 }
 
