@@ -37,8 +37,9 @@ enum Slot {
 //      V_s = k0 f0^2 + k1 f1^2 + w01 (L0 f0 - L1 f1)^2, f0 = pi f_dev + (1 - pi) f_exp)
 // star[k]: mean_x, mean_y, P_xx, P_xy, P_yy, log2 weight (weight includes the normaliser)
 // gal[k][j]: P_xx, P_xy, P_yy, log2 weight  (j < n_exp: exponential, then de Vaucouleurs)
-// rc2s[k], rc2[k][j]: squared distance from the component's centre beyond which its value
-// is below 2^-60 (from the smallest eigenvalue of its precision); -1 = negligible everywhere
+// rc2s[k], rc2[k][j]: squared distance from the component's centre beyond which flux times
+// density stays below 2^-30 (float tables) or 2^-60 (double) of the patch's smallest sky
+// value (bounded through the covariance's largest eigenvalue); -1 = negligible everywhere
 // hdr[8..9]: e0, e1 = expm1(variance of log l given the type) (for the analytic Hessian)
 // gt[k][j]: tau, tau^2, then tau^2/2 tr(E1 P E2 P) for the S-parameter pairs (xx,xx),
 //           (xx,xy), (xx,yy), (xy,xy), (xy,yy), (yy,yy)
@@ -46,7 +47,6 @@ enum Slot {
 // sq[k], gq[k][j]: (-log2(e)/2 (P_xx, P_xy, P_yy), log2 weight) -- the exponent of a
 //   component at offset d from its centre is q0 dx^2 + q1 (2 dx dy) + q2 dy^2 + q3
 //   (values-only evaluation: neighbour maps, Hessian)
-// off[k]: centre of PSF component k minus mu (the PSF mean offset)
 // rq[k][0], rq[k][1 + j]: exp(-P_xx) of the star and of galaxy component j = 2^(2 q0), the
 //   factor by which the ratio of a component's values at consecutive columns changes
 //   (values along a row by recurrence: neighbour maps; written when that map variant is on)
@@ -54,8 +54,8 @@ enum Slot {
 //   (from gq[k][j][0..2]) the own-source kernel forms the exponent as d . u' + q3 and the
 //   covariance derivative from u' u'^T - c^2 P = c^2 (u u^T - P); its mean and covariance
 //   sums are c and c^2 times the plain ones and are divided back once per slot row.  One
-//   component's eight values are one 32-byte scalar load.
-// gt is written only for the exact Hessian's preparations
+//   component's eight values are 32 bytes, copied to LDS once per work item.
+// gal and gt are written only for the exact Hessian's preparations
 template <typename T>
 // The records the pixel kernels read for every component (header, star records, cut radii,
 // exponent records) come first and together, so that a wavefront's scalar loads of one
@@ -72,9 +72,8 @@ struct alignas(64) Table {
   T gq[kMaxPsf][2 * kMaxProf][8];
   T gal[kMaxPsf][2 * kMaxProf][4];
   T gt[kMaxPsf][2 * kMaxProf][8];
-  T off[kMaxPsf][2];
   T rq[kMaxPsf][1 + 2 * kMaxProf];
-  T pad1[12];
+  T pad1[20];
 };
 
 // the exponent's scale in the own-source records: c = -log2(e) / 2

@@ -178,15 +178,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       tb->rc2s[k] = (T)rc2 + (T)0;   // (+ 0: a -0 becomes +0, for the integer-ordered cut test)
 #pragma unroll
       for (int e = 0; e < 4; ++e) tb->sq[k][e] = qv[e];
-      tb->off[k][0] = (T)ox;
-      tb->off[k][1] = (T)oy;
       if (a.records & kRecRuns) tb->rq[k][0] = (T)exp(-Pxx);
     } else {
-      T* r = tb->gal[k][j];
-      r[0] = pv[0];
-      r[1] = pv[1];
-      r[2] = pv[2];
-      r[3] = (T)lw;
       tb->rc2[k][j] = (T)rc2 + (T)0;
       if (a.records & kRecRuns) tb->rq[k][1 + j] = (T)exp(-Pxx);
 #pragma unroll
@@ -198,6 +191,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       gs[2] = (T)(c2 * Pyy);
       gs[3] = (T)(0.5 * tau);
       if (!(a.records & kRecHessian)) continue;
+      T* r = tb->gal[k][j];
+      r[0] = pv[0];
+      r[1] = pv[1];
+      r[2] = pv[2];
+      r[3] = (T)lw;
       const double h = 0.5 * tau * tau;
       T* q = tb->gt[k][j];
       q[0] = (T)tau;

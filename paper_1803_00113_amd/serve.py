@@ -37,7 +37,7 @@ VARIANTS_FD = 56             # Newton with a difference Hessian: iterate, 54 dif
 # 4 x 4, padding 4, galaxy exponent records 4 x 16 x 8, galaxy 4 x 16 x 4,
 # second-derivative terms 4 x 16 x 8, PSF offsets 4 x 2, row recurrence factors 4 x 17,
 # padding 12
-TABLE_F = 4 * (16 + 4 * 8 + 4 + 4 * 16 + 4 * 4 + 4 + 4 * 16 * 8 + 4 * 16 * 4 + 4 * 16 * 8 + 4 * 2 + 4 * 17 + 12)
+TABLE_F = 4 * (16 + 4 * 8 + 4 + 4 * 16 + 4 * 4 + 4 + 4 * 16 * 8 + 4 * 16 * 4 + 4 * 16 * 8 + 4 * 17 + 20)
 TABLE_D = 2 * TABLE_F
 CHUNK = 512                  # pixels per work item (the library's default)
 IMAGE_RECORD = 280           # sizeof(cel_image)
