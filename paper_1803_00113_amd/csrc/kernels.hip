@@ -732,15 +732,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 }
 
 // ----------------------------------------------------------------------------------------
-// k_finalize: two wavefronts per (variant, source).  The first: lanes take the source's
-// patches, partial sums are combined in a fixed pairing, lane 0 applies the shape chain
-// rule.  The second meanwhile evaluates the KL term and its gradient, which do not depend on
-// the pixels, and hands them over in LDS.
+// k_finalize: per (variant, source) a wavefront whose lanes take the source's patches,
+// partial sums combined in a fixed pairing, lane 0 applying the shape chain rule.  The KL
+// term and its gradient do not depend on the pixels: launched with two wavefronts per
+// block (small grids, where the kernel's time is one block's latency), the second evaluates
+// them meanwhile and hands them over in LDS; with one (large grids, where two wavefronts
+// per block would halve the blocks resident per compute unit) the first evaluates them
+// after its sums.  Either way the same operations give the same numbers.
 constexpr int kRed = 2 + kParamN + 3 + 1;   // pixel term, owned part, gradient, S gradient, profile
 __global__ __launch_bounds__(128) void k_finalize(FinalizeArgs a) {
   const int jj = blockIdx.x;
   const int lane = threadIdx.x & 63;
-  const bool kl_wave = threadIdx.x >= 64;
+  const bool split = blockDim.x > 64, kl_wave = threadIdx.x >= 64;
   const int s = a.job_src ? a.job_src[jj] : jj + a.src_offset;
   const int vv = blockIdx.y;
   const int v = a.variant0 + vv;
@@ -760,15 +763,18 @@ __global__ __launch_bounds__(128) void k_finalize(FinalizeArgs a) {
   double local = 0, own = 0, gS[3] = {0, 0, 0}, gpi = 0;
   const double ang = th[23], rad = exp(th[24]), prof = sigmoid(th[25]), axis = sigmoid(th[26]);
   double sig[3];
-  if (kl_wave) {
-    // KL by the whole wavefront; its gradient is subtracted from zeros here and added to the
-    // pixel gradient below (a - b and a + (0 - b) are the same number)
-    const double kl = a.no_kl ? 0.0 : kl_source_wave(*a.prior, th, g, fd_variant ? 0.0 : 1.0, lane);
+  // KL by the whole wavefront; its gradient is subtracted from zeros and added to the pixel
+  // gradient below (a - b and a + (0 - b) are the same number)
+  auto kl_to_lds = [&](double* gk) {
+    const double kl = a.no_kl ? 0.0 : kl_source_wave(*a.prior, th, gk, fd_variant ? 0.0 : 1.0, lane);
     if (lane == 0) {
       klg[0] = kl;
       #pragma unroll
-      for (int k = 0; k < kParamN; ++k) klg[1 + k] = g[k];
+      for (int k = 0; k < kParamN; ++k) klg[1 + k] = gk[k];
     }
+  };
+  if (kl_wave) {
+    kl_to_lds(g);
   } else {
     const double aa = sigmoid(th[2]);
     const double w0 = 1.0 - aa, w1 = aa;
@@ -860,6 +866,13 @@ __global__ __launch_bounds__(128) void k_finalize(FinalizeArgs a) {
   }
   __syncthreads();
   if (kl_wave) return;
+  if (!split) {
+    double gk[kThetaN];
+    #pragma unroll
+    for (int k = 0; k < kThetaN; ++k) gk[k] = 0.0;
+    kl_to_lds(gk);
+    __syncthreads();
+  }
   local = red[0];
   own = red[1];
   if (a.want_grad) {
@@ -1083,7 +1096,11 @@ hipError_t launch_maps(const MapArgs& a, int nexp, int ndev, int ppl, int n_item
 
 hipError_t launch_finalize(const FinalizeArgs& a, int n_variants, hipStream_t st) {
   if (a.n_jobs <= 0 || n_variants <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(a.n_jobs, n_variants), dim3(128), 0, st, a);
+  // the KL on its own wavefront while all blocks fit on the chip at once (two-wavefront
+  // blocks of k_finalize's ~210 registers per lane: four per compute unit, 256 units)
+  constexpr int64_t kSplitMaxBlocks = 1024;
+  const bool split = (int64_t)a.n_jobs * n_variants <= kSplitMaxBlocks;
+  hipLaunchKernelGGL(k_finalize, dim3(a.n_jobs, n_variants), dim3(split ? 128 : 64), 0, st, a);
   return hipGetLastError();
 }
 
